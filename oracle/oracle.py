@@ -1,0 +1,216 @@
+"""Python access to the FP64 CPU oracle (``gsl_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use this module; the product path never imports it.  It
+imports nothing from the GPU package, and the GPU package imports nothing
+from it; the two meet only through the seeded inputs of ``scenegen``.
+
+Functions take a ``scenegen.Scene`` (float32 arrays, widened here to float64)
+and ``scenegen.Camera`` objects and return float64 numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gsl_oracle.c")
+_LIB = os.path.join(_HERE, "libgsl_oracle.so")
+
+AMB_VALUE = 1
+AMB_GRAD = 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cam(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32), ("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("near_z", C.c_double), ("eps2d", C.c_double), ("alpha_min", C.c_double),
+                ("alpha_max", C.c_double), ("T_min", C.c_double), ("bg", C.c_double * 3),
+                ("guard", C.c_double), ("amb_rel", C.c_double)]
+
+
+@dataclass
+class Opts:
+    """Rendering constants (the paper's alpha clamp and transmittance cutoff;
+    the remaining values are this build's readings of what the paper leaves open)."""
+    near_z: float = 0.2
+    eps2d: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    bg: tuple = (0.0, 0.0, 0.0)
+    guard: float = 0.15
+    amb_rel: float = 1e-3
+
+    def c(self) -> _Opts:
+        o = _Opts()
+        o.near_z, o.eps2d, o.alpha_min, o.alpha_max, o.T_min = (
+            self.near_z, self.eps2d, self.alpha_min, self.alpha_max, self.T_min)
+        for k in range(3):
+            o.bg[k] = float(self.bg[k])
+        o.guard, o.amb_rel = self.guard, self.amb_rel
+        return o
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.orc_project.argtypes = [C.c_int64, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts), P, P, P, P, P]
+        L.orc_render_fwd.argtypes = [C.c_int64, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
+                                     C.c_int64, P, P, P, P, P, P]
+        L.orc_render_bwd.argtypes = [C.c_int64, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
+                                     C.c_int64, P, P, P, P, P, P, P, P, P]
+        L.orc_pixel_trace.argtypes = [C.c_int64, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
+                                      C.c_int32, C.c_int32, C.c_int32, P, P, P]
+        L.orc_pixel_trace.restype = C.c_int32
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def _cam(cam) -> _Cam:
+    c = _Cam()
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    R = np.asarray(cam.R_cw, np.float64).reshape(9)
+    t = np.asarray(cam.t_cw, np.float64).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    return c
+
+
+def _d(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _params(scene):
+    return (_d(scene.mean), _d(scene.scale), _d(scene.quat), _d(scene.opacity), _d(scene.color))
+
+
+def all_pixels(cam) -> np.ndarray:
+    v, u = np.mgrid[0:cam.height, 0:cam.width]
+    return np.ascontiguousarray(np.stack([u.ravel(), v.ravel()], 1).astype(np.int32))
+
+
+def project(scene, cam, opts: Opts = Opts()):
+    """Per-Gaussian projection into `cam`: p_cam (N,3), mean2d (N,2),
+    cov2d (N,3: xx, xy, yy incl. dilation), conic (N,3: A, B, C), status (N,)."""
+    N = scene.n
+    m, s, q, _, _ = _params(scene)
+    out = {k: np.zeros((N, w)) for k, w in (("p_cam", 3), ("mean2d", 2), ("cov2d", 3), ("conic", 3))}
+    out["status"] = np.zeros(N, np.int32)
+    co, oo = _cam(cam), opts.c()
+    lib().orc_project(N, _p(m), _p(s), _p(q), C.byref(co), C.byref(oo), _p(out["p_cam"]), _p(out["mean2d"]),
+                      _p(out["cov2d"]), _p(out["conic"]), _p(out["status"]))
+    return out
+
+
+def render(scene, cam, opts: Opts = Opts(), pixels=None):
+    """Composite the listed pixels ((P,2) int32 of (u, v); all pixels when None).
+
+    Returns rgb (P,3), T (P,), n (P,) contributor counts, last (P,) index of the
+    last contributor (-1 if none) and flags (P,) ambiguity bits."""
+    pix = all_pixels(cam) if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+    P = pix.shape[0]
+    m, s, q, o, c = _params(scene)
+    rgb = np.zeros((P, 3))
+    T = np.zeros(P)
+    n = np.zeros(P, np.int32)
+    last = np.zeros(P, np.int64)
+    flags = np.zeros(P, np.int32)
+    co, oo = _cam(cam), opts.c()
+    lib().orc_render_fwd(scene.n, _p(m), _p(s), _p(q), _p(o), _p(c), C.byref(co), C.byref(oo), P, _p(pix),
+                         _p(rgb), _p(T), _p(n), _p(last), _p(flags))
+    return {"rgb": rgb, "T": T, "n": n, "last": last, "flags": flags, "pixels": pix}
+
+
+def render_image(scene, cam, opts: Opts = Opts()):
+    """Full image as planar (3, H, W) plus T (H, W), n, last and flags (H, W)."""
+    r = render(scene, cam, opts)
+    H, W = cam.height, cam.width
+    return {"image": r["rgb"].T.reshape(3, H, W), "T": r["T"].reshape(H, W), "n": r["n"].reshape(H, W),
+            "last": r["last"].reshape(H, W), "flags": r["flags"].reshape(H, W)}
+
+
+def render_bwd(scene, cams, vs, opts: Opts = Opts(), pixels=None, want_g2d=False):
+    """Gradient of L = sum_c sum_p <v_c[p], I_c[p]>.
+
+    `vs[c]` is (P_c, 3) for the pixel list `pixels[c]` (all pixels when None),
+    or a planar (3, H, W) cotangent image.  Returns dict with mean (N,3),
+    scale (N,3), quat (N,4), opacity (N,), color (N,3), pose (C,6) as
+    (dphi, dt) of a left perturbation of each T_CW, and g2d (C,N,9) if asked."""
+    N = scene.n
+    m, s, q, o, c = _params(scene)
+    g = {"mean": np.zeros((N, 3)), "scale": np.zeros((N, 3)), "quat": np.zeros((N, 4)),
+         "opacity": np.zeros(N), "color": np.zeros((N, 3)), "pose": np.zeros((len(cams), 6))}
+    if want_g2d:
+        g["g2d"] = np.zeros((len(cams), N, 9))
+    oo = opts.c()
+    for ci, cam in enumerate(cams):
+        v = np.asarray(vs[ci], np.float64)
+        if pixels is None or pixels[ci] is None:
+            pix = all_pixels(cam)
+            if v.ndim == 3:
+                v = v.reshape(3, -1).T
+        else:
+            pix = np.ascontiguousarray(pixels[ci], dtype=np.int32).reshape(-1, 2)
+        v = _d(v, (-1, 3))
+        assert v.shape[0] == pix.shape[0]
+        pose = np.zeros(6)
+        g2 = np.zeros((N, 9)) if want_g2d else None
+        co = _cam(cam)
+        lib().orc_render_bwd(N, _p(m), _p(s), _p(q), _p(o), _p(c), C.byref(co), C.byref(oo), pix.shape[0],
+                             _p(pix), _p(v), _p(g["mean"]), _p(g["scale"]), _p(g["quat"]), _p(g["opacity"]),
+                             _p(g["color"]), _p(pose), _p(g2))
+        g["pose"][ci] = pose
+        if want_g2d:
+            g["g2d"][ci] = g2
+    return g
+
+
+def pixel_trace(scene, cam, u, v, opts: Opts = Opts(), cap=100000):
+    m, s, q, o, c = _params(scene)
+    ids = np.zeros(cap, np.int64)
+    al = np.zeros(cap)
+    Ts = np.zeros(cap)
+    co, oo = _cam(cam), opts.c()
+    n = lib().orc_pixel_trace(scene.n, _p(m), _p(s), _p(q), _p(o), _p(c), C.byref(co), C.byref(oo),
+                              int(u), int(v), cap, _p(ids), _p(al), _p(Ts))
+    return ids[:n].copy(), al[:n].copy(), Ts[:n].copy()

@@ -1,0 +1,394 @@
+"""Pins for the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms (single Gaussian on the optical axis, two Gaussians), library routines
+for special cases (scipy rotations), invariants (rigid motion, permutation,
+partition of unity, monotone transmittance), brute-force evaluation of the
+compositing sum as an explicit product, and central finite differences of the
+forward for every gradient, including the camera twist.
+"""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import scenegen as S
+from scenegen import Camera, Scene
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _cam(W=32, H=24, f=30.0, R=np.eye(3), t=np.zeros(3), cx=None, cy=None):
+    return Camera(f, f * 1.1, W / 2 if cx is None else cx, H / 2 if cy is None else cy, W, H, R, t)
+
+
+def _scene(mean, scale, quat, opac, color, cams):
+    return Scene(np.array(mean), np.array(scale), np.array(quat), np.array(opac), np.array(color), cams)
+
+
+def _wxyz_to_scipy(q):
+    q = np.asarray(q, np.float64)
+    return Rotation.from_quat(np.concatenate([q[..., 1:], q[..., :1]], -1))
+
+
+# ---------------------------------------------------------------- projection
+
+def test_projection_on_axis_closed_form(oracle):
+    """Gaussian at (0, 0, z) under an identity camera: mean2d = (cx, cy) and
+    Sigma2D = (f/z)^2 (R S^2 R^T)[:2, :2] + eps I, with R from scipy."""
+    cam = _cam(W=64, H=48, f=80.0)
+    rng = np.random.default_rng(0)
+    n = 20
+    z = rng.uniform(1, 4, n)
+    mean = np.stack([np.zeros(n), np.zeros(n), z], 1)
+    scale = rng.uniform(0.01, 0.2, (n, 3))
+    quat = rng.normal(size=(n, 4))
+    sc = _scene(mean, scale, quat, np.full(n, 0.5), np.ones((n, 3)), [cam])
+    o = oracle.Opts(eps2d=0.3)
+    p = oracle.project(sc, cam, o)
+    assert np.all(p["status"] & 1)
+    np.testing.assert_allclose(p["mean2d"], np.tile([cam.cx, cam.cy], (n, 1)), rtol=0, atol=1e-12)
+    m, s = sc.mean.astype(np.float64), sc.scale.astype(np.float64)
+    R = _wxyz_to_scipy(sc.quat.astype(np.float64)).as_matrix()
+    for i in range(n):
+        Sig = R[i] @ np.diag(s[i] ** 2) @ R[i].T
+        J = np.diag([cam.fx / m[i, 2], cam.fy / m[i, 2]])
+        S2 = J @ Sig[:2, :2] @ J + 0.3 * np.eye(2)
+        np.testing.assert_allclose(p["cov2d"][i], [S2[0, 0], S2[0, 1], S2[1, 1]], rtol=1e-12)
+        Q = np.linalg.inv(S2)
+        np.testing.assert_allclose(p["conic"][i], [Q[0, 0], Q[0, 1], Q[1, 1]], rtol=1e-10)
+
+
+def test_projection_roll_swaps_axes(oracle):
+    """A 90 degree rotation of the Gaussian about the optical axis swaps the
+    2D covariance axes (square pixels)."""
+    cam = Camera(50.0, 50.0, 16, 12, 32, 24, np.eye(3), np.zeros(3))
+    q0 = [1, 0, 0, 0]
+    q90 = [np.cos(np.pi / 4), 0, 0, np.sin(np.pi / 4)]
+    sc = _scene([[0, 0, 2.0], [0, 0, 2.0]], [[0.1, 0.03, 0.05]] * 2, [q0, q90], [0.5, 0.5], np.ones((2, 3)),
+                [cam])
+    p = oracle.project(sc, cam, oracle.Opts(eps2d=0.0))
+    a, b = p["cov2d"]
+    np.testing.assert_allclose([a[0], a[2]], [b[2], b[0]], rtol=1e-6)
+    np.testing.assert_allclose(a[0], (50 * float(np.float32(0.1)) / 2) ** 2, rtol=1e-6)
+
+
+def test_projection_matches_linearised_pinhole(oracle):
+    """Off-axis Gaussians under a rotated camera: mean2d is the pinhole image
+    of R_cw p + t computed with scipy, and Sigma2D - eps I equals J Sigma_C J^T
+    where J is a central-difference Jacobian of the pinhole map."""
+    rng = np.random.default_rng(1)
+    Rc = Rotation.from_rotvec(rng.normal(0, 0.3, 3)).as_matrix()
+    cam = Camera(70.0, 65.0, 33.0, 21.0, 64, 48, Rc, rng.normal(0, 0.5, 3))
+    sc = S.random_scene(30, cam, seed=7, zmin=1.5, zmax=4)
+    p = oracle.project(sc, cam, oracle.Opts(eps2d=0.3))
+    Rcw, t = cam.R_cw.astype(np.float64), cam.t_cw.astype(np.float64)
+
+    def pinhole(pc):
+        return np.array([cam.fx * pc[0] / pc[2] + cam.cx, cam.fy * pc[1] / pc[2] + cam.cy])
+
+    R = _wxyz_to_scipy(sc.quat.astype(np.float64)).as_matrix()
+    for i in range(sc.n):
+        pc = Rcw @ sc.mean[i].astype(np.float64) + t
+        np.testing.assert_allclose(p["p_cam"][i], pc, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(p["mean2d"][i], pinhole(pc), rtol=1e-12)
+        h = 1e-6
+        Jn = np.stack([(pinhole(pc + h * e) - pinhole(pc - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        s = sc.scale[i].astype(np.float64)
+        SigC = Rcw @ R[i] @ np.diag(s ** 2) @ R[i].T @ Rcw.T
+        S2 = Jn @ SigC @ Jn.T
+        np.testing.assert_allclose(p["cov2d"][i], [S2[0, 0] + 0.3, S2[0, 1], S2[1, 1] + 0.3], rtol=1e-6)
+
+
+def test_projection_culls_near_and_guard(oracle):
+    cam = _cam(W=40, H=30, f=40.0)
+    mean = [[0, 0, 0.1], [0, 0, 0.25], [100.0, 0, 1.0], [0.5, 0, 1.0]]
+    sc = _scene(mean, [[0.05] * 3] * 4, [[1, 0, 0, 0]] * 4, [0.5] * 4, np.ones((4, 3)), [cam])
+    st = oracle.project(sc, cam, oracle.Opts())["status"]
+    assert list(st & 1) == [0, 1, 0, 1]
+
+
+def test_rigid_motion_invariance(oracle):
+    """Moving the scene and the camera by the same rigid motion leaves the
+    projection and the image unchanged."""
+    cam = _cam(W=40, H=30, f=35.0)
+    sc = S.random_scene(40, cam, seed=3, zmin=1.5, zmax=4.0)
+    r0 = Rotation.from_rotvec([0.3, -0.5, 0.9])
+    t0 = np.array([1.0, -2.0, 0.5])
+    m2 = r0.apply(sc.mean.astype(np.float64)) + t0
+    q2 = (r0 * _wxyz_to_scipy(sc.quat)).as_quat()  # scipy (x, y, z, w)
+    q2 = np.concatenate([q2[:, 3:], q2[:, :3]], 1) * np.linalg.norm(sc.quat.astype(np.float64), axis=1,
+                                                                    keepdims=True)
+    R2 = cam.R_cw.astype(np.float64) @ r0.as_matrix().T
+    t2 = cam.t_cw.astype(np.float64) - R2 @ t0
+    # keep everything exactly representable: compare against the float32-rounded moved scene
+    sc2 = _scene(m2, sc.scale, q2, sc.opacity, sc.color, [])
+    cam2 = Camera(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height, R2, t2)
+    a = oracle.render_image(sc, cam, oracle.Opts())
+    b = oracle.render_image(sc2, cam2, oracle.Opts())
+    # float32 rounding of the moved inputs perturbs values at the 1e-6 level
+    ok = (a["flags"] == 0) & (b["flags"] == 0)
+    assert ok.mean() > 0.95
+    np.testing.assert_allclose(a["image"][:, ok], b["image"][:, ok], atol=2e-5)
+
+
+# ---------------------------------------------------------------- compositing
+
+def test_single_gaussian_closed_form(oracle):
+    """One Gaussian on the axis: I(x) = c min(0.99, sigma G(x)) + (1 - a) bg
+    where a >= 1/255, else bg, with G the axis-aligned 2D Gaussian."""
+    cam = _cam(W=48, H=40, f=60.0)
+    sc = _scene([[0, 0, 2.0]], [[0.08, 0.05, 0.1]], [[1, 0, 0, 0]], [0.9], [[0.3, 0.6, 0.9]], [cam])
+    bg = (0.1, 0.2, 0.05)
+    o = oracle.Opts(bg=bg, eps2d=0.3)
+    r = oracle.render_image(sc, cam, o)
+    s = sc.scale[0].astype(np.float64)
+    sxx = (cam.fx * s[0] / 2.0) ** 2 + 0.3
+    syy = (cam.fy * s[1] / 2.0) ** 2 + 0.3
+    v, u = np.mgrid[0:cam.height, 0:cam.width]
+    dx, dy = u + 0.5 - cam.cx, v + 0.5 - cam.cy
+    G = np.exp(-0.5 * (dx ** 2 / sxx + dy ** 2 / syy))
+    a = np.minimum(0.99, float(np.float32(0.9)) * G)
+    a = np.where(a >= 1 / 255, a, 0.0)
+    for ch in range(3):
+        want = float(sc.color[0, ch]) * a + (1 - a) * bg[ch]
+        np.testing.assert_allclose(r["image"][ch], want, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["T"], 1 - a, atol=1e-12)
+    assert np.all(r["n"] == (a > 0))
+
+
+def test_two_gaussian_closed_form(oracle):
+    """Front and back Gaussian: I = c_f a_f + c_b a_b (1 - a_f), the front one
+    chosen by depth whatever the index order."""
+    cam = _cam(W=24, H=20, f=40.0)
+    sc = _scene([[0.02, 0, 3.0], [0, 0.01, 1.5]], [[0.1, 0.1, 0.1], [0.05, 0.07, 0.05]],
+                [[1, 0, 0, 0], [1, 0, 0, 0]], [0.7, 0.6], [[1, 0, 0], [0, 1, 0]], [cam])
+    o = oracle.Opts(eps2d=0.3)
+    r = oracle.render_image(sc, cam, o)
+    p = oracle.project(sc, cam, o)
+    v, u = np.mgrid[0:cam.height, 0:cam.width]
+    al = []
+    for i in range(2):
+        dx, dy = u + 0.5 - p["mean2d"][i, 0], v + 0.5 - p["mean2d"][i, 1]
+        A, B, Cc = p["conic"][i]
+        a = np.minimum(0.99, float(sc.opacity[i]) * np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + Cc * dy * dy)))
+        al.append(np.where(a >= 1 / 255, a, 0.0))
+    front, back = al[1], al[0]  # index 1 is nearer
+    want = np.stack([back * (1 - front), front, np.zeros_like(front)])
+    np.testing.assert_allclose(r["image"], want, atol=1e-12)
+
+
+def test_partition_of_unity(oracle):
+    """All colours 1 and background 0: every channel equals 1 - T_final."""
+    cam = _cam(W=40, H=32, f=30.0)
+    sc = S.random_scene(200, cam, seed=11, zmin=1, zmax=3, smin=0.05, smax=0.3)
+    sc.color[:] = 1.0
+    r = oracle.render_image(sc, cam, oracle.Opts())
+    for ch in range(3):
+        np.testing.assert_allclose(r["image"][ch], 1 - r["T"], atol=1e-12)
+    assert r["T"].min() >= 1e-4  # the walk stops before crossing the cutoff
+    assert r["T"].max() <= 1.0
+
+
+def test_transmittance_monotone_and_explicit_product(oracle):
+    """Brute force on a tiny scene: the contributor set is exactly the
+    Gaussians in (float depth, index) order whose alpha reaches 1/255, cut
+    before the transmittance would drop below 1e-4; the image equals the
+    explicit sum of c_i a_i prod_{j<i}(1 - a_j) over that set."""
+    cam = _cam(W=16, H=12, f=14.0)
+    sc = S.random_scene(16, cam, seed=5, zmin=1, zmax=2, smin=0.05, smax=0.3)
+    o = oracle.Opts()
+    p = oracle.project(sc, cam, o)
+    r = oracle.render_image(sc, cam, o)
+    z32 = p["p_cam"][:, 2].astype(np.float32)
+    order = sorted([i for i in range(sc.n) if p["status"][i] & 1], key=lambda i: (z32[i], i))
+    for vv in range(cam.height):
+        for uu in range(cam.width):
+            ids, al, Ts = oracle.pixel_trace(sc, cam, uu, vv, o)
+            assert np.all(np.diff(Ts) <= 0) and np.all(Ts <= 1)
+            # brute-force contributor set
+            T = 1.0
+            want_ids, want_al = [], []
+            for i in order:
+                dx, dy = uu + 0.5 - p["mean2d"][i, 0], vv + 0.5 - p["mean2d"][i, 1]
+                A, B, Cc = p["conic"][i]
+                a = min(0.99, float(sc.opacity[i]) * np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + Cc * dy * dy)))
+                if a < 1 / 255:
+                    continue
+                if T * (1 - a) < 1e-4:
+                    break
+                want_ids.append(i)
+                want_al.append(a)
+                T *= 1 - a
+            assert list(ids) == want_ids
+            np.testing.assert_allclose(al, want_al, rtol=1e-13)
+            # explicit product form of the compositing sum
+            c = sc.color.astype(np.float64)
+            val = sum(c[i] * a * np.prod([1 - b for b in want_al[:k]]) for k, (i, a) in
+                      enumerate(zip(want_ids, want_al)))
+            np.testing.assert_allclose(r["image"][:, vv, uu], val if len(want_ids) else np.zeros(3),
+                                       atol=1e-12)
+
+
+def test_permutation_invariance(oracle):
+    cam = _cam(W=40, H=30, f=35.0)
+    sc = S.random_scene(300, cam, seed=21, smin=0.03, smax=0.2)
+    perm = np.random.default_rng(0).permutation(sc.n)
+    a = oracle.render_image(sc, cam, oracle.Opts())
+    b = oracle.render_image(sc.permuted(perm), cam, oracle.Opts())
+    np.testing.assert_array_equal(a["image"], b["image"])
+    np.testing.assert_array_equal(a["T"], b["T"])
+
+
+# ---------------------------------------------------------------- gradients
+
+def _loss(oracle, sc, cams, Ws, o):
+    tot = 0.0
+    for cam, W in zip(cams, Ws):
+        tot += float(np.sum(oracle.render_image(sc, cam, o)["image"] * W))
+    return tot
+
+
+def _flags(oracle, sc, cams, o):
+    return [oracle.render_image(sc, c, o)["flags"] for c in cams]
+
+
+def _fd_scene(seed, n=6, W=20, H=16, clamp=False):
+    cam = _cam(W=W, H=H, f=18.0)
+    sc = S.random_scene(n, cam, seed=seed, zmin=1.0, zmax=2.0, smin=0.08, smax=0.3, unnormalised_quats=True)
+    if clamp:  # opacities near 1: the alpha clamp is active around the centres
+        sc.opacity[:] = np.float32(0.995)
+    else:  # opacities away from the clamp so that no alpha sits on it
+        sc.opacity[:] = np.float32(0.3) + np.float32(0.5) * sc.opacity
+    return sc, cam
+
+
+@pytest.mark.parametrize("seed,clamp", [(1, False), (2, False), (3, True)])
+def test_gradients_match_central_differences(oracle, seed, clamp):
+    """Analytic gradients for L = <W, I> against FP64 central differences of
+    the forward, for every parameter of every Gaussian (with and without
+    pixels where the alpha clamp holds)."""
+    sc, cam = _fd_scene(seed, clamp=clamp)
+    o = oracle.Opts(bg=(0.2, 0.1, 0.3))
+    rng = np.random.default_rng(seed)
+    Wimg = rng.normal(size=(3, cam.height, cam.width))
+    fl = _flags(oracle, sc, [cam], o)[0]
+    Wimg[:, fl != 0] = 0.0
+    g = oracle.render_bwd(sc, [cam], [Wimg], o)
+    base = {k: getattr(sc, k).astype(np.float64).copy() for k in ("mean", "scale", "quat", "opacity", "color")}
+
+    def L_with(name, val):
+        params = {k: v.copy() for k, v in base.items()}
+        params[name] = val
+        s2 = Scene(params["mean"], params["scale"], params["quat"], params["opacity"], params["color"], [cam])
+        # bypass float32 rounding: the oracle works on float64 copies
+        for k in params:
+            setattr(s2, k, params[k])
+        return _loss(oracle, s2, [cam], [Wimg], o)
+
+    for name in ("mean", "scale", "quat", "opacity", "color"):
+        a = base[name]
+        fd = np.zeros_like(a)
+        for idx in np.ndindex(a.shape):
+            h = 1e-6 * max(1.0, abs(a[idx]))
+            ap, am = a.copy(), a.copy()
+            ap[idx] += h
+            am[idx] -= h
+            fd[idx] = (L_with(name, ap) - L_with(name, am)) / (2 * h)
+        an = g[name]
+        scale = np.abs(fd).max()
+        np.testing.assert_allclose(an, fd, atol=2e-6 * scale + 1e-9, rtol=2e-5, err_msg=name)
+
+
+def _rodrigues(w):
+    return Rotation.from_rotvec(w).as_matrix()
+
+
+class Cam64:
+    """A camera holding float64 pose values (exactly orthonormal rotations)."""
+
+    def __init__(self, like, R, t):
+        self.fx, self.fy, self.cx, self.cy = like.fx, like.fy, like.cx, like.cy
+        self.width, self.height = like.width, like.height
+        self.R_cw = np.asarray(R, np.float64)
+        self.t_cw = np.asarray(t, np.float64)
+
+
+def test_pose_gradient_matches_twist_differences(oracle):
+    """dL/d(dphi, dt) for T_CW <- Exp(dphi, dt) T_CW against central
+    differences, with the exponential taken from scipy."""
+    rng = np.random.default_rng(4)
+    Rc = Rotation.from_rotvec([0.1, -0.2, 0.05]).as_matrix()
+    cam0 = Camera(18.0, 19.0, 10.0, 8.0, 20, 16, Rc, [0.1, -0.05, 0.2])
+    sc = S.random_scene(8, cam0, seed=9, zmin=1.0, zmax=2.0, smin=0.08, smax=0.3)
+    sc.opacity[:] = np.float32(0.3) + np.float32(0.5) * sc.opacity
+    o = oracle.Opts()
+    Wimg = rng.normal(size=(3, cam0.height, cam0.width))
+    Wimg[:, oracle.render_image(sc, cam0, o)["flags"] != 0] = 0
+
+    def cam_at(xi):
+        E = _rodrigues(xi[:3])
+        return Cam64(cam0, E @ cam0.R_cw.astype(np.float64), E @ cam0.t_cw.astype(np.float64) + xi[3:])
+
+    g = oracle.render_bwd(sc, [cam0], [Wimg], o)["pose"][0]
+    fd = np.zeros(6)
+    for k in range(6):
+        h = 1e-6
+        e = np.zeros(6)
+        e[k] = h
+        fd[k] = (_loss(oracle, sc, [cam_at(e)], [Wimg], o) - _loss(oracle, sc, [cam_at(-e)], [Wimg], o)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=2e-5, atol=1e-6 * np.abs(fd).max())
+
+
+def test_pose_gradient_rigid_identities(oracle):
+    """Exact identities: translating the camera by dt moves every camera-frame
+    mean by dt, so dL/ddt = R_cw sum_i dL/dp_W,i; rotating it by dphi rotates
+    every camera-frame mean and orientation, so dL/ddphi is the matching sum of
+    mean and quaternion gradients."""
+    rng = np.random.default_rng(8)
+    Rc = Rotation.from_rotvec([0.2, 0.1, -0.3]).as_matrix()
+    cam32 = Camera(40.0, 42.0, 20.0, 16.0, 40, 32, Rc, [0.3, 0.1, -0.2])
+    sc = S.random_scene(60, cam32, seed=13, zmin=1.0, zmax=3.0, smin=0.03, smax=0.2, unnormalised_quats=True)
+    cam = Cam64(cam32, Rc, [0.3, 0.1, -0.2])
+    o = oracle.Opts()
+    Wimg = rng.normal(size=(3, cam.height, cam.width))
+    g = oracle.render_bwd(sc, [cam], [Wimg], o)
+    W = cam.R_cw.astype(np.float64)
+    np.testing.assert_allclose(g["pose"][0, 3:], W @ g["mean"].sum(0), rtol=1e-10,
+                               atol=1e-12 * np.abs(g["mean"]).max())
+    pC = sc.mean.astype(np.float64) @ W.T + cam.t_cw.astype(np.float64)
+    q = sc.quat.astype(np.float64)
+    want = np.zeros(3)
+    for k in range(3):
+        phi = np.zeros(3)
+        phi[k] = 1.0
+        # camera-frame means move by phi x p_C; in world coordinates W^T (phi x p_C)
+        dm = np.cross(phi, pC) @ W
+        # orientations turn by the world-frame vector W^T phi: dq = 1/2 (0, w) (x) q
+        w = W.T @ phi
+        dq = 0.5 * np.stack([-(w[0] * q[:, 1] + w[1] * q[:, 2] + w[2] * q[:, 3]),
+                             w[0] * q[:, 0] + w[1] * q[:, 3] - w[2] * q[:, 2],
+                             w[1] * q[:, 0] + w[2] * q[:, 1] - w[0] * q[:, 3],
+                             w[2] * q[:, 0] + w[0] * q[:, 2] - w[1] * q[:, 1]], 1)
+        want[k] = np.sum(g["mean"] * dm) + np.sum(g["quat"] * dq)
+    np.testing.assert_allclose(g["pose"][0, :3], want, rtol=1e-9, atol=1e-12 * np.abs(want).max())
+
+
+def test_single_gaussian_gradient_closed_forms(oracle):
+    """One unclamped Gaussian, background 0: dI_ch/dc_ch = a and
+    dI/dsigma = c G at every pixel."""
+    cam = _cam(W=24, H=20, f=30.0)
+    sc = _scene([[0, 0, 2.0]], [[0.08, 0.05, 0.1]], [[1, 0, 0, 0]], [0.6], [[0.3, 0.6, 0.9]], [cam])
+    o = oracle.Opts()
+    p = oracle.project(sc, cam, o)
+    v, u = np.mgrid[0:cam.height, 0:cam.width]
+    dx, dy = u + 0.5 - p["mean2d"][0, 0], v + 0.5 - p["mean2d"][0, 1]
+    A, B, Cc = p["conic"][0]
+    G = np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + Cc * dy * dy))
+    a = float(sc.opacity[0]) * G
+    on = a >= 1 / 255
+    for ch in range(3):
+        Wimg = np.zeros((3, cam.height, cam.width))
+        Wimg[ch] = 1.0
+        g = oracle.render_bwd(sc, [cam], [Wimg], o)
+        np.testing.assert_allclose(g["color"][0, ch], a[on].sum(), rtol=1e-12)
+        np.testing.assert_allclose(g["opacity"][0], float(sc.color[0, ch]) * G[on].sum(), rtol=1e-12)
