@@ -1,0 +1,227 @@
+/*
+ * gslivo.h — C ABI of the MI355X (gfx950) Gaussian-splatting hot path of
+ * GS-LIVO (arXiv 2501.08672): projection, tile binning with a radix sort,
+ * front-to-back alpha compositing, and the photometric backward pass to the
+ * Gaussians and to each camera's SE(3) pose.
+ *
+ * Conventions for every entry point
+ *   - Device pointers are caller-owned device memory on the context's device;
+ *     host pointers are read during the call only.  The library never
+ *     allocates or frees device memory in these calls.
+ *   - Work is enqueued on the caller's stream (`hipStream_t` passed as void*,
+ *     NULL = the null stream) with no host synchronisation, so it can be
+ *     recorded into a HIP graph.  Results are valid once the stream reaches
+ *     them.
+ *   - Return value: GSL_OK (0) or a negative GSL_E* code; nothing is thrown
+ *     across the ABI.  gsl_last_error() describes the last failure on the
+ *     calling thread.  Argument errors are detected on the host before any
+ *     launch; a capacity overflow is detected on the device and reported
+ *     through the `d_status` word of gsl_bins.
+ *   - Floating-point arrays are float32 unless stated.  Gaussian parameters
+ *     are SoA, component-major: mean[3][N], scale[3][N], quat[4][N],
+ *     opacity[N], color[3][N].
+ *   - Images of a camera set are packed: camera c occupies the planar block
+ *     image[3][H_c][W_c] starting at float offset 3 * P_c, with
+ *     P_c = sum_{j<c} W_j H_j; per-pixel arrays (T_final, n_walk) start at P_c.
+ */
+#ifndef GSLIVO_H
+#define GSLIVO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSL_ABI_VERSION 1
+
+#ifndef GSL_API
+#define GSL_API __attribute__((visibility("default")))
+#endif
+
+enum {
+    GSL_OK = 0,
+    GSL_EINVAL = -1,    /* null pointer, bad size or option */
+    GSL_ENOTSUP = -2,   /* tile size not in {8, 16, 32}, too many cameras */
+    GSL_ECAPACITY = -3, /* instance count K exceeds capacity_K (device status) */
+    GSL_EHIP = -4,      /* a HIP runtime call failed */
+    GSL_ESTATE = -5     /* context/device mismatch */
+};
+
+#define GSL_MAX_CAMERAS 1024
+
+typedef struct gsl_ctx gsl_ctx;
+
+/* Pinhole camera.  p_C = R_cw p_W + t_cw; x right, y down, z forward.
+ * Pixel (u, v) covers [u, u+1) x [v, v+1); its centre is (u + 0.5, v + 0.5). */
+typedef struct {
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float R_cw[9]; /* row-major world -> camera rotation */
+    float t_cw[3];
+} gsl_camera;
+
+/* Rendering constants.  alpha_max and T_min are the alpha clamp and the
+ * transmittance cutoff; the others are readings of what the paper leaves
+ * open (gsl_default_opts fills them). */
+typedef struct {
+    float near_z;    /* cull a Gaussian whose camera depth is <= near_z (0.2 m) */
+    float eps2d;     /* dilation added to the diagonal of Sigma2D (0.3 px^2) */
+    float alpha_min; /* skip a Gaussian whose alpha at a pixel is < alpha_min (1/255) */
+    float alpha_max; /* alpha = min(alpha_max, sigma G) (0.99) */
+    float T_min;     /* stop before a Gaussian that would take T below T_min (1e-4) */
+    float bg[3];     /* background colour (0) */
+    float guard;     /* cull when the 2D mean lies beyond guard*W / guard*H outside the image (0.15) */
+    int32_t tile;    /* tile edge in pixels: 8, 16 or 32 */
+} gsl_opts;
+
+/* Gaussians of the window (SoA, component-major, device). */
+typedef struct {
+    const float *mean;    /* [3][N] world position (m) */
+    const float *scale;   /* [3][N] per-axis standard deviation (m), activated */
+    const float *quat;    /* [4][N] rotation (w, x, y, z), any non-zero length */
+    const float *opacity; /* [N] in (0, 1), activated */
+    const float *color;   /* [3][N] degree-0 RGB */
+    int32_t N;
+} gsl_gaussians;
+
+/* One projected Gaussian in one camera (48 bytes, 16-byte aligned).  The 2D
+ * Gaussian is G(x) = exp(-1/2 |L (x - mu)|^2) with L = [[l11, l12], [0, l22]]
+ * the upper Cholesky factor of Sigma2D^{-1}.  A culled splat has depth 0 and
+ * an empty bbox (x0 > x1).  bbox is the inclusive pixel rectangle outside of
+ * which alpha < alpha_min for certain. */
+typedef struct {
+    float mx, my;
+    float l11, l12;
+    float l22, opacity;
+    float r, g;
+    float b, depth;
+    int16_t x0, y0, x1, y1;
+} gsl_splat;
+
+/* Output of gsl_project for C cameras x N Gaussians (device). */
+typedef struct {
+    gsl_splat *splats;      /* [C][N] */
+    int32_t *tiles_touched; /* [C][N] number of tiles the bbox overlaps */
+} gsl_proj;
+
+/* Tile bins (device).  After gsl_bin_sort, instances [0, K) are ordered by
+ * (global tile id, depth, Gaussian index); ranges[t] = {start, end} of tile t
+ * (end == start when empty).  The global tile id of camera c's tile
+ * (tx, ty) is tile_offset_c + ty * tiles_x_c + tx, where tiles_x_c =
+ * ceil(W_c / tile) and tile_offset_c counts the tiles of cameras before c. */
+typedef struct {
+    uint32_t *tile_ids;  /* [capacity_K] */
+    uint32_t *gauss_ids; /* [capacity_K] Gaussian index i of the instance */
+    uint32_t *ranges;    /* [T_total][2] */
+    int64_t *d_K;        /* device scalar: instance count K (even when K > capacity) */
+    int32_t *d_status;   /* device scalar: GSL_OK or GSL_ECAPACITY */
+    int64_t capacity_K;
+} gsl_bins;
+
+/* Gradient outputs (device).  g_pose is float64 [C][6]: (dphi, dt) of a left
+ * perturbation T_CW <- Exp(dphi, dt) T_CW of each camera.  Any pointer may be
+ * NULL to skip that output except g2d-dependent ones noted per call. */
+typedef struct {
+    float *g_mean;    /* [3][N] */
+    float *g_scale;   /* [3][N] */
+    float *g_quat;    /* [4][N] */
+    float *g_opacity; /* [N] */
+    float *g_color;   /* [3][N] */
+    double *g_pose;   /* [C][6] */
+} gsl_grads;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Creates a context bound to HIP device `device` (made current by the call). */
+GSL_API int gsl_create(gsl_ctx **out, int device);
+GSL_API int gsl_destroy(gsl_ctx *ctx);
+/* Message of the last failure on this thread ("" if none).  Owned by the library. */
+GSL_API const char *gsl_last_error(void);
+GSL_API void gsl_default_opts(gsl_opts *opts);
+
+/* Number of tiles and pixels of a camera set at opts->tile (host only). */
+GSL_API int gsl_layout(const gsl_camera *cams, int32_t C, int32_t tile, int64_t *T_total, int64_t *P_total);
+
+/* Bytes of device workspace the calls below need for these shapes. */
+GSL_API int gsl_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                       int64_t capacity_K, size_t *bytes);
+
+/* ---- the four steps --------------------------------------------------- */
+
+/* Projection (Sec. II-B, eqs. equ:3dgs, equ:q, equ:spat): for each camera c
+ * and Gaussian i, Sigma3D = R(q) diag(s)^2 R(q)^T, p_C = R_cw p_W + t_cw,
+ * mean2d = pinhole(p_C), Sigma2D = J R_cw Sigma3D R_cw^T J^T + eps2d I with J
+ * the pinhole Jacobian at p_C.  Culls z <= near_z, means outside the guard
+ * band and opacity < alpha_min.  Arithmetic is float64; the stored splat is
+ * rounded to float32.  `workspace` receives the camera table used by the
+ * later calls of the same camera set. */
+GSL_API int gsl_project(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                gsl_proj *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Tile binning and sorting: orders the Gaussians of every camera by depth
+ * (32-bit float key, ties by index), emits one instance per overlapped tile
+ * and sorts the instances by tile with a stable LSD radix sort, so the
+ * instance order equals a sort by the 64-bit key (tile << 32 | depth bits)
+ * with ties by index.  Writes K and, when K > capacity_K, GSL_ECAPACITY to
+ * *d_status (then the bins are incomplete; call again with more capacity). */
+GSL_API int gsl_bin_sort(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                 const gsl_proj *proj, gsl_bins *bins, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Forward compositing (eq. eq:raster): for every pixel walks its tile's list
+ * front to back, alpha = min(alpha_max, opacity G), skips alpha < alpha_min,
+ * stops before T (1 - alpha) < T_min, C += alpha T c.  Writes the packed
+ * image (C + T bg), T_final and n_walk (the list position after the last
+ * contributor: the backward pass starts there). */
+GSL_API int gsl_render_fwd(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                   const gsl_proj *proj, const gsl_bins *bins, float *image, float *T_final, uint32_t *n_walk,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward pass (eq. eq:gaussian_optimization, Appendix A): given
+ * dL_dimage (packed like the image), the forward's T_final and n_walk,
+ * walks each tile in reverse recovering T from T_final, accumulates the 2D
+ * gradients per (camera, Gaussian), then chains them in float64 to the 3D
+ * parameters (summed over cameras) and to each camera's pose.  Outputs are
+ * overwritten unless accumulate != 0. */
+GSL_API int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                   const gsl_proj *proj, const gsl_bins *bins, const float *T_final, const uint32_t *n_walk,
+                   const float *dL_dimage, int accumulate, gsl_grads *grads, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/* ---- the batched window ------------------------------------------------ */
+
+enum { GSL_LOSS_L1 = 1, GSL_LOSS_L2 = 2 };
+
+/* One optimisation pass over a window of keyframes: project, bin_sort, then
+ * one persistent fused launch over all (camera, tile) items that composites,
+ * forms the per-pixel loss gradient against `target` (packed like the image;
+ * L1: mean absolute error per frame summed over frames, L2: 1/2 sum of
+ * squares), and walks back, then the projection adjoint.  Writes the loss to
+ * *d_loss (device float64) and the gradients (overwritten); image may be NULL.
+ * The fused launch uses the kernel variant (LDS chunk depth, persistent
+ * work queue or one workgroup per item) that gsl_window_tune chose for these
+ * shapes, else the default.  With use_graph != 0 the sequence is recorded
+ * once into a HIP graph per (shapes, buffers, options, camera poses) and
+ * replayed on later calls with the same arguments. */
+GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                    const float *target, int loss, gsl_proj *proj, gsl_bins *bins, float *image,
+                    double *d_loss, gsl_grads *grads, void *workspace, size_t workspace_bytes,
+                    int use_graph, void *stream);
+
+/* Autotuner for gsl_window_step: times every tile size in {8, 16, 32} and
+ * every fused-kernel variant on the given window (eager launches on
+ * `stream`, synchronising it), keeps the fastest variant per tile size in
+ * the context and writes the fastest tile size to opts_inout->tile.  The
+ * buffers must be sized for tile 8 (the largest T_total) and enough
+ * capacity_K for every tile size; times_ms (may be NULL) receives up to
+ * `ntimes` measured milliseconds in the order tried. */
+GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, gsl_opts *opts_inout,
+                    const float *target, int loss, gsl_proj *proj, gsl_bins *bins, double *d_loss,
+                    gsl_grads *grads, void *workspace, size_t workspace_bytes, float *times_ms, int32_t ntimes,
+                    void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSLIVO_H */

@@ -1,0 +1,634 @@
+// Host side of the C ABI declared in gslivo.h: argument checks, the packed
+// tile/pixel layout of a camera set, the workspace carve-up, the launch
+// sequence of each step, HIP-graph capture of the window step and the
+// autotuner that picks tile size and fused-kernel variant.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "gslivo.h"
+
+using namespace gsl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return fail(GSL_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return GSL_OK;
+}
+
+int check_launch(const char *what)
+{
+    return check_hip(hipGetLastError(), what);
+}
+
+#define GSL_TRY(x)                \
+    do {                          \
+        int _rc = (x);            \
+        if (_rc != GSL_OK) return _rc; \
+    } while (0)
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+int ceil_log2(int64_t v)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < v) b++;
+    return b < 1 ? 1 : b;
+}
+
+// Signature of a window used to key graphs and tuning results.
+struct VariantKey {
+    std::vector<int64_t> v;
+    bool operator<(const VariantKey &o) const { return v < o.v; }
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct gsl_ctx {
+    int device = 0;
+    int num_cus = 256;
+    hipStream_t cap_stream = nullptr;
+    std::mutex mu;
+    std::map<VariantKey, int> variant;  // (window shapes, tile) -> fused variant
+    std::map<VariantKey, GraphEntry> graphs;
+};
+
+namespace {
+
+int check_opts(const gsl_opts *o)
+{
+    if (!o) return fail(GSL_EINVAL, "opts is NULL");
+    if (o->tile != 8 && o->tile != 16 && o->tile != 32)
+        return fail(GSL_ENOTSUP, "tile size %d not in {8, 16, 32}", o->tile);
+    if (!(o->alpha_min > 0.f) || !(o->alpha_max > o->alpha_min) || !(o->alpha_max < 1.f))
+        return fail(GSL_EINVAL, "need 0 < alpha_min < alpha_max < 1");
+    if (!(o->T_min > 0.f) || !(o->T_min < 1.f)) return fail(GSL_EINVAL, "need 0 < T_min < 1");
+    if (!(o->near_z > 0.f)) return fail(GSL_EINVAL, "need near_z > 0");
+    if (!(o->eps2d >= 0.f)) return fail(GSL_EINVAL, "need eps2d >= 0");
+    if (!(o->guard >= 0.f)) return fail(GSL_EINVAL, "need guard >= 0");
+    return GSL_OK;
+}
+
+DevOpts dev_opts(const gsl_opts *o)
+{
+    DevOpts d;
+    d.near_z = o->near_z;
+    d.eps2d = o->eps2d;
+    d.alpha_min = o->alpha_min;
+    d.alpha_max = o->alpha_max;
+    d.T_min = o->T_min;
+    for (int k = 0; k < 3; k++) d.bg[k] = o->bg[k];
+    d.guard = o->guard;
+    d.tile = o->tile;
+    return d;
+}
+
+int make_layout(const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, Layout &L, std::vector<DevCam> *dc)
+{
+    if (!cams) return fail(GSL_EINVAL, "cams is NULL");
+    if (C < 1 || C > GSL_MAX_CAMERAS) return fail(GSL_ENOTSUP, "camera count %d not in [1, %d]", C, GSL_MAX_CAMERAS);
+    if (N < 0) return fail(GSL_EINVAL, "negative Gaussian count");
+    if (tile != 8 && tile != 16 && tile != 32) return fail(GSL_ENOTSUP, "tile size %d not in {8, 16, 32}", tile);
+    L.C = C;
+    L.N = N;
+    L.M = (int64_t)C * N;
+    if (L.M > 0xffffffffll) return fail(GSL_EINVAL, "C*N = %lld exceeds 2^32-1", (long long)L.M);
+    L.tile = tile;
+    int64_t T = 0, P = 0;
+    if (dc) dc->resize(C);
+    for (int c = 0; c < C; c++) {
+        const gsl_camera &k = cams[c];
+        if (k.width < 1 || k.height < 1 || k.width > 32767 || k.height > 32767)
+            return fail(GSL_EINVAL, "camera %d size %dx%d out of range", c, k.width, k.height);
+        if (!(k.fx > 0.f) || !(k.fy > 0.f)) return fail(GSL_EINVAL, "camera %d focal length must be > 0", c);
+        const int tx = (k.width + tile - 1) / tile, ty = (k.height + tile - 1) / tile;
+        if (dc) {
+            DevCam &d = (*dc)[c];
+            d.fx = k.fx; d.fy = k.fy; d.cx = k.cx; d.cy = k.cy;
+            d.W = k.width; d.H = k.height;
+            for (int j = 0; j < 9; j++) d.R[j] = k.R_cw[j];
+            for (int j = 0; j < 3; j++) d.t[j] = k.t_cw[j];
+            d.tiles_x = tx; d.tiles_y = ty;
+            d.tile_offset = (int32_t)T;
+            d.pad = 0;
+            d.pix_offset = P;
+        }
+        T += (int64_t)tx * ty;
+        P += (int64_t)k.width * k.height;
+    }
+    if (T > 0x7fffffffll) return fail(GSL_EINVAL, "too many tiles");
+    L.T_total = T;
+    L.P_total = P;
+    L.tile_bits = ceil_log2(T);
+    return GSL_OK;
+}
+
+WsLayout ws_layout(const Layout &L, int64_t capacity)
+{
+    WsLayout w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const int64_t M = L.M;
+    w.cams = take(sizeof(DevCam) * (size_t)L.C);
+    w.dkey = take(4 * (size_t)M);
+    w.dval = take(4 * (size_t)M);
+    w.dkey2 = take(4 * (size_t)M);
+    w.dval2 = take(4 * (size_t)M);
+    w.counts = take(4 * (size_t)M);
+    w.offsets = take(4 * (size_t)M);
+    w.ikey2 = take(4 * (size_t)capacity);
+    w.ival2 = take(4 * (size_t)capacity);
+    const int64_t nb = (std::max<int64_t>(M, capacity) + kSortTile - 1) / kSortTile;
+    w.sort_blocks = nb;
+    w.hist = take(4 * (size_t)(256 * nb + 1));
+    w.hist_off = take(4 * (size_t)(256 * nb + 1));
+    const int64_t scan_n = std::max<int64_t>(256 * nb, M);
+    w.scan_partials = (scan_n + kScanTile - 1) / kScanTile + 1;
+    w.partial = take(8 * (size_t)w.scan_partials);
+    w.g2d = take(4 * (size_t)M * kG2);
+    w.pose_blocks = (int32_t)((L.N + kPoseThreads - 1) / kPoseThreads);
+    w.pose_part = take(8 * (size_t)std::max<int64_t>(1, (int64_t)w.pose_blocks * L.C * 6));
+    w.loss_part = take(8 * (size_t)std::max<int64_t>(1, L.T_total));
+    w.order = take(4 * (size_t)std::max<int64_t>(1, L.T_total));
+    w.misc = take(256);
+    w.total = o;
+    return w;
+}
+
+template <typename T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+struct Prepared {
+    Layout L;
+    WsLayout W;
+    std::vector<DevCam> dc;
+    DevOpts o;
+};
+
+int prepare(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts, int64_t capacity,
+            void *ws, size_t ws_bytes, Prepared &p)
+{
+    if (!ctx) return fail(GSL_EINVAL, "ctx is NULL");
+    GSL_TRY(check_opts(opts));
+    if (capacity < 0 || capacity > 0xffffffffll) return fail(GSL_EINVAL, "capacity_K out of range");
+    GSL_TRY(make_layout(cams, C, N, opts->tile, p.L, &p.dc));
+    p.W = ws_layout(p.L, capacity);
+    p.o = dev_opts(opts);
+    if (!ws) return fail(GSL_EINVAL, "workspace is NULL");
+    if (ws_bytes < p.W.total)
+        return fail(GSL_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, p.W.total);
+    int cur = -1;
+    GSL_TRY(check_hip(hipGetDevice(&cur), "hipGetDevice"));
+    if (cur != ctx->device) return fail(GSL_ESTATE, "current device %d is not the context's device %d", cur, ctx->device);
+    return GSL_OK;
+}
+
+int check_gauss(const gsl_gaussians *g, bool need_all)
+{
+    if (!g) return fail(GSL_EINVAL, "gaussians is NULL");
+    if (g->N < 0) return fail(GSL_EINVAL, "negative Gaussian count");
+    if (g->N > 0 && (!g->mean || !g->scale || !g->quat || (need_all && (!g->opacity || !g->color))))
+        return fail(GSL_EINVAL, "Gaussian parameter pointer is NULL");
+    return GSL_OK;
+}
+
+int check_proj(const gsl_proj *p, const Layout &L)
+{
+    if (!p) return fail(GSL_EINVAL, "proj is NULL");
+    if (L.M > 0 && (!p->splats || !p->tiles_touched)) return fail(GSL_EINVAL, "proj buffer is NULL");
+    return GSL_OK;
+}
+
+int check_bins(const gsl_bins *b)
+{
+    if (!b) return fail(GSL_EINVAL, "bins is NULL");
+    if (!b->ranges || !b->d_K || !b->d_status) return fail(GSL_EINVAL, "bins buffer is NULL");
+    if (b->capacity_K > 0 && (!b->tile_ids || !b->gauss_ids)) return fail(GSL_EINVAL, "bins instance buffer is NULL");
+    return GSL_OK;
+}
+
+// ---- step bodies (enqueue only) ----
+
+void do_upload(const Prepared &p, void *ws, hipStream_t s)
+{
+    launch_upload_cams(at<DevCam>(ws, p.W.cams), p.dc.data(), p.L.C, s);
+}
+
+void do_project(const Prepared &p, const gsl_gaussians *g, gsl_proj *out, void *ws, hipStream_t s)
+{
+    launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->tiles_touched, s);
+}
+
+void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *ws, hipStream_t s)
+{
+    const Layout &L = p.L;
+    const WsLayout &W = p.W;
+    uint32_t *dkey = at<uint32_t>(ws, W.dkey), *dval = at<uint32_t>(ws, W.dval);
+    uint32_t *dkey2 = at<uint32_t>(ws, W.dkey2), *dval2 = at<uint32_t>(ws, W.dval2);
+    uint32_t *hist = at<uint32_t>(ws, W.hist), *hist_off = at<uint32_t>(ws, W.hist_off);
+    uint64_t *partial = at<uint64_t>(ws, W.partial);
+    // 1. depth order of all records (ties by record index = Gaussian index per camera)
+    launch_depth_keys(proj->splats, proj->tiles_touched, L.M, dkey, dval, s);
+    int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, partial, s);
+    const uint32_t *order = where ? dval2 : dval;
+    // 2. instance offsets in that order
+    uint32_t *counts = at<uint32_t>(ws, W.counts), *offsets = at<uint32_t>(ws, W.offsets);
+    launch_gather_counts(order, proj->tiles_touched, L.M, counts, s);
+    launch_scan_u32(counts, offsets, L.M, partial, bins->d_K, s);
+    // 3. emit and sort by tile; the pass count decides which buffer is emitted into
+    const int passes = (L.tile_bits + 7) / 8;
+    uint32_t *ek = bins->tile_ids, *ev = bins->gauss_ids;
+    uint32_t *ak = at<uint32_t>(ws, W.ikey2), *av = at<uint32_t>(ws, W.ival2);
+    if (passes & 1) std::swap(ek, ak), std::swap(ev, av);
+    launch_emit(order, offsets, proj->splats, at<DevCam>(ws, W.cams), L, bins->d_K, bins->capacity_K, ek, ev,
+                bins->d_status, s);
+    launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, partial, s);
+    // 4. per-tile ranges
+    launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);
+}
+
+RenderArgs render_args(const Prepared &p, const gsl_proj *proj, const gsl_bins *bins, void *ws)
+{
+    RenderArgs a;
+    memset(&a, 0, sizeof a);
+    a.cams = at<DevCam>(ws, p.W.cams);
+    a.C = p.L.C;
+    a.N = p.L.N;
+    a.o = p.o;
+    a.splats = proj->splats;
+    a.gauss_ids = bins->gauss_ids;
+    a.ranges = bins->ranges;
+    a.T_total = p.L.T_total;
+    a.g2d = at<float>(ws, p.W.g2d);
+    a.loss_part = at<double>(ws, p.W.loss_part);
+    a.queue = at<uint32_t>(ws, p.W.misc);
+    return a;
+}
+
+void do_project_bwd(const Prepared &p, const gsl_gaussians *g, gsl_grads *grads, int accumulate, void *ws,
+                    hipStream_t s)
+{
+    double *pose_part = at<double>(ws, p.W.pose_part);
+    launch_project_bwd(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, at<float>(ws, p.W.g2d), *grads, accumulate,
+                       pose_part, p.W.pose_blocks, s);
+    if (grads->g_pose) {
+        if (p.L.N == 0) {
+            if (!accumulate) launch_fill_f64(grads->g_pose, 0.0, 6 * (int64_t)p.L.C, s);
+        } else {
+            launch_pose_reduce(pose_part, p.W.pose_blocks, p.L.C, grads->g_pose, accumulate, s);
+        }
+    }
+}
+
+void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const float *target, int loss,
+               gsl_proj *proj, gsl_bins *bins, float *image, double *d_loss, gsl_grads *grads, void *ws, int variant,
+               hipStream_t s)
+{
+    do_upload(p, ws, s);
+    do_project(p, g, proj, ws, s);
+    do_bin_sort(p, proj, bins, ws, s);
+    launch_fill_f32(at<float>(ws, p.W.g2d), 0.f, p.L.M * kG2, s);
+    launch_fill_u32(at<uint32_t>(ws, p.W.misc), 0u, 1, s);
+    RenderArgs a = render_args(p, proj, bins, ws);
+    a.image = image;
+    a.target = target;
+    a.loss = loss;
+    launch_render_fused(a, variant, ctx->num_cus, s);
+    launch_reduce_f64(at<double>(ws, p.W.loss_part), p.L.T_total, d_loss, s);
+    do_project_bwd(p, g, grads, 0, ws, s);
+}
+
+VariantKey window_key(const Layout &L, const gsl_camera *cams)
+{
+    VariantKey k;
+    k.v = {L.C, L.N, L.tile};
+    for (int c = 0; c < L.C; c++) {
+        k.v.push_back(cams[c].width);
+        k.v.push_back(cams[c].height);
+    }
+    return k;
+}
+
+}  // namespace
+
+// =====================================================================
+extern "C" {
+
+const char *gsl_last_error(void) { return g_err.c_str(); }
+
+void gsl_default_opts(gsl_opts *o)
+{
+    if (!o) return;
+    o->near_z = 0.2f;
+    o->eps2d = 0.3f;
+    o->alpha_min = 1.0f / 255.0f;
+    o->alpha_max = 0.99f;
+    o->T_min = 1e-4f;
+    o->bg[0] = o->bg[1] = o->bg[2] = 0.f;
+    o->guard = 0.15f;
+    o->tile = 16;
+}
+
+int gsl_create(gsl_ctx **out, int device)
+{
+    if (!out) return fail(GSL_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    GSL_TRY(check_hip(hipGetDeviceCount(&n), "hipGetDeviceCount"));
+    if (device < 0 || device >= n) return fail(GSL_EINVAL, "device %d not in [0, %d)", device, n);
+    GSL_TRY(check_hip(hipSetDevice(device), "hipSetDevice"));
+    gsl_ctx *c = new gsl_ctx();
+    c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->num_cus = cus;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(GSL_EHIP, "hipStreamCreateWithFlags failed");
+    }
+    *out = c;
+    g_err.clear();
+    return GSL_OK;
+}
+
+int gsl_destroy(gsl_ctx *ctx)
+{
+    if (!ctx) return GSL_OK;
+    (void)hipSetDevice(ctx->device);
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return GSL_OK;
+}
+
+int gsl_layout(const gsl_camera *cams, int32_t C, int32_t tile, int64_t *T_total, int64_t *P_total)
+{
+    Layout L;
+    GSL_TRY(make_layout(cams, C, 0, tile, L, nullptr));
+    if (T_total) *T_total = L.T_total;
+    if (P_total) *P_total = L.P_total;
+    return GSL_OK;
+}
+
+int gsl_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                       int64_t capacity_K, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_opts(opts));
+    if (capacity_K < 0 || capacity_K > 0xffffffffll) return fail(GSL_EINVAL, "capacity_K out of range");
+    Layout L;
+    GSL_TRY(make_layout(cams, C, N, opts->tile, L, nullptr));
+    *bytes = ws_layout(L, capacity_K).total;
+    return GSL_OK;
+}
+
+int gsl_project(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                gsl_proj *out, void *workspace, size_t workspace_bytes, void *stream)
+{
+    GSL_TRY(check_gauss(g, true));
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, g->N, opts, 0, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(out, p.L));
+    hipStream_t s = (hipStream_t)stream;
+    do_upload(p, workspace, s);
+    do_project(p, g, out, workspace, s);
+    return check_launch("gsl_project");
+}
+
+int gsl_bin_sort(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                 const gsl_proj *proj, gsl_bins *bins, void *workspace, size_t workspace_bytes, void *stream)
+{
+    GSL_TRY(check_bins(bins));
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    hipStream_t s = (hipStream_t)stream;
+    do_upload(p, workspace, s);
+    do_bin_sort(p, proj, bins, workspace, s);
+    return check_launch("gsl_bin_sort");
+}
+
+int gsl_render_fwd(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                   const gsl_proj *proj, const gsl_bins *bins, float *image, float *T_final, uint32_t *n_walk,
+                   void *workspace, size_t workspace_bytes, void *stream)
+{
+    GSL_TRY(check_bins(bins));
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    if (!image || !T_final || !n_walk) return fail(GSL_EINVAL, "output buffer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    do_upload(p, workspace, s);
+    RenderArgs a = render_args(p, proj, bins, workspace);
+    a.image = image;
+    a.T_final = T_final;
+    a.n_walk = n_walk;
+    launch_render_fwd(a, s);
+    return check_launch("gsl_render_fwd");
+}
+
+int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                   const gsl_proj *proj, const gsl_bins *bins, const float *T_final, const uint32_t *n_walk,
+                   const float *dL_dimage, int accumulate, gsl_grads *grads, void *workspace, size_t workspace_bytes,
+                   void *stream)
+{
+    GSL_TRY(check_gauss(g, false));
+    GSL_TRY(check_bins(bins));
+    if (!grads) return fail(GSL_EINVAL, "grads is NULL");
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, g->N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    if (!T_final || !n_walk || !dL_dimage) return fail(GSL_EINVAL, "input buffer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    do_upload(p, workspace, s);
+    launch_fill_f32(at<float>(workspace, p.W.g2d), 0.f, p.L.M * kG2, s);
+    RenderArgs a = render_args(p, proj, bins, workspace);
+    a.T_final = const_cast<float *>(T_final);
+    a.n_walk = const_cast<uint32_t *>(n_walk);
+    a.dL_dimage = dL_dimage;
+    launch_render_bwd(a, s);
+    do_project_bwd(p, g, grads, accumulate, workspace, s);
+    return check_launch("gsl_render_bwd");
+}
+
+int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                    const float *target, int loss, gsl_proj *proj, gsl_bins *bins, float *image, double *d_loss,
+                    gsl_grads *grads, void *workspace, size_t workspace_bytes, int use_graph, void *stream)
+{
+    GSL_TRY(check_gauss(g, true));
+    GSL_TRY(check_bins(bins));
+    if (!grads || !target || !d_loss) return fail(GSL_EINVAL, "NULL argument");
+    if (loss != GSL_LOSS_L1 && loss != GSL_LOSS_L2) return fail(GSL_EINVAL, "unknown loss %d", loss);
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, g->N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    hipStream_t s = (hipStream_t)stream;
+    const VariantKey vk = window_key(p.L, cams);
+    int variant = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->variant.find(vk);
+        if (it != ctx->variant.end()) variant = it->second;
+    }
+    if (!use_graph) {
+        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, s);
+        return check_launch("gsl_window_step");
+    }
+    // graph key: shapes, variant, every pointer, options and camera contents
+    VariantKey gk = vk;
+    gk.v.push_back(variant);
+    gk.v.push_back(loss);
+    auto ptr = [&](const void *q) { gk.v.push_back((int64_t)(uintptr_t)q); };
+    ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color);
+    ptr(target); ptr(proj->splats); ptr(proj->tiles_touched);
+    ptr(bins->tile_ids); ptr(bins->gauss_ids); ptr(bins->ranges); ptr(bins->d_K); ptr(bins->d_status);
+    gk.v.push_back(bins->capacity_K);
+    ptr(image); ptr(d_loss); ptr(grads->g_mean); ptr(grads->g_scale); ptr(grads->g_quat);
+    ptr(grads->g_opacity); ptr(grads->g_color); ptr(grads->g_pose); ptr(workspace);
+    {
+        const int32_t *ow = reinterpret_cast<const int32_t *>(opts);
+        for (size_t k = 0; k < sizeof(gsl_opts) / 4; k++) gk.v.push_back(ow[k]);
+        for (int c = 0; c < C; c++) {
+            const int32_t *cw = reinterpret_cast<const int32_t *>(&cams[c]);
+            for (size_t k = 0; k < sizeof(gsl_camera) / 4; k++) gk.v.push_back(cw[k]);
+        }
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->graphs.find(gk);
+    if (it == ctx->graphs.end()) {
+        GraphEntry e;
+        hipStream_t cs = ctx->cap_stream;
+        GSL_TRY(check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"));
+        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, cs);
+        hipError_t le = hipGetLastError();
+        hipError_t ce = hipStreamEndCapture(cs, &e.graph);
+        if (le != hipSuccess) return fail(GSL_EHIP, "launch during capture: %s", hipGetErrorString(le));
+        GSL_TRY(check_hip(ce, "hipStreamEndCapture"));
+        hipError_t ie = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(e.graph);
+            return fail(GSL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        }
+        if (ctx->graphs.size() > 64) {  // bound the cache
+            for (auto &kv : ctx->graphs) {
+                (void)hipGraphExecDestroy(kv.second.exec);
+                (void)hipGraphDestroy(kv.second.graph);
+            }
+            ctx->graphs.clear();
+        }
+        it = ctx->graphs.emplace(gk, e).first;
+    }
+    GSL_TRY(check_hip(hipGraphLaunch(it->second.exec, s), "hipGraphLaunch"));
+    return GSL_OK;
+}
+
+int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, gsl_opts *opts_inout,
+                    const float *target, int loss, gsl_proj *proj, gsl_bins *bins, double *d_loss, gsl_grads *grads,
+                    void *workspace, size_t workspace_bytes, float *times_ms, int32_t ntimes, void *stream)
+{
+    GSL_TRY(check_gauss(g, true));
+    GSL_TRY(check_bins(bins));
+    if (!grads || !target || !d_loss || !opts_inout) return fail(GSL_EINVAL, "NULL argument");
+    if (loss != GSL_LOSS_L1 && loss != GSL_LOSS_L2) return fail(GSL_EINVAL, "unknown loss %d", loss);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    GSL_TRY(check_hip(hipEventCreate(&e0), "hipEventCreate"));
+    GSL_TRY(check_hip(hipEventCreate(&e1), "hipEventCreate"));
+    const int tiles[3] = {8, 16, 32};
+    float best_all = 1e30f;
+    int best_tile = opts_inout->tile;
+    int k = 0;
+    int rc = GSL_OK;
+    for (int ti = 0; ti < 3 && rc == GSL_OK; ti++) {
+        gsl_opts o = *opts_inout;
+        o.tile = tiles[ti];
+        Prepared p;
+        rc = prepare(ctx, cams, C, g->N, &o, bins->capacity_K, workspace, workspace_bytes, p);
+        if (rc != GSL_OK) break;
+        rc = check_proj(proj, p.L);
+        if (rc != GSL_OK) break;
+        float best = 1e30f;
+        int best_v = 0;
+        for (int variant = 0; variant < 2; variant++) {
+            // one untimed run, then check the capacity status
+            do_window(ctx, p, g, target, loss, proj, bins, nullptr, d_loss, grads, workspace, variant, s);
+            int32_t status = 0;
+            (void)hipMemcpyAsync(&status, bins->d_status, 4, hipMemcpyDeviceToHost, s);
+            if ((rc = check_hip(hipStreamSynchronize(s), "tune sync")) != GSL_OK) break;
+            if (status != GSL_OK) {
+                rc = fail(GSL_ECAPACITY, "capacity_K too small for tile %d", tiles[ti]);
+                break;
+            }
+            const int reps = 5;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps; r++)
+                do_window(ctx, p, g, target, loss, proj, bins, nullptr, d_loss, grads, workspace, variant, s);
+            (void)hipEventRecord(e1, s);
+            if ((rc = check_hip(hipEventSynchronize(e1), "tune event")) != GSL_OK) break;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (times_ms && k < ntimes) times_ms[k] = ms;
+            k++;
+            if (ms < best) {
+                best = ms;
+                best_v = variant;
+            }
+        }
+        if (rc != GSL_OK) break;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->variant[window_key(p.L, cams)] = best_v;
+        }
+        if (best < best_all) {
+            best_all = best;
+            best_tile = tiles[ti];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != GSL_OK) return rc;
+    opts_inout->tile = best_tile;
+    return check_launch("gsl_window_tune");
+}
+
+}  // extern "C"

@@ -1,0 +1,393 @@
+// Projection of 3D Gaussians into the cameras of a window and its adjoint.
+//
+// Forward (Sec. II-B, eqs. equ:3dgs, equ:q, equ:spat): one lane per
+// (camera, Gaussian).  The arithmetic is float64 — CDNA4 runs it at half the
+// float32 rate and this kernel is bound by its 44 B in / 52 B out per lane —
+// so the float32 splat it stores carries a correctly rounded mean and conic
+// factor even for the thin, grazing surfels a LiDAR map produces.
+//
+// Sigma2D is formed as P P^T + eps I with P = (J W) R diag(s), the product of
+// the pinhole Jacobian J, the camera rotation W = R_cw and the Gaussian's
+// rotation and scale, which equals (J W) Sigma3D (J W)^T.  The conic is
+// stored as its upper Cholesky factor L (Sigma2D^{-1} = L^T L) so the
+// renderer evaluates |L d|^2 as a sum of two squares.
+//
+// Backward (Appendix A): one lane per Gaussian looping over the cameras,
+// chaining the per-(camera, Gaussian) 2D gradients to mean, scale,
+// quaternion, opacity and colour (summed in registers across cameras, so no
+// atomics) and, per camera, to the twist (dphi, dt) of a left perturbation of
+// T_CW: dL/ddt = sum_i dL/dp_C,i and dL/ddphi = sum_i p_C,i x dL/dp_C,i plus
+// the term of Sigma2D's dependence on W.  Per-workgroup pose partials are
+// summed by a second kernel, so the pose gradient is deterministic.
+#include "common.hpp"
+
+namespace gsl {
+
+namespace {
+
+struct CamBatch {
+    DevCam cams[16];
+    DevCam *dst;
+    int n;
+};
+
+__global__ void k_upload_cams(CamBatch b)
+{
+    int i = threadIdx.x;
+    if (i < b.n) b.dst[i] = b.cams[i];
+}
+
+// Everything the forward computes for one (camera, Gaussian), kept for the
+// backward, which recomputes it instead of storing it.
+struct Proj {
+    double x, y, z;     // camera-frame mean
+    double W[9];        // camera rotation
+    double Rg[9];       // Gaussian rotation (normalised quaternion)
+    double qn[4], qlen;
+    double s[3];
+    double M[6];        // J W, 2 x 3
+    double P[6];        // J W Rg diag(s), 2 x 3
+    double a, b, c;     // Sigma2D = [[a, b], [b, c]] including eps
+    double det;
+    double mx, my;
+};
+
+__device__ __forceinline__ void quat_rot(const double q[4], double R[9])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Returns false when the Gaussian is behind the near plane (only x, y, z are
+// valid then).
+__device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, const float *__restrict__ scale,
+                                             const float *__restrict__ quat, int N, int i, const DevCam &cam,
+                                             float eps2d, float near_z, Proj &p)
+{
+    const double px = mean[i], py = mean[N + i], pz = mean[2 * N + i];
+    for (int k = 0; k < 9; k++) p.W[k] = cam.R[k];
+    p.x = p.W[0] * px + p.W[1] * py + p.W[2] * pz + (double)cam.t[0];
+    p.y = p.W[3] * px + p.W[4] * py + p.W[5] * pz + (double)cam.t[1];
+    p.z = p.W[6] * px + p.W[7] * py + p.W[8] * pz + (double)cam.t[2];
+    if (!(p.z > (double)near_z)) return false;
+    const double iz = 1.0 / p.z;
+    const double fx = cam.fx, fy = cam.fy;
+    p.mx = fx * p.x * iz + (double)cam.cx;
+    p.my = fy * p.y * iz + (double)cam.cy;
+    // J W: rows (fx/z) (W0 - x/z W2) and (fy/z) (W1 - y/z W2)
+    const double ux = p.x * iz, uy = p.y * iz;
+    for (int k = 0; k < 3; k++) {
+        p.M[k] = fx * iz * (p.W[k] - ux * p.W[6 + k]);
+        p.M[3 + k] = fy * iz * (p.W[3 + k] - uy * p.W[6 + k]);
+    }
+    double q[4] = {quat[i], quat[N + i], quat[2 * N + i], quat[3 * N + i]};
+    p.qlen = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double il = 1.0 / p.qlen;
+    for (int k = 0; k < 4; k++) p.qn[k] = q[k] * il;
+    quat_rot(p.qn, p.Rg);
+    p.s[0] = scale[i];
+    p.s[1] = scale[N + i];
+    p.s[2] = scale[2 * N + i];
+    for (int r = 0; r < 2; r++)
+        for (int k = 0; k < 3; k++) {
+            const double mr = p.M[3 * r] * p.Rg[k] + p.M[3 * r + 1] * p.Rg[3 + k] + p.M[3 * r + 2] * p.Rg[6 + k];
+            p.P[3 * r + k] = mr * p.s[k];
+        }
+    p.a = p.P[0] * p.P[0] + p.P[1] * p.P[1] + p.P[2] * p.P[2] + (double)eps2d;
+    p.b = p.P[0] * p.P[3] + p.P[1] * p.P[4] + p.P[2] * p.P[5];
+    p.c = p.P[3] * p.P[3] + p.P[4] * p.P[4] + p.P[5] * p.P[5] + (double)eps2d;
+    p.det = p.a * p.c - p.b * p.b;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean, const float *__restrict__ scale,
+                                                 const float *__restrict__ quat,
+                                                 const float *__restrict__ opacity,
+                                                 const float *__restrict__ color, int N, int64_t M,
+                                                 const DevCam *__restrict__ cams, DevOpts o,
+                                                 gsl_splat *__restrict__ out, int32_t *__restrict__ tiles)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int c = (int)(m / N);
+    const int i = (int)(m - (int64_t)c * N);
+    const DevCam cam = cams[c];
+
+    gsl_splat sp;
+    sp.mx = sp.my = sp.l11 = sp.l12 = sp.l22 = 0.f;
+    sp.opacity = opacity[i];
+    sp.r = color[i];
+    sp.g = color[N + i];
+    sp.b = color[2 * N + i];
+    sp.depth = 0.f;
+    sp.x0 = 0; sp.y0 = 0; sp.x1 = -1; sp.y1 = -1;
+    int32_t ntiles = 0;
+
+    Proj p;
+    bool kept = compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
+    if (kept) {
+        const double W = cam.W, H = cam.H, g = o.guard;
+        if (p.mx < -g * W || p.mx > (1.0 + g) * W || p.my < -g * H || p.my > (1.0 + g) * H) kept = false;
+        if (!(p.det > 0.0)) kept = false;
+        const double sigma = sp.opacity;
+        if (!(sigma >= (double)o.alpha_min)) kept = false;
+        if (kept) {
+            // |L d|^2 <= k  <=>  sigma G(d) >= alpha_min;  the bbox of that
+            // ellipse is |dx| <= sqrt(k a), |dy| <= sqrt(k c).  The margin
+            // covers float32 evaluation of the power in the renderer.
+            const double k = 2.0 * log(sigma / (double)o.alpha_min) + 0.01;
+            const double hx = sqrt(k * p.a) + 0.01, hy = sqrt(k * p.c) + 0.01;
+            double x0 = ceil(p.mx - hx - 0.5), x1 = floor(p.mx + hx - 0.5);
+            double y0 = ceil(p.my - hy - 0.5), y1 = floor(p.my + hy - 0.5);
+            x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+            x1 = fmin(x1, W - 1.0); y1 = fmin(y1, H - 1.0);
+            if (x0 > x1 || y0 > y1) {
+                kept = false;
+            } else {
+                const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
+                const int T = o.tile;
+                ntiles = (ix1 / T - ix0 / T + 1) * (iy1 / T - iy0 / T + 1);
+                sp.x0 = (int16_t)ix0; sp.x1 = (int16_t)ix1;
+                sp.y0 = (int16_t)iy0; sp.y1 = (int16_t)iy1;
+                const double l22 = 1.0 / sqrt(p.c);
+                const double l11 = sqrt(p.c / p.det);
+                const double l12 = -p.b / sqrt(p.c * p.det);
+                sp.mx = (float)p.mx;
+                sp.my = (float)p.my;
+                sp.l11 = (float)l11;
+                sp.l12 = (float)l12;
+                sp.l22 = (float)l22;
+                sp.depth = (float)p.z;
+            }
+        }
+    }
+    out[m] = sp;
+    tiles[m] = ntiles;
+}
+
+// ------------------------------------------------------------------ backward
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
+    const float *__restrict__ mean, const float *__restrict__ scale, const float *__restrict__ quat, int N, int C,
+    const DevCam *__restrict__ cams, DevOpts o, const float *__restrict__ g2d, gsl_grads out, int accumulate,
+    double *__restrict__ pose_part)
+{
+    __shared__ double s_red[kPoseThreads / kWave][6];
+    const int i = blockIdx.x * kPoseThreads + threadIdx.x;
+    const bool valid = i < N;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+
+    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0, gc[3] = {0, 0, 0};
+    for (int c = 0; c < C; c++) {
+        double pose[6] = {0, 0, 0, 0, 0, 0};
+        bool any = false;
+        float g2[kG2];
+        if (valid) {
+            const float *src = g2d + ((int64_t)c * N + i) * kG2;
+            for (int k = 0; k < kG2; k++) {
+                g2[k] = src[k];
+                any |= g2[k] != 0.f;
+            }
+        }
+        if (any) {
+            const DevCam cam = cams[c];
+            Proj p;
+            compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
+            gop += g2[5];
+            gc[0] += g2[6]; gc[1] += g2[7]; gc[2] += g2[8];
+            // conic (A, B, C) = Sigma2D^{-1};  dL/dSigma2D = -Q Gq Q with
+            // Gq = [[gA, gB/2], [gB/2, gC]]
+            const double id = 1.0 / p.det;
+            const double QA = p.c * id, QB = -p.b * id, QC = p.a * id;
+            const double gA = g2[2], gB = 0.5 * (double)g2[3], gC = g2[4];
+            // T = Q Gq
+            const double t00 = QA * gA + QB * gB, t01 = QA * gB + QB * gC;
+            const double t10 = QB * gA + QC * gB, t11 = QB * gB + QC * gC;
+            const double S00 = -(t00 * QA + t01 * QB);
+            const double S01 = -(t00 * QB + t01 * QC);
+            const double S11 = -(t10 * QB + t11 * QC);
+            // Sigma2D = P P^T + eps I:  dL/dP = 2 S P
+            double GP[6];
+            for (int k = 0; k < 3; k++) {
+                GP[k] = 2.0 * (S00 * p.P[k] + S01 * p.P[3 + k]);
+                GP[3 + k] = 2.0 * (S01 * p.P[k] + S11 * p.P[3 + k]);
+            }
+            // P = M Rg diag(s):  dL/dM = GP diag(s) Rg^T,  dL/d(Rg diag s) = M^T GP
+            double GM[6];
+            for (int r = 0; r < 2; r++)
+                for (int j = 0; j < 3; j++) {
+                    double acc = 0;
+                    for (int k = 0; k < 3; k++) acc += GP[3 * r + k] * p.s[k] * p.Rg[3 * j + k];
+                    GM[3 * r + j] = acc;
+                }
+            double GRg[9];
+            for (int j = 0; j < 3; j++)
+                for (int k = 0; k < 3; k++) {
+                    const double gn = p.M[j] * GP[k] + p.M[3 + j] * GP[3 + k];
+                    GRg[3 * j + k] = gn * p.s[k];
+                    gs[k] += gn * p.Rg[3 * j + k];
+                }
+            // Rg from the normalised quaternion
+            {
+                const double w = p.qn[0], x = p.qn[1], y = p.qn[2], z = p.qn[3];
+                const double *G = GRg;
+                double dw = 2.0 * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+                double dx = 2.0 * (y * G[1] + z * G[2] + y * G[3] - 2.0 * x * G[4] - w * G[5] + z * G[6] + w * G[7] -
+                                   2.0 * x * G[8]);
+                double dy = 2.0 * (-2.0 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] -
+                                   2.0 * y * G[8]);
+                double dz = 2.0 * (-2.0 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.0 * z * G[4] + y * G[5] +
+                                   x * G[6] + y * G[7]);
+                const double dot = dw * w + dx * x + dy * y + dz * z;
+                const double il = 1.0 / p.qlen;
+                gq[0] += (dw - w * dot) * il;
+                gq[1] += (dx - x * dot) * il;
+                gq[2] += (dy - y * dot) * il;
+                gq[3] += (dz - z * dot) * il;
+            }
+            // M = J W:  dL/dJ = GM W^T,  dL/dW (through Sigma2D) = J^T GM
+            const double iz = 1.0 / p.z, fx = cam.fx, fy = cam.fy;
+            const double J00 = fx * iz, J02 = -fx * p.x * iz * iz, J11 = fy * iz, J12 = -fy * p.y * iz * iz;
+            double GJ[6];
+            for (int r = 0; r < 2; r++)
+                for (int j = 0; j < 3; j++)
+                    GJ[3 * r + j] = GM[3 * r] * p.W[3 * j] + GM[3 * r + 1] * p.W[3 * j + 1] +
+                                    GM[3 * r + 2] * p.W[3 * j + 2];
+            double GW[9];
+            for (int k = 0; k < 3; k++) {
+                GW[k] = J00 * GM[k];
+                GW[3 + k] = J11 * GM[3 + k];
+                GW[6 + k] = J02 * GM[k] + J12 * GM[3 + k];
+            }
+            // dL/dp_C: through mean2d (Jacobian J) and through J(p_C)
+            const double gmx = g2[0], gmy = g2[1];
+            const double iz2 = iz * iz, iz3 = iz2 * iz;
+            double gpx = J00 * gmx + GJ[2] * (-fx * iz2);
+            double gpy = J11 * gmy + GJ[5] * (-fy * iz2);
+            double gpz = J02 * gmx + J12 * gmy + GJ[0] * (-fx * iz2) + GJ[2] * (2.0 * fx * p.x * iz3) +
+                         GJ[4] * (-fy * iz2) + GJ[5] * (2.0 * fy * p.y * iz3);
+            // p_C = W p_W + t
+            gm[0] += p.W[0] * gpx + p.W[3] * gpy + p.W[6] * gpz;
+            gm[1] += p.W[1] * gpx + p.W[4] * gpy + p.W[7] * gpz;
+            gm[2] += p.W[2] * gpx + p.W[5] * gpy + p.W[8] * gpz;
+            // left twist: p_C <- p_C + dphi x p_C + dt,  W <- W + dphi^ W
+            // X = GW W^T;  the W term is (X21 - X12, X02 - X20, X10 - X01)
+            double X[9];
+            for (int r = 0; r < 3; r++)
+                for (int j = 0; j < 3; j++)
+                    X[3 * r + j] = GW[3 * r] * p.W[3 * j] + GW[3 * r + 1] * p.W[3 * j + 1] +
+                                   GW[3 * r + 2] * p.W[3 * j + 2];
+            pose[0] = p.y * gpz - p.z * gpy + (X[7] - X[5]);
+            pose[1] = p.z * gpx - p.x * gpz + (X[2] - X[6]);
+            pose[2] = p.x * gpy - p.y * gpx + (X[3] - X[1]);
+            pose[3] = gpx;
+            pose[4] = gpy;
+            pose[5] = gpz;
+        }
+        // per-camera block partial of the pose gradient (skipped when no lane
+        // of the workgroup sees this camera)
+        if (__syncthreads_or(any)) {
+            for (int k = 0; k < 6; k++) {
+                const double v = wave_sum_f64(pose[k]);
+                if (lane == 0) s_red[wv][k] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x < 6) {
+                double v = 0;
+                for (int w = 0; w < kPoseThreads / kWave; w++) v += s_red[w][threadIdx.x];
+                pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = v;
+            }
+            __syncthreads();
+        } else if (threadIdx.x < 6) {
+            pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = 0.0;
+        }
+    }
+    if (!valid) return;
+    auto put = [&](float *dst, int64_t idx, double v) {
+        if (!dst) return;
+        if (accumulate) dst[idx] += (float)v;
+        else dst[idx] = (float)v;
+    };
+    for (int k = 0; k < 3; k++) {
+        put(out.g_mean, (int64_t)k * N + i, gm[k]);
+        put(out.g_scale, (int64_t)k * N + i, gs[k]);
+        put(out.g_color, (int64_t)k * N + i, gc[k]);
+    }
+    for (int k = 0; k < 4; k++) put(out.g_quat, (int64_t)k * N + i, gq[k]);
+    put(out.g_opacity, i, gop);
+}
+
+__global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ part, int blocks, int C,
+                                                     double *__restrict__ g_pose, int accumulate)
+{
+    __shared__ double s_red[256 / kWave][6];
+    const int c = blockIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < blocks; b += 256)
+        for (int k = 0; k < 6; k++) acc[k] += part[((int64_t)b * C + c) * 6 + k];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (int k = 0; k < 6; k++) {
+        const double v = wave_sum_f64(acc[k]);
+        if (lane == 0) s_red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0;
+        for (int w = 0; w < 256 / kWave; w++) v += s_red[w][threadIdx.x];
+        if (accumulate) g_pose[c * 6 + threadIdx.x] += v;
+        else g_pose[c * 6 + threadIdx.x] = v;
+    }
+}
+
+}  // namespace
+
+void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t s)
+{
+    for (int b = 0; b < C; b += 16) {
+        CamBatch cb;
+        cb.n = C - b < 16 ? C - b : 16;
+        cb.dst = d_cams + b;
+        for (int k = 0; k < cb.n; k++) cb.cams[k] = h_cams[b + k];
+        hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(64), 0, s, cb);
+    }
+}
+
+void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
+                    gsl_splat *splats, int32_t *tiles_touched, hipStream_t s)
+{
+    if (L.M == 0) return;
+    const int64_t blocks = (L.M + 255) / 256;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
+                       g.color, g.N, L.M, cams, o, splats, tiles_touched);
+}
+
+void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
+                        const float *g2d, const gsl_grads &out, int accumulate, double *pose_part,
+                        int pose_blocks, hipStream_t s)
+{
+    if (L.N == 0 || pose_blocks == 0) return;
+    hipLaunchKernelGGL(k_project_bwd, dim3(pose_blocks), dim3(kPoseThreads), 0, s, g.mean, g.scale, g.quat, g.N,
+                       L.C, cams, o, g2d, out, accumulate, pose_part);
+}
+
+void launch_pose_reduce(const double *pose_part, int blocks, int C, double *g_pose, int accumulate, hipStream_t s)
+{
+    if (!g_pose || C == 0) return;
+    hipLaunchKernelGGL(k_pose_reduce, dim3(C), dim3(256), 0, s, pose_part, blocks, C, g_pose, accumulate);
+}
+
+}  // namespace gsl

@@ -1,0 +1,421 @@
+// Tile binning and the device radix sort.
+//
+// The paper's renderer orders each tile's Gaussians by depth (tile-based
+// depth sorting, Sec. II-C).  Here the order is built in two stable passes
+// that together equal one sort by the 64-bit key (tile << 32 | depth bits)
+// with ties by Gaussian index:
+//   1. the C*N projection records are sorted by their 32-bit depth key
+//      (LSD radix, 4 passes over the records, culled records last);
+//   2. every record, in that order, emits one (tile id, Gaussian index)
+//      instance per overlapped tile, and the K instances are sorted by tile
+//      id alone (LSD radix over only the ceil(log2 T) significant bits).
+// Stability of pass 2 keeps the depth order inside each tile, so the K-sized
+// sort moves 8 B per instance per pass over 1-3 passes instead of 12 B over
+// 6-7 passes.
+//
+// Radix pass design for wave64: per 4096-key block, each wave ranks its keys
+// with a ballot-based multisplit (8 ballots give the mask of lanes sharing a
+// digit; the rank is the popcount of that mask below the lane), the block
+// reorders its keys by digit in LDS, and writes them out in digit runs so the
+// global stores are contiguous.  Digit histograms are stored digit-major
+// ([256][blocks]) so one exclusive scan gives every block's output offsets.
+#include "common.hpp"
+
+namespace gsl {
+
+namespace {
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (lane == 0) ? 0ull : (~0ull >> (64 - lane)); }
+
+// ------------------------------------------------------------------ fills
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+__global__ void k_fill_f32(float *p, float v, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+__global__ void k_fill_f64(double *p, double v, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+inline unsigned fill_blocks(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// ------------------------------------------------------------------ scan
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane)
+{
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t o = __shfl_up(v, off, kWave);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Sum of each kScanTile-sized block.
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                              uint64_t *__restrict__ partial)
+{
+    __shared__ uint64_t s[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint64_t acc = 0;
+    for (int k = 0; k < kScanItems; k++) {
+        const int64_t j = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (j < n) acc += in[j];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanThreads / kWave; w++) t += s[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the block sums in one workgroup; writes the total.
+__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ partial, int64_t nb,
+                                                        int64_t *__restrict__ d_total)
+{
+    __shared__ uint64_t s_w[1024 / kWave];
+    __shared__ uint64_t s_carry;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t j = base + threadIdx.x;
+        const uint64_t v = j < nb ? partial[j] : 0;
+        const uint64_t inc = wave_incl_scan_u64(v, lane);
+        if (lane == 63) s_w[wv] = inc;
+        __syncthreads();
+        uint64_t wbase = 0, tot = 0;
+        for (int w = 0; w < 1024 / kWave; w++) {
+            if (w < wv) wbase += s_w[w];
+            tot += s_w[w];
+        }
+        const uint64_t carry = s_carry;
+        if (j < nb) partial[j] = carry + wbase + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && d_total) *d_total = (int64_t)s_carry;
+}
+
+// Block-local exclusive scan plus the block's offset.  Offsets beyond 2^32
+// wrap; the callers compare the 64-bit total against their capacity first.
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *__restrict__ in, int64_t n,
+                                                            const uint64_t *__restrict__ partial,
+                                                            uint32_t *__restrict__ out)
+{
+    __shared__ uint64_t s_w[kScanThreads / kWave];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // each thread owns kScanItems consecutive elements
+    uint32_t v[kScanItems];
+    uint64_t sum = 0;
+    const int64_t mybase = base + (int64_t)threadIdx.x * kScanItems;
+    for (int k = 0; k < kScanItems; k++) {
+        const int64_t j = mybase + k;
+        v[k] = j < n ? in[j] : 0u;
+        sum += v[k];
+    }
+    const uint64_t inc = wave_incl_scan_u64(sum, lane);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (int w = 0; w < wv; w++) wbase += s_w[w];
+    uint64_t run = partial[blockIdx.x] + wbase + inc - sum;
+    for (int k = 0; k < kScanItems; k++) {
+        const int64_t j = mybase + k;
+        if (j < n) out[j] = (uint32_t)run;
+        run += v[k];
+    }
+}
+
+// ------------------------------------------------------------------ radix sort
+
+__device__ __forceinline__ int64_t live_count(const int64_t *d_n, int64_t n_max)
+{
+    if (!d_n) return n_max;
+    const int64_t n = *d_n;
+    return n < n_max ? n : n_max;
+}
+
+// Mask of the lanes of this wave whose digit equals this lane's digit.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// Digit histogram of one 4096-key block, digit-major output hist[d * nb + block].
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__restrict__ keys, int64_t n_max,
+                                                          const int64_t *__restrict__ d_n, int shift,
+                                                          uint32_t *__restrict__ hist, int64_t nb)
+{
+    __shared__ uint32_t s_cnt[kSortThreads / kWave][256];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
+    for (int k = threadIdx.x; k < (kSortThreads / kWave) * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
+    __syncthreads();
+    const int64_t n = live_count(d_n, n_max);
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wv * (kSortTile / (kSortThreads / kWave));
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t j = base + (int64_t)r * kWave + lane;
+        const bool valid = j < n;
+        const uint32_t d = valid ? (keys[j] >> shift) & 0xffu : 0u;
+        const uint64_t peers = digit_peers(d, valid);
+        if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) s_cnt[wv][d] += __popcll(peers);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += kSortThreads) {
+        uint32_t t = 0;
+        for (int w = 0; w < kSortThreads / kWave; w++) t += s_cnt[w][d];
+        hist[(int64_t)d * nb + blockIdx.x] = t;
+    }
+}
+
+// Stable scatter of one block using the scanned digit-major histogram.
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__restrict__ kin,
+                                                             const uint32_t *__restrict__ vin,
+                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                             int64_t n_max, const int64_t *__restrict__ d_n, int shift,
+                                                             const uint32_t *__restrict__ hist_off, int64_t nb)
+{
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t s_cnt[NW][256];   // per-wave running digit counts, then wave bases
+    __shared__ uint32_t s_loc[256];       // block-local first position of each digit
+    __shared__ uint32_t s_glob[256];      // global first position of each digit for this block
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
+    for (int k = threadIdx.x; k < NW * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
+    __syncthreads();
+    const int64_t n = live_count(d_n, n_max);
+    const int64_t block_base = (int64_t)blockIdx.x * kSortTile;
+    if (block_base >= n) return;
+    const int64_t base = block_base + (int64_t)wv * (kSortTile / NW);
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t j = base + (int64_t)r * kWave + lane;
+        const bool valid = j < n;
+        key[r] = valid ? kin[j] : 0xffffffffu;
+        val[r] = valid ? vin[j] : 0u;
+        const uint32_t d = (key[r] >> shift) & 0xffu;
+        const uint64_t peers = digit_peers(d, valid);
+        const uint32_t before = valid ? s_cnt[wv][d] : 0u;
+        rank[r] = before + (uint32_t)__popcll(peers & lanemask_lt(lane));
+        if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) s_cnt[wv][d] = before + __popcll(peers);
+        if (!valid) rank[r] = 0xffffffffu;
+    }
+    __syncthreads();
+    // block-local digit starts and per-wave bases
+    if (threadIdx.x < 256) {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+        for (int w = 0; w < NW; w++) {
+            const uint32_t c = s_cnt[w][d];
+            s_cnt[w][d] = run;
+            run += c;
+        }
+        s_loc[d] = run;  // total of digit d in this block (scanned below)
+        s_glob[d] = hist_off[(int64_t)d * nb + blockIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        // exclusive scan of the 256 digit totals by one wave (4 per lane)
+        uint32_t t[4], sum = 0;
+        for (int k = 0; k < 4; k++) {
+            t[k] = s_loc[lane * 4 + k];
+            sum += t[k];
+        }
+        uint32_t inc = sum;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        uint32_t run = inc - sum;
+        for (int k = 0; k < 4; k++) {
+            s_loc[lane * 4 + k] = run;
+            run += t[k];
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < kSortItems; r++) {
+        if (rank[r] == 0xffffffffu) continue;
+        const uint32_t d = (key[r] >> shift) & 0xffu;
+        const uint32_t pos = s_loc[d] + s_cnt[wv][d] + rank[r];
+        s_key[pos] = key[r];
+        s_val[pos] = val[r];
+    }
+    __syncthreads();
+    const int64_t nloc64 = n - block_base;
+    const int nloc = nloc64 < kSortTile ? (int)nloc64 : kSortTile;
+    for (int p = threadIdx.x; p < nloc; p += kSortThreads) {
+        const uint32_t k = s_key[p];
+        const uint32_t d = (k >> shift) & 0xffu;
+        const uint32_t dst = s_glob[d] + (uint32_t)p - s_loc[d];
+        kout[dst] = k;
+        vout[dst] = s_val[p];
+    }
+}
+
+// ------------------------------------------------------------------ binning
+
+__global__ void k_depth_keys(const gsl_splat *__restrict__ splats, const int32_t *__restrict__ tiles, int64_t M,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    keys[m] = tiles[m] > 0 ? __float_as_uint(splats[m].depth) : 0xffffffffu;
+    vals[m] = (uint32_t)m;
+}
+
+__global__ void k_gather_counts(const uint32_t *__restrict__ order, const int32_t *__restrict__ tiles, int64_t M,
+                                uint32_t *__restrict__ counts)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    counts[j] = (uint32_t)tiles[order[j]];
+}
+
+__global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
+                       const gsl_splat *__restrict__ splats, const DevCam *__restrict__ cams, int N, int64_t M,
+                       int tile, const int64_t *__restrict__ d_K, int64_t capacity, uint32_t *__restrict__ tile_ids,
+                       uint32_t *__restrict__ gauss_ids, int32_t *__restrict__ d_status)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t K = *d_K;
+    if (j == 0) *d_status = K > capacity ? GSL_ECAPACITY : GSL_OK;
+    if (j >= M || K > capacity) return;
+    const uint32_t m = order[j];
+    const gsl_splat s = splats[m];
+    if (s.x0 > s.x1) return;
+    const int c = (int)(m / (uint32_t)N);
+    const uint32_t i = m - (uint32_t)c * (uint32_t)N;
+    const int tx = cams[c].tiles_x, toff = cams[c].tile_offset;
+    const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
+    uint32_t o = offsets[j];
+    for (int ty = ty0; ty <= ty1; ty++)
+        for (int x = tx0; x <= tx1; x++) {
+            tile_ids[o] = (uint32_t)(toff + ty * tx + x);
+            gauss_ids[o] = i;
+            o++;
+        }
+}
+
+__global__ void k_ranges(const uint32_t *__restrict__ tile_ids, const int64_t *__restrict__ d_K, int64_t capacity,
+                         uint32_t *__restrict__ ranges)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t K = *d_K;
+    if (K > capacity) return;
+    if (k >= K) return;
+    const uint32_t t = tile_ids[k];
+    if (k == 0 || tile_ids[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
+    if (k == K - 1 || tile_ids[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+}
+void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_f32, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+}
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint64_t *partial, int64_t *d_total,
+                     hipStream_t s)
+{
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        if (d_total) launch_fill_f64(reinterpret_cast<double *>(d_total), 0.0, 1, s);  // all-zero bits == int64 0
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, d_total);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, partial, offsets);
+}
+
+int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
+                      const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint64_t *partial,
+                      hipStream_t s)
+{
+    const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
+    if (nb == 0 || bits <= 0) return 0;
+    uint32_t *kin = keys, *vin = vals, *kout = keys2, *vout = vals2;
+    int where = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, n_max, d_n, shift, hist, nb);
+        launch_scan_u32(hist, hist_off, 256 * nb, partial, nullptr, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_max,
+                           d_n, shift, hist_off, nb);
+        uint32_t *tk = kin, *tv = vin;
+        kin = kout; vin = vout;
+        kout = tk; vout = tv;
+        where ^= 1;
+    }
+    return where;
+}
+
+void launch_depth_keys(const gsl_splat *splats, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
+                       hipStream_t s)
+{
+    if (M > 0)
+        hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, splats, tiles, M, keys,
+                           vals);
+}
+
+void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, uint32_t *counts, hipStream_t s)
+{
+    if (M > 0)
+        hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, order, tiles, M,
+                           counts);
+}
+
+void launch_emit(const uint32_t *order, const uint32_t *offsets, const gsl_splat *splats, const DevCam *cams,
+                 const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids, uint32_t *gauss_ids,
+                 int32_t *d_status, hipStream_t s)
+{
+    const int64_t blocks = L.M > 0 ? (L.M + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, splats, cams, L.N, L.M,
+                       L.tile, d_K, capacity, tile_ids, gauss_ids, d_status);
+}
+
+void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,
+                   uint32_t *ranges, hipStream_t s)
+{
+    launch_fill_u32(ranges, 0u, 2 * T_total, s);
+    if (capacity > 0)
+        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s, tile_ids, d_K,
+                           capacity, ranges);
+}
+
+}  // namespace gsl

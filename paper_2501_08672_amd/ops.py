@@ -1,0 +1,333 @@
+"""PyTorch-facing binding of the C ABI (argument marshalling only).
+
+Tensors provide device memory and the current HIP stream; every step of the
+path runs in libgslivo's kernels.  Names follow the ABI: project, bin_sort,
+render_fwd, render_bwd, window_step, window_tune.
+
+Layouts (all CUDA/HIP tensors, contiguous):
+  Gaussian parameters, SoA: mean (3, N), scale (3, N), quat (4, N) as
+  (w, x, y, z), opacity (N,), color (3, N); float32.
+  Images of a camera set are packed: camera c's planar (3, H, W) block starts
+  at float 3 * P_c with P_c the pixel count of the cameras before it
+  (CameraSet.unpack / CameraSet.pack convert).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+LOSS = {"l1": A.GSL_LOSS_L1, "l2": A.GSL_LOSS_L2}
+
+
+def _p(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def opts(tile: int = 16, **kw) -> A.Opts:
+    """Default rendering constants (alpha clamp 0.99, cutoff 1e-4, skip 1/255,
+    near 0.2 m, dilation 0.3 px^2, guard band 0.15, background 0)."""
+    return A.default_opts(tile, **kw)
+
+
+def _opts_copy(o: A.Opts, **kw) -> A.Opts:
+    n = A.Opts()
+    C.memmove(C.byref(n), C.byref(o), C.sizeof(A.Opts))
+    for k, v in kw.items():
+        setattr(n, k, v)
+    return n
+
+
+class Context:
+    """A gsl_ctx bound to one device, plus a growable scratch workspace."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the gslivo path runs only on the GPU")
+        torch.cuda.set_device(device)
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        A.check(A.lib().gsl_create(C.byref(h), int(device)))
+        self.h = h
+        self._ws = None
+        self.capacity = {}
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def close(self):
+        if self.h:
+            A.lib().gsl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CameraSet:
+    """Host description of the C cameras of a window."""
+
+    def __init__(self, cams):
+        self.cams = list(cams)
+        self.C = len(self.cams)
+        self.arr = A.camera_array(self.cams)
+        self.sizes = [(int(c.height), int(c.width)) for c in self.cams]
+        self.pix_offsets = np.concatenate([[0], np.cumsum([h * w for h, w in self.sizes])]).astype(np.int64)
+        self.P_total = int(self.pix_offsets[-1])
+
+    def tiles(self, tile: int) -> int:
+        T = C.c_int64()
+        P = C.c_int64()
+        A.check(A.lib().gsl_layout(self.arr, self.C, int(tile), C.byref(T), C.byref(P)))
+        return int(T.value)
+
+    def unpack(self, packed: torch.Tensor, channels: int = 3) -> List[torch.Tensor]:
+        out = []
+        for c, (h, w) in enumerate(self.sizes):
+            o = int(self.pix_offsets[c]) * channels
+            out.append(packed[o:o + channels * h * w].view(channels, h, w) if channels > 1
+                       else packed[o:o + h * w].view(h, w))
+        return out
+
+    def pack(self, images, channels: int = 3) -> torch.Tensor:
+        return torch.cat([im.reshape(-1) for im in images]).contiguous()
+
+
+@dataclass
+class Gaussians:
+    mean: torch.Tensor
+    scale: torch.Tensor
+    quat: torch.Tensor
+    opacity: torch.Tensor
+    color: torch.Tensor
+
+    @property
+    def N(self) -> int:
+        return int(self.opacity.shape[0])
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "Gaussians":
+        def soa(a):
+            return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32).T)).to(device)
+        return Gaussians(soa(scene.mean), soa(scene.scale), soa(scene.quat),
+                         torch.from_numpy(np.ascontiguousarray(scene.opacity, np.float32)).to(device),
+                         soa(scene.color))
+
+    def struct(self) -> A.Gaussians:
+        for t in (self.mean, self.scale, self.quat, self.opacity, self.color):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("Gaussian parameters must be contiguous float32 device tensors")
+        g = A.Gaussians()
+        g.mean, g.scale, g.quat = self.mean.data_ptr(), self.scale.data_ptr(), self.quat.data_ptr()
+        g.opacity, g.color = self.opacity.data_ptr(), self.color.data_ptr()
+        g.N = self.N
+        return g
+
+    def zeros_like(self) -> "Gaussians":
+        return Gaussians(*(torch.zeros_like(t) for t in (self.mean, self.scale, self.quat, self.opacity, self.color)))
+
+
+class Proj:
+    """gsl_project output: splats (C, N, 48 B) and tiles_touched (C, N)."""
+
+    def __init__(self, C_: int, N: int, device):
+        self.splats = torch.empty((C_, N, A.SPLAT_BYTES), dtype=torch.uint8, device=device)
+        self.tiles_touched = torch.empty((C_, N), dtype=torch.int32, device=device)
+
+    def struct(self) -> A.Proj:
+        p = A.Proj()
+        p.splats, p.tiles_touched = self.splats.data_ptr(), self.tiles_touched.data_ptr()
+        return p
+
+    def fields(self):
+        """Host copy of the splats as named numpy arrays (for tests)."""
+        raw = self.splats.cpu().numpy()
+        f = raw.view(np.float32).reshape(raw.shape[0], raw.shape[1], 12)
+        b = raw.view(np.int16).reshape(raw.shape[0], raw.shape[1], 24)
+        names = ["mx", "my", "l11", "l12", "l22", "opacity", "r", "g", "b", "depth"]
+        out = {n: f[..., k].copy() for k, n in enumerate(names)}
+        out["bbox"] = b[..., 20:24].copy()
+        out["tiles_touched"] = self.tiles_touched.cpu().numpy()
+        return out
+
+
+class Bins:
+    def __init__(self, capacity: int, T_total: int, device):
+        self.capacity = int(capacity)
+        self.tile_ids = torch.empty(max(1, self.capacity), dtype=torch.int32, device=device)
+        self.gauss_ids = torch.empty(max(1, self.capacity), dtype=torch.int32, device=device)
+        self.ranges = torch.empty((max(1, T_total), 2), dtype=torch.int32, device=device)
+        self.d_K = torch.zeros(1, dtype=torch.int64, device=device)
+        self.d_status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.T_total = T_total
+
+    def struct(self) -> A.Bins:
+        b = A.Bins()
+        b.tile_ids, b.gauss_ids, b.ranges = self.tile_ids.data_ptr(), self.gauss_ids.data_ptr(), self.ranges.data_ptr()
+        b.d_K, b.d_status = self.d_K.data_ptr(), self.d_status.data_ptr()
+        b.capacity_K = self.capacity
+        return b
+
+    @property
+    def K(self) -> int:
+        return int(self.d_K.item())
+
+
+class Grads:
+    def __init__(self, N: int, C_: int, device):
+        self.mean = torch.empty((3, N), dtype=torch.float32, device=device)
+        self.scale = torch.empty((3, N), dtype=torch.float32, device=device)
+        self.quat = torch.empty((4, N), dtype=torch.float32, device=device)
+        self.opacity = torch.empty((N,), dtype=torch.float32, device=device)
+        self.color = torch.empty((3, N), dtype=torch.float32, device=device)
+        self.pose = torch.empty((C_, 6), dtype=torch.float64, device=device)
+
+    def struct(self) -> A.Grads:
+        g = A.Grads()
+        g.g_mean, g.g_scale, g.g_quat = self.mean.data_ptr(), self.scale.data_ptr(), self.quat.data_ptr()
+        g.g_opacity, g.g_color, g.g_pose = self.opacity.data_ptr(), self.color.data_ptr(), self.pose.data_ptr()
+        return g
+
+
+def workspace_size(ctx: Context, cams: CameraSet, N: int, o: A.Opts, capacity: int) -> int:
+    n = C.c_size_t()
+    A.check(A.lib().gsl_workspace_size(ctx.h, cams.arr, cams.C, int(N), C.byref(o), int(capacity), C.byref(n)))
+    return int(n.value)
+
+
+# ---------------------------------------------------------------- the steps
+
+def project(ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, out: Optional[Proj] = None) -> Proj:
+    out = out or Proj(cams.C, g.N, ctx.device)
+    nb = workspace_size(ctx, cams, g.N, o, 0)
+    ws = ctx.workspace(nb)
+    gs, ps = g.struct(), out.struct()
+    A.check(A.lib().gsl_project(ctx.h, C.byref(gs), cams.arr, cams.C, C.byref(o), C.byref(ps), _p(ws),
+                                ws.numel(), _stream()))
+    return out
+
+
+def bin_sort(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, capacity: Optional[int] = None,
+             bins: Optional[Bins] = None, grow: bool = True) -> Bins:
+    """Eager binning.  With grow=True the call synchronises to read K and
+    repeats with a larger capacity when K exceeds it."""
+    T_total = cams.tiles(o.tile)
+    key = (cams.C, N, int(o.tile), tuple(cams.sizes))
+    cap = capacity if capacity is not None else ctx.capacity.get(key, max(1 << 16, 4 * cams.C * N))
+    for _ in range(3):
+        if bins is None or bins.capacity < cap or bins.T_total != T_total:
+            bins = Bins(cap, T_total, ctx.device)
+        nb = workspace_size(ctx, cams, N, o, bins.capacity)
+        ws = ctx.workspace(nb)
+        ps, bs = proj.struct(), bins.struct()
+        A.check(A.lib().gsl_bin_sort(ctx.h, cams.arr, cams.C, int(N), C.byref(o), C.byref(ps), C.byref(bs),
+                                     _p(ws), ws.numel(), _stream()))
+        if not grow:
+            return bins
+        status = int(bins.d_status.item())
+        if status == A.GSL_OK:
+            return bins
+        cap = int(bins.K * 1.25) + 1024
+        ctx.capacity[key] = cap
+        bins = None
+    raise A.GslError(A.GSL_ECAPACITY, "instance capacity could not be satisfied")
+
+
+def render_fwd(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, bins: Bins):
+    """Returns (packed image (3 P_total,), T_final (P_total,), n_walk (P_total,) int32)."""
+    image = torch.empty(3 * cams.P_total, dtype=torch.float32, device=ctx.device)
+    T_final = torch.empty(cams.P_total, dtype=torch.float32, device=ctx.device)
+    n_walk = torch.empty(cams.P_total, dtype=torch.int32, device=ctx.device)
+    nb = workspace_size(ctx, cams, N, o, bins.capacity)
+    ws = ctx.workspace(nb)
+    ps, bs = proj.struct(), bins.struct()
+    A.check(A.lib().gsl_render_fwd(ctx.h, cams.arr, cams.C, int(N), C.byref(o), C.byref(ps), C.byref(bs),
+                                   _p(image), _p(T_final), _p(n_walk), _p(ws), ws.numel(), _stream()))
+    return image, T_final, n_walk
+
+
+def render_bwd(ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, proj: Proj, bins: Bins, T_final, n_walk,
+               dL_dimage: torch.Tensor, accumulate: bool = False, out: Optional[Grads] = None) -> Grads:
+    out = out or Grads(g.N, cams.C, ctx.device)
+    nb = workspace_size(ctx, cams, g.N, o, bins.capacity)
+    ws = ctx.workspace(nb)
+    gs, ps, bs, gr = g.struct(), proj.struct(), bins.struct(), out.struct()
+    dl = dL_dimage.contiguous()
+    A.check(A.lib().gsl_render_bwd(ctx.h, C.byref(gs), cams.arr, cams.C, C.byref(o), C.byref(ps), C.byref(bs),
+                                   _p(T_final), _p(n_walk), _p(dl), int(bool(accumulate)), C.byref(gr), _p(ws),
+                                   ws.numel(), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- window
+
+class Window:
+    """All buffers of one batched-window optimisation pass (gsl_window_step).
+
+    The buffers are owned here so that a captured HIP graph can be replayed:
+    after the first graph-mode step, later steps with the same objects only
+    launch the graph."""
+
+    def __init__(self, ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, target: torch.Tensor,
+                 loss: str = "l1", capacity: Optional[int] = None, keep_image: bool = False, headroom=1.15):
+        self.ctx, self.g, self.cams, self.opts = ctx, g, cams, _opts_copy(o)
+        self.target = target.contiguous()
+        self.loss = LOSS[loss]
+        self.keep_image = keep_image
+        self.headroom = headroom
+        self.grads = Grads(g.N, cams.C, ctx.device)
+        self.d_loss = torch.zeros(1, dtype=torch.float64, device=ctx.device)
+        self.image = torch.empty(3 * cams.P_total, dtype=torch.float32, device=ctx.device) if keep_image else None
+        self._alloc(capacity)
+
+    def _alloc(self, capacity):
+        o = self.opts
+        self.proj = Proj(self.cams.C, self.g.N, self.ctx.device)
+        if capacity is None:
+            project(self.ctx, self.g, self.cams, o, out=self.proj)
+            b = bin_sort(self.ctx, self.cams, self.g.N, o, self.proj)
+            capacity = int(b.K * self.headroom) + 4096
+            del b
+        self.bins = Bins(capacity, self.cams.tiles(o.tile), self.ctx.device)
+        nb = workspace_size(self.ctx, self.cams, self.g.N, o, capacity)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=self.ctx.device)
+
+    def step(self, use_graph: bool = True):
+        gs, ps, bs, gr = self.g.struct(), self.proj.struct(), self.bins.struct(), self.grads.struct()
+        A.check(A.lib().gsl_window_step(self.ctx.h, C.byref(gs), self.cams.arr, self.cams.C, C.byref(self.opts),
+                                        _p(self.target), self.loss, C.byref(ps), C.byref(bs), _p(self.image),
+                                        _p(self.d_loss), C.byref(gr), _p(self.ws), self.ws.numel(),
+                                        int(bool(use_graph)), _stream()))
+
+    def status(self) -> int:
+        return int(self.bins.d_status.item())
+
+    def tune(self):
+        """Autotune tile size and fused variant; re-allocates for the chosen tile."""
+        o8 = _opts_copy(self.opts, tile=8)
+        save = self.opts
+        self.opts = o8
+        self._alloc(None)  # capacity and ranges for tile 8 bound every tile size
+        times = (C.c_float * 6)()
+        gs, ps, bs, gr = self.g.struct(), self.proj.struct(), self.bins.struct(), self.grads.struct()
+        ot = _opts_copy(save)
+        A.check(A.lib().gsl_window_tune(self.ctx.h, C.byref(gs), self.cams.arr, self.cams.C, C.byref(ot),
+                                        _p(self.target), self.loss, C.byref(ps), C.byref(bs), _p(self.d_loss),
+                                        C.byref(gr), _p(self.ws), self.ws.numel(), times, 6, _stream()))
+        self.opts = ot
+        self._alloc(None)
+        return int(ot.tile), [float(t) for t in times]
