@@ -29,11 +29,15 @@
  * by index, which is the order a 32-bit depth key gives.
  *
  * Ambiguity flags: a pixel whose result hinges on a threshold decision that
- * FP32 arithmetic may take the other way (alpha within a relative band of
- * a_min, transmittance within the band of T_min, a cull decision within a
- * tiny band) is flagged AMB_VALUE; a contributor whose sigma*G lies within the
- * band of a_max (where the clamp switches the alpha gradient on or off) sets
- * AMB_GRAD.
+ * FP32 arithmetic may take the other way is flagged AMB_VALUE: sigma*G within
+ * its FP32 error bound of a_min, T(1 - a) within the accumulated bound of
+ * T_min, or a cull decision within a tiny band.  A contributor whose sigma*G
+ * lies within the bound of a_max (where the clamp switches the alpha gradient
+ * on or off) sets AMB_GRAD.  The bound is first order in the FP32 unit
+ * roundoff u = 2^-24: the rounding of the 2D mean and of the conic factor,
+ * the evaluation of the quadratic form, exp and the products, times the
+ * safety factor amb_rel; for T it accumulates a (dalpha)/(1 - a) per
+ * contributor.
  */
 #include <math.h>
 #include <stdint.h>
@@ -58,7 +62,7 @@ typedef struct {
     double T_min;     /* transmittance cutoff */
     double bg[3];     /* background colour */
     double guard;     /* cull when the 2D mean is beyond guard*W (guard*H) outside the image */
-    double amb_rel;   /* relative band around a_min, a_max and T_min for the ambiguity flags */
+    double amb_rel;   /* safety factor on the FP32 error bound used by the ambiguity flags */
 } orc_opts;
 
 enum { ORC_KEPT = 1, ORC_BORDER = 2 };
@@ -258,7 +262,8 @@ static double composite_pixel(double px, double py, int64_t M, const int64_t *or
     double T = 1.0, C[3] = {0, 0, 0};
     int32_t n = 0, flags = 0;
     int64_t last = -1;
-    const double amb = o->amb_rel;
+    const double amb = o->amb_rel, u = 0x1p-24;
+    double eT = 0.0; /* relative FP32 error bound accumulated on T */
     for (int64_t k = 0; k < M; k++) {
         int64_t i = order[k];
         const proj_t *p = &proj[i];
@@ -266,19 +271,29 @@ static double composite_pixel(double px, double py, int64_t M, const int64_t *or
         double power = -0.5 * (p->Q[0] * dx * dx + 2.0 * p->Q[1] * dx * dy + p->Q[2] * dy * dy);
         double G = exp(power);
         double s = opacity[i] * G;
+        /* first-order relative error bound of an FP32 evaluation of s */
+        double gx = p->Q[0] * dx + p->Q[1] * dy, gy = p->Q[1] * dx + p->Q[2] * dy;
+        double sa = sqrt(p->Q[0]);
+        double t1 = fabs(sa * dx + p->Q[1] / sa * dy), e1 = sa * fabs(dx) + fabs(p->Q[1]) / sa * fabs(dy);
+        double ds = amb * u *
+                    (16.0 + 4.0 * fabs(power) + 2.0 * (fabs(gx) * (fabs(p->mu[0]) + fabs(dx)) +
+                                                       fabs(gy) * (fabs(p->mu[1]) + fabs(dy))) +
+                     2.0 * t1 * e1);
         if (!(p->status & ORC_KEPT)) { /* on a cull border only: flag if it would matter here */
-            if (s >= o->alpha_min * (1 - amb)) flags |= AMB_VALUE;
+            if (s >= o->alpha_min * (1 - ds)) flags |= AMB_VALUE;
             continue;
         }
         if (p->status & ORC_BORDER)
-            if (s >= o->alpha_min * (1 - amb)) flags |= AMB_VALUE;
-        if (fabs(s - o->alpha_min) <= amb * o->alpha_min) flags |= AMB_VALUE;
+            if (s >= o->alpha_min * (1 - ds)) flags |= AMB_VALUE;
+        if (fabs(s - o->alpha_min) <= ds * o->alpha_min) flags |= AMB_VALUE;
         double a = s < o->alpha_max ? s : o->alpha_max;
         if (a < o->alpha_min) continue;
-        if (fabs(s - o->alpha_max) <= amb * o->alpha_max) flags |= AMB_GRAD;
+        if (fabs(s - o->alpha_max) <= ds * o->alpha_max) flags |= AMB_GRAD;
         double Tn = T * (1.0 - a);
-        if (fabs(Tn - o->T_min) <= amb * o->T_min) flags |= AMB_VALUE;
+        double da = s < o->alpha_max ? a * ds / (1.0 - a) : 0.0;
+        if (fabs(Tn - o->T_min) <= o->T_min * (eT + da + amb * 4.0 * u)) flags |= AMB_VALUE;
         if (Tn < o->T_min) break;
+        eT += da + amb * 4.0 * u;
         for (int ch = 0; ch < 3; ch++) C[ch] += a * T * color[3 * i + ch];
         if (list) {
             list[n].id = i;

@@ -57,7 +57,7 @@ class Opts:
     T_min: float = 1e-4
     bg: tuple = (0.0, 0.0, 0.0)
     guard: float = 0.15
-    amb_rel: float = 1e-3
+    amb_rel: float = 4.0  # safety factor on the FP32 error bound of the ambiguity flags
 
     def c(self) -> _Opts:
         o = _Opts()
