@@ -1,0 +1,96 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and compare it with the FP64 oracle under the parity rules.
+
+Parity rules (FP32 GPU against FP64 oracle):
+  * images: |GPU - oracle| <= 1e-4 on every pixel the oracle does not flag as
+    threshold-ambiguous (alpha within 0.1% of 1/255, T(1 - alpha) within 0.1%
+    of the 1e-4 cutoff, a cull decision on its border); flagged pixels are
+    counted and must stay a small fraction;
+  * gradients: per tensor, max |GPU - oracle| <= 1e-3 max |oracle|, and per
+    element |GPU - oracle| <= 1e-3 |oracle| wherever |oracle| >= 1e-2 max|oracle|
+    (loosened only where the test says so, with the reason);
+  * integer and index results: bit-exact.
+"""
+import numpy as np
+import torch
+
+IMG_TOL = 1e-4
+GRAD_REL = 1e-3
+
+
+def ops():
+    from paper_2501_08672_amd import ops as O
+    return O
+
+
+_CTX = {}
+
+
+def context():
+    O = ops()
+    if "ctx" not in _CTX:
+        _CTX["ctx"] = O.Context(0)
+    return _CTX["ctx"]
+
+
+def gpu_forward(scene, cams, tile=16, **optkw):
+    O = ops()
+    ctx = context()
+    o = O.opts(tile, **optkw)
+    g = O.Gaussians.from_scene(scene)
+    cs = O.CameraSet(cams)
+    proj = O.project(ctx, g, cs, o)
+    bins = O.bin_sort(ctx, cs, g.N, o, proj)
+    image, T, nw = O.render_fwd(ctx, cs, g.N, o, proj, bins)
+    torch.cuda.synchronize()
+    return {"ctx": ctx, "opts": o, "g": g, "cams": cs, "proj": proj, "bins": bins, "image": image, "T": T,
+            "n_walk": nw}
+
+
+def gpu_backward(state, v_packed, accumulate=False):
+    O = ops()
+    s = state
+    gr = O.render_bwd(s["ctx"], s["g"], s["cams"], s["opts"], s["proj"], s["bins"], s["T"], s["n_walk"],
+                      v_packed, accumulate=accumulate)
+    torch.cuda.synchronize()
+    return {"mean": gr.mean.cpu().numpy().T.astype(np.float64), "scale": gr.scale.cpu().numpy().T.astype(np.float64),
+            "quat": gr.quat.cpu().numpy().T.astype(np.float64), "opacity": gr.opacity.cpu().numpy().astype(np.float64),
+            "color": gr.color.cpu().numpy().T.astype(np.float64), "pose": gr.pose.cpu().numpy()}
+
+
+def oracle_opts(O_oracle, **kw):
+    return O_oracle.Opts(**kw)
+
+
+def compare_images(gpu_img, orc_img, flags, tol=IMG_TOL, max_flag_frac=0.02, name=""):
+    """gpu_img, orc_img: (3, H, W); flags (H, W).  Returns (max error, flagged count)."""
+    ok = (flags & 1) == 0
+    err = np.abs(gpu_img.astype(np.float64) - orc_img)
+    bad = err[:, ok]
+    mx = float(bad.max()) if bad.size else 0.0
+    assert mx <= tol, f"{name}: max |GPU - oracle| = {mx:.3g} > {tol} on unflagged pixels"
+    nflag = int((~ok).sum())
+    assert nflag <= max_flag_frac * ok.size + 2, f"{name}: {nflag} ambiguous pixels of {ok.size}"
+    return mx, nflag
+
+
+def compare_grads(gpu, orc, rel=GRAD_REL, keys=("mean", "scale", "quat", "opacity", "color"), elem_rel=None,
+                  name=""):
+    elem_rel = rel if elem_rel is None else elem_rel
+    report = {}
+    for k in keys:
+        a, b = np.asarray(gpu[k], np.float64), np.asarray(orc[k], np.float64)
+        assert a.shape == b.shape, (k, a.shape, b.shape)
+        m = float(np.abs(b).max())
+        d = np.abs(a - b)
+        report[k] = (float(d.max()), m)
+        assert d.max() <= rel * m + 1e-12, f"{name} {k}: max diff {d.max():.3g} > {rel} * {m:.3g}"
+        big = np.abs(b) >= 1e-2 * m
+        if big.any():
+            r = (d[big] / np.abs(b[big])).max()
+            assert r <= elem_rel, f"{name} {k}: element relative error {r:.3g} > {elem_rel}"
+    return report
+
+
+def unpack_np(cs, packed, channels=3):
+    return [t.cpu().numpy() for t in cs.unpack(packed, channels)]

@@ -1,0 +1,387 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
+
+Sizes span several tiles, several radix-sort blocks and ragged tails; the
+full-size workloads are checked on sampled pixels the oracle computes one by
+one.  Tolerances are the ones stated in tests/gpuutil.py.
+"""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import scenegen as S
+from scenegen import Camera
+
+from gpuutil import (compare_grads, compare_images, context, gpu_backward, gpu_forward, ops, unpack_np)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rot_cam(W, H, f, seed):
+    rng = np.random.default_rng(seed)
+    R = Rotation.from_rotvec(rng.normal(0, 0.2, 3)).as_matrix()
+    return Camera(f, f * 1.02, W / 2 + 3.3, H / 2 - 2.1, W, H, R, rng.normal(0, 0.3, 3))
+
+
+def _scene_multi(n, seed):
+    """A scene seen by three cameras of different sizes and poses."""
+    cams = [_rot_cam(96, 80, 90.0, seed), _rot_cam(130, 70, 110.0, seed + 1), _rot_cam(64, 64, 60.0, seed + 2)]
+    sc = S.random_scene(n, cams[0], seed, zmin=1.0, zmax=4.0, unnormalised_quats=True)
+    sc.cams = cams
+    return sc
+
+
+# ------------------------------------------------------------------ project
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_project_matches_oracle(oracle, seed):
+    sc = _scene_multi(3000, seed)
+    st = gpu_forward(sc, sc.cams, tile=16)
+    f = st["proj"].fields()
+    o = oracle.Opts()
+    for c, cam in enumerate(sc.cams):
+        p = oracle.project(sc, cam, o)
+        kept_g = f["depth"][c] > 0
+        kept_o = (p["status"] & 1) == 1
+        # every splat the GPU keeps, the oracle keeps
+        assert not np.any(kept_g & ~kept_o)
+        # a splat only the oracle keeps cannot reach alpha_min on any pixel
+        only_o = np.nonzero(kept_o & ~kept_g)[0]
+        v, u = np.mgrid[0:cam.height, 0:cam.width]
+        for i in only_o[:200]:
+            A, B, Cc = p["conic"][i]
+            dx, dy = u + 0.5 - p["mean2d"][i, 0], v + 0.5 - p["mean2d"][i, 1]
+            a = sc.opacity[i] * np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + Cc * dy * dy))
+            assert a.max() < o.alpha_min
+        k = np.nonzero(kept_g)[0]
+        np.testing.assert_allclose(f["mx"][c, k], p["mean2d"][k, 0], atol=2e-5 * max(cam.width, 1) / 64 + 1e-5)
+        np.testing.assert_allclose(f["my"][c, k], p["mean2d"][k, 1], atol=2e-5 * max(cam.height, 1) / 64 + 1e-5)
+        l11, l12, l22 = (f[n][c, k].astype(np.float64) for n in ("l11", "l12", "l22"))
+        conic = np.stack([l11 * l11, l11 * l12, l12 * l12 + l22 * l22], 1)
+        scale = np.abs(p["conic"][k]).max(1, keepdims=True)
+        np.testing.assert_allclose(conic, p["conic"][k], rtol=0, atol=1e-6 * scale.max())
+        assert np.all(np.abs(conic - p["conic"][k]) <= 2e-6 * scale)
+        z32 = p["p_cam"][k, 2].astype(np.float32)
+        assert np.all(np.abs(f["depth"][c, k] - z32) <= np.spacing(z32))
+        # bbox is conservative: every pixel with oracle alpha >= alpha_min lies inside it
+        bb = f["bbox"][c]
+        for i in k[:400]:
+            A, B, Cc = p["conic"][i]
+            dx, dy = u + 0.5 - p["mean2d"][i, 0], v + 0.5 - p["mean2d"][i, 1]
+            a = np.minimum(o.alpha_max, sc.opacity[i] * np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + Cc * dy * dy)))
+            hit = a >= o.alpha_min * (1 - 1e-6)
+            if hit.any():
+                uu, vv = u[hit], v[hit]
+                assert bb[i, 0] <= uu.min() and uu.max() <= bb[i, 2], (c, i)
+                assert bb[i, 1] <= vv.min() and vv.max() <= bb[i, 3], (c, i)
+        # tiles touched = tile span of the bbox
+        T = 16
+        span = (bb[k, 2] // T - bb[k, 0] // T + 1) * (bb[k, 3] // T - bb[k, 1] // T + 1)
+        np.testing.assert_array_equal(f["tiles_touched"][c, k], span)
+        assert np.all(f["tiles_touched"][c, ~kept_g] == 0)
+
+
+# ------------------------------------------------------------------ bin_sort
+
+def _expected_instances(f, cams, tile, N):
+    tiles_x = [(c.width + tile - 1) // tile for c in cams]
+    tiles_y = [(c.height + tile - 1) // tile for c in cams]
+    toff = np.concatenate([[0], np.cumsum([a * b for a, b in zip(tiles_x, tiles_y)])])
+    tid, dbits, gid = [], [], []
+    for c in range(len(cams)):
+        bb = f["bbox"][c]
+        d = f["depth"][c].view(np.uint32)
+        for i in np.nonzero(f["tiles_touched"][c] > 0)[0]:
+            for ty in range(bb[i, 1] // tile, bb[i, 3] // tile + 1):
+                for tx in range(bb[i, 0] // tile, bb[i, 2] // tile + 1):
+                    tid.append(toff[c] + ty * tiles_x[c] + tx)
+                    dbits.append(d[i])
+                    gid.append(i)
+    tid, dbits, gid = np.array(tid, np.int64), np.array(dbits, np.int64), np.array(gid, np.int64)
+    order = np.lexsort((gid, dbits, tid))
+    return tid[order], gid[order], int(toff[-1])
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_bin_sort_bit_exact(tile):
+    sc = _scene_multi(6000, 7)
+    st = gpu_forward(sc, sc.cams, tile=tile)
+    f = st["proj"].fields()
+    b = st["bins"]
+    K = b.K
+    assert int(b.d_status.item()) == 0
+    want_t, want_g, T_total = _expected_instances(f, sc.cams, tile, sc.n)
+    assert K == len(want_t) == int(f["tiles_touched"].sum())
+    assert K > 3 * 4096  # several radix-sort blocks plus a ragged tail
+    np.testing.assert_array_equal(b.tile_ids[:K].cpu().numpy(), want_t)
+    np.testing.assert_array_equal(b.gauss_ids[:K].cpu().numpy(), want_g)
+    rng = b.ranges.cpu().numpy()
+    starts = np.searchsorted(want_t, np.arange(T_total), "left")
+    ends = np.searchsorted(want_t, np.arange(T_total), "right")
+    np.testing.assert_array_equal(rng[:, 0][ends > starts], starts[ends > starts])
+    np.testing.assert_array_equal(rng[:, 1][ends > starts], ends[ends > starts])
+    assert np.all(rng[ends == starts, 0] == rng[ends == starts, 1])
+
+
+def test_bin_sort_capacity_overflow():
+    O = ops()
+    sc = _scene_multi(4000, 3)
+    ctx = context()
+    o = O.opts(16)
+    g = O.Gaussians.from_scene(sc)
+    cs = O.CameraSet(sc.cams)
+    proj = O.project(ctx, g, cs, o)
+    small = O.bin_sort(ctx, cs, g.N, o, proj, capacity=100, grow=False)
+    torch.cuda.synchronize()
+    assert int(small.d_status.item()) == -3  # GSL_ECAPACITY
+    K = small.K
+    assert K > 100
+    full = O.bin_sort(ctx, cs, g.N, o, proj, capacity=K, grow=False)
+    assert int(full.d_status.item()) == 0 and full.K == K
+
+
+# ------------------------------------------------------------------ render_fwd
+
+def test_render_fwd_config1(oracle):
+    sc = S.config1()
+    st = gpu_forward(sc, sc.cams, tile=16)
+    img = unpack_np(st["cams"], st["image"])[0]
+    r = oracle.render_image(sc, sc.cams[0], oracle.Opts())
+    compare_images(img, r["image"], r["flags"], name="config1")
+    T = unpack_np(st["cams"], st["T"], 1)[0]
+    ok = r["flags"] == 0
+    assert np.abs(T[ok] - r["T"][ok]).max() <= 1e-4
+
+
+def test_render_fwd_multicam_background(oracle):
+    sc = _scene_multi(4000, 11)
+    bg = (0.25, 0.5, 0.125)
+    st = gpu_forward(sc, sc.cams, tile=16, bg=bg)
+    imgs = unpack_np(st["cams"], st["image"])
+    for c, cam in enumerate(sc.cams):
+        r = oracle.render_image(sc, cam, oracle.Opts(bg=bg))
+        compare_images(imgs[c], r["image"], r["flags"], name=f"cam{c}")
+
+
+def test_render_last_contributor_matches(oracle):
+    """The Gaussian at the end of each pixel's walk is the oracle's last contributor."""
+    sc = S.config1(seed=3)
+    st = gpu_forward(sc, sc.cams, tile=16)
+    cam = sc.cams[0]
+    nw = unpack_np(st["cams"], st["n_walk"], 1)[0]
+    r = oracle.render_image(sc, cam, oracle.Opts())
+    rng = st["bins"].ranges.cpu().numpy()
+    gids = st["bins"].gauss_ids.cpu().numpy()
+    tx = (cam.width + 15) // 16
+    ok = r["flags"] == 0
+    for v in range(cam.height):
+        for u in range(cam.width):
+            if not ok[v, u]:
+                continue
+            t = (v // 16) * tx + u // 16
+            n = nw[v, u]
+            got = gids[rng[t, 0] + n - 1] if n > 0 else -1
+            assert got == r["last"][v, u], (u, v)
+
+
+def test_render_tile_size_invariance():
+    sc = _scene_multi(3000, 5)
+    imgs = [gpu_forward(sc, sc.cams, tile=t)["image"].cpu().numpy() for t in (8, 16, 32)]
+    np.testing.assert_array_equal(imgs[0], imgs[1])
+    np.testing.assert_array_equal(imgs[1], imgs[2])
+
+
+def test_render_permutation_invariance():
+    sc = _scene_multi(3000, 6)
+    perm = np.random.default_rng(0).permutation(sc.n)
+    sp = sc.permuted(perm)
+    sp.cams = sc.cams
+    a = gpu_forward(sc, sc.cams)["image"].cpu().numpy()
+    b = gpu_forward(sp, sc.cams)["image"].cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+
+
+def test_render_config2_sampled(oracle):
+    """Full-size 100k / 640x512 workload: 3000 sampled pixels."""
+    sc, _ = S.config2()
+    st = gpu_forward(sc, sc.cams, tile=16)
+    img = unpack_np(st["cams"], st["image"])[0]
+    cam = sc.cams[0]
+    rng = np.random.default_rng(0)
+    pix = np.stack([rng.integers(0, cam.width, 3000), rng.integers(0, cam.height, 3000)], 1).astype(np.int32)
+    r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
+    got = img[:, pix[:, 1], pix[:, 0]]
+    ok = (r["flags"] & 1) == 0
+    err = np.abs(got.T - r["rgb"])[ok]
+    assert err.max() <= 1e-4, err.max()
+    assert (~ok).sum() <= 0.01 * len(ok)
+
+
+def test_render_empty_and_degenerate():
+    O = ops()
+    # all Gaussians behind the camera: background everywhere, K = 0
+    cam = Camera(50.0, 50.0, 20.0, 15.0, 40, 30, np.eye(3), np.zeros(3))
+    sc = S.random_scene(500, cam, 1)
+    sc.mean[:, 2] = -sc.mean[:, 2]
+    st = gpu_forward(sc, [cam], tile=16, bg=(0.1, 0.2, 0.3))
+    assert st["bins"].K == 0
+    img = unpack_np(st["cams"], st["image"])[0]
+    np.testing.assert_allclose(img, np.broadcast_to(np.float32([0.1, 0.2, 0.3])[:, None, None], img.shape))
+    # a single-pixel camera and a camera smaller than one tile
+    cams = [Camera(5.0, 5.0, 0.5, 0.5, 1, 1, np.eye(3), np.zeros(3)),
+            Camera(20.0, 20.0, 3.0, 2.5, 7, 5, np.eye(3), np.zeros(3))]
+    sc2 = S.random_scene(300, cams[1], 2, smin=0.05, smax=0.3)
+    st2 = gpu_forward(sc2, cams, tile=32)
+    assert np.isfinite(st2["image"].cpu().numpy()).all()
+
+
+# ------------------------------------------------------------------ backward
+
+def _cotangent(oracle, sc, cams, seed, o_kw=None):
+    """Random cotangents, zero on pixels the oracle flags as ambiguous."""
+    rng = np.random.default_rng(seed)
+    vs = []
+    for cam in cams:
+        r = oracle.render_image(sc, cam, oracle.Opts(**(o_kw or {})))
+        v = rng.normal(size=(3, cam.height, cam.width))
+        v[:, r["flags"] != 0] = 0.0
+        vs.append(v)
+    return vs
+
+
+def test_render_bwd_config1(oracle):
+    sc = S.config1()
+    st = gpu_forward(sc, sc.cams, tile=16)
+    vs = _cotangent(oracle, sc, sc.cams, 0)
+    v_packed = torch.from_numpy(np.concatenate([v.astype(np.float32).ravel() for v in vs])).cuda()
+    gg = gpu_backward(st, v_packed)
+    go = oracle.render_bwd(sc, sc.cams, vs, oracle.Opts())
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name="config1")
+
+
+def test_render_bwd_multicam_pose(oracle):
+    sc = _scene_multi(2500, 21)
+    bg = (0.2, 0.1, 0.3)
+    st = gpu_forward(sc, sc.cams, tile=16, bg=bg)
+    vs = _cotangent(oracle, sc, sc.cams, 1, {"bg": bg})
+    v_packed = torch.from_numpy(np.concatenate([v.astype(np.float32).ravel() for v in vs])).cuda()
+    gg = gpu_backward(st, v_packed)
+    go = oracle.render_bwd(sc, sc.cams, vs, oracle.Opts(bg=bg))
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name="multicam")
+
+
+def test_render_bwd_accumulate():
+    sc = _scene_multi(1500, 22)
+    st = gpu_forward(sc, sc.cams, tile=16)
+    v = torch.randn(3 * st["cams"].P_total, device="cuda")
+    a = gpu_backward(st, v)
+    O = ops()
+    gr = O.render_bwd(st["ctx"], st["g"], st["cams"], st["opts"], st["proj"], st["bins"], st["T"], st["n_walk"], v)
+    O.render_bwd(st["ctx"], st["g"], st["cams"], st["opts"], st["proj"], st["bins"], st["T"], st["n_walk"], v,
+                 accumulate=True, out=gr)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(gr.mean.cpu().numpy().T, 2 * a["mean"], rtol=1e-5, atol=1e-6 * np.abs(a["mean"]).max())
+    # the 2D gradients come from float atomics, so two runs differ in summation order
+    np.testing.assert_allclose(gr.pose.cpu().numpy(), 2 * a["pose"], rtol=1e-5, atol=1e-6 * np.abs(a["pose"]).max())
+
+
+def test_render_bwd_config2_sampled(oracle):
+    """Full-size 100k / 640x512 with the cotangent non-zero on 400 sampled pixels."""
+    sc, _ = S.config2()
+    cam = sc.cams[0]
+    st = gpu_forward(sc, sc.cams, tile=16)
+    rng = np.random.default_rng(5)
+    pix = np.stack([rng.integers(0, cam.width, 400), rng.integers(0, cam.height, 400)], 1).astype(np.int32)
+    pix = np.unique(pix, axis=0)
+    r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
+    pix = pix[r["flags"] == 0]
+    v = rng.normal(size=(len(pix), 3))
+    vimg = np.zeros((3, cam.height, cam.width), np.float32)
+    vimg[:, pix[:, 1], pix[:, 0]] = v.T
+    gg = gpu_backward(st, torch.from_numpy(vimg.ravel()).cuda())
+    go = oracle.render_bwd(sc, [cam], [v], oracle.Opts(), pixels=[pix])
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name="config2")
+
+
+# ------------------------------------------------------------------ window
+
+def _window(sc, target_packed, tile, loss, keep_image=True):
+    O = ops()
+    ctx = context()
+    g = O.Gaussians.from_scene(sc)
+    cs = O.CameraSet(sc.cams)
+    w = O.Window(ctx, g, cs, O.opts(tile), target_packed, loss=loss, keep_image=keep_image)
+    return w
+
+
+def test_window_step_matches_separate_calls():
+    """Fused forward + loss gradient + backward equals render_fwd, the loss
+    gradient formed on the host side, and render_bwd."""
+    sc = _scene_multi(4000, 31)
+    tgt_scene = S.jitter_means(sc, 0.02, 5)
+    tgt_scene.cams = sc.cams
+    tgt = gpu_forward(tgt_scene, sc.cams)["image"]
+    for loss in ("l2", "l1"):
+        w = _window(sc, tgt, 16, loss)
+        w.step(use_graph=False)
+        torch.cuda.synchronize()
+        st = gpu_forward(sc, sc.cams, tile=16)
+        np.testing.assert_array_equal(w.image.cpu().numpy(), st["image"].cpu().numpy())
+        r = st["image"] - tgt
+        if loss == "l2":
+            v = r
+            want_loss = 0.5 * float((r.double() ** 2).sum())
+        else:
+            inv = torch.cat([torch.full((3 * h * wd,), 1.0 / (3 * h * wd), device="cuda")
+                             for h, wd in st["cams"].sizes])
+            v = torch.sign(r) * inv
+            want_loss = float((r.abs().double() * inv.double()).sum())
+        gg = gpu_backward(st, v.float())
+        got = {"mean": w.grads.mean.cpu().numpy().T, "scale": w.grads.scale.cpu().numpy().T,
+               "quat": w.grads.quat.cpu().numpy().T, "opacity": w.grads.opacity.cpu().numpy(),
+               "color": w.grads.color.cpu().numpy().T, "pose": w.grads.pose.cpu().numpy()}
+        compare_grads(got, gg, rel=1e-5, keys=("mean", "scale", "quat", "opacity", "color", "pose"),
+                      elem_rel=1e-4, name=f"window {loss}")
+        assert abs(float(w.d_loss.item()) - want_loss) <= 1e-5 * abs(want_loss)
+
+
+def test_window_graph_replay_and_variants():
+    sc = _scene_multi(3000, 41)
+    tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda")
+    w = _window(sc, tgt, 16, "l2")
+    w.step(use_graph=False)
+    torch.cuda.synchronize()
+    ref = (w.grads.mean.clone(), w.grads.pose.clone(), w.d_loss.clone(), w.image.clone())
+    for _ in range(3):
+        w.step(use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(w.image, ref[3])
+        assert abs(float(w.d_loss.item()) - float(ref[2].item())) <= 1e-9 * abs(float(ref[2].item()))
+        torch.testing.assert_close(w.grads.mean, ref[0], rtol=1e-5, atol=1e-6 * float(ref[0].abs().max()))
+        torch.testing.assert_close(w.grads.pose, ref[1], rtol=1e-6, atol=1e-9)
+        # eager work between replays
+        _ = (w.target * 2).sum().item()
+    tile, times = w.tune()
+    assert tile in (8, 16, 32)
+    w.step(use_graph=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(w.image.cpu().numpy(), ref[3].cpu().numpy())
+
+
+def test_rasterize_autograd():
+    O = ops()
+    from paper_2501_08672_amd.autograd import rasterize
+    sc = _scene_multi(2000, 51)
+    ctx = context()
+    cs = O.CameraSet(sc.cams)
+    g = O.Gaussians.from_scene(sc)
+    params = [t.clone().requires_grad_(True) for t in (g.mean, g.scale, g.quat, g.opacity, g.color)]
+    pose = torch.zeros((cs.C, 6), dtype=torch.float64, device="cuda", requires_grad=True)
+    img, T = rasterize(*params, cs, ctx, O.opts(16), pose)
+    wgt = torch.randn_like(img)
+    (img * wgt).sum().backward()
+    st = gpu_forward(sc, sc.cams)
+    gg = gpu_backward(st, wgt)
+    np.testing.assert_allclose(params[0].grad.cpu().numpy().T, gg["mean"], rtol=1e-5,
+                               atol=1e-6 * np.abs(gg["mean"]).max())
+    np.testing.assert_allclose(pose.grad.cpu().numpy(), gg["pose"], rtol=1e-5, atol=1e-9)
