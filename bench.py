@@ -1,21 +1,24 @@
 """Benchmark of the batched-window hot path on one MI355X.
 
-Workload (default): 500k surfel Gaussians on 50 random planes, 8 keyframes at
-1280x1024 on a smooth trajectory (0.3 m / 5 degrees apart), L1 photometric
-loss against a target rendered from a jittered copy.  One step = one pass of
-the whole path over the window: projection, depth sort + tile binning + tile
-sort, one fused forward/loss/backward launch over every (camera, tile) item,
-and the projection adjoint to means, scales, quaternions, opacities, colours
-and the 8 camera poses, replayed as one captured HIP graph.
+Workload: 500k surfel Gaussians on 50 random planes, 8 keyframes at 1280x1024
+on a smooth trajectory (0.3 m / 5 degrees apart), L1 photometric loss against
+a target rendered from a copy with means jittered by N(0, 0.02 m).  One step
+is one pass of the whole path over the window — projection, depth sort, tile
+binning, tile sort, one fused forward/loss/backward launch over every
+(camera, tile) item, the projection adjoint to means, scales, quaternions,
+opacities, colours and the 8 camera poses — replayed as one HIP graph.
+Inputs are resident in HBM before the timed region.
 
-Prints one JSON line:
-  value            fwd+bwd Mpixels/s of the window step (8 * 1280 * 1024 / t)
-  fwd_ms_per_frame forward-only (project + bin_sort + render_fwd) ms / frame
-  per_frame        the same window done as 8 sequential single-camera steps
-  roofline         the fused render kernel, timed with HIP events on its stream
-  cpu_baseline     the FP64 oracle on a pixel sample of the same workload
+Prints one JSON line; besides the metric it carries
+  fwd_ms_per_frame  forward only (project + bin_sort + render_fwd) per frame
+  per_frame         the same window as 8 sequential single-camera eager steps
+  roofline          the fused render kernel (dominant), ALU-bound: algorithmic
+                    FLOPs from the pair counts / its duration (HIP events on
+                    its stream) against the FP32 vector peak
+  cpu_baseline      the FP64 oracle, forward + backward, on a pixel sample
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,7 +29,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 4 SIMD x 16 lanes x 2 FMA x 2 packed x 2.4 GHz)
+# FLOPs per (pixel, Gaussian) pair, counted from the per-pair formulas of the
+# compositing and its adjoint (add/mul/min/exp = 1, fma = 2):
+F_EVAL = 13        # alpha of one pair (forward walk, and again in the backward walk)
+F_CONTRIB = 52     # a contributor: 9 in the forward, 43 in the backward
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_render_traffic.txt")
+RENDER_SRC = os.path.join(ROOT, "paper_2501_08672_amd", "csrc", "render.hip")
 
 
 def log(*a):
@@ -38,12 +48,63 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=192, help="oracle sample: pixels per camera")
+    ap.add_argument("--cpu-pixels", type=int, default=320, help="oracle sample: pixels per camera")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration runs)")
     return ap.parse_args()
+
+
+def source_digest():
+    return hashlib.sha1(open(RENDER_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per fused launch from the committed counter summary, or None
+    when it is missing or was taken on a different render.hip."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for ln in open(TRAFFIC_FILE):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("render_hip_sha1") != source_digest():
+            return None
+        f = float(kv["copy_bytes"]) / (float(kv["copy_fetch_kib"]) * 1024)
+        w = float(kv["copy_bytes"]) / (float(kv["copy_write_kib"]) * 1024)
+        return float(kv["fused_fetch_kib"]) * 1024 * f + float(kv["fused_write_kib"]) * 1024 * w
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
+def cpu_baseline(sc, cams, per_cam, seed=0):
+    """The FP64 oracle, as it stands, on `per_cam` seeded pixels of every camera."""
+    from oracle import oracle as O
+    O.build(force=False)
+    rng = np.random.default_rng(seed)
+    pix, vs = [], []
+    for cam in cams:
+        p = np.stack([rng.integers(0, cam.width, per_cam), rng.integers(0, cam.height, per_cam)], 1)
+        pix.append(p.astype(np.int32))
+        vs.append(rng.normal(size=(per_cam, 3)))
+    o = O.Opts()
+    t0 = time.perf_counter()
+    for cam, p in zip(cams, pix):
+        O.render(sc, cam, o, pixels=p)
+    t1 = time.perf_counter()
+    O.render_bwd(sc, cams, vs, o, pixels=pix)
+    t2 = time.perf_counter()
+    n = per_cam * len(cams)
+    return {"value": round(n / (t2 - t0) / 1e6, 6), "unit": "Mpixels/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{per_cam} seeded pixels per camera x {len(cams)} cameras of the same window; forward "
+                      f"{t1 - t0:.2f} s + backward (random cotangent on those pixels) {t2 - t1:.2f} s; each call "
+                      f"projects and depth-orders all {sc.n} Gaussians"}
 
 
 def main():
@@ -56,39 +117,45 @@ def main():
     import scenegen as S
     from paper_2501_08672_amd import ops
 
-    if args.config != 3:
-        raise SystemExit("bench.py measures the 500k / 8-keyframe window workload (--config 3)")
+    if args.copy_calib_mib:
+        nb = args.copy_calib_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda").random_(0, 255)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes x 3")
+        del src, dst
+
     t0 = time.time()
     sc, tgt_sc = S.config3()
-    log(f"scene generated in {time.time() - t0:.1f}s: N={sc.n}, cams={len(sc.cams)}")
+    log(f"scene generated in {time.time() - t0:.1f}s: N={sc.n}, cams={len(sc.cams)}, digest {sc.digest()}")
     ctx = ops.Context(0)
     cs = ops.CameraSet(sc.cams)
     g = ops.Gaussians.from_scene(sc)
     gt = ops.Gaussians.from_scene(tgt_sc)
     o = ops.opts(16)
-    # target images: the jittered scene rendered by the same path
     pt = ops.project(ctx, gt, cs, o)
     bt = ops.bin_sort(ctx, cs, gt.N, o, pt)
     target, _, _ = ops.render_fwd(ctx, cs, gt.N, o, pt, bt)
-    del pt, bt
+    del pt, bt, gt
     torch.cuda.synchronize()
 
     win = ops.Window(ctx, g, cs, o, target, loss="l1")
     tune_times = None
     if args.tile == 0:
         tile, tune_times = win.tune()
-        log(f"autotune: tile {tile}, ms per tried variant {['%.2f' % t for t in tune_times]}")
+        log(f"autotune: tile {tile}; ms per (tile, variant) tried: {['%.2f' % t for t in tune_times]}")
     else:
         win.opts = ops._opts_copy(o, tile=args.tile)
         win._alloc(None)
     tile = int(win.opts.tile)
-    K = win.bins  # capacity holder
     use_graph = not args.no_graph
     for _ in range(args.warmup):
         win.step(use_graph)
     torch.cuda.synchronize()
     assert win.status() == 0, "instance capacity exceeded"
-    Kval = win.bins.K
+    K = win.bins.K
     t_start = time.perf_counter()
     for _ in range(args.steps):
         win.step(use_graph)
@@ -96,44 +163,67 @@ def main():
     t_win = (time.perf_counter() - t_start) / args.steps
     P = cs.P_total
     mpix = P / t_win / 1e6
-    log(f"window step {t_win * 1e3:.3f} ms, {mpix:.1f} Mpix/s, K={Kval}, loss={float(win.d_loss.item()):.5f}")
+    log(f"window step {t_win * 1e3:.3f} ms, {mpix:.1f} Mpix/s, K={K}, loss={float(win.d_loss.item()):.6f}")
+
+    # stage times of eager steps (HIP events on the launch stream)
+    stages = np.array([win.profiled_step() for _ in range(5)])
+    st_ms = stages.mean(0)
+    log("eager stage ms (project, bin_sort, fused render, adjoint, total): " + " ".join(f"{x:.3f}" for x in st_ms))
+    fused_ms = float(st_ms[2])
+
+    # pair counts of the compositing on the window's bins -> algorithmic FLOPs
+    ev_f, n_contrib, ev_b = ops.render_stats(ctx, cs, g.N, win.opts, win.proj, win.bins)
+    flops = F_EVAL * (ev_f + ev_b) + F_CONTRIB * n_contrib
+    achieved = flops / (fused_ms * 1e-3) / 1e12
+    visible = [int((win.proj.tiles_touched[c] > 0).sum().item()) for c in range(cs.C)]
+    log(f"pairs: fwd {ev_f}, contributors {n_contrib}, bwd {ev_b}; visible per camera {visible}")
+
+    # algorithmic bytes of the fused kernel: instance list, splat records and
+    # 2D-gradient records of the visible Gaussians, target read, image write
+    fused_bytes = 4 * K + 72 * sum(visible) + 8 * cs.tiles(tile) + 24 * P
+    # whole-step algorithmic bytes (every logical array read/written once per stage)
+    N, C_ = g.N, cs.C
+    step_bytes = N * 144 + C_ * N * 60 + sum(visible) * 144 + K * 48 + cs.tiles(tile) * 16 + P * 32
 
     # forward only, eager: project + bin_sort + render_fwd over the window
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fo = win.opts
     proj = ops.Proj(cs.C, g.N, ctx.device)
     bins = ops.Bins(win.bins.capacity, cs.tiles(tile), ctx.device)
-    for it in range(3):
+    for it in range(4):
         if it == 1:
             ev0.record()
-        ops.project(ctx, g, cs, fo, out=proj)
-        ops.bin_sort(ctx, cs, g.N, fo, proj, capacity=bins.capacity, bins=bins, grow=False)
-        ops.render_fwd(ctx, cs, g.N, fo, proj, bins)
+        ops.project(ctx, g, cs, win.opts, out=proj)
+        ops.bin_sort(ctx, cs, g.N, win.opts, proj, capacity=bins.capacity, bins=bins, grow=False)
+        ops.render_fwd(ctx, cs, g.N, win.opts, proj, bins)
     ev1.record()
     torch.cuda.synchronize()
-    fwd_ms = ev0.elapsed_time(ev1) / 2
+    fwd_ms = ev0.elapsed_time(ev1) / 3
+    del proj, bins
     log(f"forward only {fwd_ms:.3f} ms per window, {fwd_ms / cs.C:.3f} ms/frame")
 
-    # per-frame plain launches: the same work as 8 sequential single-camera eager steps
-    frames = []
-    for c in range(cs.C):
-        c1 = ops.CameraSet([sc.cams[c]])
-        tc = cs.unpack(target)[c].reshape(-1).contiguous()
-        w1 = ops.Window(ctx, g, c1, win.opts, tc, loss="l1")
-        frames.append(w1)
-    for w1 in frames:
-        w1.step(False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    reps = max(2, args.steps // 4)
-    for _ in range(reps):
+    per_frame = None
+    if not args.no_per_frame:
+        frames = []
+        for c in range(cs.C):
+            c1 = ops.CameraSet([sc.cams[c]])
+            tc = cs.unpack(target)[c].reshape(-1).contiguous()
+            frames.append(ops.Window(ctx, g, c1, win.opts, tc, loss="l1"))
         for w1 in frames:
             w1.step(False)
-    torch.cuda.synchronize()
-    t_pf = (time.perf_counter() - t1) / reps
-    log(f"per-frame plain launches {t_pf * 1e3:.3f} ms per window ({P / t_pf / 1e6:.1f} Mpix/s)")
-    del frames
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            for w1 in frames:
+                w1.step(False)
+        torch.cuda.synchronize()
+        t_pf = (time.perf_counter() - t1) / reps
+        per_frame = {"ms_per_window": round(t_pf * 1e3, 4), "mpix_s": round(P / t_pf / 1e6, 2),
+                     "how": "8 sequential single-camera eager window steps, same tile and kernels"}
+        log(f"per-frame plain launches {t_pf * 1e3:.3f} ms per window ({P / t_pf / 1e6:.1f} Mpix/s)")
+        del frames
 
+    traffic = read_traffic()
     result = {
         "metric": "fwd+bwd Mpixels/s at 500k Gaussians, 8-frame window; fwd ms/frame",
         "value": round(mpix, 2),
@@ -148,14 +238,31 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched window: 500k surfel Gaussians on 50 planes, 8 keyframes 1280x1024, "
-                               "L1 loss, fwd+bwd incl. pose gradients",
+                               "L1 loss, fwd+bwd to all Gaussian parameters and the 8 poses",
                    "gaussians": sc.n, "frames": cs.C, "width": 1280, "height": 1024, "tile": tile,
-                   "instances_K": Kval, "hip_graph": use_graph},
+                   "instances_K": K, "hip_graph": use_graph},
         "fwd_ms_per_frame": round(fwd_ms / cs.C, 4),
-        "per_frame": {"ms_per_window": round(t_pf * 1e3, 4), "mpix_s": round(P / t_pf / 1e6, 2)},
+        "per_frame": per_frame,
+        "stage_ms": {"project": round(st_ms[0], 4), "bin_sort": round(st_ms[1], 4),
+                     "fused_render": round(st_ms[2], 4), "adjoint": round(st_ms[3], 4)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None if traffic is None else int(traffic),
+                     "kernel": "k_render_fused", "kernel_ms": round(fused_ms, 4),
+                     "algorithmic_flops": int(flops),
+                     "pairs": {"fwd_evaluated": ev_f, "contributors": n_contrib, "bwd_evaluated": ev_b},
+                     "hbm_view": {"algorithmic_bytes": int(fused_bytes),
+                                  "gbs": round(fused_bytes / (fused_ms * 1e-3) / 1e9, 1),
+                                  "frac": round(fused_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
+        "window_hbm": {"algorithmic_bytes": int(step_bytes),
+                       "frac": round(step_bytes / t_win / 1e9 / HBM_PEAK_GBS, 4)},
     }
     if tune_times is not None:
         result["autotune_ms"] = [round(t, 3) for t in tune_times]
+    if not args.no_cpu:
+        log("oracle baseline on a pixel sample ...")
+        result["cpu_baseline"] = cpu_baseline(sc, sc.cams, args.cpu_pixels)
+        log(f"oracle: {result['cpu_baseline']}")
     print(json.dumps(result), flush=True)
     ctx.close()
 

@@ -189,6 +189,15 @@ GSL_API int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camer
                    const float *dL_dimage, int accumulate, gsl_grads *grads, void *workspace,
                    size_t workspace_bytes, void *stream);
 
+/* Work counts of the compositing on these bins (for throughput accounting):
+ * d_counts[0] = (pixel, Gaussian) pairs the forward walk evaluates, up to
+ * and including the one that stops it; d_counts[1] = contributing pairs;
+ * d_counts[2] = pairs the backward walk evaluates (the sum of walk lengths).
+ * d_counts is device uint64[3], overwritten. */
+GSL_API int gsl_render_stats(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                             const gsl_proj *proj, const gsl_bins *bins, uint64_t *d_counts, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
 /* ---- the batched window ------------------------------------------------ */
 
 enum { GSL_LOSS_L1 = 1, GSL_LOSS_L2 = 2 };
@@ -208,6 +217,14 @@ GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
                     const float *target, int loss, gsl_proj *proj, gsl_bins *bins, float *image,
                     double *d_loss, gsl_grads *grads, void *workspace, size_t workspace_bytes,
                     int use_graph, void *stream);
+
+/* Profiling hook: while enabled, every eager (use_graph == 0) window step
+ * records HIP events on its stream between its stages.  gsl_profile_read
+ * waits for the last profiled step and writes up to n milliseconds:
+ * [0] upload + project, [1] bin_sort, [2] the fused render launch,
+ * [3] loss reduction + projection adjoint, [4] the whole step. */
+GSL_API int gsl_profile(gsl_ctx *ctx, int enable);
+GSL_API int gsl_profile_read(gsl_ctx *ctx, float *ms, int32_t n);
 
 /* Autotuner for gsl_window_step: times every tile size in {8, 16, 32} and
  * every fused-kernel variant on the given window (eager launches on

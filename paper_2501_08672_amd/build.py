@@ -18,7 +18,10 @@ OBJ = os.path.join(ROOT, "_build", "obj")
 ARCH = os.environ.get("GSL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["project.hip", "sort.hip", "render.hip", "api.cpp"]
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# no packed FP32, and no implicit contraction: every fused multiply-add in the
+# kernels is written out, so the same expression rounds the same way in every
+# kernel and template instantiation
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off"]
 
 
 def _compile(src):

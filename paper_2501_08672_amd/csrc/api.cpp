@@ -73,10 +73,16 @@ struct GraphEntry {
 
 }  // namespace
 
+// Stages of a window step timed by the profiling hook.
+enum { kStProject, kStBinSort, kStRender, kStProjectBwd, kStages };
+
 struct gsl_ctx {
     int device = 0;
     int num_cus = 256;
     hipStream_t cap_stream = nullptr;
+    bool profile = false;
+    hipEvent_t ev[kStages + 1] = {};
+    bool ev_recorded = false;
     std::mutex mu;
     std::map<VariantKey, int> variant;  // (window shapes, tile) -> fused variant
     std::map<VariantKey, GraphEntry> graphs;
@@ -316,12 +322,19 @@ void do_project_bwd(const Prepared &p, const gsl_gaussians *g, gsl_grads *grads,
     }
 }
 
+// Enqueues one window step.  With `timed`, HIP events are recorded on the
+// stream between the stages (never while capturing a graph).
 void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const float *target, int loss,
                gsl_proj *proj, gsl_bins *bins, float *image, double *d_loss, gsl_grads *grads, void *ws, int variant,
-               hipStream_t s)
+               hipStream_t s, bool timed = false)
 {
+    auto mark = [&](int k) {
+        if (timed) (void)hipEventRecord(ctx->ev[k], s);
+    };
+    mark(kStProject);
     do_upload(p, ws, s);
     do_project(p, g, proj, ws, s);
+    mark(kStBinSort);
     do_bin_sort(p, proj, bins, ws, s);
     launch_fill_f32(at<float>(ws, p.W.g2d), 0.f, p.L.M * kG2, s);
     launch_fill_u32(at<uint32_t>(ws, p.W.misc), 0u, 1, s);
@@ -329,9 +342,13 @@ void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const fl
     a.image = image;
     a.target = target;
     a.loss = loss;
+    mark(kStRender);
     launch_render_fused(a, variant, ctx->num_cus, s);
+    mark(kStProjectBwd);
     launch_reduce_f64(at<double>(ws, p.W.loss_part), p.L.T_total, d_loss, s);
     do_project_bwd(p, g, grads, 0, ws, s);
+    mark(kStages);
+    if (timed) ctx->ev_recorded = true;
 }
 
 VariantKey window_key(const Layout &L, const gsl_camera *cams)
@@ -396,6 +413,8 @@ int gsl_destroy(gsl_ctx *ctx)
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
     return GSL_OK;
 }
@@ -466,6 +485,23 @@ int gsl_render_fwd(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, c
     return check_launch("gsl_render_fwd");
 }
 
+int gsl_render_stats(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
+                     const gsl_proj *proj, const gsl_bins *bins, uint64_t *d_counts, void *workspace,
+                     size_t workspace_bytes, void *stream)
+{
+    GSL_TRY(check_bins(bins));
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    if (!d_counts) return fail(GSL_EINVAL, "d_counts is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    do_upload(p, workspace, s);
+    launch_fill_f64(reinterpret_cast<double *>(d_counts), 0.0, 3, s);  // all-zero bits
+    RenderArgs a = render_args(p, proj, bins, workspace);
+    launch_render_count(a, reinterpret_cast<unsigned long long *>(d_counts), s);
+    return check_launch("gsl_render_stats");
+}
+
 int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
                    const gsl_proj *proj, const gsl_bins *bins, const float *T_final, const uint32_t *n_walk,
                    const float *dL_dimage, int accumulate, gsl_grads *grads, void *workspace, size_t workspace_bytes,
@@ -510,7 +546,7 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
         if (it != ctx->variant.end()) variant = it->second;
     }
     if (!use_graph) {
-        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, s);
+        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, s, ctx->profile);
         return check_launch("gsl_window_step");
     }
     // graph key: shapes, variant, every pointer, options and camera contents
@@ -558,6 +594,28 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
         it = ctx->graphs.emplace(gk, e).first;
     }
     GSL_TRY(check_hip(hipGraphLaunch(it->second.exec, s), "hipGraphLaunch"));
+    return GSL_OK;
+}
+
+int gsl_profile(gsl_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(GSL_EINVAL, "ctx is NULL");
+    if (enable && !ctx->ev[0])
+        for (auto &e : ctx->ev) GSL_TRY(check_hip(hipEventCreate(&e), "hipEventCreate"));
+    ctx->profile = enable != 0;
+    ctx->ev_recorded = false;
+    return GSL_OK;
+}
+
+int gsl_profile_read(gsl_ctx *ctx, float *ms, int32_t n)
+{
+    if (!ctx || !ms) return fail(GSL_EINVAL, "NULL argument");
+    if (!ctx->ev_recorded) return fail(GSL_ESTATE, "no profiled window step has been enqueued");
+    GSL_TRY(check_hip(hipEventSynchronize(ctx->ev[kStages]), "hipEventSynchronize"));
+    for (int k = 0; k < kStages && k < n; k++)
+        GSL_TRY(check_hip(hipEventElapsedTime(&ms[k], ctx->ev[k], ctx->ev[k + 1]), "hipEventElapsedTime"));
+    if (n > kStages) GSL_TRY(check_hip(hipEventElapsedTime(&ms[kStages], ctx->ev[0], ctx->ev[kStages]),
+                                       "hipEventElapsedTime"));
     return GSL_OK;
 }
 

@@ -139,6 +139,8 @@ void launch_render_fwd(const RenderArgs &a, hipStream_t s);
 void launch_render_bwd(const RenderArgs &a, hipStream_t s);
 // variant: 0 = one workgroup per (camera, tile) item, 1 = persistent work queue
 void launch_render_fused(const RenderArgs &a, int variant, int num_cus, hipStream_t s);
+// counts[3] (device, accumulated): forward pairs evaluated, contributors, backward pairs
+void launch_render_count(const RenderArgs &a, unsigned long long *counts, hipStream_t s);
 void launch_reduce_f64(const double *part, int64_t n, double *out, hipStream_t s);
 void launch_pose_reduce(const double *pose_part, int blocks, int C, double *g_pose, int accumulate,
                         hipStream_t s);

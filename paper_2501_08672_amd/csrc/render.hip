@@ -1,11 +1,13 @@
 // Front-to-back alpha compositing (eq. eq:raster) and its hand-written
 // adjoint (eq. eq:gaussian_optimization), per (camera, tile) work item.
 //
-// One workgroup owns one tile of TS x TS pixels, one lane per pixel.  The
-// tile's depth-ordered instance list is staged through LDS in chunks of up to
-// TS*TS splats (48 B each, loaded as three float4 by one lane per splat) and
-// every lane walks the chunk from LDS with broadcast reads.  A per-workgroup
-// vote ends the walk once every pixel is done.
+// Layout for wave64: a workgroup of NW waves owns one TS x TS tile; wave w
+// owns TS/NW rows of it and each lane owns PPL pixels of one column of that
+// strip (PPL = 4 for 16x16 tiles with one wave).  The tile's depth-ordered
+// instance list is staged through LDS in chunks of 64*NW splats (48 B each,
+// one lane loads one splat as three float4) and every lane walks the chunk
+// with broadcast LDS reads, evaluating its PPL pixels against each splat.
+// The walk ends for the wave as soon as none of its pixels is still open.
 //
 // Per pixel (centre x = (u + 0.5, v + 0.5)):
 //   power = -1/2 |L (x - mu)|^2,  alpha = min(alpha_max, sigma exp(power))
@@ -18,15 +20,17 @@
 // contributor by dividing by (1 - alpha), and carries the suffix
 // S = sum_{j>k} c_j alpha_j T_j + T_final bg, so that
 //   dI/dc_k = alpha_k T_k,  dI/dalpha_k = T_k c_k - S / (1 - alpha_k).
-// The nine 2D gradients of a Gaussian are summed over the 64 lanes of a wave
-// (skipped when no lane contributed) and added with one float atomic per
-// value per wave into the per-(camera, Gaussian) record.
+// Each lane first sums the nine 2D gradients of a splat over its own pixels;
+// the wave then sums them with DPP adds on the VALU (no LDS permutes), and a
+// single atomic instruction with nine active lanes adds the totals into the
+// per-(camera, Gaussian) record.  A splat no pixel of the wave used costs no
+// reduction and no atomic.
 //
-// The fused kernel runs forward, the per-pixel loss gradient against a target
-// image (L1 or L2, local to the pixel) and the backward walk in one pass over
-// each item, keeping T, the walk length and the colour in registers.  Its
-// persistent variant launches a few workgroups per CU that pull items from an
-// atomic counter.
+// The fused kernel runs the forward walk, the per-pixel loss and its
+// gradient against the target image (L1 or L2, local to the pixel) and the
+// backward walk for one item, keeping T, the walk lengths and the colours in
+// registers.  Its persistent variant launches a few workgroups per CU that
+// take items from an atomic counter.
 #include "common.hpp"
 
 namespace gsl {
@@ -35,8 +39,45 @@ namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
 
-__device__ __forceinline__ float exp_fast(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <int TS, int NW>
+struct Geo {
+    static constexpr int BS = kWave * NW;          // lanes per workgroup
+    static constexpr int ROWS = TS / NW;           // tile rows per wave
+    static constexpr int PPL = TS * ROWS / kWave;  // pixels per lane
+    static constexpr int RSTEP = kWave / TS;       // row stride between a lane's pixels
+    static constexpr int CH = BS;                  // splats staged per chunk
+    static_assert(TS * ROWS % kWave == 0 && PPL >= 1, "tile/wave layout");
+};
+
+// DPP sum of a wave: the total lands in lane 63.
+__device__ __forceinline__ float dpp_sum63(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ float wave_total(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dpp_sum63(v)), 63));
+}
+
+__device__ __forceinline__ uint32_t wave_total_u32(uint32_t v)
+{
+    v += __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x141, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x140, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false);
+    return __builtin_amdgcn_readlane(v, 63);
+}
 
 __device__ __forceinline__ int find_cam(const DevCam *__restrict__ cams, int C, int t)
 {
@@ -49,48 +90,55 @@ __device__ __forceinline__ int find_cam(const DevCam *__restrict__ cams, int C, 
     return lo;
 }
 
+// Where one lane's pixels are.
+template <int TS, int NW>
 struct TileInfo {
+    using G = Geo<TS, NW>;
     int c;
     int W, H;
-    int px, py;
-    bool inside;
-    uint32_t rs, re;
-    int64_t pix;       // packed pixel index of this lane
-    int64_t plane0;    // float offset of this camera's image
-    int64_t npix;      // W * H
+    int px;             // column of this lane
+    int py0;            // row of the lane's first pixel; pixel k is at py0 + k * RSTEP
+    uint32_t rs, re;    // the tile's instance range
+    int64_t pix0;       // packed pixel index of the lane's first pixel
+    int64_t plane0;     // float offset of the camera's image
+    int64_t npix;       // W * H
+    __device__ bool inside(int k) const { return px < W && py0 + k * G::RSTEP < H; }
+    __device__ int64_t pix(int k) const { return pix0 + (int64_t)k * G::RSTEP * W; }
+    __device__ int64_t off(int k) const { return (int64_t)(py0 + k * G::RSTEP) * W + px; }
 };
 
-template <int TS>
-__device__ __forceinline__ TileInfo tile_info(const RenderArgs &a, int t)
+template <int TS, int NW>
+__device__ __forceinline__ TileInfo<TS, NW> tile_info(const RenderArgs &a, int t)
 {
-    TileInfo ti;
+    using G = Geo<TS, NW>;
+    TileInfo<TS, NW> ti;
     ti.c = find_cam(a.cams, a.C, t);
     const DevCam &cam = a.cams[ti.c];
     ti.W = cam.W;
     ti.H = cam.H;
     const int local = t - cam.tile_offset;
     const int ty = local / cam.tiles_x, tx = local - ty * cam.tiles_x;
-    ti.px = tx * TS + (int)(threadIdx.x % TS);
-    ti.py = ty * TS + (int)(threadIdx.x / TS);
-    ti.inside = ti.px < ti.W && ti.py < ti.H;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    ti.px = tx * TS + lane % TS;
+    ti.py0 = ty * TS + w * G::ROWS + lane / TS;
     ti.rs = a.ranges[2 * (int64_t)t];
     ti.re = a.ranges[2 * (int64_t)t + 1];
     ti.npix = (int64_t)ti.W * ti.H;
-    ti.pix = cam.pix_offset + (int64_t)ti.py * ti.W + ti.px;
+    ti.pix0 = cam.pix_offset + (int64_t)ti.py0 * ti.W + ti.px;
     ti.plane0 = 3 * cam.pix_offset;
     return ti;
 }
 
-template <int BS>
+template <int CH>
 struct Stage {
-    float4 p0[BS];  // mx, my, l11, l12
-    float4 p1[BS];  // l22, opacity, r, g
-    float p2[BS];   // b
-    uint32_t gid[BS];
+    float4 p0[CH];  // mx, my, l11, l12
+    float4 p1[CH];  // l22, opacity, r, g
+    float p2[CH];   // b
+    uint32_t gid[CH];
 };
 
-template <int BS>
-__device__ __forceinline__ void stage_load(Stage<BS> &st, const RenderArgs &a, const gsl_splat *__restrict__ rec,
+template <int CH>
+__device__ __forceinline__ void stage_load(Stage<CH> &st, const RenderArgs &a, const gsl_splat *__restrict__ rec,
                                            uint32_t k, uint32_t end)
 {
     if (k < end) {
@@ -103,182 +151,270 @@ __device__ __forceinline__ void stage_load(Stage<BS> &st, const RenderArgs &a, c
     }
 }
 
-struct PixState {
-    float T;
-    float C0, C1, C2;
-    uint32_t nwalk;
+// Alpha of one (pixel, splat) pair.  Every walk (forward, backward,
+// counting) evaluates it with this same instruction sequence — the file is
+// compiled without floating-point contraction and the fused multiply-adds are
+// explicit — so the backward reproduces the forward's alpha bit for bit and
+// the result does not depend on the tile size or the lane layout.
+struct PairEval {
+    float dy, t1, t2, G, s, alpha;
 };
 
-// Forward walk over the tile list; every lane of the workgroup must call it.
-template <int TS>
-__device__ __forceinline__ PixState fwd_walk(const RenderArgs &a, const TileInfo &ti, Stage<TS * TS> &st)
+__device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1, float ax, float fy, float amax)
 {
-    constexpr int BS = TS * TS;
+    PairEval e;
+    e.dy = fy - p0.y;
+    e.t1 = fmaf(p0.w, e.dy, ax);
+    e.t2 = p1.x * e.dy;
+    const float q = fmaf(e.t1, e.t1, e.t2 * e.t2);
+    e.G = __builtin_amdgcn_exp2f(q * (-0.5f * kLog2e));
+    e.s = p1.y * e.G;
+    e.alpha = fminf(amax, e.s);
+    return e;
+}
+
+template <int PPL>
+struct PixState {
+    float T[PPL];
+    float C0[PPL], C1[PPL], C2[PPL];
+    uint32_t nwalk[PPL];
+};
+
+// Work counters of the forward walk (only the counting kernel uses them).
+struct NoCount {
+    __device__ void eval() {}
+    __device__ void contrib() {}
+};
+struct Count {
+    uint32_t evald = 0, ncontrib = 0;
+    __device__ void eval() { evald++; }
+    __device__ void contrib() { ncontrib++; }
+};
+
+// Forward walk over the tile list; every lane of the workgroup calls it.
+template <int TS, int NW, typename Counter>
+__device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti,
+                                                                Stage<Geo<TS, NW>::CH> &st, Counter &cnt)
+{
+    using G = Geo<TS, NW>;
+    constexpr int PPL = G::PPL;
     const gsl_splat *rec = a.splats + (int64_t)ti.c * a.N;
-    const float fx = ti.px + 0.5f, fy = ti.py + 0.5f;
+    const float fx = ti.px + 0.5f;
     const float amin = a.o.alpha_min, amax = a.o.alpha_max, Tmin = a.o.T_min;
-    PixState ps{1.f, 0.f, 0.f, 0.f, 0u};
-    bool done = !ti.inside;
-    for (uint32_t start = ti.rs; start < ti.re; start += BS) {
-        if (__syncthreads_count(done) == BS) break;
-        stage_load<BS>(st, a, rec, start + threadIdx.x, ti.re);
+    PixState<PPL> ps;
+    bool done[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        ps.T[k] = 1.f;
+        ps.C0[k] = ps.C1[k] = ps.C2[k] = 0.f;
+        ps.nwalk[k] = 0;
+        done[k] = !ti.inside(k);
+    }
+    auto open = [&]() {
+        bool o = false;
+#pragma unroll
+        for (int k = 0; k < PPL; k++) o |= !done[k];
+        return o;
+    };
+    for (uint32_t start = ti.rs; start < ti.re; start += G::CH) {
+        if (__syncthreads_count(open()) == 0) break;
+        stage_load<G::CH>(st, a, rec, start + threadIdx.x, ti.re);
         __syncthreads();
-        const int cnt = (int)min((uint32_t)BS, ti.re - start);
-        for (int j = 0; !done && j < cnt; j++) {
+        const int n = (int)min((uint32_t)G::CH, ti.re - start);
+        for (int j = 0; j < n; j++) {
+            if (!__any(open())) break;
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
-            const float dx = fx - p0.x, dy = fy - p0.y;
-            const float t1 = p0.z * dx + p0.w * dy, t2 = p1.x * dy;
-            const float alpha = fminf(amax, p1.y * exp_fast(-0.5f * (t1 * t1 + t2 * t2)));
-            if (alpha < amin) continue;
-            const float Tn = ps.T * (1.f - alpha);
-            if (Tn < Tmin) {
-                done = true;
-                break;
+            const float cb = st.p2[j];
+            const float dx = fx - p0.x;
+            const float ax = p0.z * dx;
+#pragma unroll
+            for (int k = 0; k < PPL; k++) {
+                if (done[k]) continue;
+                cnt.eval();
+                const PairEval e = eval_pair(p0, p1, ax, (float)(ti.py0 + k * G::RSTEP) + 0.5f, amax);
+                const float alpha = e.alpha;
+                if (alpha < amin) continue;
+                const float Tn = ps.T[k] * (1.f - alpha);
+                if (Tn < Tmin) {
+                    done[k] = true;
+                    continue;
+                }
+                cnt.contrib();
+                const float w = alpha * ps.T[k];
+                ps.C0[k] = fmaf(w, p1.z, ps.C0[k]);
+                ps.C1[k] = fmaf(w, p1.w, ps.C1[k]);
+                ps.C2[k] = fmaf(w, cb, ps.C2[k]);
+                ps.T[k] = Tn;
+                ps.nwalk[k] = start + (uint32_t)j + 1u - ti.rs;
             }
-            const float w = alpha * ps.T;
-            ps.C0 += w * p1.z;
-            ps.C1 += w * p1.w;
-            ps.C2 += w * st.p2[j];
-            ps.T = Tn;
-            ps.nwalk = start + (uint32_t)j + 1u - ti.rs;
         }
+        __syncthreads();
     }
     return ps;
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// Backward walk.  Tf[k] is the final transmittance of pixel k, v its cotangent.
+template <int TS, int NW>
+__device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti, Stage<Geo<TS, NW>::CH> &st,
+                                         const float (&Tf)[Geo<TS, NW>::PPL],
+                                         const uint32_t (&nw_in)[Geo<TS, NW>::PPL],
+                                         const float (&v)[Geo<TS, NW>::PPL][3], uint32_t *s_max)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
-// Backward walk.  T is the final transmittance, v the cotangent of the pixel.
-template <int TS>
-__device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo &ti, Stage<TS * TS> &st, float T,
-                                         uint32_t nwalk, float v0, float v1, float v2, uint32_t *s_max)
-{
-    constexpr int BS = TS * TS;
+    using G = Geo<TS, NW>;
+    constexpr int PPL = G::PPL;
     const gsl_splat *rec = a.splats + (int64_t)ti.c * a.N;
     float *g2d = a.g2d + (int64_t)ti.c * a.N * kG2;
-    const float fx = ti.px + 0.5f, fy = ti.py + 0.5f;
+    const float fx = ti.px + 0.5f;
     const float amin = a.o.alpha_min, amax = a.o.alpha_max;
     const int lane = threadIdx.x & (kWave - 1);
-    float S0 = T * a.o.bg[0], S1 = T * a.o.bg[1], S2 = T * a.o.bg[2];
-    if (!ti.inside) nwalk = 0;
-    if (nwalk > ti.re - ti.rs) nwalk = ti.re - ti.rs;  // never walk past the tile's list
+    const uint32_t len = ti.re - ti.rs;
+    float T[PPL], S0[PPL], S1[PPL], S2[PPL];
+    uint32_t nw[PPL];
+    uint32_t lane_max = 0;
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        T[k] = Tf[k];
+        S0[k] = T[k] * a.o.bg[0];
+        S1[k] = T[k] * a.o.bg[1];
+        S2[k] = T[k] * a.o.bg[2];
+        nw[k] = ti.inside(k) ? min(nw_in[k], len) : 0u;  // never walk past the tile's list
+        lane_max = max(lane_max, nw[k]);
+    }
     __syncthreads();
     if (threadIdx.x == 0) *s_max = 0;
     __syncthreads();
-    if (nwalk) atomicMax(s_max, nwalk);
+    if (lane_max) atomicMax(s_max, lane_max);
     __syncthreads();
     const uint32_t maxn = *s_max;
     const int64_t lo = ti.rs;
-    for (int64_t end = lo + maxn; end > lo; end -= BS) {
-        const int64_t start = end - BS > lo ? end - BS : lo;
+    for (int64_t end = lo + maxn; end > lo; end -= G::CH) {
+        const int64_t start = end - G::CH > lo ? end - G::CH : lo;
         __syncthreads();
-        stage_load<BS>(st, a, rec, (uint32_t)(start + threadIdx.x), (uint32_t)end);
+        stage_load<G::CH>(st, a, rec, (uint32_t)(start + threadIdx.x), (uint32_t)end);
         __syncthreads();
         for (int j = (int)(end - start) - 1; j >= 0; j--) {
             const uint32_t pos = (uint32_t)(start - lo) + (uint32_t)j;
+            if (!__any(pos < lane_max)) continue;
+            const float4 p0 = st.p0[j];
+            const float4 p1 = st.p1[j];
+            const float cb = st.p2[j];
+            const float dx = fx - p0.x;
+            const float ax = p0.z * dx;
             float g[kG2];
 #pragma unroll
             for (int f = 0; f < kG2; f++) g[f] = 0.f;
-            bool contrib = false;
-            if (pos < nwalk) {
-                const float4 p0 = st.p0[j];
-                const float4 p1 = st.p1[j];
-                const float dx = fx - p0.x, dy = fy - p0.y;
-                const float t1 = p0.z * dx + p0.w * dy, t2 = p1.x * dy;
-                const float G = exp_fast(-0.5f * (t1 * t1 + t2 * t2));
-                const float s = p1.y * G;
-                const float alpha = fminf(amax, s);
-                if (alpha >= amin) {
-                    contrib = true;
-                    const float r = rcp_fast(1.f - alpha);
-                    T = T * r;  // transmittance before this Gaussian
-                    const float w = alpha * T;
-                    const float c0 = p1.z, c1 = p1.w, c2 = st.p2[j];
-                    g[6] = w * v0;
-                    g[7] = w * v1;
-                    g[8] = w * v2;
-                    const float ga = v0 * (T * c0 - S0 * r) + v1 * (T * c1 - S1 * r) + v2 * (T * c2 - S2 * r);
-                    S0 += c0 * w;
-                    S1 += c1 * w;
-                    S2 += c2 * w;
-                    if (s < amax) {
-                        g[5] = G * ga;
-                        const float gp = s * ga;
-                        g[0] = gp * (p0.z * t1);
-                        g[1] = gp * (p0.w * t1 + p1.x * t2);
-                        g[2] = -0.5f * gp * dx * dx;
-                        g[3] = -gp * dx * dy;
-                        g[4] = -0.5f * gp * dy * dy;
-                    }
+            bool used = false;
+#pragma unroll
+            for (int k = 0; k < PPL; k++) {
+                if (pos >= nw[k]) continue;
+                const PairEval e = eval_pair(p0, p1, ax, (float)(ti.py0 + k * G::RSTEP) + 0.5f, amax);
+                const float alpha = e.alpha;
+                if (alpha < amin) continue;
+                used = true;
+                const float r = rcp_fast(1.f - alpha);
+                T[k] *= r;  // transmittance before this Gaussian
+                const float w = alpha * T[k];
+                g[6] = fmaf(w, v[k][0], g[6]);
+                g[7] = fmaf(w, v[k][1], g[7]);
+                g[8] = fmaf(w, v[k][2], g[8]);
+                const float ga = fmaf(v[k][0], fmaf(T[k], p1.z, -S0[k] * r),
+                                      fmaf(v[k][1], fmaf(T[k], p1.w, -S1[k] * r),
+                                           v[k][2] * fmaf(T[k], cb, -S2[k] * r)));
+                S0[k] = fmaf(p1.z, w, S0[k]);
+                S1[k] = fmaf(p1.w, w, S1[k]);
+                S2[k] = fmaf(cb, w, S2[k]);
+                if (e.s < amax) {
+                    g[5] = fmaf(e.G, ga, g[5]);
+                    const float gp = e.s * ga;
+                    const float hx = gp * dx, hy = gp * e.dy;
+                    g[0] = fmaf(gp, p0.z * e.t1, g[0]);
+                    g[1] = fmaf(gp, fmaf(p0.w, e.t1, p1.x * e.t2), g[1]);
+                    g[2] = fmaf(-0.5f * hx, dx, g[2]);
+                    g[3] = fmaf(-hx, e.dy, g[3]);
+                    g[4] = fmaf(-0.5f * hy, e.dy, g[4]);
                 }
             }
-            if (__ballot(contrib) != 0ull) {
+            if (__any(used)) {
+                float mine = 0.f;
 #pragma unroll
-                for (int f = 0; f < kG2; f++) g[f] = wave_sum(g[f]);
-                if (lane == 0) {
-                    float *dst = g2d + (int64_t)st.gid[j] * kG2;
-#pragma unroll
-                    for (int f = 0; f < kG2; f++)
-                        if (g[f] != 0.f) unsafeAtomicAdd(dst + f, g[f]);
+                for (int f = 0; f < kG2; f++) {
+                    const float tot = wave_total(g[f]);
+                    if (lane == f) mine = tot;
                 }
+                if (lane < kG2 && mine != 0.f) unsafeAtomicAdd(g2d + (int64_t)st.gid[j] * kG2 + lane, mine);
             }
         }
     }
 }
 
-template <int TS>
-__global__ __launch_bounds__(TS *TS) void k_render_fwd(RenderArgs a)
+template <int TS, int NW>
+__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fwd(RenderArgs a)
 {
-    __shared__ Stage<TS * TS> st;
-    const TileInfo ti = tile_info<TS>(a, (int)blockIdx.x);
-    const PixState ps = fwd_walk<TS>(a, ti, st);
-    if (!ti.inside) return;
-    const int64_t off = (int64_t)ti.py * ti.W + ti.px;
-    a.image[ti.plane0 + off] = ps.C0 + ps.T * a.o.bg[0];
-    a.image[ti.plane0 + ti.npix + off] = ps.C1 + ps.T * a.o.bg[1];
-    a.image[ti.plane0 + 2 * ti.npix + off] = ps.C2 + ps.T * a.o.bg[2];
-    a.T_final[ti.pix] = ps.T;
-    a.n_walk[ti.pix] = ps.nwalk;
+    using G = Geo<TS, NW>;
+    __shared__ Stage<G::CH> st;
+    const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, (int)blockIdx.x);
+    NoCount nc;
+    const PixState<G::PPL> ps = fwd_walk<TS, NW>(a, ti, st, nc);
+#pragma unroll
+    for (int k = 0; k < G::PPL; k++) {
+        if (!ti.inside(k)) continue;
+        const int64_t off = ti.off(k);
+        a.image[ti.plane0 + off] = ps.C0[k] + ps.T[k] * a.o.bg[0];
+        a.image[ti.plane0 + ti.npix + off] = ps.C1[k] + ps.T[k] * a.o.bg[1];
+        a.image[ti.plane0 + 2 * ti.npix + off] = ps.C2[k] + ps.T[k] * a.o.bg[2];
+        a.T_final[ti.pix(k)] = ps.T[k];
+        a.n_walk[ti.pix(k)] = ps.nwalk[k];
+    }
 }
 
-template <int TS>
-__global__ __launch_bounds__(TS *TS) void k_render_bwd(RenderArgs a)
+template <int TS, int NW>
+__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_bwd(RenderArgs a)
 {
-    __shared__ Stage<TS * TS> st;
+    using G = Geo<TS, NW>;
+    __shared__ Stage<G::CH> st;
     __shared__ uint32_t s_max;
-    const TileInfo ti = tile_info<TS>(a, (int)blockIdx.x);
-    float T = 1.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
-    uint32_t nw = 0;
-    if (ti.inside) {
-        const int64_t off = (int64_t)ti.py * ti.W + ti.px;
-        T = a.T_final[ti.pix];
-        nw = a.n_walk[ti.pix];
-        v0 = a.dL_dimage[ti.plane0 + off];
-        v1 = a.dL_dimage[ti.plane0 + ti.npix + off];
-        v2 = a.dL_dimage[ti.plane0 + 2 * ti.npix + off];
+    const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, (int)blockIdx.x);
+    float T[G::PPL], v[G::PPL][3];
+    uint32_t nw[G::PPL];
+#pragma unroll
+    for (int k = 0; k < G::PPL; k++) {
+        T[k] = 1.f;
+        nw[k] = 0;
+        v[k][0] = v[k][1] = v[k][2] = 0.f;
+        if (ti.inside(k)) {
+            const int64_t off = ti.off(k);
+            T[k] = a.T_final[ti.pix(k)];
+            nw[k] = a.n_walk[ti.pix(k)];
+            v[k][0] = a.dL_dimage[ti.plane0 + off];
+            v[k][1] = a.dL_dimage[ti.plane0 + ti.npix + off];
+            v[k][2] = a.dL_dimage[ti.plane0 + 2 * ti.npix + off];
+        }
     }
-    bwd_walk<TS>(a, ti, st, T, nw, v0, v1, v2, &s_max);
+    bwd_walk<TS, NW>(a, ti, st, T, nw, v, &s_max);
 }
 
 // Forward, per-pixel loss and its gradient, backward for one item.
-template <int TS>
-__device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<TS * TS> &st, uint32_t *s_max,
+template <int TS, int NW>
+__device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<Geo<TS, NW>::CH> &st, uint32_t *s_max,
                                            float *s_loss)
 {
-    constexpr int BS = TS * TS;
-    const TileInfo ti = tile_info<TS>(a, t);
-    const PixState ps = fwd_walk<TS>(a, ti, st);
-    float v0 = 0.f, v1 = 0.f, v2 = 0.f, lpix = 0.f;
-    if (ti.inside) {
-        const int64_t off = (int64_t)ti.py * ti.W + ti.px;
-        const float I0 = ps.C0 + ps.T * a.o.bg[0];
-        const float I1 = ps.C1 + ps.T * a.o.bg[1];
-        const float I2 = ps.C2 + ps.T * a.o.bg[2];
+    using G = Geo<TS, NW>;
+    constexpr int PPL = G::PPL;
+    const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, t);
+    NoCount nc;
+    const PixState<PPL> ps = fwd_walk<TS, NW>(a, ti, st, nc);
+    float v[PPL][3];
+    float lsum = 0.f;
+    const float inv = 1.f / (3.f * (float)ti.npix);
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        v[k][0] = v[k][1] = v[k][2] = 0.f;
+        if (!ti.inside(k)) continue;
+        const int64_t off = ti.off(k);
+        const float I0 = ps.C0[k] + ps.T[k] * a.o.bg[0];
+        const float I1 = ps.C1[k] + ps.T[k] * a.o.bg[1];
+        const float I2 = ps.C2[k] + ps.T[k] * a.o.bg[2];
         if (a.image) {
             a.image[ti.plane0 + off] = I0;
             a.image[ti.plane0 + ti.npix + off] = I1;
@@ -288,48 +424,47 @@ __device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<TS 
         const float r1 = I1 - a.target[ti.plane0 + ti.npix + off];
         const float r2 = I2 - a.target[ti.plane0 + 2 * ti.npix + off];
         if (a.loss == GSL_LOSS_L1) {
-            const float inv = 1.f / (3.f * (float)ti.npix);
             auto sgn = [](float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); };
-            v0 = sgn(r0) * inv;
-            v1 = sgn(r1) * inv;
-            v2 = sgn(r2) * inv;
-            lpix = (fabsf(r0) + fabsf(r1) + fabsf(r2)) * inv;
+            v[k][0] = sgn(r0) * inv;
+            v[k][1] = sgn(r1) * inv;
+            v[k][2] = sgn(r2) * inv;
+            lsum += (fabsf(r0) + fabsf(r1) + fabsf(r2)) * inv;
         } else {
-            v0 = r0;
-            v1 = r1;
-            v2 = r2;
-            lpix = 0.5f * (r0 * r0 + r1 * r1 + r2 * r2);
+            v[k][0] = r0;
+            v[k][1] = r1;
+            v[k][2] = r2;
+            lsum += 0.5f * (r0 * r0 + r1 * r1 + r2 * r2);
         }
     }
     // per-item loss partial
-    float ls = wave_sum(lpix);
+    const float ls = wave_total(lsum);
     if ((threadIdx.x & (kWave - 1)) == 0) s_loss[threadIdx.x / kWave] = ls;
     __syncthreads();
     if (threadIdx.x == 0) {
         double tot = 0;
-        for (int w = 0; w < (BS + kWave - 1) / kWave; w++) tot += s_loss[w];
+        for (int w = 0; w < NW; w++) tot += s_loss[w];
         a.loss_part[t] = tot;
     }
-    bwd_walk<TS>(a, ti, st, ps.T, ps.nwalk, v0, v1, v2, s_max);
+    bwd_walk<TS, NW>(a, ti, st, ps.T, ps.nwalk, v, s_max);
 }
 
-template <int TS>
-__global__ __launch_bounds__(TS *TS) void k_render_fused(RenderArgs a)
+template <int TS, int NW>
+__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused(RenderArgs a)
 {
-    __shared__ Stage<TS * TS> st;
+    __shared__ Stage<Geo<TS, NW>::CH> st;
     __shared__ uint32_t s_max;
-    __shared__ float s_loss[(TS * TS + kWave - 1) / kWave];
+    __shared__ float s_loss[NW];
     const int t = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
-    fused_item<TS>(a, t, st, &s_max, s_loss);
+    fused_item<TS, NW>(a, t, st, &s_max, s_loss);
 }
 
-template <int TS>
-__global__ __launch_bounds__(TS *TS) void k_render_fused_persistent(RenderArgs a)
+template <int TS, int NW>
+__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused_persistent(RenderArgs a)
 {
-    __shared__ Stage<TS * TS> st;
+    __shared__ Stage<Geo<TS, NW>::CH> st;
     __shared__ uint32_t s_max;
     __shared__ uint32_t s_item;
-    __shared__ float s_loss[(TS * TS + kWave - 1) / kWave];
+    __shared__ float s_loss[NW];
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1u);
@@ -337,7 +472,30 @@ __global__ __launch_bounds__(TS *TS) void k_render_fused_persistent(RenderArgs a
         const uint32_t item = s_item;
         if (item >= (uint32_t)a.T_total) break;
         const int t = a.order ? (int)a.order[item] : (int)item;
-        fused_item<TS>(a, t, st, &s_max, s_loss);
+        fused_item<TS, NW>(a, t, st, &s_max, s_loss);
+    }
+}
+
+// Work counts of the compositing, by the per-pixel rule on the tile lists:
+// counts[0] = (pixel, Gaussian) pairs the forward walk evaluates (up to and
+// including the Gaussian that stops it), counts[1] = contributors,
+// counts[2] = pairs the backward walk evaluates (sum of walk lengths).
+template <int TS, int NW>
+__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_count(RenderArgs a, unsigned long long *counts)
+{
+    using G = Geo<TS, NW>;
+    __shared__ Stage<G::CH> st;
+    const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, (int)blockIdx.x);
+    Count cnt;
+    const PixState<G::PPL> ps = fwd_walk<TS, NW>(a, ti, st, cnt);
+    uint32_t nw = 0;
+#pragma unroll
+    for (int k = 0; k < G::PPL; k++) nw += ps.nwalk[k];
+    const uint32_t e = wave_total_u32(cnt.evald), c = wave_total_u32(cnt.ncontrib), w = wave_total_u32(nw);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd(&counts[0], (unsigned long long)e);
+        atomicAdd(&counts[1], (unsigned long long)c);
+        atomicAdd(&counts[2], (unsigned long long)w);
     }
 }
 
@@ -356,30 +514,55 @@ __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ p
     }
 }
 
+// waves per tile for each tile size
+template <int TS>
+struct Waves {
+    static constexpr int NW = TS == 32 ? 4 : 1;
+};
+
 template <int TS>
 void launch_fwd_t(const RenderArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_render_fwd<TS>, dim3((unsigned)a.T_total), dim3(TS * TS), 0, s, a);
+    constexpr int NW = Waves<TS>::NW;
+    hipLaunchKernelGGL((k_render_fwd<TS, NW>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s, a);
 }
 template <int TS>
 void launch_bwd_t(const RenderArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_render_bwd<TS>, dim3((unsigned)a.T_total), dim3(TS * TS), 0, s, a);
+    constexpr int NW = Waves<TS>::NW;
+    hipLaunchKernelGGL((k_render_bwd<TS, NW>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s, a);
+}
+template <int TS>
+void launch_count_t(const RenderArgs &a, unsigned long long *counts, hipStream_t s)
+{
+    constexpr int NW = Waves<TS>::NW;
+    hipLaunchKernelGGL((k_render_count<TS, NW>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s, a, counts);
 }
 template <int TS>
 void launch_fused_t(const RenderArgs &a, int variant, int num_cus, hipStream_t s)
 {
+    constexpr int NW = Waves<TS>::NW;
     if (variant == 1) {
-        const int per_cu = TS == 8 ? 8 : (TS == 16 ? 4 : 1);
+        const int per_cu = 32 / NW;
         int64_t g = (int64_t)num_cus * per_cu;
         if (g > a.T_total) g = a.T_total;
-        hipLaunchKernelGGL(k_render_fused_persistent<TS>, dim3((unsigned)g), dim3(TS * TS), 0, s, a);
+        hipLaunchKernelGGL((k_render_fused_persistent<TS, NW>), dim3((unsigned)g), dim3(Geo<TS, NW>::BS), 0, s, a);
     } else {
-        hipLaunchKernelGGL(k_render_fused<TS>, dim3((unsigned)a.T_total), dim3(TS * TS), 0, s, a);
+        hipLaunchKernelGGL((k_render_fused<TS, NW>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s, a);
     }
 }
 
 }  // namespace
+
+void launch_render_count(const RenderArgs &a, unsigned long long *counts, hipStream_t s)
+{
+    if (a.T_total == 0) return;
+    switch (a.o.tile) {
+    case 8: launch_count_t<8>(a, counts, s); break;
+    case 16: launch_count_t<16>(a, counts, s); break;
+    default: launch_count_t<32>(a, counts, s); break;
+    }
+}
 
 void launch_render_fwd(const RenderArgs &a, hipStream_t s)
 {

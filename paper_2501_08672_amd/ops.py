@@ -273,6 +273,17 @@ def render_bwd(ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, proj: Pro
     return out
 
 
+def render_stats(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, bins: Bins):
+    """(forward pairs evaluated, contributing pairs, backward pairs evaluated)."""
+    counts = torch.zeros(3, dtype=torch.int64, device=ctx.device)
+    nb = workspace_size(ctx, cams, N, o, bins.capacity)
+    ws = ctx.workspace(nb)
+    ps, bs = proj.struct(), bins.struct()
+    A.check(A.lib().gsl_render_stats(ctx.h, cams.arr, cams.C, int(N), C.byref(o), C.byref(ps), C.byref(bs),
+                                     _p(counts), _p(ws), ws.numel(), _stream()))
+    return tuple(int(x) for x in counts.cpu().tolist())
+
+
 # ---------------------------------------------------------------- window
 
 class Window:
@@ -312,6 +323,18 @@ class Window:
                                         _p(self.target), self.loss, C.byref(ps), C.byref(bs), _p(self.image),
                                         _p(self.d_loss), C.byref(gr), _p(self.ws), self.ws.numel(),
                                         int(bool(use_graph)), _stream()))
+
+    def profiled_step(self):
+        """One eager step with HIP events between its stages; returns the
+        milliseconds of (project, bin_sort, fused render, adjoint, total)."""
+        A.check(A.lib().gsl_profile(self.ctx.h, 1))
+        try:
+            self.step(use_graph=False)
+            ms = (C.c_float * 5)()
+            A.check(A.lib().gsl_profile_read(self.ctx.h, ms, 5))
+        finally:
+            A.lib().gsl_profile(self.ctx.h, 0)
+        return [float(x) for x in ms]
 
     def status(self) -> int:
         return int(self.bins.d_status.item())
