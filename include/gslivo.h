@@ -113,7 +113,9 @@ typedef struct {
  * ceil(W_c / tile) and tile_offset_c counts the tiles of cameras before c. */
 typedef struct {
     uint32_t *tile_ids;  /* [capacity_K] */
-    uint32_t *gauss_ids; /* [capacity_K] Gaussian index i of the instance */
+    uint32_t *gauss_ids; /* [capacity_K] low 28 bits: Gaussian index i of the instance;
+                            top 4 bits: bit q set when the splat can reach rows
+                            [q*tile/4, (q+1)*tile/4) of the tile */
     uint32_t *ranges;    /* [T_total][2] */
     int64_t *d_K;        /* device scalar: instance count K (even when K > capacity) */
     int32_t *d_status;   /* device scalar: GSL_OK or GSL_ECAPACITY */
@@ -164,7 +166,10 @@ GSL_API int gsl_project(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *
  * (32-bit float key, ties by index), emits one instance per overlapped tile
  * and sorts the instances by tile with a stable LSD radix sort, so the
  * instance order equals a sort by the 64-bit key (tile << 32 | depth bits)
- * with ties by index.  Writes K and, when K > capacity_K, GSL_ECAPACITY to
+ * with ties by index.  A Gaussian is binned into the tiles whose pixel-centre
+ * rectangle its alpha_min ellipse reaches (a superset of every pixel where
+ * alpha >= alpha_min, so the image does not depend on the tile size); N must
+ * be below 2^28.  Writes K and, when K > capacity_K, GSL_ECAPACITY to
  * *d_status (then the bins are incomplete; call again with more capacity). */
 GSL_API int gsl_bin_sort(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
                  const gsl_proj *proj, gsl_bins *bins, void *workspace, size_t workspace_bytes, void *stream);
@@ -203,14 +208,14 @@ GSL_API int gsl_render_stats(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, in
 enum { GSL_LOSS_L1 = 1, GSL_LOSS_L2 = 2 };
 
 /* One optimisation pass over a window of keyframes: project, bin_sort, then
- * one persistent fused launch over all (camera, tile) items that composites,
+ * one fused launch over all (camera, tile) items that composites,
  * forms the per-pixel loss gradient against `target` (packed like the image;
  * L1: mean absolute error per frame summed over frames, L2: 1/2 sum of
  * squares), and walks back, then the projection adjoint.  Writes the loss to
  * *d_loss (device float64) and the gradients (overwritten); image may be NULL.
- * The fused launch uses the kernel variant (LDS chunk depth, persistent
- * work queue or one workgroup per item) that gsl_window_tune chose for these
- * shapes, else the default.  With use_graph != 0 the sequence is recorded
+ * The fused launch uses the kernel variant (persistent work queue or one
+ * workgroup per item; items in tile order or longest list first) that
+ * gsl_window_tune chose for these shapes, else the default.  With use_graph != 0 the sequence is recorded
  * once into a HIP graph per (shapes, buffers, options, camera poses) and
  * replayed on later calls with the same arguments. */
 GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
@@ -232,7 +237,8 @@ GSL_API int gsl_profile_read(gsl_ctx *ctx, float *ms, int32_t n);
  * the context and writes the fastest tile size to opts_inout->tile.  The
  * buffers must be sized for tile 8 (the largest T_total) and enough
  * capacity_K for every tile size; times_ms (may be NULL) receives up to
- * `ntimes` measured milliseconds in the order tried. */
+ * `ntimes` measured milliseconds in the order tried (tiles 8, 16, 32; per
+ * tile the four variants: plain, persistent, ordered, persistent+ordered). */
 GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, gsl_opts *opts_inout,
                     const float *target, int loss, gsl_proj *proj, gsl_bins *bins, double *d_loss,
                     gsl_grads *grads, void *workspace, size_t workspace_bytes, float *times_ms, int32_t ntimes,

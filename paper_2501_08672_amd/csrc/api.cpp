@@ -123,6 +123,7 @@ int make_layout(const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, Layo
     if (!cams) return fail(GSL_EINVAL, "cams is NULL");
     if (C < 1 || C > GSL_MAX_CAMERAS) return fail(GSL_ENOTSUP, "camera count %d not in [1, %d]", C, GSL_MAX_CAMERAS);
     if (N < 0) return fail(GSL_EINVAL, "negative Gaussian count");
+    if (N > (int32_t)kGidMask) return fail(GSL_EINVAL, "N = %d exceeds 2^28 - 1", N);
     if (tile != 8 && tile != 16 && tile != 32) return fail(GSL_ENOTSUP, "tile size %d not in {8, 16, 32}", tile);
     L.C = C;
     L.N = N;
@@ -282,8 +283,8 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     uint32_t *ek = bins->tile_ids, *ev = bins->gauss_ids;
     uint32_t *ak = at<uint32_t>(ws, W.ikey2), *av = at<uint32_t>(ws, W.ival2);
     if (passes & 1) std::swap(ek, ak), std::swap(ev, av);
-    launch_emit(order, offsets, proj->splats, at<DevCam>(ws, W.cams), L, bins->d_K, bins->capacity_K, ek, ev,
-                bins->d_status, s);
+    launch_emit(order, offsets, counts, proj->splats, at<DevCam>(ws, W.cams), L, p.o.alpha_min, bins->d_K,
+                bins->capacity_K, ek, ev, bins->d_status, s);
     launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, partial, s);
     // 4. per-tile ranges
     launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);
@@ -342,6 +343,11 @@ void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const fl
     a.image = image;
     a.target = target;
     a.loss = loss;
+    if (variant & 2) {
+        uint32_t *order = at<uint32_t>(ws, p.W.order);
+        launch_order_by_length(bins->ranges, p.L.T_total, order, s);
+        a.order = order;
+    }
     mark(kStRender);
     launch_render_fused(a, variant, ctx->num_cus, s);
     mark(kStProjectBwd);
@@ -646,7 +652,7 @@ int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
         if (rc != GSL_OK) break;
         float best = 1e30f;
         int best_v = 0;
-        for (int variant = 0; variant < 2; variant++) {
+        for (int variant = 0; variant < kVariants; variant++) {
             // one untimed run, then check the capacity status
             do_window(ctx, p, g, target, loss, proj, bins, nullptr, d_loss, grads, workspace, variant, s);
             int32_t status = 0;

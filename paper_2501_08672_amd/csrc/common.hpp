@@ -38,6 +38,63 @@ struct DevOpts {
 // one cache line.
 constexpr int kG2 = 9;
 
+// ---------------------------------------------------------------- binning rule
+// Threshold of the alpha_min ellipse, |L d|^2 <= kq, with a margin of 0.01 on
+// top of 2 ln(sigma / alpha_min) that covers the float32 evaluation of the
+// power in the renderer.  Computed in float64 and rounded once, so every
+// kernel that needs it gets the same float.
+__device__ __forceinline__ float ellipse_k(float opacity, float alpha_min)
+{
+    return (float)(2.0 * log((double)opacity / (double)alpha_min) + 0.01);
+}
+
+// Does the ellipse |L (x - mu)|^2 <= kq reach the rectangle [x0, x1] x [y0, y1]
+// of pixel centres?  The minimum of the convex quadratic over the rectangle is
+// at mu when mu lies inside, else on one of its edges, where it has a closed
+// form.  The projection kernel (counting) and the emit kernel (writing) both
+// call this, so the instance count matches the instances written exactly.
+__device__ __forceinline__ bool ellipse_hits_rect(float mx, float my, float l11, float l12, float l22, float kq,
+                                                  float x0, float x1, float y0, float y1)
+{
+    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
+    const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
+    const float cc = l12 * l12 + l22 * l22;
+    float best = 3.0e38f;
+    // vertical edges: dx fixed, dy free in [dy0, dy1]
+    for (int e = 0; e < 2; e++) {
+        const float dx = e ? dx1 : dx0;
+        const float a = l11 * dx;
+        const float dy = fminf(fmaxf(-(a * l12) / cc, dy0), dy1);
+        const float u = a + l12 * dy, w = l22 * dy;
+        best = fminf(best, u * u + w * w);
+    }
+    // horizontal edges: dy fixed, dx free in [dx0, dx1]
+    for (int e = 0; e < 2; e++) {
+        const float dy = e ? dy1 : dy0;
+        const float b = l12 * dy, w = l22 * dy;
+        const float dx = fminf(fmaxf(-b / l11, dx0), dx1);
+        const float u = l11 * dx + b;
+        best = fminf(best, u * u + w * w);
+    }
+    return best <= kq;
+}
+
+// Pixel-centre rectangle of tile (tx, ty) clipped to a W x H image.
+__device__ __forceinline__ void tile_rect(int tx, int ty, int T, int W, int H, float &x0, float &x1, float &y0,
+                                          float &y1)
+{
+    x0 = (float)(tx * T) + 0.5f;
+    x1 = (float)min((tx + 1) * T, W) - 0.5f;
+    y0 = (float)(ty * T) + 0.5f;
+    y1 = (float)min((ty + 1) * T, H) - 0.5f;
+}
+
+// Instance payload: the Gaussian index in the low 28 bits and, in the top 4
+// bits, which quarter-row bands of the tile the alpha_min ellipse reaches
+// (bit q: rows [q*T/4, (q+1)*T/4) of the tile).
+constexpr uint32_t kGidBits = 28;
+constexpr uint32_t kGidMask = (1u << kGidBits) - 1u;
+
 // ---------------------------------------------------------------- host-side
 struct Layout {
     int32_t C = 0, N = 0;
@@ -105,9 +162,12 @@ void launch_depth_keys(const gsl_splat *splats, const int32_t *tiles, int64_t M,
                        hipStream_t s);
 void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, uint32_t *counts,
                           hipStream_t s);
-void launch_emit(const uint32_t *order, const uint32_t *offsets, const gsl_splat *splats, const DevCam *cams,
-                 const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids, uint32_t *gauss_ids,
-                 int32_t *d_status, hipStream_t s);
+// tiles_touched of every (camera, Gaussian) record under the binning rule
+void launch_count_tiles(const gsl_splat *splats, const DevCam *cams, const Layout &L, float alpha_min,
+                        int32_t *tiles_touched, hipStream_t s);
+void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_splat *splats,
+                 const DevCam *cams, const Layout &L, float alpha_min, const int64_t *d_K, int64_t capacity,
+                 uint32_t *tile_ids, uint32_t *gauss_ids, int32_t *d_status, hipStream_t s);
 void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,
                    uint32_t *ranges, hipStream_t s);
 
@@ -137,8 +197,11 @@ struct RenderArgs {
 };
 void launch_render_fwd(const RenderArgs &a, hipStream_t s);
 void launch_render_bwd(const RenderArgs &a, hipStream_t s);
-// variant: 0 = one workgroup per (camera, tile) item, 1 = persistent work queue
+// variant bit 0: persistent work queue (else one workgroup per item);
+// bit 1: items in a.order (heaviest first) rather than tile order
+constexpr int kVariants = 4;
 void launch_render_fused(const RenderArgs &a, int variant, int num_cus, hipStream_t s);
+void launch_order_by_length(const uint32_t *ranges, int64_t T, uint32_t *order, hipStream_t s);
 // counts[3] (device, accumulated): forward pairs evaluated, contributors, backward pairs
 void launch_render_count(const RenderArgs &a, unsigned long long *counts, hipStream_t s);
 void launch_reduce_f64(const double *part, int64_t n, double *out, hipStream_t s);

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                                                  const float *__restrict__ opacity,
                                                  const float *__restrict__ color, int N, int64_t M,
                                                  const DevCam *__restrict__ cams, DevOpts o,
-                                                 gsl_splat *__restrict__ out, int32_t *__restrict__ tiles)
+                                                 gsl_splat *__restrict__ out)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
@@ -129,7 +129,6 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
     sp.b = color[2 * N + i];
     sp.depth = 0.f;
     sp.x0 = 0; sp.y0 = 0; sp.x1 = -1; sp.y1 = -1;
-    int32_t ntiles = 0;
 
     Proj p;
     bool kept = compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
@@ -153,8 +152,6 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                 kept = false;
             } else {
                 const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
-                const int T = o.tile;
-                ntiles = (ix1 / T - ix0 / T + 1) * (iy1 / T - iy0 / T + 1);
                 sp.x0 = (int16_t)ix0; sp.x1 = (int16_t)ix1;
                 sp.y0 = (int16_t)iy0; sp.y1 = (int16_t)iy1;
                 const double l22 = 1.0 / sqrt(p.c);
@@ -170,7 +167,6 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
         }
     }
     out[m] = sp;
-    tiles[m] = ntiles;
 }
 
 // ------------------------------------------------------------------ backward
@@ -372,7 +368,8 @@ void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L,
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
-                       g.color, g.N, L.M, cams, o, splats, tiles_touched);
+                       g.color, g.N, L.M, cams, o, splats);
+    launch_count_tiles(splats, cams, L, o.alpha_min, tiles_touched, s);
 }
 
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,

@@ -21,15 +21,17 @@
 // S = sum_{j>k} c_j alpha_j T_j + T_final bg, so that
 //   dI/dc_k = alpha_k T_k,  dI/dalpha_k = T_k c_k - S / (1 - alpha_k).
 // Each lane first sums the nine 2D gradients of a splat over its own pixels;
-// the wave then sums them with DPP adds on the VALU (no LDS permutes), and a
-// single atomic instruction with nine active lanes adds the totals into the
+// the wave then reduce-scatters them on the VALU (lane swaps and DPP, no LDS
+// permutes) so that nine lanes hold the nine totals, and a single atomic
+// instruction with those nine lanes active adds them into the
 // per-(camera, Gaussian) record.  A splat no pixel of the wave used costs no
 // reduction and no atomic.
 //
 // The fused kernel runs the forward walk, the per-pixel loss and its
 // gradient against the target image (L1 or L2, local to the pixel) and the
 // backward walk for one item, keeping T, the walk lengths and the colours in
-// registers.  Its persistent variant launches a few workgroups per CU that
+// registers, plus one bit per list position and wave (in LDS) telling the
+// backward walk where the forward walk found no contributor.  Its persistent variant launches a few workgroups per CU that
 // take items from an atomic counter.
 #include "common.hpp"
 
@@ -48,7 +50,11 @@ struct Geo {
     static constexpr int PPL = TS * ROWS / kWave;  // pixels per lane
     static constexpr int RSTEP = kWave / TS;       // row stride between a lane's pixels
     static constexpr int CH = BS;                  // splats staged per chunk
+    // pixel slot k of every lane of wave w lies in the quarter-row band
+    // (w * ROWS + k * RSTEP) / (TS / 4) when the RSTEP rows it spans fit in a band
+    static constexpr bool BANDS = RSTEP <= TS / 4;
     static_assert(TS * ROWS % kWave == 0 && PPL >= 1, "tile/wave layout");
+    __device__ static int band(int w, int k) { return (w * ROWS + k * RSTEP) / (TS / 4); }
 };
 
 // DPP sum of a wave: the total lands in lane 63.
@@ -77,6 +83,60 @@ __device__ __forceinline__ uint32_t wave_total_u32(uint32_t v)
     v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false);
     v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false);
     return __builtin_amdgcn_readlane(v, 63);
+}
+
+// ---- reduce-scatter of the nine 2D-gradient slots across a wave ----------
+// Level 32 and 16 pair up slots with the gfx950 half/row swaps (each pair of
+// values becomes one value whose two halves, then four rows, carry different
+// slots), levels 8 and 4 with DPP mirrors inside a row, and the last two with
+// quad permutes.  Each lane ends with the complete sum of one slot (shared by
+// the four lanes of a quad) or of a padding slot.  ~27 VALU instead of nine
+// full wave reductions.
+__device__ __forceinline__ float swap_add32(float a, float b)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float a, float b)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// lanes with `hi` keep b's partial, the others a's; partner = mirror lane
+template <int CTRL>
+__device__ __forceinline__ float mirror_add(float a, float b, bool hi)
+{
+    const float keep = hi ? b : a, send = hi ? a : b;
+    return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float reduce9(const float (&g)[kG2], int lane)
+{
+    const float y0 = swap_add32(g[0], g[1]);
+    const float y1 = swap_add32(g[2], g[3]);
+    const float y2 = swap_add32(g[4], g[5]);
+    const float y3 = swap_add32(g[6], g[7]);
+    const float y4 = swap_add32(g[8], 0.f);
+    const float z0 = swap_add16(y0, y1);
+    const float z1 = swap_add16(y2, y3);
+    const float z2 = swap_add16(y4, 0.f);
+    const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
+    const float w0 = mirror_add<0x140>(z0, z1, h8);   // row_mirror
+    const float w1 = mirror_add<0x140>(z2, 0.f, h8);
+    float u = mirror_add<0x141>(w0, w1, h4);          // row_half_mirror
+    u += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u), 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
+    u += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u), 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
+    return u;
+}
+
+// Slot whose total reduce9 leaves in this lane (-1 for a padding slot), found
+// by pushing slot tags through the same network.  Call with all lanes active.
+__device__ __forceinline__ int reduce9_slot(int lane)
+{
+    float tag[kG2];
+#pragma unroll
+    for (int f = 0; f < kG2; f++) tag[f] = lane == 0 ? (float)(f + 1) : 0.f;
+    return (int)reduce9(tag, lane) - 1;
 }
 
 __device__ __forceinline__ int find_cam(const DevCam *__restrict__ cams, int C, int t)
@@ -134,7 +194,7 @@ struct Stage {
     float4 p0[CH];  // mx, my, l11, l12
     float4 p1[CH];  // l22, opacity, r, g
     float p2[CH];   // b
-    uint32_t gid[CH];
+    uint32_t gid[CH];  // Gaussian index | band mask << 28
 };
 
 template <int CH>
@@ -142,13 +202,21 @@ __device__ __forceinline__ void stage_load(Stage<CH> &st, const RenderArgs &a, c
                                            uint32_t k, uint32_t end)
 {
     if (k < end) {
-        const uint32_t gid = a.gauss_ids[k];
-        const float4 *r4 = reinterpret_cast<const float4 *>(rec + gid);
+        const uint32_t val = a.gauss_ids[k];
+        const float4 *r4 = reinterpret_cast<const float4 *>(rec + (val & kGidMask));
         st.p0[threadIdx.x] = r4[0];
         st.p1[threadIdx.x] = r4[1];
         st.p2[threadIdx.x] = r4[2].x;
-        st.gid[threadIdx.x] = gid;
+        st.gid[threadIdx.x] = val;
     }
+}
+
+// Does splat `val` reach the band of pixel slot k of this wave?
+template <int TS, int NW>
+__device__ __forceinline__ bool in_band(uint32_t val, int w, int k)
+{
+    if (!Geo<TS, NW>::BANDS) return true;
+    return (val >> (kGidBits + Geo<TS, NW>::band(w, k))) & 1u;
 }
 
 // Alpha of one (pixel, splat) pair.  Every walk (forward, backward,
@@ -182,19 +250,27 @@ struct PixState {
 
 // Work counters of the forward walk (only the counting kernel uses them).
 struct NoCount {
-    __device__ void eval() {}
-    __device__ void contrib() {}
+    __device__ void eval(bool) {}
+    __device__ void contrib(bool) {}
 };
 struct Count {
     uint32_t evald = 0, ncontrib = 0;
-    __device__ void eval() { evald++; }
-    __device__ void contrib() { ncontrib++; }
+    __device__ void eval(bool b) { evald += b ? 1u : 0u; }
+    __device__ void contrib(bool b) { ncontrib += b ? 1u : 0u; }
 };
 
+// Per-wave record of the list positions where at least one pixel of the wave
+// contributed (forward walk), consulted by the backward walk of the same
+// item to skip positions nothing used.  Positions beyond the record are
+// always walked.
+constexpr int kHitWords = 128;  // 4096 positions
+
 // Forward walk over the tile list; every lane of the workgroup calls it.
+// `hits` (may be null) receives this wave's contribution bits.
 template <int TS, int NW, typename Counter>
 __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti,
-                                                                Stage<Geo<TS, NW>::CH> &st, Counter &cnt)
+                                                                Stage<Geo<TS, NW>::CH> &st, Counter &cnt,
+                                                                uint32_t *hits = nullptr)
 {
     using G = Geo<TS, NW>;
     constexpr int PPL = G::PPL;
@@ -210,6 +286,13 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
         ps.nwalk[k] = 0;
         done[k] = !ti.inside(k);
     }
+    float fy[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; k++) fy[k] = (float)(ti.py0 + k * G::RSTEP) + 0.5f;
+    const int wv = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t hbits = 0;
+    int hword = 0;
     auto open = [&]() {
         bool o = false;
 #pragma unroll
@@ -226,31 +309,46 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
+            const uint32_t val = st.gid[j];
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
+            const uint32_t pos1 = start + (uint32_t)j + 1u - ti.rs;
+            bool used = false;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (done[k]) continue;
-                cnt.eval();
-                const PairEval e = eval_pair(p0, p1, ax, (float)(ti.py0 + k * G::RSTEP) + 0.5f, amax);
-                const float alpha = e.alpha;
-                if (alpha < amin) continue;
-                const float Tn = ps.T[k] * (1.f - alpha);
-                if (Tn < Tmin) {
-                    done[k] = true;
-                    continue;
-                }
-                cnt.contrib();
-                const float w = alpha * ps.T[k];
+                // a band the ellipse does not reach has alpha < alpha_min everywhere
+                if (!in_band<TS, NW>(val, wv, k)) continue;
+                // predicated: every lane evaluates, selects decide what changes
+                const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
+                const bool live = !done[k];
+                const bool hit = live && e.alpha >= amin;
+                const float Tn = ps.T[k] * (1.f - e.alpha);
+                const bool stop = hit && Tn < Tmin;
+                const bool acc = hit && !stop;
+                cnt.eval(live);
+                cnt.contrib(acc);
+                done[k] = done[k] || stop;
+                const float w = acc ? e.alpha * ps.T[k] : 0.f;
                 ps.C0[k] = fmaf(w, p1.z, ps.C0[k]);
                 ps.C1[k] = fmaf(w, p1.w, ps.C1[k]);
                 ps.C2[k] = fmaf(w, cb, ps.C2[k]);
-                ps.T[k] = Tn;
-                ps.nwalk[k] = start + (uint32_t)j + 1u - ti.rs;
+                ps.T[k] = acc ? Tn : ps.T[k];
+                ps.nwalk[k] = acc ? pos1 : ps.nwalk[k];
+                used = used || acc;
+            }
+            if (hits) {
+                const int pos = (int)pos1 - 1, wd = pos >> 5;
+                if (wd != hword) {
+                    if (lane == 0 && hword < kHitWords) hits[hword] = hbits;
+                    hbits = 0;
+                    hword = wd;
+                }
+                if (__any(used)) hbits |= 1u << (pos & 31);
             }
         }
         __syncthreads();
     }
+    if (hits && lane == 0 && hword < kHitWords) hits[hword] = hbits;
     return ps;
 }
 
@@ -259,7 +357,8 @@ template <int TS, int NW>
 __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti, Stage<Geo<TS, NW>::CH> &st,
                                          const float (&Tf)[Geo<TS, NW>::PPL],
                                          const uint32_t (&nw_in)[Geo<TS, NW>::PPL],
-                                         const float (&v)[Geo<TS, NW>::PPL][3], uint32_t *s_max)
+                                         const float (&v)[Geo<TS, NW>::PPL][3], uint32_t *s_max,
+                                         const uint32_t *hits = nullptr)
 {
     using G = Geo<TS, NW>;
     constexpr int PPL = G::PPL;
@@ -267,9 +366,9 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
     float *g2d = a.g2d + (int64_t)ti.c * a.N * kG2;
     const float fx = ti.px + 0.5f;
     const float amin = a.o.alpha_min, amax = a.o.alpha_max;
-    const int lane = threadIdx.x & (kWave - 1);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const uint32_t len = ti.re - ti.rs;
-    float T[PPL], S0[PPL], S1[PPL], S2[PPL];
+    float T[PPL], S0[PPL], S1[PPL], S2[PPL], fy[PPL];
     uint32_t nw[PPL];
     uint32_t lane_max = 0;
 #pragma unroll
@@ -280,6 +379,7 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
         S2[k] = T[k] * a.o.bg[2];
         nw[k] = ti.inside(k) ? min(nw_in[k], len) : 0u;  // never walk past the tile's list
         lane_max = max(lane_max, nw[k]);
+        fy[k] = (float)(ti.py0 + k * G::RSTEP) + 0.5f;
     }
     __syncthreads();
     if (threadIdx.x == 0) *s_max = 0;
@@ -287,6 +387,8 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
     if (lane_max) atomicMax(s_max, lane_max);
     __syncthreads();
     const uint32_t maxn = *s_max;
+    const int slot = reduce9_slot(lane);
+    const bool writer = slot >= 0 && (lane & 3) == 0;
     const int64_t lo = ti.rs;
     for (int64_t end = lo + maxn; end > lo; end -= G::CH) {
         const int64_t start = end - G::CH > lo ? end - G::CH : lo;
@@ -296,9 +398,12 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
         for (int j = (int)(end - start) - 1; j >= 0; j--) {
             const uint32_t pos = (uint32_t)(start - lo) + (uint32_t)j;
             if (!__any(pos < lane_max)) continue;
+            // the forward walk of this item saw no contributor of this wave here
+            if (hits && pos < 32u * kHitWords && !((hits[pos >> 5] >> (pos & 31)) & 1u)) continue;
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
+            const uint32_t val = st.gid[j];
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
             float g[kG2];
@@ -307,42 +412,40 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
             bool used = false;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (pos >= nw[k]) continue;
-                const PairEval e = eval_pair(p0, p1, ax, (float)(ti.py0 + k * G::RSTEP) + 0.5f, amax);
-                const float alpha = e.alpha;
-                if (alpha < amin) continue;
+                if (!in_band<TS, NW>(val, wv, k)) continue;  // wave-uniform skips
+                if (!__any(pos < nw[k])) continue;
+                const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
+                const bool hit = pos < nw[k] && e.alpha >= amin;
+                if (!__any(hit)) continue;          // wave-uniform skip
                 used = true;
-                const float r = rcp_fast(1.f - alpha);
-                T[k] *= r;  // transmittance before this Gaussian
-                const float w = alpha * T[k];
+                // predicated from here: non-contributing lanes add zeros
+                const float r = rcp_fast(1.f - e.alpha);
+                const float Tk = hit ? T[k] * r : T[k];  // transmittance before this Gaussian
+                T[k] = Tk;
+                const float w = hit ? e.alpha * Tk : 0.f;
                 g[6] = fmaf(w, v[k][0], g[6]);
                 g[7] = fmaf(w, v[k][1], g[7]);
                 g[8] = fmaf(w, v[k][2], g[8]);
-                const float ga = fmaf(v[k][0], fmaf(T[k], p1.z, -S0[k] * r),
-                                      fmaf(v[k][1], fmaf(T[k], p1.w, -S1[k] * r),
-                                           v[k][2] * fmaf(T[k], cb, -S2[k] * r)));
+                const float ga = fmaf(v[k][0], fmaf(Tk, p1.z, -S0[k] * r),
+                                      fmaf(v[k][1], fmaf(Tk, p1.w, -S1[k] * r),
+                                           v[k][2] * fmaf(Tk, cb, -S2[k] * r)));
                 S0[k] = fmaf(p1.z, w, S0[k]);
                 S1[k] = fmaf(p1.w, w, S1[k]);
                 S2[k] = fmaf(cb, w, S2[k]);
-                if (e.s < amax) {
-                    g[5] = fmaf(e.G, ga, g[5]);
-                    const float gp = e.s * ga;
-                    const float hx = gp * dx, hy = gp * e.dy;
-                    g[0] = fmaf(gp, p0.z * e.t1, g[0]);
-                    g[1] = fmaf(gp, fmaf(p0.w, e.t1, p1.x * e.t2), g[1]);
-                    g[2] = fmaf(-0.5f * hx, dx, g[2]);
-                    g[3] = fmaf(-hx, e.dy, g[3]);
-                    g[4] = fmaf(-0.5f * hy, e.dy, g[4]);
-                }
+                // alpha is clamped where sigma G >= alpha_max: no gradient to sigma, G
+                const float gam = (hit && e.s < amax) ? ga : 0.f;
+                g[5] = fmaf(e.G, gam, g[5]);
+                const float gp = e.s * gam;
+                const float hx = gp * dx, hy = gp * e.dy;
+                g[0] = fmaf(gp, p0.z * e.t1, g[0]);
+                g[1] = fmaf(gp, fmaf(p0.w, e.t1, p1.x * e.t2), g[1]);
+                g[2] = fmaf(-0.5f * hx, dx, g[2]);
+                g[3] = fmaf(-hx, e.dy, g[3]);
+                g[4] = fmaf(-0.5f * hy, e.dy, g[4]);
             }
-            if (__any(used)) {
-                float mine = 0.f;
-#pragma unroll
-                for (int f = 0; f < kG2; f++) {
-                    const float tot = wave_total(g[f]);
-                    if (lane == f) mine = tot;
-                }
-                if (lane < kG2 && mine != 0.f) unsafeAtomicAdd(g2d + (int64_t)st.gid[j] * kG2 + lane, mine);
+            if (used) {
+                const float tot = reduce9(g, lane);
+                if (writer && tot != 0.f) unsafeAtomicAdd(g2d + (int64_t)(val & kGidMask) * kG2 + slot, tot);
             }
         }
     }
@@ -397,13 +500,14 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_bwd(RenderArgs a)
 // Forward, per-pixel loss and its gradient, backward for one item.
 template <int TS, int NW>
 __device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<Geo<TS, NW>::CH> &st, uint32_t *s_max,
-                                           float *s_loss)
+                                           float *s_loss, uint32_t (*s_hits)[kHitWords])
 {
     using G = Geo<TS, NW>;
     constexpr int PPL = G::PPL;
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, t);
     NoCount nc;
-    const PixState<PPL> ps = fwd_walk<TS, NW>(a, ti, st, nc);
+    uint32_t *hits = s_hits[threadIdx.x / kWave];
+    const PixState<PPL> ps = fwd_walk<TS, NW>(a, ti, st, nc, hits);
     float v[PPL][3];
     float lsum = 0.f;
     const float inv = 1.f / (3.f * (float)ti.npix);
@@ -445,7 +549,7 @@ __device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<Geo
         for (int w = 0; w < NW; w++) tot += s_loss[w];
         a.loss_part[t] = tot;
     }
-    bwd_walk<TS, NW>(a, ti, st, ps.T, ps.nwalk, v, s_max);
+    bwd_walk<TS, NW>(a, ti, st, ps.T, ps.nwalk, v, s_max, hits);
 }
 
 template <int TS, int NW>
@@ -454,8 +558,9 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused(RenderArgs a
     __shared__ Stage<Geo<TS, NW>::CH> st;
     __shared__ uint32_t s_max;
     __shared__ float s_loss[NW];
+    __shared__ uint32_t s_hits[NW][kHitWords];
     const int t = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
-    fused_item<TS, NW>(a, t, st, &s_max, s_loss);
+    fused_item<TS, NW>(a, t, st, &s_max, s_loss, s_hits);
 }
 
 template <int TS, int NW>
@@ -465,6 +570,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused_persistent(R
     __shared__ uint32_t s_max;
     __shared__ uint32_t s_item;
     __shared__ float s_loss[NW];
+    __shared__ uint32_t s_hits[NW][kHitWords];
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1u);
@@ -472,7 +578,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused_persistent(R
         const uint32_t item = s_item;
         if (item >= (uint32_t)a.T_total) break;
         const int t = a.order ? (int)a.order[item] : (int)item;
-        fused_item<TS, NW>(a, t, st, &s_max, s_loss);
+        fused_item<TS, NW>(a, t, st, &s_max, s_loss, s_hits);
     }
 }
 
@@ -497,6 +603,34 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_count(RenderArgs a
         atomicAdd(&counts[1], (unsigned long long)c);
         atomicAdd(&counts[2], (unsigned long long)w);
     }
+}
+
+// Work order of the fused launch: tiles by descending list length (buckets
+// of equal floor(log2 length), empty tiles last), so that the longest items
+// start first.  One workgroup; the order inside a bucket is whatever the LDS
+// atomics give, which only affects scheduling.
+__global__ __launch_bounds__(1024) void k_order_by_length(const uint32_t *__restrict__ ranges, int64_t T,
+                                                          uint32_t *__restrict__ order)
+{
+    __shared__ uint32_t s_hist[33];
+    __shared__ uint32_t s_cur[33];
+    auto bucket = [&](int64_t t) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        return len == 0 ? 32u : (uint32_t)__clz(len);  // 31 - floor(log2 len): longest first
+    };
+    if (threadIdx.x < 33) s_hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) atomicAdd(&s_hist[bucket(t)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < 33; b++) {
+            s_cur[b] = run;
+            run += s_hist[b];
+        }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) order[atomicAdd(&s_cur[bucket(t)], 1u)] = (uint32_t)t;
 }
 
 __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ part, int64_t n, double *__restrict__ out)
@@ -542,7 +676,7 @@ template <int TS>
 void launch_fused_t(const RenderArgs &a, int variant, int num_cus, hipStream_t s)
 {
     constexpr int NW = Waves<TS>::NW;
-    if (variant == 1) {
+    if (variant & 1) {
         const int per_cu = 32 / NW;
         int64_t g = (int64_t)num_cus * per_cu;
         if (g > a.T_total) g = a.T_total;
@@ -592,6 +726,11 @@ void launch_render_fused(const RenderArgs &a, int variant, int num_cus, hipStrea
     case 16: launch_fused_t<16>(a, variant, num_cus, s); break;
     default: launch_fused_t<32>(a, variant, num_cus, s); break;
     }
+}
+
+void launch_order_by_length(const uint32_t *ranges, int64_t T, uint32_t *order, hipStream_t s)
+{
+    if (T > 0) hipLaunchKernelGGL(k_order_by_length, dim3(1), dim3(1024), 0, s, ranges, T, order);
 }
 
 void launch_reduce_f64(const double *part, int64_t n, double *out, hipStream_t s)

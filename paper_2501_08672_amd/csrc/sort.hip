@@ -297,29 +297,173 @@ __global__ void k_gather_counts(const uint32_t *__restrict__ order, const int32_
     counts[j] = (uint32_t)tiles[order[j]];
 }
 
-__global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
-                       const gsl_splat *__restrict__ splats, const DevCam *__restrict__ cams, int N, int64_t M,
-                       int tile, const int64_t *__restrict__ d_K, int64_t capacity, uint32_t *__restrict__ tile_ids,
-                       uint32_t *__restrict__ gauss_ids, int32_t *__restrict__ d_status)
+// Tiles a splat's alpha_min ellipse reaches, with the quarter-row band mask of
+// each (bit q: rows [q*T/4, (q+1)*T/4) of the tile).
+__device__ __forceinline__ bool tile_hit(const gsl_splat &s, const DevCam &cam, int tile, float kq, int tx, int ty,
+                                         uint32_t *bands)
 {
+    float rx0, rx1, ry0, ry1;
+    tile_rect(tx, ty, tile, cam.W, cam.H, rx0, rx1, ry0, ry1);
+    if (!ellipse_hits_rect(s.mx, s.my, s.l11, s.l12, s.l22, kq, rx0, rx1, ry0, ry1)) return false;
+    if (bands) {
+        const int q = tile / 4;
+        uint32_t b = 0;
+        for (int k = 0; k < 4; k++) {
+            const float by0 = (float)(ty * tile + k * q) + 0.5f;
+            const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1);
+            if (by0 <= by1 && ellipse_hits_rect(s.mx, s.my, s.l11, s.l12, s.l22, kq, rx0, rx1, by0, by1))
+                b |= 1u << k;
+        }
+        *bands = b;
+    }
+    return true;
+}
+
+// Counting and emitting share one walk over a record's bbox tiles.  A lane
+// walks its own record when the bbox spans at most kSmallTiles tiles; larger
+// records are walked by the whole wave afterwards, one at a time, lane l
+// testing tile t0 + l, with a ballot and the popcount below the lane giving
+// each hit's slot.  So a large splat neither stalls a wave nor leaves it idle
+// on small ones, and the hit decisions are the same code for both kernels.
+constexpr int kSmallTiles = 8;
+
+template <bool emit>
+__device__ __forceinline__ uint32_t lane_record_tiles(const gsl_splat &s, const DevCam &cam, int tile, float kq,
+                                                      uint32_t base, uint32_t limit, uint32_t i,
+                                                      uint32_t *tile_ids, uint32_t *gauss_ids)
+{
+    const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
+    uint32_t n = 0;
+    for (int ty = ty0; ty <= ty1; ty++)
+        for (int tx = tx0; tx <= tx1; tx++) {
+            uint32_t bands = 0;
+            if (!tile_hit(s, cam, tile, kq, tx, ty, emit ? &bands : nullptr)) continue;
+            if (emit && n < limit) {  // never beyond the record's counted range
+                tile_ids[base + n] = (uint32_t)(cam.tile_offset + ty * cam.tiles_x + tx);
+                gauss_ids[base + n] = i | (bands << kGidBits);
+            }
+            n++;
+        }
+    return n;
+}
+
+template <bool emit>
+__device__ __forceinline__ uint32_t wave_record_tiles(const gsl_splat &s, const DevCam &cam, int tile, float kq,
+                                                      int lane, uint32_t base, uint32_t limit, uint32_t i,
+                                                      uint32_t *tile_ids, uint32_t *gauss_ids)
+{
+    const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
+    const int nx = tx1 - tx0 + 1, nt = nx * (ty1 - ty0 + 1);
+    uint32_t n = 0;
+    for (int t0 = 0; t0 < nt; t0 += kWave) {
+        const int t = t0 + lane;
+        bool hit = false;
+        int tx = 0, ty = 0;
+        uint32_t bands = 0;
+        if (t < nt) {
+            ty = ty0 + t / nx;
+            tx = tx0 + t - (ty - ty0) * nx;
+            hit = tile_hit(s, cam, tile, kq, tx, ty, emit ? &bands : nullptr);
+        }
+        const uint64_t mask = __ballot(hit);
+        if (emit && hit) {
+            const uint32_t r = n + (uint32_t)__popcll(mask & lanemask_lt(lane));
+            if (r < limit) {  // never beyond the record's counted range
+                tile_ids[base + r] = (uint32_t)(cam.tile_offset + ty * cam.tiles_x + tx);
+                gauss_ids[base + r] = i | (bands << kGidBits);
+            }
+        }
+        n += (uint32_t)__popcll(mask);
+    }
+    return n;
+}
+
+__device__ __forceinline__ int bbox_tiles(const gsl_splat &s, int tile)
+{
+    if (s.x0 > s.x1) return 0;
+    return (s.x1 / tile - s.x0 / tile + 1) * (s.y1 / tile - s.y0 / tile + 1);
+}
+
+// tiles_touched of every record (natural order), one lane per record.
+__global__ __launch_bounds__(256) void k_count_tiles(const gsl_splat *__restrict__ splats,
+                                                     const DevCam *__restrict__ cams, int N, int64_t M, int tile,
+                                                     float alpha_min, int32_t *__restrict__ tiles)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    gsl_splat s;
+    int nt = 0;
+    if (m < M) {
+        s = splats[m];
+        nt = bbox_tiles(s, tile);
+    }
+    const bool big = nt > kSmallTiles;
+    if (m < M && !big) {
+        uint32_t n = 0;
+        if (nt > 0) {
+            const int c = (int)(m / N);
+            n = lane_record_tiles<false>(s, cams[c], tile, ellipse_k(s.opacity, alpha_min), 0, 0, 0, nullptr,
+                                         nullptr);
+        }
+        tiles[m] = (int32_t)n;
+    }
+    uint64_t todo = __ballot(big);
+    while (todo) {
+        const int src = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int64_t mb = __shfl(m, src, kWave);
+        const gsl_splat sb = splats[mb];
+        const int c = (int)(mb / N);
+        const uint32_t n = wave_record_tiles<false>(sb, cams[c], tile, ellipse_k(sb.opacity, alpha_min), lane, 0, 0,
+                                                    0, nullptr, nullptr);
+        if (lane == 0) tiles[mb] = (int32_t)n;
+    }
+}
+
+// One (tile, Gaussian | bands) instance per reached tile, records in depth order.
+__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
+                                              const uint32_t *__restrict__ counts,
+                                              const gsl_splat *__restrict__ splats, const DevCam *__restrict__ cams,
+                                              int N, int64_t M, int tile, float alpha_min,
+                                              const int64_t *__restrict__ d_K, int64_t capacity,
+                                              uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ gauss_ids,
+                                              int32_t *__restrict__ d_status)
+{
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t K = *d_K;
     if (j == 0) *d_status = K > capacity ? GSL_ECAPACITY : GSL_OK;
-    if (j >= M || K > capacity) return;
-    const uint32_t m = order[j];
-    const gsl_splat s = splats[m];
-    if (s.x0 > s.x1) return;
-    const int c = (int)(m / (uint32_t)N);
-    const uint32_t i = m - (uint32_t)c * (uint32_t)N;
-    const int tx = cams[c].tiles_x, toff = cams[c].tile_offset;
-    const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
-    uint32_t o = offsets[j];
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int x = tx0; x <= tx1; x++) {
-            tile_ids[o] = (uint32_t)(toff + ty * tx + x);
-            gauss_ids[o] = i;
-            o++;
+    if (K > capacity) return;  // uniform: every lane reads the same K
+    uint32_t cnt = 0, m = 0;
+    gsl_splat s;
+    int nt = 0;
+    if (j < M) {
+        cnt = counts[j];
+        if (cnt) {
+            m = order[j];
+            s = splats[m];
+            nt = bbox_tiles(s, tile);
         }
+    }
+    const bool big = nt > kSmallTiles;
+    if (cnt && !big) {
+        const int c = (int)(m / (uint32_t)N);
+        const uint32_t i = m - (uint32_t)c * (uint32_t)N;
+        lane_record_tiles<true>(s, cams[c], tile, ellipse_k(s.opacity, alpha_min), offsets[j], cnt, i, tile_ids,
+                                gauss_ids);
+    }
+    uint64_t todo = __ballot(big);
+    while (todo) {
+        const int src = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int64_t jb = __shfl(j, src, kWave);
+        const uint32_t mb = order[jb];
+        const gsl_splat sb = splats[mb];
+        const int c = (int)(mb / (uint32_t)N);
+        const uint32_t i = mb - (uint32_t)c * (uint32_t)N;
+        wave_record_tiles<true>(sb, cams[c], tile, ellipse_k(sb.opacity, alpha_min), lane, offsets[jb], counts[jb],
+                                i, tile_ids, gauss_ids);
+    }
 }
 
 __global__ void k_ranges(const uint32_t *__restrict__ tile_ids, const int64_t *__restrict__ d_K, int64_t capacity,
@@ -400,13 +544,22 @@ void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M
                            counts);
 }
 
-void launch_emit(const uint32_t *order, const uint32_t *offsets, const gsl_splat *splats, const DevCam *cams,
-                 const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids, uint32_t *gauss_ids,
-                 int32_t *d_status, hipStream_t s)
+void launch_count_tiles(const gsl_splat *splats, const DevCam *cams, const Layout &L, float alpha_min,
+                        int32_t *tiles_touched, hipStream_t s)
+{
+    if (L.M == 0) return;
+    const int64_t blocks = (L.M + 255) / 256;
+    hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)blocks), dim3(256), 0, s, splats, cams, L.N, L.M, L.tile,
+                       alpha_min, tiles_touched);
+}
+
+void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_splat *splats,
+                 const DevCam *cams, const Layout &L, float alpha_min, const int64_t *d_K, int64_t capacity,
+                 uint32_t *tile_ids, uint32_t *gauss_ids, int32_t *d_status, hipStream_t s)
 {
     const int64_t blocks = L.M > 0 ? (L.M + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, splats, cams, L.N, L.M,
-                       L.tile, d_K, capacity, tile_ids, gauss_ids, d_status);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, counts, splats, cams, L.N,
+                       L.M, L.tile, alpha_min, d_K, capacity, tile_ids, gauss_ids, d_status);
 }
 
 void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,

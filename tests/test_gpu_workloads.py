@@ -1,0 +1,171 @@
+"""GPU checks at the full sizes of the larger workloads, through the C ABI.
+
+* 200k surfels, 640x512, 32 perturbed poses batched: the pose gradient of
+  1/2 sum r^2 (r = render at the perturbed pose - render at the true pose)
+  against the oracle on sampled pixels, and against central differences of
+  the twist evaluated with the GPU forward.
+* 500k surfels, 8 keyframes 1280x1024: sampled pixels of the window image and
+  the gradient of a sparse cotangent against the oracle.
+* 2M surfels, 16 cameras 320x256 .. 1920x1080: sampled pixels against the
+  oracle, and the batched window step against per-camera steps.
+"""
+import numpy as np
+import pytest
+
+import scenegen as S
+
+from gpuutil import compare_grads, context, gpu_backward, gpu_forward, ops, unpack_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _sample(cam, n, rng):
+    p = np.stack([rng.integers(0, cam.width, n), rng.integers(0, cam.height, n)], 1).astype(np.int32)
+    return np.unique(p, axis=0)
+
+
+@pytest.fixture(scope="module")
+def pose_batch():
+    sc, true_cam, cams, tw = S.config4()
+    ref = gpu_forward(sc, [true_cam], tile=16)
+    I_true = unpack_np(ref["cams"], ref["image"])[0]
+    st = gpu_forward(sc, cams, tile=16)
+    return sc, true_cam, cams, tw, I_true, st
+
+
+def test_pose_batch_vs_oracle(oracle, pose_batch):
+    """32 poses in one batch; cotangent r = I(T_pert) - I(T_true) on 96 sampled
+    pixels per pose (oracle-unambiguous ones), elsewhere 0."""
+    sc, true_cam, cams, tw, I_true, st = pose_batch
+    rng = np.random.default_rng(1)
+    imgs = unpack_np(st["cams"], st["image"])
+    vs, pix_list, v_packed = [], [], []
+    sel = [0, 5, 11, 17, 23, 31]  # oracle on a subset of the 32 poses keeps the test short
+    for c, cam in enumerate(cams):
+        v = np.zeros((3, cam.height, cam.width), np.float32)
+        if c in sel:
+            pix = _sample(cam, 96, rng)
+            r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
+            pix = pix[r["flags"] == 0]
+            res = imgs[c][:, pix[:, 1], pix[:, 0]] - I_true[:, pix[:, 1], pix[:, 0]]
+            v[:, pix[:, 1], pix[:, 0]] = res
+            vs.append(res.T.astype(np.float64))
+            pix_list.append(pix)
+        v_packed.append(v.ravel())
+    gg = gpu_backward(st, torch.from_numpy(np.concatenate(v_packed)).cuda())
+    go = oracle.render_bwd(sc, [cams[c] for c in sel], vs, oracle.Opts(), pixels=pix_list)
+    compare_grads({"pose": gg["pose"][sel]}, {"pose": go["pose"]}, keys=("pose",), name="pose batch")
+    # poses with a zero cotangent get an exactly zero gradient
+    others = [c for c in range(len(cams)) if c not in sel]
+    assert np.all(gg["pose"][others] == 0)
+
+
+def test_pose_batch_vs_twist_differences(pose_batch):
+    """Directional central differences of L(xi) = 1/2 sum (I(Exp(xi) T) - I_true)^2
+    with the GPU forward.  L has jumps where a Gaussian crosses the 1/255
+    skip or the cutoff at some pixel; the analytic gradient is the derivative
+    of its smooth part.  Pixels whose second difference shows a jump are
+    therefore left out of both sides: the FD of the remaining pixels' loss is
+    compared with the gradient of the same pixels' loss."""
+    sc, true_cam, cams, tw, I_true, st = pose_batch
+    imgs = unpack_np(st["cams"], st["image"])
+    rng = np.random.default_rng(2)
+    h = 1.0
+    for c in (0, 7):
+        d = rng.normal(size=6)
+        d[:3] *= 2e-4 / np.linalg.norm(d[:3])
+        d[3:] *= 4e-4 / np.linalg.norm(d[3:])
+
+        def render(sgn):
+            cam = S.perturb_camera(cams[c], sgn * h * d[:3], sgn * h * d[3:])
+            s2 = gpu_forward(sc, [cam], tile=16)
+            return unpack_np(s2["cams"], s2["image"])[0].astype(np.float64)
+
+        I0, Ip, Im = imgs[c].astype(np.float64), render(1.0), render(-1.0)
+        smooth = np.abs(Ip + Im - 2 * I0).max(0) <= 2e-5
+        assert smooth.mean() > 0.9, smooth.mean()
+        fd = (0.5 * (((Ip - I_true) ** 2)[:, smooth]).sum() - 0.5 * (((Im - I_true) ** 2)[:, smooth]).sum()) / (2 * h)
+        v = []
+        for k, cam in enumerate(cams):
+            vk = np.zeros((3, cam.height, cam.width), np.float32)
+            if k == c:
+                vk[:, smooth] = (I0 - I_true)[:, smooth]
+            v.append(vk.ravel())
+        gg = gpu_backward(st, torch.from_numpy(np.concatenate(v)).cuda())
+        an = float(gg["pose"][c] @ d)
+        assert abs(fd - an) <= 1e-2 * abs(an) + 1e-6, (c, fd, an, smooth.mean())
+
+
+def test_window_500k_sampled(oracle):
+    sc, _ = S.config3()
+    st = gpu_forward(sc, sc.cams, tile=16)
+    imgs = unpack_np(st["cams"], st["image"])
+    rng = np.random.default_rng(3)
+    vparts, pix_l, vs = [], [], []
+    for c, cam in enumerate(sc.cams):
+        pix = _sample(cam, 48, rng)
+        r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
+        ok = (r["flags"] & 1) == 0
+        got = imgs[c][:, pix[:, 1], pix[:, 0]].T
+        assert np.abs(got - r["rgb"])[ok].max() <= 1e-4
+        pix = pix[r["flags"] == 0]
+        v = rng.normal(size=(len(pix), 3))
+        vi = np.zeros((3, cam.height, cam.width), np.float32)
+        vi[:, pix[:, 1], pix[:, 0]] = v.T
+        vparts.append(vi.ravel())
+        pix_l.append(pix)
+        vs.append(v)
+    gg = gpu_backward(st, torch.from_numpy(np.concatenate(vparts)).cuda())
+    go = oracle.render_bwd(sc, sc.cams, vs, oracle.Opts(), pixels=pix_l)
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name="window 500k")
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    sc, tgt = S.config5()
+    return sc, tgt
+
+
+def test_uneven_batch_sampled(oracle, uneven):
+    sc, _ = uneven
+    st = gpu_forward(sc, sc.cams, tile=8)
+    imgs = unpack_np(st["cams"], st["image"])
+    rng = np.random.default_rng(4)
+    for c in (0, 5, 15):
+        cam = sc.cams[c]
+        pix = _sample(cam, 24, rng)
+        r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
+        ok = (r["flags"] & 1) == 0
+        got = imgs[c][:, pix[:, 1], pix[:, 0]].T
+        assert np.abs(got - r["rgb"])[ok].max() <= 1e-4, c
+
+
+def test_uneven_batch_window_vs_per_camera(uneven):
+    """One batched window step over 16 mixed-size cameras equals 16
+    single-camera steps: images bit-identical, per-camera losses and pose
+    gradients equal, Gaussian gradients equal to their sum."""
+    O = ops()
+    sc, tgt_sc = uneven
+    ctx = context()
+    cs = O.CameraSet(sc.cams)
+    g = O.Gaussians.from_scene(sc)
+    tgt = gpu_forward(tgt_sc, sc.cams, tile=16)["image"]
+    w = O.Window(ctx, g, cs, O.opts(16), tgt, loss="l1", keep_image=True)
+    w.step(use_graph=True)
+    torch.cuda.synchronize()
+    tot_mean = torch.zeros_like(w.grads.mean)
+    loss = 0.0
+    for c, cam in enumerate(sc.cams):
+        c1 = O.CameraSet([cam])
+        w1 = O.Window(ctx, g, c1, O.opts(16), cs.unpack(tgt)[c].reshape(-1).contiguous(), loss="l1",
+                      keep_image=True)
+        w1.step(use_graph=False)
+        torch.cuda.synchronize()
+        assert torch.equal(w1.image, cs.unpack(w.image)[c].reshape(-1))
+        torch.testing.assert_close(w1.grads.pose[0], w.grads.pose[c], rtol=1e-5, atol=1e-9)
+        tot_mean += w1.grads.mean
+        loss += float(w1.d_loss.item())
+        del w1
+    assert abs(loss - float(w.d_loss.item())) <= 1e-6 * abs(loss)
+    torch.testing.assert_close(tot_mean, w.grads.mean, rtol=1e-4, atol=1e-5 * float(tot_mean.abs().max()))
