@@ -29,11 +29,16 @@
  * by index, which is the order a 32-bit depth key gives.
  *
  * Ambiguity flags: a pixel whose result hinges on a threshold decision that
- * FP32 arithmetic may take the other way is flagged AMB_VALUE: sigma*G within
- * its FP32 error bound of a_min, T(1 - a) within the accumulated bound of
- * T_min, or a cull decision within a tiny band.  A contributor whose sigma*G
- * lies within the bound of a_max (where the clamp switches the alpha gradient
- * on or off) sets AMB_GRAD.  The bound is first order in the FP32 unit
+ * FP32 arithmetic may take the other way is flagged.  AMB_VALUE: sigma*G
+ * within its FP32 error bound of a_min, or a cull decision within a tiny
+ * band, or T(1 - a) within the accumulated bound of T_min at a Gaussian
+ * whose weight a T exceeds T_min (the pixel may change by a whole
+ * contribution).  AMB_TCUT: the same cutoff ambiguity at a Gaussian with
+ * a T <= T_min (the walk may stop one Gaussian earlier or later; that
+ * Gaussian and everything after it weigh at most about 2 T_min, so the pixel
+ * changes by at most 2.01 T_min (max c + bg)).  AMB_GRAD: a contributor whose
+ * sigma*G lies within the bound of a_max, where the clamp switches the alpha
+ * gradient on or off.  The bound is first order in the FP32 unit
  * roundoff u = 2^-24: the rounding of the 2D mean and of the conic factor,
  * the evaluation of the quadratic form, exp and the products, times the
  * safety factor amb_rel; for T it accumulates a (dalpha)/(1 - a) per
@@ -66,7 +71,7 @@ typedef struct {
 } orc_opts;
 
 enum { ORC_KEPT = 1, ORC_BORDER = 2 };
-enum { AMB_VALUE = 1, AMB_GRAD = 2 };
+enum { AMB_VALUE = 1, AMB_GRAD = 2, AMB_TCUT = 4 };
 
 /* ------------------------------------------------------------------------ */
 /* small dense helpers                                                      */
@@ -291,7 +296,8 @@ static double composite_pixel(double px, double py, int64_t M, const int64_t *or
         if (fabs(s - o->alpha_max) <= ds * o->alpha_max) flags |= AMB_GRAD;
         double Tn = T * (1.0 - a);
         double da = s < o->alpha_max ? a * ds / (1.0 - a) : 0.0;
-        if (fabs(Tn - o->T_min) <= o->T_min * (eT + da + amb * 4.0 * u)) flags |= AMB_VALUE;
+        if (fabs(Tn - o->T_min) <= o->T_min * (eT + da + amb * 4.0 * u))
+            flags |= a * T <= o->T_min ? AMB_TCUT : AMB_VALUE;
         if (Tn < o->T_min) break;
         eT += da + amb * 4.0 * u;
         for (int ch = 0; ch < 3; ch++) C[ch] += a * T * color[3 * i + ch];

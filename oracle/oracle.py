@@ -21,8 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gsl_oracle.c")
 _LIB = os.path.join(_HERE, "libgsl_oracle.so")
 
-AMB_VALUE = 1
-AMB_GRAD = 2
+AMB_VALUE = 1   # an alpha-threshold or cull decision: the pixel may differ by a whole contribution
+AMB_GRAD = 2    # the alpha clamp switches at a contributor: its alpha gradient may differ
+AMB_TCUT = 4    # a small-step cutoff decision: the pixel may differ by at most 2.01 T_min (max c + bg)
 
 
 def build(force: bool = True) -> str:
