@@ -29,11 +29,15 @@
  * by index, which is the order a 32-bit depth key gives.
  *
  * Ambiguity flags: a pixel whose result hinges on a threshold decision that
- * FP32 arithmetic may take the other way is flagged.  AMB_VALUE: sigma*G
- * within its FP32 error bound of a_min, or a cull decision within a tiny
- * band, or T(1 - a) within the accumulated bound of T_min at a Gaussian
- * whose weight a T exceeds T_min (the pixel may change by a whole
- * contribution).  AMB_TCUT: the same cutoff ambiguity at a Gaussian with
+ * FP32 arithmetic may take the other way is flagged.  A flip of the a_min
+ * decision (or of a cull decision on its border) at transmittance T moves the
+ * pixel by at most 2 a T (max |c| + max |bg|) — the Gaussian's own term and the
+ * rescaling of the rest of the walk by (1 - a) — and the relative error of T
+ * by a.  Such flips are left unflagged while their summed bound stays within
+ * amb_ignore, their T effect being added to the transmittance bound; beyond
+ * that the pixel is flagged AMB_VALUE.  AMB_VALUE also marks T(1 - a) within
+ * the accumulated bound of T_min at a Gaussian whose weight a T exceeds T_min
+ * (the pixel may change by a whole contribution).  AMB_TCUT: the same cutoff ambiguity at a Gaussian with
  * a T <= T_min (the walk may stop one Gaussian earlier or later; that
  * Gaussian and everything after it weigh at most about 2 T_min, so the pixel
  * changes by at most 2.01 T_min (max c + bg)).  AMB_GRAD: a contributor whose
@@ -68,6 +72,7 @@ typedef struct {
     double bg[3];     /* background colour */
     double guard;     /* cull when the 2D mean is beyond guard*W (guard*H) outside the image */
     double amb_rel;   /* safety factor on the FP32 error bound used by the ambiguity flags */
+    double amb_ignore; /* pixel deviation budget for alpha-threshold flips left unflagged */
 } orc_opts;
 
 enum { ORC_KEPT = 1, ORC_BORDER = 2 };
@@ -221,6 +226,15 @@ static int cmp_order(const void *a, const void *b)
 
 /* Projects every Gaussian and returns those kept or on a cull border, in
  * ascending (float depth, index) order. */
+/* max |colour| + max |bg|: bounds how much one Gaussian's presence can move a pixel */
+static double colour_bound(int64_t N, const double *color, const orc_opts *o)
+{
+    double cm = 0.0, bm = 0.0;
+    for (int64_t k = 0; k < 3 * N; k++) cm = fmax(cm, fabs(color[k]));
+    for (int ch = 0; ch < 3; ch++) bm = fmax(bm, fabs(o->bg[ch]));
+    return cm + bm;
+}
+
 static int64_t build_order(int64_t N, const double *mean, const double *scale, const double *quat,
                            const orc_camera *cam, const orc_opts *o, proj_t **proj_out, int64_t **order_out)
 {
@@ -260,7 +274,7 @@ typedef struct {
 /* Walks the ordered Gaussians for the pixel centre (px, py).  Fills rgb,
  * returns the final transmittance; records contributors when `list` is set. */
 static double composite_pixel(double px, double py, int64_t M, const int64_t *order, const proj_t *proj,
-                              const double *opacity, const double *color, const orc_opts *o,
+                              const double *opacity, const double *color, const orc_opts *o, double cb,
                               double rgb[3], int32_t *n_out, int64_t *last_out, int32_t *flags_out,
                               contrib_t *list)
 {
@@ -268,7 +282,19 @@ static double composite_pixel(double px, double py, int64_t M, const int64_t *or
     int32_t n = 0, flags = 0;
     int64_t last = -1;
     const double amb = o->amb_rel, u = 0x1p-24;
-    double eT = 0.0; /* relative FP32 error bound accumulated on T */
+    double eT = 0.0;   /* relative FP32 error bound accumulated on T */
+    double ign = 0.0;  /* summed deviation bound of the a_min flips left unflagged */
+    /* a flip of the a_min decision for a Gaussian of value s at transmittance T */
+#define ORC_ALPHA_FLIP(s_)                                   \
+    do {                                                     \
+        const double eff_ = 2.0 * (s_) * T * cb;             \
+        if (ign + eff_ <= o->amb_ignore) {                   \
+            ign += eff_;                                     \
+            eT += (s_);                                      \
+        } else {                                             \
+            flags |= AMB_VALUE;                              \
+        }                                                    \
+    } while (0)
     for (int64_t k = 0; k < M; k++) {
         int64_t i = order[k];
         const proj_t *p = &proj[i];
@@ -284,13 +310,13 @@ static double composite_pixel(double px, double py, int64_t M, const int64_t *or
                     (16.0 + 4.0 * fabs(power) + 2.0 * (fabs(gx) * (fabs(p->mu[0]) + fabs(dx)) +
                                                        fabs(gy) * (fabs(p->mu[1]) + fabs(dy))) +
                      2.0 * t1 * e1);
-        if (!(p->status & ORC_KEPT)) { /* on a cull border only: flag if it would matter here */
-            if (s >= o->alpha_min * (1 - ds)) flags |= AMB_VALUE;
+        if (!(p->status & ORC_KEPT)) { /* on a cull border only: it may be kept in FP32 */
+            if (s >= o->alpha_min * (1 - ds)) ORC_ALPHA_FLIP(s < o->alpha_max ? s : o->alpha_max);
             continue;
         }
         if (p->status & ORC_BORDER)
-            if (s >= o->alpha_min * (1 - ds)) flags |= AMB_VALUE;
-        if (fabs(s - o->alpha_min) <= ds * o->alpha_min) flags |= AMB_VALUE;
+            if (s >= o->alpha_min * (1 - ds)) ORC_ALPHA_FLIP(s < o->alpha_max ? s : o->alpha_max);
+        if (fabs(s - o->alpha_min) <= ds * o->alpha_min) ORC_ALPHA_FLIP(s);
         double a = s < o->alpha_max ? s : o->alpha_max;
         if (a < o->alpha_min) continue;
         if (fabs(s - o->alpha_max) <= ds * o->alpha_max) flags |= AMB_GRAD;
@@ -314,6 +340,7 @@ static double composite_pixel(double px, double py, int64_t M, const int64_t *or
         n++;
         last = i;
     }
+#undef ORC_ALPHA_FLIP
     for (int ch = 0; ch < 3; ch++) rgb[ch] = C[ch] + T * o->bg[ch];
     if (n_out) *n_out = n;
     if (last_out) *last_out = last;
@@ -329,13 +356,14 @@ int orc_render_fwd(int64_t N, const double *mean, const double *scale, const dou
     proj_t *proj;
     int64_t *order;
     int64_t M = build_order(N, mean, scale, quat, cam, o, &proj, &order);
+    const double cb = colour_bound(N, color, o);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < npix; p++) {
         double px = pix[2 * p] + 0.5, py = pix[2 * p + 1] + 0.5;
         double c[3];
         int32_t n, f;
         int64_t last;
-        double T = composite_pixel(px, py, M, order, proj, opacity, color, o, c, &n, &last, &f, NULL);
+        double T = composite_pixel(px, py, M, order, proj, opacity, color, o, cb, c, &n, &last, &f, NULL);
         rgb[3 * p] = c[0]; rgb[3 * p + 1] = c[1]; rgb[3 * p + 2] = c[2];
         if (T_final) T_final[p] = T;
         if (n_contrib) n_contrib[p] = n;
@@ -359,7 +387,8 @@ int32_t orc_pixel_trace(int64_t N, const double *mean, const double *scale, cons
     contrib_t *list = (contrib_t *)malloc(sizeof(contrib_t) * (size_t)(M > 0 ? M : 1));
     double c[3];
     int32_t n;
-    composite_pixel(u + 0.5, v + 0.5, M, order, proj, opacity, color, o, c, &n, NULL, NULL, list);
+    composite_pixel(u + 0.5, v + 0.5, M, order, proj, opacity, color, o, colour_bound(N, color, o), c, &n, NULL,
+                    NULL, list);
     for (int32_t k = 0; k < n && k < cap; k++) {
         ids[k] = list[k].id;
         alphas[k] = list[k].alpha;
@@ -386,7 +415,7 @@ static void pixel_adjoint(double px, double py, const double v[3], int64_t M, co
 {
     double rgb[3];
     int32_t n;
-    double Tf = composite_pixel(px, py, M, order, proj, opacity, color, o, rgb, &n, NULL, NULL, list);
+    double Tf = composite_pixel(px, py, M, order, proj, opacity, color, o, 0.0, rgb, &n, NULL, NULL, list);
     /* S = sum_{j > k} c_j a_j T_j + T_final bg, built from the back */
     double S[3] = {Tf * o->bg[0], Tf * o->bg[1], Tf * o->bg[2]};
     for (int32_t k = n - 1; k >= 0; k--) {

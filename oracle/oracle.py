@@ -44,7 +44,7 @@ class _Cam(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("near_z", C.c_double), ("eps2d", C.c_double), ("alpha_min", C.c_double),
                 ("alpha_max", C.c_double), ("T_min", C.c_double), ("bg", C.c_double * 3),
-                ("guard", C.c_double), ("amb_rel", C.c_double)]
+                ("guard", C.c_double), ("amb_rel", C.c_double), ("amb_ignore", C.c_double)]
 
 
 @dataclass
@@ -59,6 +59,7 @@ class Opts:
     bg: tuple = (0.0, 0.0, 0.0)
     guard: float = 0.15
     amb_rel: float = 4.0  # safety factor on the FP32 error bound of the ambiguity flags
+    amb_ignore: float = 5e-5  # deviation budget (half the image tolerance) for alpha-threshold flips left unflagged
 
     def c(self) -> _Opts:
         o = _Opts()
@@ -66,7 +67,7 @@ class Opts:
             self.near_z, self.eps2d, self.alpha_min, self.alpha_max, self.T_min)
         for k in range(3):
             o.bg[k] = float(self.bg[k])
-        o.guard, o.amb_rel = self.guard, self.amb_rel
+        o.guard, o.amb_rel, o.amb_ignore = self.guard, self.amb_rel, self.amb_ignore
         return o
 
 

@@ -392,3 +392,43 @@ def test_single_gaussian_gradient_closed_forms(oracle):
         g = oracle.render_bwd(sc, [cam], [Wimg], o)
         np.testing.assert_allclose(g["color"][0, ch], a[on].sum(), rtol=1e-12)
         np.testing.assert_allclose(g["opacity"][0], float(sc.color[0, ch]) * G[on].sum(), rtol=1e-12)
+
+
+def test_alpha_threshold_flip_bound(oracle):
+    """A Gaussian whose alpha sits on the 1/255 skip threshold, once with
+    nothing in front of it and once behind two occluders (T = 0.01 * 0.5).
+    Taking the decision either way moves the pixel by alpha T |c - bg| at
+    most, well inside 2 alpha T (max c + bg): the oracle flags the pixel when
+    that bound exceeds the 5e-5 budget (open view) and leaves it unflagged
+    when it does not (occluded), in which case the two sides of the threshold
+    agree to the budget."""
+    cam = _cam(W=9, H=9, f=20.0, cx=4.5, cy=4.5)
+    probe = dict(mean=[0, 0, 3.0], scale=[0.3, 0.3, 0.3], color=[1.0, 0.0, 0.5])
+    occ_mean, occ_scale = [[0, 0, 1.0], [0, 0, 1.5]], [[1.0, 1.0, 1.0], [1.0, 1.0, 1.0]]
+    pix = np.array([[4, 4]], np.int32)
+    o = oracle.Opts()
+    for occluded in (False, True):
+        res = []
+        for side in (-1, 1):
+            mean = ([probe["mean"]] + (occ_mean if occluded else []))
+            scale = ([probe["scale"]] + (occ_scale if occluded else []))
+            n = len(mean)
+            sc = _scene(mean, scale, [[1, 0, 0, 0]] * n, [1.0] + [0.99, 0.5][: n - 1],
+                        [probe["color"]] + [[0.2, 0.2, 0.2]] * (n - 1), [cam])
+            p = oracle.project(sc, cam, o)
+            A, B, Cc = p["conic"][0]
+            d = 4.5 - p["mean2d"][0]
+            G = np.exp(-0.5 * (A * d[0] ** 2 + 2 * B * d[0] * d[1] + Cc * d[1] ** 2))
+            sc.opacity[0] = np.float32((1 / 255) / G * (1 + side * 1e-6))
+            res.append(oracle.render(sc, cam, o, pixels=pix))
+        lo, hi = res
+        assert hi["n"][0] == lo["n"][0] + 1  # the probe is skipped on one side only
+        dev = float(np.abs(hi["rgb"] - lo["rgb"]).max())
+        T = 1.0 if not occluded else (1 - 0.99) * (1 - 0.5)
+        assert dev <= (1 / 255) * T * 1.0 * (1 + 1e-5)
+        if occluded:
+            assert (lo["flags"][0] & 1) == 0 and (hi["flags"][0] & 1) == 0  # (2: the occluder sits on the clamp)
+            assert dev <= o.amb_ignore
+            assert oracle.render(sc, cam, oracle.Opts(amb_ignore=0.0), pixels=pix)["flags"][0] & 1
+        else:
+            assert lo["flags"][0] & 1 and hi["flags"][0] & 1
