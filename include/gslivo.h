@@ -223,6 +223,12 @@ GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
                     double *d_loss, gsl_grads *grads, void *workspace, size_t workspace_bytes,
                     int use_graph, void *stream);
 
+/* Pins the fused-kernel variant gsl_window_step uses for these shapes (the
+ * value gsl_window_tune would store): bit 0 persistent work queue, bit 1
+ * longest list first, 4 = contiguous tile runs per XCD; 0..4 are valid. */
+GSL_API int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile,
+                               int32_t variant);
+
 /* Profiling hook: while enabled, every eager (use_graph == 0) window step
  * records HIP events on its stream between its stages.  gsl_profile_read
  * waits for the last profiled step and writes up to n milliseconds:
@@ -238,7 +244,7 @@ GSL_API int gsl_profile_read(gsl_ctx *ctx, float *ms, int32_t n);
  * buffers must be sized for tile 8 (the largest T_total) and enough
  * capacity_K for every tile size; times_ms (may be NULL) receives up to
  * `ntimes` measured milliseconds in the order tried (tiles 8, 16, 32; per
- * tile the four variants: plain, persistent, ordered, persistent+ordered). */
+ * tile the five variants 0..4 of gsl_window_variant). */
 GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, gsl_opts *opts_inout,
                     const float *target, int loss, gsl_proj *proj, gsl_bins *bins, double *d_loss,
                     gsl_grads *grads, void *workspace, size_t workspace_bytes, float *times_ms, int32_t ntimes,

@@ -28,7 +28,7 @@ _NAMES = {GSL_EINVAL: "EINVAL", GSL_ENOTSUP: "ENOTSUP", GSL_ECAPACITY: "ECAPACIT
 
 EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "gsl_layout", "gsl_workspace_size",
            "gsl_project", "gsl_bin_sort", "gsl_render_fwd", "gsl_render_bwd", "gsl_render_stats", "gsl_window_step",
-           "gsl_window_tune", "gsl_profile", "gsl_profile_read"]
+           "gsl_window_tune", "gsl_window_variant", "gsl_profile", "gsl_profile_read"]
 
 
 class GslError(RuntimeError):
@@ -96,6 +96,7 @@ def lib() -> C.CDLL:
     L.gsl_render_fwd.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, P, P, P, C.c_size_t, P]
     L.gsl_render_bwd.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, C.c_int, pgr, P, C.c_size_t, P]
     L.gsl_render_stats.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, P, C.c_size_t, P]
+    L.gsl_window_variant.argtypes = [P, pc, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.gsl_profile.argtypes = [P, C.c_int]
     L.gsl_profile_read.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
     L.gsl_window_step.argtypes = [P, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, P, pgr, P, C.c_size_t, C.c_int, P]

@@ -603,6 +603,17 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
     return GSL_OK;
 }
 
+int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, int32_t variant)
+{
+    if (!ctx) return fail(GSL_EINVAL, "ctx is NULL");
+    if (variant < 0 || variant >= kVariants) return fail(GSL_EINVAL, "variant %d not in [0, %d)", variant, kVariants);
+    Layout L;
+    GSL_TRY(make_layout(cams, C, N, tile, L, nullptr));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->variant[window_key(L, cams)] = variant;
+    return GSL_OK;
+}
+
 int gsl_profile(gsl_ctx *ctx, int enable)
 {
     if (!ctx) return fail(GSL_EINVAL, "ctx is NULL");

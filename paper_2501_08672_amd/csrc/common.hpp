@@ -48,35 +48,54 @@ __device__ __forceinline__ float ellipse_k(float opacity, float alpha_min)
     return (float)(2.0 * log((double)opacity / (double)alpha_min) + 0.01);
 }
 
-// Does the ellipse |L (x - mu)|^2 <= kq reach the rectangle [x0, x1] x [y0, y1]
-// of pixel centres?  The minimum of the convex quadratic over the rectangle is
-// at mu when mu lies inside, else on one of its edges, where it has a closed
-// form.  The projection kernel (counting) and the emit kernel (writing) both
-// call this, so the instance count matches the instances written exactly.
-__device__ __forceinline__ bool ellipse_hits_rect(float mx, float my, float l11, float l12, float l22, float kq,
-                                                  float x0, float x1, float y0, float y1)
+// Does the ellipse |L (x - mu)|^2 <= kq reach a rectangle [x0, x1] x [y0, y1]
+// of pixel centres?  The minimum of the convex quadratic over the rectangle
+// is 0 when mu lies inside; otherwise it lies on an edge that faces mu (the
+// segment from any other boundary point to mu would cross such an edge at a
+// lower value), so at most one vertical and one horizontal edge are
+// evaluated, each in closed form: on x = const the minimiser is dy = kv dx,
+// on y = const it is dx = kh dy, clamped to the edge.  The projection-side
+// count and the emit kernel both call this, so the instance count matches
+// the instances written exactly.
+struct EllipseTest {
+    float mx, my, l11, l12, l22, kq;
+    float kv;  // -(l11 l12) / (l12^2 + l22^2)
+    float kh;  // -l12 / l11
+};
+
+__device__ __forceinline__ EllipseTest ellipse_test(const gsl_splat &s, float kq)
 {
-    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
-    const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
-    const float cc = l12 * l12 + l22 * l22;
+    EllipseTest e;
+    e.mx = s.mx;
+    e.my = s.my;
+    e.l11 = s.l11;
+    e.l12 = s.l12;
+    e.l22 = s.l22;
+    e.kq = kq;
+    const float cc = s.l12 * s.l12 + s.l22 * s.l22;
+    e.kv = -(s.l11 * s.l12) / cc;
+    e.kh = -s.l12 / s.l11;
+    return e;
+}
+
+__device__ __forceinline__ bool ellipse_hits_rect(const EllipseTest &e, float x0, float x1, float y0, float y1)
+{
+    const bool in_x = e.mx >= x0 && e.mx <= x1, in_y = e.my >= y0 && e.my <= y1;
+    if (in_x && in_y) return true;
     float best = 3.0e38f;
-    // vertical edges: dx fixed, dy free in [dy0, dy1]
-    for (int e = 0; e < 2; e++) {
-        const float dx = e ? dx1 : dx0;
-        const float a = l11 * dx;
-        const float dy = fminf(fmaxf(-(a * l12) / cc, dy0), dy1);
-        const float u = a + l12 * dy, w = l22 * dy;
+    if (!in_x) {  // the vertical edge facing mu
+        const float dx = (e.mx < x0 ? x0 : x1) - e.mx;
+        const float dy = fminf(fmaxf(e.kv * dx, y0 - e.my), y1 - e.my);
+        const float u = e.l11 * dx + e.l12 * dy, w = e.l22 * dy;
+        best = u * u + w * w;
+    }
+    if (!in_y) {  // the horizontal edge facing mu
+        const float dy = (e.my < y0 ? y0 : y1) - e.my;
+        const float dx = fminf(fmaxf(e.kh * dy, x0 - e.mx), x1 - e.mx);
+        const float u = e.l11 * dx + e.l12 * dy, w = e.l22 * dy;
         best = fminf(best, u * u + w * w);
     }
-    // horizontal edges: dy fixed, dx free in [dx0, dx1]
-    for (int e = 0; e < 2; e++) {
-        const float dy = e ? dy1 : dy0;
-        const float b = l12 * dy, w = l22 * dy;
-        const float dx = fminf(fmaxf(-b / l11, dx0), dx1);
-        const float u = l11 * dx + b;
-        best = fminf(best, u * u + w * w);
-    }
-    return best <= kq;
+    return best <= e.kq;
 }
 
 // Pixel-centre rectangle of tile (tx, ty) clipped to a W x H image.
@@ -198,8 +217,10 @@ struct RenderArgs {
 void launch_render_fwd(const RenderArgs &a, hipStream_t s);
 void launch_render_bwd(const RenderArgs &a, hipStream_t s);
 // variant bit 0: persistent work queue (else one workgroup per item);
-// bit 1: items in a.order (heaviest first) rather than tile order
-constexpr int kVariants = 4;
+// bit 1: items in a.order (heaviest first) rather than tile order;
+// bit 2: one workgroup per item with contiguous runs of tiles per XCD
+// (variants 0..4 are the distinct ones)
+constexpr int kVariants = 5;
 void launch_render_fused(const RenderArgs &a, int variant, int num_cus, hipStream_t s);
 void launch_order_by_length(const uint32_t *ranges, int64_t T, uint32_t *order, hipStream_t s);
 // counts[3] (device, accumulated): forward pairs evaluated, contributors, backward pairs

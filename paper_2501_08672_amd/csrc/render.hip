@@ -322,10 +322,11 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const bool live = !done[k];
                 const bool hit = live && e.alpha >= amin;
+                cnt.eval(live);
+                if (!__any(hit)) continue;  // wave-uniform: nothing changes for this slot
                 const float Tn = ps.T[k] * (1.f - e.alpha);
                 const bool stop = hit && Tn < Tmin;
                 const bool acc = hit && !stop;
-                cnt.eval(live);
                 cnt.contrib(acc);
                 done[k] = done[k] || stop;
                 const float w = acc ? e.alpha * ps.T[k] : 0.f;
@@ -552,14 +553,27 @@ __device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<Geo
     bwd_walk<TS, NW>(a, ti, st, ps.T, ps.nwalk, v, s_max, hits);
 }
 
-template <int TS, int NW>
+// Item of workgroup b.  Workgroups are dispatched to the 8 XCDs round-robin
+// (b mod 8); with `xcd_chunks` each XCD gets a contiguous run of tiles
+// (b mod 8) * chunk + b / 8, so neighbouring tiles, which share most of
+// their splats, meet in the same L2.
+__device__ __forceinline__ int item_of_block(const RenderArgs &a, uint32_t b, bool xcd_chunks)
+{
+    if (a.order) return (int)a.order[b];
+    if (!xcd_chunks) return (int)b;
+    const uint32_t chunk = (uint32_t)((a.T_total + 7) / 8);
+    return (int)((b & 7u) * chunk + (b >> 3));
+}
+
+template <int TS, int NW, bool XCD>
 __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused(RenderArgs a)
 {
     __shared__ Stage<Geo<TS, NW>::CH> st;
     __shared__ uint32_t s_max;
     __shared__ float s_loss[NW];
     __shared__ uint32_t s_hits[NW][kHitWords];
-    const int t = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
+    const int t = item_of_block(a, blockIdx.x, XCD);
+    if (t >= a.T_total) return;  // padding of the XCD-chunked grid (uniform per workgroup)
     fused_item<TS, NW>(a, t, st, &s_max, s_loss, s_hits);
 }
 
@@ -681,8 +695,12 @@ void launch_fused_t(const RenderArgs &a, int variant, int num_cus, hipStream_t s
         int64_t g = (int64_t)num_cus * per_cu;
         if (g > a.T_total) g = a.T_total;
         hipLaunchKernelGGL((k_render_fused_persistent<TS, NW>), dim3((unsigned)g), dim3(Geo<TS, NW>::BS), 0, s, a);
+    } else if ((variant & 4) && !a.order) {
+        const int64_t g = 8 * ((a.T_total + 7) / 8);
+        hipLaunchKernelGGL((k_render_fused<TS, NW, true>), dim3((unsigned)g), dim3(Geo<TS, NW>::BS), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_render_fused<TS, NW>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s, a);
+        hipLaunchKernelGGL((k_render_fused<TS, NW, false>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s,
+                           a);
     }
 }
 

@@ -299,20 +299,19 @@ __global__ void k_gather_counts(const uint32_t *__restrict__ order, const int32_
 
 // Tiles a splat's alpha_min ellipse reaches, with the quarter-row band mask of
 // each (bit q: rows [q*T/4, (q+1)*T/4) of the tile).
-__device__ __forceinline__ bool tile_hit(const gsl_splat &s, const DevCam &cam, int tile, float kq, int tx, int ty,
+__device__ __forceinline__ bool tile_hit(const EllipseTest &e, const DevCam &cam, int tile, int tx, int ty,
                                          uint32_t *bands)
 {
     float rx0, rx1, ry0, ry1;
     tile_rect(tx, ty, tile, cam.W, cam.H, rx0, rx1, ry0, ry1);
-    if (!ellipse_hits_rect(s.mx, s.my, s.l11, s.l12, s.l22, kq, rx0, rx1, ry0, ry1)) return false;
+    if (!ellipse_hits_rect(e, rx0, rx1, ry0, ry1)) return false;
     if (bands) {
         const int q = tile / 4;
         uint32_t b = 0;
         for (int k = 0; k < 4; k++) {
             const float by0 = (float)(ty * tile + k * q) + 0.5f;
             const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1);
-            if (by0 <= by1 && ellipse_hits_rect(s.mx, s.my, s.l11, s.l12, s.l22, kq, rx0, rx1, by0, by1))
-                b |= 1u << k;
+            if (by0 <= by1 && ellipse_hits_rect(e, rx0, rx1, by0, by1)) b |= 1u << k;
         }
         *bands = b;
     }
@@ -332,12 +331,13 @@ __device__ __forceinline__ uint32_t lane_record_tiles(const gsl_splat &s, const 
                                                       uint32_t base, uint32_t limit, uint32_t i,
                                                       uint32_t *tile_ids, uint32_t *gauss_ids)
 {
+    const EllipseTest e = ellipse_test(s, kq);
     const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
     uint32_t n = 0;
     for (int ty = ty0; ty <= ty1; ty++)
         for (int tx = tx0; tx <= tx1; tx++) {
             uint32_t bands = 0;
-            if (!tile_hit(s, cam, tile, kq, tx, ty, emit ? &bands : nullptr)) continue;
+            if (!tile_hit(e, cam, tile, tx, ty, emit ? &bands : nullptr)) continue;
             if (emit && n < limit) {  // never beyond the record's counted range
                 tile_ids[base + n] = (uint32_t)(cam.tile_offset + ty * cam.tiles_x + tx);
                 gauss_ids[base + n] = i | (bands << kGidBits);
@@ -352,6 +352,7 @@ __device__ __forceinline__ uint32_t wave_record_tiles(const gsl_splat &s, const 
                                                       int lane, uint32_t base, uint32_t limit, uint32_t i,
                                                       uint32_t *tile_ids, uint32_t *gauss_ids)
 {
+    const EllipseTest e = ellipse_test(s, kq);
     const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
     const int nx = tx1 - tx0 + 1, nt = nx * (ty1 - ty0 + 1);
     uint32_t n = 0;
@@ -363,7 +364,7 @@ __device__ __forceinline__ uint32_t wave_record_tiles(const gsl_splat &s, const 
         if (t < nt) {
             ty = ty0 + t / nx;
             tx = tx0 + t - (ty - ty0) * nx;
-            hit = tile_hit(s, cam, tile, kq, tx, ty, emit ? &bands : nullptr);
+            hit = tile_hit(e, cam, tile, tx, ty, emit ? &bands : nullptr);
         }
         const uint64_t mask = __ballot(hit);
         if (emit && hit) {

@@ -336,6 +336,11 @@ class Window:
             A.lib().gsl_profile(self.ctx.h, 0)
         return [float(x) for x in ms]
 
+    def set_variant(self, variant: int):
+        """Pin the fused-kernel variant for this window's shapes (see gsl_window_variant)."""
+        A.check(A.lib().gsl_window_variant(self.ctx.h, self.cams.arr, self.cams.C, self.g.N, int(self.opts.tile),
+                                           int(variant)))
+
     def status(self) -> int:
         return int(self.bins.d_status.item())
 
@@ -345,12 +350,12 @@ class Window:
         save = self.opts
         self.opts = o8
         self._alloc(None)  # capacity and ranges for tile 8 bound every tile size
-        times = (C.c_float * 12)()
+        times = (C.c_float * 15)()
         gs, ps, bs, gr = self.g.struct(), self.proj.struct(), self.bins.struct(), self.grads.struct()
         ot = _opts_copy(save)
         A.check(A.lib().gsl_window_tune(self.ctx.h, C.byref(gs), self.cams.arr, self.cams.C, C.byref(ot),
                                         _p(self.target), self.loss, C.byref(ps), C.byref(bs), _p(self.d_loss),
-                                        C.byref(gr), _p(self.ws), self.ws.numel(), times, 12, _stream()))
+                                        C.byref(gr), _p(self.ws), self.ws.numel(), times, 15, _stream()))
         self.opts = ot
         self._alloc(None)
         return int(ot.tile), [float(t) for t in times]

@@ -11,7 +11,8 @@ from scipy.spatial.transform import Rotation
 import scenegen as S
 from scenegen import Camera
 
-from gpuutil import (compare_grads, compare_images, context, gpu_backward, gpu_forward, ops, unpack_np)
+from gpuutil import (compare_grads, compare_images, context, gpu_backward, gpu_forward, ops, pixel_tolerance,
+                     unpack_np)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -90,23 +91,24 @@ F32 = np.float32
 
 def _ellipse_hits_f32(mx, my, l11, l12, l22, kq, x0, x1, y0, y1):
     """CPU recount of the binning rule in float32 (same operations, same order
-    as the kernel): minimum of |L d|^2 over a rectangle of pixel centres.
-    Returns (hit, best) so callers can spot exact-boundary cases."""
-    inside = (mx >= x0) & (mx <= x1) & (my >= y0) & (my <= y1)
-    dx0, dx1, dy0, dy1 = x0 - mx, x1 - mx, y0 - my, y1 - my
+    as the kernel): minimum of |L d|^2 over a rectangle of pixel centres,
+    evaluated on the edges that face the centre.  Returns (hit, best) so
+    callers can spot exact-boundary cases."""
     cc = l12 * l12 + l22 * l22
-    best = np.full(np.shape(mx), F32(3.0e38), F32)
-    for dx in (dx0, dx1):
-        a = l11 * dx
-        dy = np.minimum(np.maximum(-(a * l12) / cc, dy0), dy1)
-        u, w = a + l12 * dy, l22 * dy
-        best = np.minimum(best, u * u + w * w)
-    for dy in (dy0, dy1):
-        b, w = l12 * dy, l22 * dy
-        dx = np.minimum(np.maximum(-b / l11, dx0), dx1)
-        u = l11 * dx + b
-        best = np.minimum(best, u * u + w * w)
-    best = np.where(inside, F32(0), best)
+    kv = -(l11 * l12) / cc
+    kh = -l12 / l11
+    in_x = (mx >= x0) & (mx <= x1)
+    in_y = (my >= y0) & (my <= y1)
+    best = np.full(np.shape(x0), F32(3.0e38), F32)
+    dx = np.where(mx < x0, x0, x1) - mx
+    dy = np.minimum(np.maximum(kv * dx, y0 - my), y1 - my)
+    u, w = l11 * dx + l12 * dy, l22 * dy
+    best = np.where(in_x, best, u * u + w * w)
+    dy = np.where(my < y0, y0, y1) - my
+    dx = np.minimum(np.maximum(kh * dy, x0 - mx), x1 - mx)
+    u, w = l11 * dx + l12 * dy, l22 * dy
+    best = np.where(in_y, best, np.minimum(best, u * u + w * w))
+    best = np.where(in_x & in_y, F32(0), best)
     return best <= kq, best
 
 
@@ -243,7 +245,7 @@ def test_render_fwd_multicam_background(oracle):
     imgs = unpack_np(st["cams"], st["image"])
     for c, cam in enumerate(sc.cams):
         r = oracle.render_image(sc, cam, oracle.Opts(bg=bg))
-        compare_images(imgs[c], r["image"], r["flags"], name=f"cam{c}")
+        compare_images(imgs[c], r["image"], r["flags"], name=f"cam{c}", bg=bg)
 
 
 def test_render_last_contributor_matches(oracle):
@@ -294,10 +296,10 @@ def test_render_config2_sampled(oracle):
     pix = np.stack([rng.integers(0, cam.width, 3000), rng.integers(0, cam.height, 3000)], 1).astype(np.int32)
     r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
     got = img[:, pix[:, 1], pix[:, 0]]
-    ok = (r["flags"] & 1) == 0
-    err = np.abs(got.T - r["rgb"])[ok]
-    assert err.max() <= 1e-4, err.max()
-    assert (~ok).sum() <= 0.01 * len(ok)
+    tl = pixel_tolerance(r["flags"])
+    err = np.abs(got.T - r["rgb"]).max(1)
+    assert np.all(err <= tl), (err - tl).max()
+    assert np.isinf(tl).sum() <= 0.01 * len(tl)
 
 
 def test_render_empty_and_degenerate():
@@ -327,7 +329,7 @@ def _cotangent(oracle, sc, cams, seed, o_kw=None):
     for cam in cams:
         r = oracle.render_image(sc, cam, oracle.Opts(**(o_kw or {})))
         v = rng.normal(size=(3, cam.height, cam.width))
-        v[:, r["flags"] != 0] = 0.0
+        v[:, (r["flags"] & 3) != 0] = 0.0  # alpha-threshold or clamp ambiguity
         vs.append(v)
     return vs
 
@@ -377,7 +379,7 @@ def test_render_bwd_config2_sampled(oracle):
     pix = np.stack([rng.integers(0, cam.width, 400), rng.integers(0, cam.height, 400)], 1).astype(np.int32)
     pix = np.unique(pix, axis=0)
     r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
-    pix = pix[r["flags"] == 0]
+    pix = pix[(r["flags"] & 3) == 0]
     v = rng.normal(size=(len(pix), 3))
     vimg = np.zeros((3, cam.height, cam.width), np.float32)
     vimg[:, pix[:, 1], pix[:, 0]] = v.T
@@ -449,6 +451,26 @@ def test_window_graph_replay_and_variants():
     w.step(use_graph=True)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(w.image.cpu().numpy(), ref[3].cpu().numpy())
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_window_variants_agree(tile):
+    """Every fused-kernel variant (plain, persistent, longest first, both,
+    XCD-chunked) gives the same image, loss and gradients."""
+    sc = _scene_multi(3000, 43)
+    tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda")
+    w = _window(sc, tgt, tile, "l1")
+    res = []
+    for variant in range(5):
+        w.set_variant(variant)
+        w.step(use_graph=False)
+        torch.cuda.synchronize()
+        res.append((w.image.clone(), float(w.d_loss.item()), w.grads.mean.clone(), w.grads.pose.clone()))
+    for img, loss, gm, gp in res[1:]:
+        assert torch.equal(img, res[0][0])
+        assert abs(loss - res[0][1]) <= 1e-9 * abs(res[0][1])
+        torch.testing.assert_close(gm, res[0][2], rtol=1e-5, atol=1e-6 * float(res[0][2].abs().max()))
+        torch.testing.assert_close(gp, res[0][3], rtol=1e-5, atol=1e-9)
 
 
 def test_rasterize_autograd():

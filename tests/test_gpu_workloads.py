@@ -14,7 +14,7 @@ import pytest
 
 import scenegen as S
 
-from gpuutil import compare_grads, context, gpu_backward, gpu_forward, ops, unpack_np
+from gpuutil import compare_grads, context, gpu_backward, gpu_forward, ops, pixel_tolerance, unpack_np
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -47,7 +47,7 @@ def test_pose_batch_vs_oracle(oracle, pose_batch):
         if c in sel:
             pix = _sample(cam, 96, rng)
             r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
-            pix = pix[r["flags"] == 0]
+            pix = pix[(r["flags"] & 3) == 0]
             res = imgs[c][:, pix[:, 1], pix[:, 0]] - I_true[:, pix[:, 1], pix[:, 0]]
             v[:, pix[:, 1], pix[:, 0]] = res
             vs.append(res.T.astype(np.float64))
@@ -63,38 +63,40 @@ def test_pose_batch_vs_oracle(oracle, pose_batch):
 
 def test_pose_batch_vs_twist_differences(pose_batch):
     """Directional central differences of L(xi) = 1/2 sum (I(Exp(xi) T) - I_true)^2
-    with the GPU forward.  L has jumps where a Gaussian crosses the 1/255
-    skip or the cutoff at some pixel; the analytic gradient is the derivative
-    of its smooth part.  Pixels whose second difference shows a jump are
-    therefore left out of both sides: the FD of the remaining pixels' loss is
-    compared with the gradient of the same pixels' loss."""
+    with the GPU forward.  L jumps wherever a Gaussian crosses the 1/255 skip
+    or the cutoff at some pixel, and the analytic gradient is the derivative
+    of its smooth part; so the check is made on the pixels whose central
+    differences at steps h and 2h agree (no jump within +-2h), with the
+    gradient taken for the loss of those same pixels."""
     sc, true_cam, cams, tw, I_true, st = pose_batch
     imgs = unpack_np(st["cams"], st["image"])
     rng = np.random.default_rng(2)
-    h = 1.0
     for c in (0, 7):
         d = rng.normal(size=6)
-        d[:3] *= 2e-4 / np.linalg.norm(d[:3])
-        d[3:] *= 4e-4 / np.linalg.norm(d[3:])
+        d[:3] *= 1e-4 / np.linalg.norm(d[:3])
+        d[3:] *= 2e-4 / np.linalg.norm(d[3:])
 
-        def render(sgn):
-            cam = S.perturb_camera(cams[c], sgn * h * d[:3], sgn * h * d[3:])
+        def render(h):
+            cam = S.perturb_camera(cams[c], h * d[:3], h * d[3:])
             s2 = gpu_forward(sc, [cam], tile=16)
             return unpack_np(s2["cams"], s2["image"])[0].astype(np.float64)
 
-        I0, Ip, Im = imgs[c].astype(np.float64), render(1.0), render(-1.0)
-        smooth = np.abs(Ip + Im - 2 * I0).max(0) <= 2e-5
-        assert smooth.mean() > 0.9, smooth.mean()
-        fd = (0.5 * (((Ip - I_true) ** 2)[:, smooth]).sum() - 0.5 * (((Im - I_true) ** 2)[:, smooth]).sum()) / (2 * h)
+        I0 = imgs[c].astype(np.float64)
+        D1 = (render(1.0) - render(-1.0)) / 2.0
+        D2 = (render(2.0) - render(-2.0)) / 4.0
+        smooth = (np.abs(D1 - D2) <= 0.05 * np.abs(D1) + 1e-6).all(0)
+        assert smooth.mean() > 0.5, smooth.mean()
+        r = I0 - I_true
+        fd = float((r * D1)[:, smooth].sum())
         v = []
         for k, cam in enumerate(cams):
             vk = np.zeros((3, cam.height, cam.width), np.float32)
             if k == c:
-                vk[:, smooth] = (I0 - I_true)[:, smooth]
+                vk[:, smooth] = r[:, smooth]
             v.append(vk.ravel())
         gg = gpu_backward(st, torch.from_numpy(np.concatenate(v)).cuda())
         an = float(gg["pose"][c] @ d)
-        assert abs(fd - an) <= 1e-2 * abs(an) + 1e-6, (c, fd, an, smooth.mean())
+        assert abs(fd - an) <= 1e-2 * abs(an), (c, fd, an, smooth.mean())
 
 
 def test_window_500k_sampled(oracle):
@@ -106,10 +108,9 @@ def test_window_500k_sampled(oracle):
     for c, cam in enumerate(sc.cams):
         pix = _sample(cam, 48, rng)
         r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
-        ok = (r["flags"] & 1) == 0
         got = imgs[c][:, pix[:, 1], pix[:, 0]].T
-        assert np.abs(got - r["rgb"])[ok].max() <= 1e-4
-        pix = pix[r["flags"] == 0]
+        assert np.all(np.abs(got - r["rgb"]).max(1) <= pixel_tolerance(r["flags"]))
+        pix = pix[(r["flags"] & 3) == 0]
         v = rng.normal(size=(len(pix), 3))
         vi = np.zeros((3, cam.height, cam.width), np.float32)
         vi[:, pix[:, 1], pix[:, 0]] = v.T
@@ -136,9 +137,9 @@ def test_uneven_batch_sampled(oracle, uneven):
         cam = sc.cams[c]
         pix = _sample(cam, 24, rng)
         r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
-        ok = (r["flags"] & 1) == 0
         got = imgs[c][:, pix[:, 1], pix[:, 0]].T
-        assert np.abs(got - r["rgb"])[ok].max() <= 1e-4, c
+        assert np.all(np.abs(got - r["rgb"]).max(1) <= pixel_tolerance(r["flags"])), c
+        assert (r["flags"] & 1).sum() <= len(pix) // 4 + 1
 
 
 def test_uneven_batch_window_vs_per_camera(uneven):
@@ -163,7 +164,10 @@ def test_uneven_batch_window_vs_per_camera(uneven):
         w1.step(use_graph=False)
         torch.cuda.synchronize()
         assert torch.equal(w1.image, cs.unpack(w.image)[c].reshape(-1))
-        torch.testing.assert_close(w1.grads.pose[0], w.grads.pose[c], rtol=1e-5, atol=1e-9)
+        # the 2D gradients are summed with float atomics in a different order;
+        # the pose is a sum over all Gaussians with cancellation
+        scale = float(w.grads.pose[c].abs().max())
+        torch.testing.assert_close(w1.grads.pose[0], w.grads.pose[c], rtol=1e-4, atol=1e-4 * scale)
         tot_mean += w1.grads.mean
         loss += float(w1.d_loss.item())
         del w1
