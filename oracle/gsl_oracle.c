@@ -586,6 +586,136 @@ int orc_render_bwd(int64_t N, const double *mean, const double *scale, const dou
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* forward-mode derivative with respect to the camera twist                 */
+/* ------------------------------------------------------------------------ */
+
+/* Derivatives of one Gaussian's 2D mean and conic along the six twist
+ * directions (dphi_x, dphi_y, dphi_z, dt_x, dt_y, dt_z) of the left
+ * perturbation T_CW <- Exp(dphi, dt) T_CW, to first order
+ * p_C <- p_C + dphi x p_C + dt and W <- W + dphi^ W (the chains of eqs.
+ * eqn:grad_meani_rcw ... eqn:grad_covi_tcw, taken forward).  dmu[2][6] and
+ * dQ[3][6] (rows A, B, C of the conic), row-major. */
+static void project_tangent(const proj_t *p, const orc_camera *cam, double dmu[12], double dQ[18])
+{
+    const double x = p->pC[0], y = p->pC[1], z = p->pC[2];
+    const double fx = cam->fx, fy = cam->fy;
+    const double Qm[4] = {p->Q[0], p->Q[1], p->Q[1], p->Q[2]};
+    double Jt[6];
+    transpose(p->J, Jt, 2, 3);
+    for (int k = 0; k < 6; k++) {
+        double e[3] = {0, 0, 0}, dp[3] = {0, 0, 0};
+        if (k < 3) { /* rotation about axis k: dp = e x p_C */
+            e[k] = 1;
+            dp[0] = e[1] * z - e[2] * y;
+            dp[1] = e[2] * x - e[0] * z;
+            dp[2] = e[0] * y - e[1] * x;
+        } else { /* translation along axis k - 3 */
+            dp[k - 3] = 1;
+        }
+        /* mu = (fx x / z + cx, fy y / z + cy):  dmu = J dp */
+        dmu[k] = p->J[0] * dp[0] + p->J[1] * dp[1] + p->J[2] * dp[2];
+        dmu[6 + k] = p->J[3] * dp[0] + p->J[4] * dp[1] + p->J[5] * dp[2];
+        /* J(p_C) moves with p_C */
+        double dJ[6] = {-fx * dp[2] / (z * z), 0, -fx * (dp[0] / (z * z) - 2 * x * dp[2] / (z * z * z)),
+                        0, -fy * dp[2] / (z * z), -fy * (dp[1] / (z * z) - 2 * y * dp[2] / (z * z * z))};
+        /* M3 = W Sigma3 W^T with dW = E W, E = [e]x:  dM3 = E M3 - M3 E */
+        double dM3[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (k < 3) {
+            double E[9] = {0, -e[2], e[1], e[2], 0, -e[0], -e[1], e[0], 0}, A1[9], A2[9];
+            matmul(E, p->M3, A1, 3, 3, 3);
+            matmul(p->M3, E, A2, 3, 3, 3);
+            for (int m = 0; m < 9; m++) dM3[m] = A1[m] - A2[m];
+        }
+        /* Sigma2D = J M3 J^T + eps I:  dSigma2D = dJ M3 J^T + J dM3 J^T + J M3 dJ^T */
+        double dJt[6], t23[6], Sa[4], Sb[4], Sc[4], dS[4];
+        transpose(dJ, dJt, 2, 3);
+        matmul(dJ, p->M3, t23, 2, 3, 3);
+        matmul(t23, Jt, Sa, 2, 3, 2);
+        matmul(p->J, dM3, t23, 2, 3, 3);
+        matmul(t23, Jt, Sb, 2, 3, 2);
+        matmul(p->J, p->M3, t23, 2, 3, 3);
+        matmul(t23, dJt, Sc, 2, 3, 2);
+        for (int m = 0; m < 4; m++) dS[m] = Sa[m] + Sb[m] + Sc[m];
+        /* Q = Sigma2D^{-1}:  dQ = -Q dSigma2D Q */
+        double T1[4], T2[4];
+        matmul(Qm, dS, T1, 2, 2, 2);
+        matmul(T1, Qm, T2, 2, 2, 2);
+        dQ[k] = -T2[0];
+        dQ[6 + k] = -T2[1];
+        dQ[12 + k] = -T2[3];
+    }
+}
+
+/* dI/dxi of one pixel (jac[3][6], channel-major), with the contributor set
+ * held fixed: along the walk T_{k+1} = T_k (1 - a_k), so
+ * dT_{k+1} = dT_k (1 - a_k) - T_k da_k and the pixel gains
+ * c_k (T_k da_k + a_k dT_k); the background adds bg dT_final.  A clamped
+ * alpha has da = 0; otherwise da = a dpower with
+ * dpower = (Q d) . dmu - 1/2 d^T dQ d, d = x - mu. */
+static void pixel_tangent(double px, double py, int64_t M, const int64_t *order, const proj_t *proj,
+                          const double *opacity, const double *color, const orc_opts *o, const double *dmu_all,
+                          const double *dQ_all, contrib_t *list, double rgb[3], double jac[18])
+{
+    int32_t n;
+    composite_pixel(px, py, M, order, proj, opacity, color, o, 0.0, rgb, &n, NULL, NULL, list);
+    double dT[6] = {0, 0, 0, 0, 0, 0};
+    for (int m = 0; m < 18; m++) jac[m] = 0;
+    for (int32_t k = 0; k < n; k++) {
+        const contrib_t *e = &list[k];
+        const int64_t i = e->id;
+        const double *c = color + 3 * i, *Q = proj[i].Q;
+        const double *dmu = dmu_all + 12 * i, *dQ = dQ_all + 18 * i;
+        const double dx = e->dx, dy = e->dy;
+        double da[6] = {0, 0, 0, 0, 0, 0};
+        if (!e->clamped) {
+            const double gx = Q[0] * dx + Q[1] * dy, gy = Q[1] * dx + Q[2] * dy;
+            for (int j = 0; j < 6; j++) {
+                double dpow = gx * dmu[j] + gy * dmu[6 + j] -
+                              0.5 * (dQ[j] * dx * dx + 2.0 * dQ[6 + j] * dx * dy + dQ[12 + j] * dy * dy);
+                da[j] = e->alpha * dpow;
+            }
+        }
+        for (int j = 0; j < 6; j++) {
+            for (int ch = 0; ch < 3; ch++) jac[6 * ch + j] += c[ch] * (e->T * da[j] + e->alpha * dT[j]);
+            dT[j] = dT[j] * (1.0 - e->alpha) - e->T * da[j];
+        }
+    }
+    for (int ch = 0; ch < 3; ch++)
+        for (int j = 0; j < 6; j++) jac[6 * ch + j] += o->bg[ch] * dT[j];
+}
+
+/* Per-pixel Jacobian of the rendered colour with respect to the camera twist
+ * (dphi, dt) of the left perturbation of T_CW, for the listed pixels:
+ * jac (npix x 3 x 6), and the colour itself in rgb (npix x 3). */
+int orc_render_jvp(int64_t N, const double *mean, const double *scale, const double *quat,
+                   const double *opacity, const double *color, const orc_camera *cam, const orc_opts *o,
+                   int64_t npix, const int32_t *pix, double *rgb, double *jac)
+{
+    proj_t *proj;
+    int64_t *order;
+    int64_t M = build_order(N, mean, scale, quat, cam, o, &proj, &order);
+    double *dmu = (double *)calloc((size_t)(N > 0 ? N : 1) * 12, sizeof(double));
+    double *dQ = (double *)calloc((size_t)(N > 0 ? N : 1) * 18, sizeof(double));
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; i++)
+        if (proj[i].status & ORC_KEPT) project_tangent(&proj[i], cam, dmu + 12 * i, dQ + 18 * i);
+    #pragma omp parallel
+    {
+        contrib_t *list = (contrib_t *)malloc(sizeof(contrib_t) * (size_t)(M > 0 ? M : 1));
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < npix; p++)
+            pixel_tangent(pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5, M, order, proj, opacity, color, o, dmu, dQ, list,
+                          rgb + 3 * p, jac + 18 * p);
+        free(list);
+    }
+    free(dmu);
+    free(dQ);
+    free(proj);
+    free(order);
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

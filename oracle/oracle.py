@@ -89,6 +89,8 @@ def lib():
         L.orc_pixel_trace.argtypes = [C.c_int64, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
                                       C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.orc_pixel_trace.restype = C.c_int32
+        L.orc_render_jvp.argtypes = [C.c_int64, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
+                                     C.c_int64, P, P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -216,3 +218,71 @@ def pixel_trace(scene, cam, u, v, opts: Opts = Opts(), cap=100000):
     n = lib().orc_pixel_trace(scene.n, _p(m), _p(s), _p(q), _p(o), _p(c), C.byref(co), C.byref(oo),
                               int(u), int(v), cap, _p(ids), _p(al), _p(Ts))
     return ids[:n].copy(), al[:n].copy(), Ts[:n].copy()
+
+
+# ---------------------------------------------------------------- pose Jacobians and the IESKF update
+
+def render_jvp(scene, cam, opts: Opts = Opts(), pixels=None):
+    """Per-pixel Jacobian of the rendered colour with respect to the camera
+    twist xi = (dphi, dt) of the left perturbation T_CW <- Exp(xi) T_CW
+    (contributor sets held fixed).  Returns rgb (P,3), jac (P,3,6), pixels."""
+    pix = all_pixels(cam) if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+    P = pix.shape[0]
+    m, s, q, o, c = _params(scene)
+    rgb = np.zeros((P, 3))
+    jac = np.zeros((P, 3, 6))
+    co, oo = _cam(cam), opts.c()
+    lib().orc_render_jvp(scene.n, _p(m), _p(s), _p(q), _p(o), _p(c), C.byref(co), C.byref(oo), P, _p(pix),
+                         _p(rgb), _p(jac))
+    return {"rgb": rgb, "jac": jac, "pixels": pix}
+
+
+def normal_equations(jac, residual, weight=None):
+    """H^T R^-1 H (6,6) and H^T R^-1 z (6,) of the stacked measurement model
+    z_p + H_p xi (Appendix A, IESKF update): one row per pixel and channel,
+    H_p = jac[p] (3,6), z_p = residual[p] (3,), R^-1 = diag(weight[p]) per
+    pixel (1 when None).  Also returns z^T R^-1 z."""
+    jac = np.asarray(jac, np.float64).reshape(-1, 3, 6)
+    z = np.asarray(residual, np.float64).reshape(-1, 3)
+    w = np.ones(len(z)) if weight is None else np.asarray(weight, np.float64).reshape(-1)
+    H = jac.reshape(-1, 6)
+    zz = z.reshape(-1)
+    ww = np.repeat(w, 3)
+    return H.T @ (ww[:, None] * H), H.T @ (ww * zz), float(zz @ (ww * zz))
+
+
+def skew(v):
+    v = np.asarray(v, np.float64)
+    return np.array([[0, -v[2], v[1]], [v[2], 0, -v[0]], [-v[1], v[0], 0]])
+
+
+def imu_to_camera_twist(R_CI, t_CI, R_CW):
+    """A (6,6) with xi_cam = A xi_imu, to first order, from the perturbation
+    model (Appendix A): (T(xi_c) T_CW)^-1 T_CI = T_WI [+] T(xi_i), where the
+    IMU pose is perturbed as (R_WI Exp(dphi_i), t_WI + dt_i).  Rotation:
+    dphi_c = -R_CI dphi_i.  Translation: R_WC (t_CI^ dphi_c - dt_c) = dt_i."""
+    R_CI = np.asarray(R_CI, np.float64).reshape(3, 3)
+    R_CW = np.asarray(R_CW, np.float64).reshape(3, 3)
+    A = np.zeros((6, 6))
+    A[:3, :3] = -R_CI
+    A[3:, :3] = skew(t_CI) @ A[:3, :3]
+    A[3:, 3:] = -R_CW
+    return A
+
+
+def ieskf_pose_update(HtRH, HtRz, P_prior, x_minus_prior=None):
+    """One IESKF update of a pose state from the normal equations (Appendix A):
+    K = (H^T R^-1 H + P^-1)^-1 H^T R^-1,
+    delta = -K z - (I - K H) (x_hat [-] x_bar),  Sigma = (I - K H) P,
+    with the Jacobian of [-] taken as the identity.  K z and K H are formed
+    from H^T R^-1 z and H^T R^-1 H."""
+    HtRH = np.asarray(HtRH, np.float64)
+    HtRz = np.asarray(HtRz, np.float64)
+    P = np.asarray(P_prior, np.float64)
+    n = P.shape[0]
+    Ainv = np.linalg.inv(HtRH + np.linalg.inv(P))
+    KH = Ainv @ HtRH
+    Kz = Ainv @ HtRz
+    dx = np.zeros(n) if x_minus_prior is None else np.asarray(x_minus_prior, np.float64)
+    delta = -Kz - (np.eye(n) - KH) @ dx
+    return delta, (np.eye(n) - KH) @ P

@@ -432,3 +432,122 @@ def test_alpha_threshold_flip_bound(oracle):
             assert oracle.render(sc, cam, oracle.Opts(amb_ignore=0.0), pixels=pix)["flags"][0] & 1
         else:
             assert lo["flags"][0] & 1 and hi["flags"][0] & 1
+
+
+# ---------------------------------------------------------------- pose Jacobians and the IESKF update
+
+def _twist_scene(seed):
+    Rc = Rotation.from_rotvec([0.1, -0.2, 0.05]).as_matrix()
+    cam0 = Camera(18.0, 19.0, 10.0, 8.0, 20, 16, Rc, [0.1, -0.05, 0.2])
+    sc = S.random_scene(10, cam0, seed=seed, zmin=1.0, zmax=2.0, smin=0.08, smax=0.3)
+    sc.opacity[:] = np.float32(0.3) + np.float32(0.5) * sc.opacity
+    return sc, cam0
+
+
+def test_pose_jvp_matches_twist_differences(oracle):
+    """Per-pixel dI/d(dphi, dt) against central differences of the rendered
+    colour under T_CW <- Exp(dphi, dt) T_CW (exponential from scipy), on the
+    pixels where the steps h and 2h agree (no threshold crossed)."""
+    sc, cam0 = _twist_scene(9)
+    o = oracle.Opts(bg=(0.2, 0.1, 0.3))
+    J = oracle.render_jvp(sc, cam0, o)
+    flags = oracle.render(sc, cam0, o)["flags"]
+
+    def cam_at(xi):
+        E = _rodrigues(xi[:3])
+        return Cam64(cam0, E @ cam0.R_cw.astype(np.float64), E @ cam0.t_cw.astype(np.float64) + xi[3:])
+
+    h = 1e-6
+    checked = 0
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        fd1 = (oracle.render(sc, cam_at(e), o)["rgb"] - oracle.render(sc, cam_at(-e), o)["rgb"]) / (2 * h)
+        fd2 = (oracle.render(sc, cam_at(2 * e), o)["rgb"] - oracle.render(sc, cam_at(-2 * e), o)["rgb"]) / (4 * h)
+        smooth = (np.abs(fd1 - fd2).max(1) <= 1e-4 * (1 + np.abs(fd1).max(1))) & (flags == 0)
+        scale = np.abs(fd1[smooth]).max()
+        np.testing.assert_allclose(J["jac"][smooth, :, k], fd1[smooth], rtol=1e-4, atol=1e-6 * scale)
+        checked += int(smooth.sum())
+    assert checked > 0.8 * 6 * cam0.width * cam0.height
+
+
+@pytest.mark.parametrize("seed", [3, 17])
+def test_pose_jvp_adjoint_identity(oracle, seed):
+    """Forward and reverse mode are two separate derivations of one Jacobian:
+    sum_p <v_p, dI_p/dxi> equals the pose gradient of L = sum_p <v_p, I_p>
+    for any cotangent v, with background, clamped alphas and cut-off walks."""
+    rng = np.random.default_rng(seed)
+    Rc = Rotation.from_rotvec(rng.normal(0, 0.2, 3)).as_matrix()
+    cam = Cam64(Camera(30.0, 33.0, 16.0, 12.0, 32, 24, Rc, [0, 0, 0]), Rc, rng.normal(0, 0.2, 3))
+    sc = S.random_scene(120, cam, seed=seed, zmin=1.0, zmax=3.0, smin=0.05, smax=0.3, unnormalised_quats=True)
+    sc.opacity[:20] = 0.999  # clamped at 0.99 near their centres
+    o = oracle.Opts(bg=(0.3, 0.6, 0.1))
+    J = oracle.render_jvp(sc, cam, o)
+    r = oracle.render(sc, cam, o)
+    assert np.array_equal(J["rgb"], r["rgb"])
+    v = rng.normal(size=(cam.width * cam.height, 3))
+    g = oracle.render_bwd(sc, [cam], [v], o)["pose"][0]
+    lhs = np.einsum("pc,pcj->j", v, J["jac"])
+    np.testing.assert_allclose(lhs, g, rtol=1e-9, atol=1e-12 * np.abs(g).max())
+
+
+def test_imu_to_camera_twist_matches_perturbation_model(oracle):
+    """xi_cam = A xi_imu against central differences of the exact relation
+    T(xi_c) T_CW = T_CI (T_WI [+] xi_i)^-1 with (R_WI Exp(dphi), t_WI + dt)."""
+    rng = np.random.default_rng(5)
+    R_CI = _rodrigues(rng.normal(0, 1, 3))
+    t_CI = rng.normal(0, 0.3, 3)
+    R_WI = _rodrigues(rng.normal(0, 1, 3))
+    t_WI = rng.normal(0, 2, 3)
+
+    def T_CW_of(R_wi, t_wi):
+        # T_CW = T_CI T_WI^-1
+        R_iw, t_iw = R_wi.T, -R_wi.T @ t_wi
+        return R_CI @ R_iw, R_CI @ t_iw + t_CI
+
+    R_CW, t_CW = T_CW_of(R_WI, t_WI)
+    A = oracle.imu_to_camera_twist(R_CI, t_CI, R_CW)
+
+    def xi_c(xi_i):
+        Rp, tp = T_CW_of(R_WI @ _rodrigues(xi_i[:3]), t_WI + xi_i[3:])
+        E = Rp @ R_CW.T
+        phi = Rotation.from_matrix(E).as_rotvec()
+        return np.concatenate([phi, tp - E @ t_CW])
+
+    h = 1e-6
+    fd = np.zeros((6, 6))
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        fd[:, k] = (xi_c(e) - xi_c(-e)) / (2 * h)
+    np.testing.assert_allclose(A, fd, atol=1e-7)
+
+
+def test_ieskf_update_matches_gain_form(oracle):
+    """The information-form update from H^T R^-1 H and H^T R^-1 z equals the
+    gain form K = P H^T (H P H^T + R)^-1 on an explicit stacked model, and
+    the posterior covariance equals (H^T R^-1 H + P^-1)^-1."""
+    rng = np.random.default_rng(11)
+    m = 40
+    H = rng.normal(size=(m, 6))
+    Rd = rng.uniform(0.5, 2.0, m)
+    z = rng.normal(size=m)
+    L = rng.normal(size=(6, 6))
+    P = L @ L.T + 0.5 * np.eye(6)
+    dxp = rng.normal(0, 0.1, 6)
+    HtRH = H.T @ (H / Rd[:, None])
+    HtRz = H.T @ (z / Rd)
+    delta, Pn = oracle.ieskf_pose_update(HtRH, HtRz, P, dxp)
+    K = P @ H.T @ np.linalg.inv(H @ P @ H.T + np.diag(Rd))
+    np.testing.assert_allclose(delta, -K @ z - (np.eye(6) - K @ H) @ dxp, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Pn, (np.eye(6) - K @ H) @ P, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Pn, np.linalg.inv(HtRH + np.linalg.inv(P)), rtol=1e-9, atol=1e-12)
+    # the normal equations of the oracle's per-pixel form agree with the explicit stacking
+    jac = H[: 3 * (m // 3)].reshape(-1, 3, 6)
+    res = z[: 3 * (m // 3)].reshape(-1, 3)
+    w = rng.uniform(0.5, 2.0, m // 3)
+    A, b, zz = oracle.normal_equations(jac, res, w)
+    Hs = jac.reshape(-1, 6)
+    ws = np.repeat(w, 3)
+    np.testing.assert_allclose(A, sum(ws[i] * np.outer(Hs[i], Hs[i]) for i in range(len(ws))), rtol=1e-12)
+    np.testing.assert_allclose(b, sum(ws[i] * Hs[i] * res.reshape(-1)[i] for i in range(len(ws))), rtol=1e-12)
