@@ -16,6 +16,8 @@ Prints one JSON line; besides the metric it carries
                     FLOPs from the pair counts / its duration (HIP events on
                     its stream) against the FP32 vector peak
   cpu_baseline      the FP64 oracle, forward + backward, on a pixel sample
+  pose_jacobian     the IESKF measurement model (per-pixel twist Jacobians and
+                    normal equations) on 32 perturbed poses of a 640x512 view
 """
 import argparse
 import hashlib
@@ -35,6 +37,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 4 SIMD x 16 lane
 # compositing and its adjoint (add/mul/min/exp = 1, fma = 2):
 F_EVAL = 13        # alpha of one pair (forward walk, and again in the backward walk)
 F_CONTRIB = 52     # a contributor: 9 in the forward, 43 in the backward
+F_JVP_CONTRIB = 145  # a contributor in the forward-mode pose walk: 9 colour + 136 for the 6 twist tangents
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_render_traffic.txt")
 RENDER_SRC = os.path.join(ROOT, "paper_2501_08672_amd", "csrc", "render.hip")
 
@@ -53,6 +56,7 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=320, help="oracle sample: pixels per camera")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--no-jac", action="store_true", help="skip the pose-Jacobian measurement")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration runs)")
     return ap.parse_args()
@@ -105,6 +109,51 @@ def cpu_baseline(sc, cams, per_cam, seed=0):
             "sample": f"{per_cam} seeded pixels per camera x {len(cams)} cameras of the same window; forward "
                       f"{t1 - t0:.2f} s + backward (random cotangent on those pixels) {t2 - t1:.2f} s; each call "
                       f"projects and depth-orders all {sc.n} Gaussians"}
+
+
+def pose_jacobian_bench(ctx, ops, S, torch, reps=5):
+    """The IESKF measurement model on a batch of 32 perturbed poses of one
+    view (200k surfels on 20 planes, 640x512): project + bin_sort +
+    gsl_pose_jacobian (per-pixel twist Jacobians and the per-camera normal
+    equations against the image at the true pose)."""
+    sc, true_cam, cams, _ = S.config4()
+    g = ops.Gaussians.from_scene(sc)
+    c1 = ops.CameraSet([true_cam])
+    o = ops.opts(16)
+    p1 = ops.project(ctx, g, c1, o)
+    b1 = ops.bin_sort(ctx, c1, g.N, o, p1)
+    img, _, _ = ops.render_fwd(ctx, c1, g.N, o, p1, b1)
+    cs = ops.CameraSet(cams)
+    target = img.repeat(cs.C).contiguous()
+    proj = ops.project(ctx, g, cs, o)
+    bins = ops.bin_sort(ctx, cs, g.N, o, proj)
+    ops.pose_jacobian(ctx, g, cs, o, proj, bins, target=target)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    t_all, t_jac = [], []
+    for _ in range(reps):
+        e0.record()
+        ops.project(ctx, g, cs, o, out=proj)
+        ops.bin_sort(ctx, cs, g.N, o, proj, capacity=bins.capacity, bins=bins, grow=False)
+        e1.record()
+        pj = ops.pose_jacobian(ctx, g, cs, o, proj, bins, target=target)
+        e2.record()
+        torch.cuda.synchronize()
+        t_all.append(e0.elapsed_time(e2))
+        t_jac.append(e1.elapsed_time(e2))
+    ms, jac_ms = float(np.median(t_all)), float(np.median(t_jac))
+    ev_f, n_contrib, _ = ops.render_stats(ctx, cs, g.N, o, proj, bins)
+    flops = F_EVAL * ev_f + F_JVP_CONTRIB * n_contrib
+    P = cs.P_total
+    ach = flops / (jac_ms * 1e-3) / 1e12
+    return {"workload": "IESKF photometric model: 200k surfels on 20 planes, 32 perturbed poses of a 640x512 view "
+                        "(0.05 m, 1 deg), per-pixel twist Jacobians + per-camera normal equations",
+            "ms_per_batch": round(ms, 4), "mpix_s": round(P / (ms * 1e-3) / 1e6, 2),
+            "jacobian_ms": round(jac_ms, 4), "tile": 16, "instances_K": bins.K,
+            "alu": {"achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "pairs": {"evaluated": ev_f, "contributors": n_contrib}},
+            "residual_rms": round(float(np.sqrt(pj.zz.sum().item() / (3 * P))), 5)}
 
 
 def main():
@@ -223,6 +272,11 @@ def main():
         log(f"per-frame plain launches {t_pf * 1e3:.3f} ms per window ({P / t_pf / 1e6:.1f} Mpix/s)")
         del frames
 
+    pose_jac = None
+    if not args.no_jac:
+        pose_jac = pose_jacobian_bench(ctx, ops, S, torch)
+        log(f"pose Jacobian batch: {pose_jac}")
+
     traffic = read_traffic()
     result = {
         "metric": "fwd+bwd Mpixels/s at 500k Gaussians, 8-frame window; fwd ms/frame",
@@ -257,6 +311,8 @@ def main():
         "window_hbm": {"algorithmic_bytes": int(step_bytes),
                        "frac": round(step_bytes / t_win / 1e9 / HBM_PEAK_GBS, 4)},
     }
+    if pose_jac is not None:
+        result["pose_jacobian"] = pose_jac
     if tune_times is not None:
         result["autotune_ms"] = [round(t, 3) for t in tune_times]
     if not args.no_cpu:

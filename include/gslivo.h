@@ -250,6 +250,54 @@ GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
                     gsl_grads *grads, void *workspace, size_t workspace_bytes, float *times_ms, int32_t ntimes,
                     void *stream);
 
+/* ---- pose Jacobians for the IESKF visual update -------------------------- */
+
+/* Workspace bytes for gsl_pose_jacobian: the bytes gsl_workspace_size gives
+ * for the same arguments, plus 128 B per (camera, Gaussian) record for its
+ * twist tangents and 224 B per tile for the per-tile partial sums. */
+GSL_API int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,
+                                             const gsl_opts *opts, int64_t capacity_K, size_t *bytes);
+
+/* Photometric measurement model of the visual update (Sec. III-D, eq.
+ * eq:minimization; Appendix A): the Jacobian of the rendered colour with
+ * respect to each camera's twist xi = (dphi, dt) of the left perturbation
+ * T_CW <- Exp(xi) T_CW, by forward-mode differentiation through the
+ * projection (eqs. eqn:grad_meani_rcw ... eqn:grad_covi_tcw) and the same
+ * front-to-back walk as gsl_render_fwd (same contributors; the thresholds
+ * are held fixed).  Needs gsl_project and gsl_bin_sort outputs for these
+ * Gaussians and cameras.  Device outputs, each may be NULL:
+ *   image  float[3 * P_total]  the rendered colour, packed as gsl_render_fwd;
+ *   jac    float[18 * P_total] plane 6 * ch + j holds dI_ch/dxi_j of every
+ *          pixel in the packed pixel order (plane stride P_total);
+ *   HtH    double[C][36], Htz double[C][6], zz double[C]: per camera the sums
+ *          over its pixels p and channels of w_p h h^T, w_p h z and w_p z^2,
+ *          where h = dI_ch/dxi (6), z = I_ch - target_ch, and w_p = weight[p]
+ *          (device float[P_total], R^-1 of the pixel) or 1 when weight is
+ *          NULL.  These need target (packed like the image).
+ * The workspace must hold gsl_pose_jacobian_workspace_size bytes.
+ * Stream-ordered, no host synchronisation. */
+GSL_API int gsl_pose_jacobian(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C,
+                              const gsl_opts *opts, const gsl_proj *proj, const gsl_bins *bins, const float *target,
+                              const float *weight, float *image, float *jac, double *HtH, double *Htz, double *zz,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Host helpers (plain double arrays in host memory, row-major; no device
+ * work).  gsl_imu_to_camera_twist writes A (6x6) with xi_cam = A xi_imu to
+ * first order, from the perturbation model of Appendix A (eq.
+ * eq:perturbation): (T(xi_cam) T_CW)^-1 T_CI = T_WI [+] xi_imu, the IMU
+ * pose perturbed as (R_WI Exp(dphi), t_WI + dt); so dphi_cam = -R_CI dphi_imu
+ * and dt_cam = t_CI^ dphi_cam - R_CW dt_imu.  H_imu = H_cam A. */
+GSL_API int gsl_imu_to_camera_twist(const double R_CI[9], const double t_CI[3], const double R_CW[9], double A[36]);
+
+/* One IESKF update of a 6-dof pose from its normal equations (Appendix A):
+ * K = (H^T R^-1 H + P^-1)^-1 H^T R^-1,
+ * delta = -K z - (I - K H) dx_prior,  P_post = (I - K H) P,
+ * with dx_prior = x_hat [-] x_bar (NULL: zero, the first iteration) and the
+ * Jacobian of [-] taken as the identity.  HtRH, P, P_post are 6x6, HtRz,
+ * delta 6-vectors.  GSL_EINVAL when P or H^T R^-1 H + P^-1 is singular. */
+GSL_API int gsl_ieskf_pose_update(const double HtRH[36], const double HtRz[6], const double P[36],
+                                  const double dx_prior[6], double delta[6], double P_post[36]);
+
 #ifdef __cplusplus
 }
 #endif

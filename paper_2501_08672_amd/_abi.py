@@ -28,7 +28,9 @@ _NAMES = {GSL_EINVAL: "EINVAL", GSL_ENOTSUP: "ENOTSUP", GSL_ECAPACITY: "ECAPACIT
 
 EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "gsl_layout", "gsl_workspace_size",
            "gsl_project", "gsl_bin_sort", "gsl_render_fwd", "gsl_render_bwd", "gsl_render_stats", "gsl_window_step",
-           "gsl_window_tune", "gsl_window_variant", "gsl_profile", "gsl_profile_read"]
+           "gsl_window_tune", "gsl_window_variant", "gsl_profile", "gsl_profile_read",
+           "gsl_pose_jacobian_workspace_size", "gsl_pose_jacobian", "gsl_imu_to_camera_twist",
+           "gsl_ieskf_pose_update"]
 
 
 class GslError(RuntimeError):
@@ -102,6 +104,11 @@ def lib() -> C.CDLL:
     L.gsl_window_step.argtypes = [P, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, P, pgr, P, C.c_size_t, C.c_int, P]
     L.gsl_window_tune.argtypes = [P, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, pgr, P, C.c_size_t,
                                   C.POINTER(C.c_float), C.c_int32, P]
+    L.gsl_pose_jacobian_workspace_size.argtypes = [P, pc, C.c_int32, C.c_int32, po, C.c_int64,
+                                                   C.POINTER(C.c_size_t)]
+    L.gsl_pose_jacobian.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, P, P, P, P, P, C.c_size_t, P]
+    L.gsl_imu_to_camera_twist.argtypes = [P, P, P, P]
+    L.gsl_ieskf_pose_update.argtypes = [P, P, P, P, P, P]
     for name in EXPORTS:
         if name not in ("gsl_last_error", "gsl_default_opts"):
             getattr(L, name).restype = C.c_int

@@ -270,13 +270,15 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     uint32_t *dkey2 = at<uint32_t>(ws, W.dkey2), *dval2 = at<uint32_t>(ws, W.dval2);
     uint32_t *hist = at<uint32_t>(ws, W.hist), *hist_off = at<uint32_t>(ws, W.hist_off);
     uint64_t *partial = at<uint64_t>(ws, W.partial);
-    // 1. depth order of all records (ties by record index = Gaussian index per camera)
+    // 1. depth order of the records that reach a tile (ties by record index =
+    // Gaussian index per camera); the first pass drops the others
+    int64_t *d_V = at<int64_t>(ws, W.misc + 64);
     launch_depth_keys(proj->splats, proj->tiles_touched, L.M, dkey, dval, s);
-    int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, partial, s);
+    int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, partial, s, d_V);
     const uint32_t *order = where ? dval2 : dval;
     // 2. instance offsets in that order
     uint32_t *counts = at<uint32_t>(ws, W.counts), *offsets = at<uint32_t>(ws, W.offsets);
-    launch_gather_counts(order, proj->tiles_touched, L.M, counts, s);
+    launch_gather_counts(order, proj->tiles_touched, L.M, d_V, counts, s);
     launch_scan_u32(counts, offsets, L.M, partial, bins->d_K, s);
     // 3. emit and sort by tile; the pass count decides which buffer is emitted into
     const int passes = (L.tile_bits + 7) / 8;
@@ -366,6 +368,42 @@ VariantKey window_key(const Layout &L, const gsl_camera *cams)
         k.v.push_back(cams[c].height);
     }
     return k;
+}
+
+// Bytes gsl_pose_jacobian needs past the common workspace: per-record
+// tangents, then per-item normal-equation partials.
+size_t jvp_tangent_bytes(const Layout &L) { return align_up(4 * (size_t)kTangent * (size_t)L.M); }
+size_t jvp_extra_bytes(const Layout &L)
+{
+    return jvp_tangent_bytes(L) + align_up(8 * (size_t)kNrm * (size_t)std::max<int64_t>(1, L.T_total));
+}
+
+// In-place Gauss-Jordan inverse of a 6x6 row-major matrix with partial
+// pivoting; false when a pivot vanishes.
+bool invert6(const double *A, double *X)
+{
+    double M[6][12];
+    for (int r = 0; r < 6; r++)
+        for (int c = 0; c < 12; c++) M[r][c] = c < 6 ? A[6 * r + c] : (c - 6 == r ? 1.0 : 0.0);
+    for (int k = 0; k < 6; k++) {
+        int piv = k;
+        for (int r = k + 1; r < 6; r++)
+            if (std::fabs(M[r][k]) > std::fabs(M[piv][k])) piv = r;
+        if (!(std::fabs(M[piv][k]) > 0.0) || !std::isfinite(M[piv][k])) return false;
+        if (piv != k)
+            for (int c = 0; c < 12; c++) std::swap(M[k][c], M[piv][c]);
+        const double inv = 1.0 / M[k][k];
+        for (int c = 0; c < 12; c++) M[k][c] *= inv;
+        for (int r = 0; r < 6; r++) {
+            if (r == k) continue;
+            const double f = M[r][k];
+            if (f != 0.0)
+                for (int c = 0; c < 12; c++) M[r][c] -= f * M[k][c];
+        }
+    }
+    for (int r = 0; r < 6; r++)
+        for (int c = 0; c < 6; c++) X[6 * r + c] = M[r][6 + c];
+    return true;
 }
 
 }  // namespace
@@ -704,6 +742,103 @@ int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
     if (rc != GSL_OK) return rc;
     opts_inout->tile = best_tile;
     return check_launch("gsl_window_tune");
+}
+
+int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,
+                                     const gsl_opts *opts, int64_t capacity_K, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_opts(opts));
+    if (capacity_K < 0 || capacity_K > 0xffffffffll) return fail(GSL_EINVAL, "capacity_K out of range");
+    Layout L;
+    GSL_TRY(make_layout(cams, C, N, opts->tile, L, nullptr));
+    *bytes = ws_layout(L, capacity_K).total + jvp_extra_bytes(L);
+    return GSL_OK;
+}
+
+int gsl_pose_jacobian(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                      const gsl_proj *proj, const gsl_bins *bins, const float *target, const float *weight,
+                      float *image, float *jac, double *HtH, double *Htz, double *zz, void *workspace,
+                      size_t workspace_bytes, void *stream)
+{
+    GSL_TRY(check_gauss(g, false));
+    GSL_TRY(check_bins(bins));
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, g->N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    const size_t need = p.W.total + jvp_extra_bytes(p.L);
+    if (workspace_bytes < need)
+        return fail(GSL_EINVAL, "workspace too small for the pose Jacobian: %zu < %zu bytes", workspace_bytes, need);
+    const bool normal = HtH || Htz || zz;
+    if (normal && !target) return fail(GSL_EINVAL, "the normal equations need the target image");
+    hipStream_t s = (hipStream_t)stream;
+    do_upload(p, workspace, s);
+    float *tangent = at<float>(workspace, p.W.total);
+    double *part = at<double>(workspace, p.W.total + jvp_tangent_bytes(p.L));
+    launch_project_tangent(*g, at<DevCam>(workspace, p.W.cams), p.L, p.o, proj->tiles_touched, tangent, s);
+    RenderArgs a = render_args(p, proj, bins, workspace);
+    a.image = image;
+    a.target = normal ? target : nullptr;
+    a.weight = weight;
+    a.jac = jac;
+    a.tangent = tangent;
+    a.P_total = p.L.P_total;
+    a.nrm_part = normal ? part : nullptr;
+    launch_render_jvp(a, s);
+    if (normal) launch_normal_reduce(part, at<DevCam>(workspace, p.W.cams), p.L.C, HtH, Htz, zz, s);
+    return check_launch("gsl_pose_jacobian");
+}
+
+int gsl_imu_to_camera_twist(const double R_CI[9], const double t_CI[3], const double R_CW[9], double A[36])
+{
+    if (!R_CI || !t_CI || !R_CW || !A) return fail(GSL_EINVAL, "NULL argument");
+    for (int k = 0; k < 36; k++) A[k] = 0.0;
+    // dphi_cam = -R_CI dphi_imu
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) A[6 * r + c] = -R_CI[3 * r + c];
+    // dt_cam = t_CI^ dphi_cam - R_CW dt_imu = -(t_CI^ R_CI) dphi_imu - R_CW dt_imu
+    const double tx[9] = {0.0, -t_CI[2], t_CI[1], t_CI[2], 0.0, -t_CI[0], -t_CI[1], t_CI[0], 0.0};
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double v = 0.0;
+            for (int k = 0; k < 3; k++) v += tx[3 * r + k] * R_CI[3 * k + c];
+            A[6 * (3 + r) + c] = -v;
+            A[6 * (3 + r) + 3 + c] = -R_CW[3 * r + c];
+        }
+    return GSL_OK;
+}
+
+int gsl_ieskf_pose_update(const double HtRH[36], const double HtRz[6], const double P[36], const double dx_prior[6],
+                          double delta[6], double P_post[36])
+{
+    if (!HtRH || !HtRz || !P || !delta || !P_post) return fail(GSL_EINVAL, "NULL argument");
+    double Pinv[36], S[36], Sinv[36], KH[36], IKH[36];
+    if (!invert6(P, Pinv)) return fail(GSL_EINVAL, "prior covariance is singular");
+    for (int k = 0; k < 36; k++) S[k] = HtRH[k] + Pinv[k];
+    if (!invert6(S, Sinv)) return fail(GSL_EINVAL, "H^T R^-1 H + P^-1 is singular");
+    // K H = S^-1 H^T R^-1 H,  K z = S^-1 H^T R^-1 z
+    for (int r = 0; r < 6; r++)
+        for (int c = 0; c < 6; c++) {
+            double v = 0.0;
+            for (int k = 0; k < 6; k++) v += Sinv[6 * r + k] * HtRH[6 * k + c];
+            KH[6 * r + c] = v;
+            IKH[6 * r + c] = (r == c ? 1.0 : 0.0) - v;
+        }
+    for (int r = 0; r < 6; r++) {
+        double kz = 0.0, px = 0.0;
+        for (int k = 0; k < 6; k++) {
+            kz += Sinv[6 * r + k] * HtRz[k];
+            if (dx_prior) px += IKH[6 * r + k] * dx_prior[k];
+        }
+        delta[r] = -kz - px;
+    }
+    for (int r = 0; r < 6; r++)
+        for (int c = 0; c < 6; c++) {
+            double v = 0.0;
+            for (int k = 0; k < 6; k++) v += IKH[6 * r + k] * P[6 * k + c];
+            P_post[6 * r + c] = v;
+        }
+    return GSL_OK;
 }
 
 }  // extern "C"

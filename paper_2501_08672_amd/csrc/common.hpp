@@ -138,7 +138,7 @@ struct WsLayout {
     size_t pose_part = 0;   // double[pose_blocks][C][6]
     size_t loss_part = 0;   // double[T_total]
     size_t order = 0;       // u32[T_total] work order of the fused kernel
-    size_t misc = 0;        // small scalars: queue counter, internal K
+    size_t misc = 0;        // small scalars: work-queue counter (byte 0), kept-record count (byte 64)
     size_t total = 0;
     int64_t sort_blocks = 0;
     int64_t scan_partials = 0;
@@ -162,6 +162,11 @@ void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L,
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                         const float *g2d, const gsl_grads &out, int accumulate, double *pose_part,
                         int pose_blocks, hipStream_t s);
+// Per-record derivatives of the 2D mean and conic along the camera twist,
+// kTangent floats per record (records that reach no tile are not written).
+constexpr int kTangent = 32;
+void launch_project_tangent(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
+                            const int32_t *tiles_touched, float *tangent, hipStream_t s);
 
 // sort.hip
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -174,13 +179,16 @@ void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint6
 // stable LSD radix sort of (key, val) pairs over bits [0, bits); n_max bounds
 // the grid, d_n (may be null) holds the live count on the device.  Returns the
 // buffer index (0: keys/vals, 1: keys2/vals2) that holds the result.
+// Stable LSD sort of `bits` low key bits; returns 1 when the result is in
+// keys2/vals2.  With d_kept, keys 0xffffffff are dropped by the first pass and
+// the number kept is written to *d_kept (later passes sort only those).
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint64_t *partial,
-                      hipStream_t s);
+                      hipStream_t s, int64_t *d_kept = nullptr);
 void launch_depth_keys(const gsl_splat *splats, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
                        hipStream_t s);
-void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, uint32_t *counts,
-                          hipStream_t s);
+void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, const int64_t *d_V,
+                          uint32_t *counts, hipStream_t s);
 // tiles_touched of every (camera, Gaussian) record under the binning rule
 void launch_count_tiles(const gsl_splat *splats, const DevCam *cams, const Layout &L, float alpha_min,
                         int32_t *tiles_touched, hipStream_t s);
@@ -213,7 +221,19 @@ struct RenderArgs {
     // persistent work queue
     const uint32_t *order;
     uint32_t *queue;
+    // pose Jacobian (forward mode)
+    const float *tangent;   // [M][kTangent]
+    const float *weight;    // per-pixel R^-1 weight or NULL (1)
+    int64_t P_total;        // pixels of all cameras (plane stride of jac)
+    float *jac;             // [18][P_total] dI_ch/dxi_j planes (plane 6 ch + j) or NULL
+    double *nrm_part;       // [T_total][kNrm] per-item normal-equation sums
 };
+// per item: H^T R^-1 H (21, upper triangle row by row), H^T R^-1 z (6), z^T R^-1 z
+constexpr int kNrm = 28;
+void launch_render_jvp(const RenderArgs &a, hipStream_t s);
+// Per-camera sums of the item partials: HtH [C][36] (full), Htz [C][6], zz [C]; each may be NULL.
+void launch_normal_reduce(const double *nrm_part, const DevCam *cams, int C, double *HtH, double *Htz, double *zz,
+                          hipStream_t s);
 void launch_render_fwd(const RenderArgs &a, hipStream_t s);
 void launch_render_bwd(const RenderArgs &a, hipStream_t s);
 // variant bit 0: persistent work queue (else one workgroup per item);

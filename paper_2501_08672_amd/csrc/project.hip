@@ -169,6 +169,85 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
     out[m] = sp;
 }
 
+// ------------------------------------------------------------------ pose tangents
+
+// Derivatives of one splat's 2D mean and conic along the six twist
+// directions (dphi, dt) of the left perturbation T_CW <- Exp(dphi, dt) T_CW
+// (Sec. III-D and Appendix A, the chains of eqs. eqn:grad_meani_rcw ...
+// eqn:grad_covi_tcw taken forward): to first order p_C moves by
+// dphi x p_C + dt and W by dphi^ W.  With M = J W and P = M Rg diag(s),
+//   dmu = J dp_C,  dM = dJ(dp_C) W + J dW,  dP = dM Rg diag(s),
+//   dSigma2D = dP P^T + P dP^T,  dconic = -conic dSigma2D conic.
+// Record m gets kTangent floats: dmx[6], dmy[6], dA[6], dB[6], dC[6] of the
+// conic (A, B, C) = Sigma2D^{-1}, then two unused.  Only records that reach a
+// tile are written (no other record is ever read).
+__global__ __launch_bounds__(256) void k_project_tangent(const float *__restrict__ mean,
+                                                         const float *__restrict__ scale,
+                                                         const float *__restrict__ quat, int N, int64_t M,
+                                                         const DevCam *__restrict__ cams, DevOpts o,
+                                                         const int32_t *__restrict__ tiles_touched,
+                                                         float *__restrict__ tangent)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || tiles_touched[m] <= 0) return;
+    const int c = (int)(m / N);
+    const int i = (int)(m - (int64_t)c * N);
+    const DevCam cam = cams[c];
+    Proj p;
+    if (!compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p)) return;
+    const double iz = 1.0 / p.z, fx = cam.fx, fy = cam.fy;
+    const double J00 = fx * iz, J02 = -fx * p.x * iz * iz, J11 = fy * iz, J12 = -fy * p.y * iz * iz;
+    const double id = 1.0 / p.det;
+    const double QA = p.c * id, QB = -p.b * id, QC = p.a * id;
+    float *out = tangent + m * kTangent;
+    for (int k = 0; k < 6; k++) {
+        double dp[3] = {0.0, 0.0, 0.0};
+        double E[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // [e]x for a rotation direction
+        if (k < 3) {
+            const double e0 = k == 0, e1 = k == 1, e2 = k == 2;
+            dp[0] = e1 * p.z - e2 * p.y;
+            dp[1] = e2 * p.x - e0 * p.z;
+            dp[2] = e0 * p.y - e1 * p.x;
+            E[1] = -e2; E[2] = e1; E[3] = e2; E[5] = -e0; E[6] = -e1; E[7] = e0;
+        } else {
+            dp[k - 3] = 1.0;
+        }
+        out[k] = (float)(J00 * dp[0] + J02 * dp[2]);
+        out[6 + k] = (float)(J11 * dp[1] + J12 * dp[2]);
+        const double dz = dp[2];
+        const double dJ00 = -fx * dz * iz * iz, dJ11 = -fy * dz * iz * iz;
+        const double dJ02 = -fx * (dp[0] * iz * iz - 2.0 * p.x * dz * iz * iz * iz);
+        const double dJ12 = -fy * (dp[1] * iz * iz - 2.0 * p.y * dz * iz * iz * iz);
+        // dW = E W;  dM = dJ W + J E W
+        double EW[9];
+        for (int r = 0; r < 3; r++)
+            for (int q = 0; q < 3; q++)
+                EW[3 * r + q] = E[3 * r] * p.W[q] + E[3 * r + 1] * p.W[3 + q] + E[3 * r + 2] * p.W[6 + q];
+        double dM[6];
+        for (int q = 0; q < 3; q++) {
+            dM[q] = dJ00 * p.W[q] + dJ02 * p.W[6 + q] + J00 * EW[q] + J02 * EW[6 + q];
+            dM[3 + q] = dJ11 * p.W[3 + q] + dJ12 * p.W[6 + q] + J11 * EW[3 + q] + J12 * EW[6 + q];
+        }
+        double dP[6];
+        for (int r = 0; r < 2; r++)
+            for (int q = 0; q < 3; q++)
+                dP[3 * r + q] = (dM[3 * r] * p.Rg[q] + dM[3 * r + 1] * p.Rg[3 + q] + dM[3 * r + 2] * p.Rg[6 + q]) *
+                                p.s[q];
+        const double da = 2.0 * (dP[0] * p.P[0] + dP[1] * p.P[1] + dP[2] * p.P[2]);
+        const double db = dP[0] * p.P[3] + dP[1] * p.P[4] + dP[2] * p.P[5] + p.P[0] * dP[3] + p.P[1] * dP[4] +
+                          p.P[2] * dP[5];
+        const double dc = 2.0 * (dP[3] * p.P[3] + dP[4] * p.P[4] + dP[5] * p.P[5]);
+        // dQ = -Q dS Q with Q = [[QA, QB], [QB, QC]], dS = [[da, db], [db, dc]]
+        const double t00 = QA * da + QB * db, t01 = QA * db + QB * dc;
+        const double t10 = QB * da + QC * db, t11 = QB * db + QC * dc;
+        out[12 + k] = (float)(-(t00 * QA + t01 * QB));
+        out[18 + k] = (float)(-(t00 * QB + t01 * QC));
+        out[24 + k] = (float)(-(t10 * QB + t11 * QC));
+    }
+    out[30] = 0.f;
+    out[31] = 0.f;
+}
+
 // ------------------------------------------------------------------ backward
 
 __device__ __forceinline__ double wave_sum_f64(double v)
@@ -370,6 +449,15 @@ void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L,
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
                        g.color, g.N, L.M, cams, o, splats);
     launch_count_tiles(splats, cams, L, o.alpha_min, tiles_touched, s);
+}
+
+void launch_project_tangent(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
+                            const int32_t *tiles_touched, float *tangent, hipStream_t s)
+{
+    if (L.M == 0) return;
+    const int64_t blocks = (L.M + 255) / 256;
+    hipLaunchKernelGGL(k_project_tangent, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.N, L.M,
+                       cams, o, tiles_touched, tangent);
 }
 
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,

@@ -19,7 +19,8 @@
 // pixel: it walks the same list from the back, recovers T before each
 // contributor by dividing by (1 - alpha), and carries the suffix
 // S = sum_{j>k} c_j alpha_j T_j + T_final bg, so that
-//   dI/dc_k = alpha_k T_k,  dI/dalpha_k = T_k c_k - S / (1 - alpha_k).
+//   dI/dc_k = alpha_k T_k,  dI/dalpha_k = T_k c_k - S / (1 - alpha_k)
+// (only v . S is kept, v the pixel's cotangent).
 // Each lane first sums the nine 2D gradients of a splat over its own pixels;
 // the wave then reduce-scatters them on the VALU (lane swaps and DPP, no LDS
 // permutes) so that nine lanes hold the nine totals, and a single atomic
@@ -55,6 +56,8 @@ struct Geo {
     static constexpr bool BANDS = RSTEP <= TS / 4;
     static_assert(TS * ROWS % kWave == 0 && PPL >= 1, "tile/wave layout");
     __device__ static int band(int w, int k) { return (w * ROWS + k * RSTEP) / (TS / 4); }
+    // all pixel slots of a wave lie in one band: the band test is per splat
+    static constexpr bool ONE_BAND = BANDS && ROWS <= TS / 4 && (TS / 4) % ROWS == 0;
 };
 
 // DPP sum of a wave: the total lands in lane 63.
@@ -289,7 +292,7 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
     float fy[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; k++) fy[k] = (float)(ti.py0 + k * G::RSTEP) + 0.5f;
-    const int wv = threadIdx.x / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
     uint32_t hbits = 0;
     int hword = 0;
@@ -309,21 +312,22 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
-            const uint32_t val = st.gid[j];
+            const uint32_t val = __builtin_amdgcn_readfirstlane(st.gid[j]);  // same for every lane
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
             const uint32_t pos1 = start + (uint32_t)j + 1u - ti.rs;
             bool used = false;
+            // a band the ellipse does not reach has alpha < alpha_min everywhere
+            const bool wave_in = !G::ONE_BAND || in_band<TS, NW>(val, wv, 0);
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                // a band the ellipse does not reach has alpha < alpha_min everywhere
-                if (!in_band<TS, NW>(val, wv, k)) continue;
+                if (!wave_in) break;
+                if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;
                 // predicated: every lane evaluates, selects decide what changes
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const bool live = !done[k];
                 const bool hit = live && e.alpha >= amin;
                 cnt.eval(live);
-                if (!__any(hit)) continue;  // wave-uniform: nothing changes for this slot
                 const float Tn = ps.T[k] * (1.f - e.alpha);
                 const bool stop = hit && Tn < Tmin;
                 const bool acc = hit && !stop;
@@ -367,17 +371,18 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
     float *g2d = a.g2d + (int64_t)ti.c * a.N * kG2;
     const float fx = ti.px + 0.5f;
     const float amin = a.o.alpha_min, amax = a.o.alpha_max;
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const uint32_t len = ti.re - ti.rs;
-    float T[PPL], S0[PPL], S1[PPL], S2[PPL], fy[PPL];
+    // SV[k] = v . S with S the colour composited behind the current splat
+    // (background included): dI/dalpha = T c - S / (1 - alpha) enters only as
+    // v . dI/dalpha, so one scalar per pixel carries the suffix.
+    float T[PPL], SV[PPL], fy[PPL];
     uint32_t nw[PPL];
     uint32_t lane_max = 0;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         T[k] = Tf[k];
-        S0[k] = T[k] * a.o.bg[0];
-        S1[k] = T[k] * a.o.bg[1];
-        S2[k] = T[k] * a.o.bg[2];
+        SV[k] = T[k] * fmaf(v[k][0], a.o.bg[0], fmaf(v[k][1], a.o.bg[1], v[k][2] * a.o.bg[2]));
         nw[k] = ti.inside(k) ? min(nw_in[k], len) : 0u;  // never walk past the tile's list
         lane_max = max(lane_max, nw[k]);
         fy[k] = (float)(ti.py0 + k * G::RSTEP) + 0.5f;
@@ -404,16 +409,19 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
-            const uint32_t val = st.gid[j];
+            const uint32_t val = __builtin_amdgcn_readfirstlane(st.gid[j]);  // same for every lane
+            if (G::ONE_BAND && !in_band<TS, NW>(val, wv, 0)) continue;
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
-            float g[kG2];
-#pragma unroll
-            for (int f = 0; f < kG2; f++) g[f] = 0.f;
+            // Per lane: gp = dL/dpower of each pixel; the lane's pixels share
+            // dx, so the 2D-mean and conic gradients need only P = sum gp,
+            // Q = sum gp dy and R = sum gp dy^2 (t1 = l11 dx + l12 dy,
+            // t2 = l22 dy, power = -(t1^2 + t2^2) / 2).
+            float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gop = 0.f, P = 0.f, Q = 0.f, R = 0.f;
             bool used = false;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (!in_band<TS, NW>(val, wv, k)) continue;  // wave-uniform skips
+                if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;  // wave-uniform skips
                 if (!__any(pos < nw[k])) continue;
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const bool hit = pos < nw[k] && e.alpha >= amin;
@@ -424,27 +432,33 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
                 const float Tk = hit ? T[k] * r : T[k];  // transmittance before this Gaussian
                 T[k] = Tk;
                 const float w = hit ? e.alpha * Tk : 0.f;
-                g[6] = fmaf(w, v[k][0], g[6]);
-                g[7] = fmaf(w, v[k][1], g[7]);
-                g[8] = fmaf(w, v[k][2], g[8]);
-                const float ga = fmaf(v[k][0], fmaf(Tk, p1.z, -S0[k] * r),
-                                      fmaf(v[k][1], fmaf(Tk, p1.w, -S1[k] * r),
-                                           v[k][2] * fmaf(Tk, cb, -S2[k] * r)));
-                S0[k] = fmaf(p1.z, w, S0[k]);
-                S1[k] = fmaf(p1.w, w, S1[k]);
-                S2[k] = fmaf(cb, w, S2[k]);
+                gc0 = fmaf(w, v[k][0], gc0);
+                gc1 = fmaf(w, v[k][1], gc1);
+                gc2 = fmaf(w, v[k][2], gc2);
+                const float vc = fmaf(v[k][0], p1.z, fmaf(v[k][1], p1.w, v[k][2] * cb));
+                const float ga = fmaf(Tk, vc, -SV[k] * r);
+                SV[k] = fmaf(w, vc, SV[k]);
                 // alpha is clamped where sigma G >= alpha_max: no gradient to sigma, G
                 const float gam = (hit && e.s < amax) ? ga : 0.f;
-                g[5] = fmaf(e.G, gam, g[5]);
+                gop = fmaf(e.G, gam, gop);
                 const float gp = e.s * gam;
-                const float hx = gp * dx, hy = gp * e.dy;
-                g[0] = fmaf(gp, p0.z * e.t1, g[0]);
-                g[1] = fmaf(gp, fmaf(p0.w, e.t1, p1.x * e.t2), g[1]);
-                g[2] = fmaf(-0.5f * hx, dx, g[2]);
-                g[3] = fmaf(-hx, e.dy, g[3]);
-                g[4] = fmaf(-0.5f * hy, e.dy, g[4]);
+                const float hy = gp * e.dy;
+                P += gp;
+                Q += hy;
+                R = fmaf(hy, e.dy, R);
             }
             if (used) {
+                float g[kG2];
+                const float u = fmaf(ax, P, p0.w * Q);  // sum of gp t1
+                g[0] = p0.z * u;
+                g[1] = fmaf(p0.w, u, p1.x * (p1.x * Q));
+                g[2] = -0.5f * (dx * dx) * P;
+                g[3] = -dx * Q;
+                g[4] = -0.5f * R;
+                g[5] = gop;
+                g[6] = gc0;
+                g[7] = gc1;
+                g[8] = gc2;
                 const float tot = reduce9(g, lane);
                 if (writer && tot != 0.f) unsafeAtomicAdd(g2d + (int64_t)(val & kGidMask) * kG2 + slot, tot);
             }
@@ -662,6 +676,247 @@ __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ p
     }
 }
 
+// ------------------------------------------------------------------ pose Jacobian
+
+// Forward-mode walk for the IESKF visual update (Sec. III-D, Appendix A):
+// per pixel, alongside T and the colour, the six tangents dT and the 3 x 6
+// tangents of the colour with respect to the camera twist, with every
+// threshold decision taken exactly as in the forward walk (same alpha
+// evaluation), so the contributor set is the image's.  For a contributor with
+// alpha a (da = 0 where the clamp holds, else a dpower, dpower = (Q d) . dmu
+// - 1/2 d^T dQ d from the splat's tangent record):
+//   dC += c (T da + a dT),   dT <- dT (1 - a) - T da,
+// and at the end dI = dC + bg dT.  The item then sums, over its pixels, the
+// normal-equation terms of the stacked model z + H xi with z = I - target:
+// H^T R^-1 H (21), H^T R^-1 z (6) and z^T R^-1 z, R^-1 a per-pixel weight.
+// One pixel per lane for 8x8 and 16x16 tiles, two for 32x32; the splats and
+// their tangent records are staged in chunks of up to 256.
+template <int CH>
+struct TanStage {
+    float4 p0[CH];
+    float4 p1[CH];
+    float p2[CH];
+    uint32_t gid[CH];
+    float4 t[kTangent / 4][CH];
+};
+
+template <int TS, int NW>
+__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
+{
+    using G = Geo<TS, NW>;
+    constexpr int PPL = G::PPL;
+    constexpr int CH = G::BS < 256 ? G::BS : 256;
+    __shared__ TanStage<CH> st;
+    __shared__ double s_nrm[NW][kNrm];
+    const int t = (int)blockIdx.x;
+    const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, t);
+    const gsl_splat *rec = a.splats + (int64_t)ti.c * a.N;
+    const float *tan = a.tangent + (int64_t)ti.c * a.N * kTangent;
+    const float fx = ti.px + 0.5f;
+    const float amin = a.o.alpha_min, amax = a.o.alpha_max, Tmin = a.o.T_min;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    float T[PPL], C0[PPL], C1[PPL], C2[PPL], fy[PPL], dT[PPL][6], dC[PPL][3][6];
+    bool done[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        T[k] = 1.f;
+        C0[k] = C1[k] = C2[k] = 0.f;
+        done[k] = !ti.inside(k);
+        fy[k] = (float)(ti.py0 + k * G::RSTEP) + 0.5f;
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            dT[k][j] = 0.f;
+            dC[k][0][j] = dC[k][1][j] = dC[k][2][j] = 0.f;
+        }
+    }
+    auto open = [&]() {
+        bool o = false;
+#pragma unroll
+        for (int k = 0; k < PPL; k++) o |= !done[k];
+        return o;
+    };
+    for (uint32_t start = ti.rs; start < ti.re; start += CH) {
+        if (__syncthreads_count(open()) == 0) break;
+        if (threadIdx.x < CH && start + threadIdx.x < ti.re) {
+            const uint32_t val = a.gauss_ids[start + threadIdx.x];
+            const uint32_t gi = val & kGidMask;
+            const float4 *r4 = reinterpret_cast<const float4 *>(rec + gi);
+            st.p0[threadIdx.x] = r4[0];
+            st.p1[threadIdx.x] = r4[1];
+            st.p2[threadIdx.x] = r4[2].x;
+            st.gid[threadIdx.x] = val;
+            const float4 *t4 = reinterpret_cast<const float4 *>(tan + (int64_t)gi * kTangent);
+#pragma unroll
+            for (int q = 0; q < kTangent / 4; q++) st.t[q][threadIdx.x] = t4[q];
+        }
+        __syncthreads();
+        const int n = (int)min((uint32_t)CH, ti.re - start);
+        for (int j = 0; j < n; j++) {
+            if (!__any(open())) break;
+            const uint32_t val = __builtin_amdgcn_readfirstlane(st.gid[j]);
+            if (G::ONE_BAND && !in_band<TS, NW>(val, wv, 0)) continue;
+            const float4 p0 = st.p0[j];
+            const float4 p1 = st.p1[j];
+            const float cb = st.p2[j];
+            const float dx = fx - p0.x;
+            const float ax = p0.z * dx;
+            // conic (A, B, C) = L^T L from the Cholesky factor (l11, l12; 0, l22)
+            const float cA = p0.z * p0.z, cB = p0.z * p0.w, cC = fmaf(p0.w, p0.w, p1.x * p1.x);
+#pragma unroll
+            for (int k = 0; k < PPL; k++) {
+                if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;
+                const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
+                const bool hit = !done[k] && e.alpha >= amin;
+                const float Tn = T[k] * (1.f - e.alpha);
+                const bool stop = hit && Tn < Tmin;
+                const bool acc = hit && !stop;
+                done[k] = done[k] || stop;
+                if (!__any(acc)) continue;
+                // a contributor moves the state; others act as alpha = 0, dalpha = 0
+                const float al = acc ? e.alpha : 0.f;
+                const float sg = (acc && e.s < amax) ? e.alpha : 0.f;  // dalpha = sg * dpower
+                const float gx = fmaf(cA, dx, cB * e.dy), gy = fmaf(cB, dx, cC * e.dy);
+                const float k2 = -0.5f * dx * dx, k3 = -dx * e.dy, k4 = -0.5f * e.dy * e.dy;
+                float da[6];
+                {
+                    const float4 t0 = st.t[0][j], t1 = st.t[1][j], t2 = st.t[2][j], t3 = st.t[3][j];
+                    const float4 t4 = st.t[4][j], t5 = st.t[5][j], t6 = st.t[6][j], t7 = st.t[7][j];
+                    const float tv[30] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w, t2.x, t2.y,
+                                          t2.z, t2.w, t3.x, t3.y, t3.z, t3.w, t4.x, t4.y, t4.z, t4.w,
+                                          t5.x, t5.y, t5.z, t5.w, t6.x, t6.y, t6.z, t6.w, t7.x, t7.y};
+#pragma unroll
+                    for (int q = 0; q < 6; q++) {
+                        float dp = gx * tv[q];
+                        dp = fmaf(gy, tv[6 + q], dp);
+                        dp = fmaf(k2, tv[12 + q], dp);
+                        dp = fmaf(k3, tv[18 + q], dp);
+                        dp = fmaf(k4, tv[24 + q], dp);
+                        da[q] = sg * dp;
+                    }
+                }
+                const float Tk = T[k];
+#pragma unroll
+                for (int q = 0; q < 6; q++) {
+                    const float w = fmaf(Tk, da[q], al * dT[k][q]);
+                    dC[k][0][q] = fmaf(p1.z, w, dC[k][0][q]);
+                    dC[k][1][q] = fmaf(p1.w, w, dC[k][1][q]);
+                    dC[k][2][q] = fmaf(cb, w, dC[k][2][q]);
+                    dT[k][q] = fmaf(dT[k][q], 1.f - al, -Tk * da[q]);
+                }
+                const float wgt = al * Tk;
+                C0[k] = fmaf(wgt, p1.z, C0[k]);
+                C1[k] = fmaf(wgt, p1.w, C1[k]);
+                C2[k] = fmaf(wgt, cb, C2[k]);
+                T[k] = acc ? Tn : Tk;
+            }
+        }
+        __syncthreads();
+    }
+    // per-pixel outputs and the item's normal-equation sums
+    float nrm[kNrm];
+#pragma unroll
+    for (int q = 0; q < kNrm; q++) nrm[q] = 0.f;
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        if (!ti.inside(k)) continue;
+        const int64_t off = ti.off(k);
+        // the same expression as the forward kernels, so the colour matches theirs bit for bit
+        const float I[3] = {C0[k] + T[k] * a.o.bg[0], C1[k] + T[k] * a.o.bg[1], C2[k] + T[k] * a.o.bg[2]};
+        float Jp[3][6];
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++)
+#pragma unroll
+            for (int q = 0; q < 6; q++) Jp[ch][q] = fmaf(a.o.bg[ch], dT[k][q], dC[k][ch][q]);
+        if (a.image)
+            for (int ch = 0; ch < 3; ch++) a.image[ti.plane0 + ch * ti.npix + off] = I[ch];
+        if (a.jac)
+            for (int ch = 0; ch < 3; ch++)
+                for (int q = 0; q < 6; q++) a.jac[(int64_t)(6 * ch + q) * a.P_total + ti.pix(k)] = Jp[ch][q];
+        if (a.target) {
+            const float w = a.weight ? a.weight[ti.pix(k)] : 1.f;
+            float z[3];
+            for (int ch = 0; ch < 3; ch++) z[ch] = I[ch] - a.target[ti.plane0 + ch * ti.npix + off];
+            int idx = 0;
+#pragma unroll
+            for (int r = 0; r < 6; r++)
+#pragma unroll
+                for (int q = r; q < 6; q++) {
+                    float h = Jp[0][r] * Jp[0][q];
+                    h = fmaf(Jp[1][r], Jp[1][q], h);
+                    h = fmaf(Jp[2][r], Jp[2][q], h);
+                    nrm[idx] = fmaf(w, h, nrm[idx]);
+                    idx++;
+                }
+#pragma unroll
+            for (int r = 0; r < 6; r++) {
+                float h = Jp[0][r] * z[0];
+                h = fmaf(Jp[1][r], z[1], h);
+                h = fmaf(Jp[2][r], z[2], h);
+                nrm[21 + r] = fmaf(w, h, nrm[21 + r]);
+            }
+            nrm[27] = fmaf(w, fmaf(z[0], z[0], fmaf(z[1], z[1], z[2] * z[2])), nrm[27]);
+        }
+    }
+    if (a.nrm_part) {
+#pragma unroll
+        for (int q = 0; q < kNrm; q++) {
+            const float v = wave_total(nrm[q]);
+            if (lane == 0) s_nrm[wv][q] = (double)v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kNrm) {
+            double v = 0.0;
+            for (int w = 0; w < NW; w++) v += s_nrm[w][threadIdx.x];
+            a.nrm_part[(int64_t)t * kNrm + threadIdx.x] = v;
+        }
+    }
+}
+
+// Per-camera FP64 sums of the item partials (the camera's tiles are the
+// contiguous range [tile_offset, tile_offset + tiles_x * tiles_y)).
+__global__ __launch_bounds__(256) void k_normal_reduce(const double *__restrict__ part,
+                                                       const DevCam *__restrict__ cams, double *__restrict__ HtH,
+                                                       double *__restrict__ Htz, double *__restrict__ zz)
+{
+    __shared__ double s[256 / kWave][kNrm];
+    const int c = blockIdx.x;
+    const int64_t t0 = cams[c].tile_offset, nt = (int64_t)cams[c].tiles_x * cams[c].tiles_y;
+    double acc[kNrm];
+    for (int q = 0; q < kNrm; q++) acc[q] = 0.0;
+    for (int64_t t = threadIdx.x; t < nt; t += 256)
+        for (int q = 0; q < kNrm; q++) acc[q] += part[(t0 + t) * kNrm + q];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (int q = 0; q < kNrm; q++) {
+        double v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+        if (lane == 0) s[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNrm) {
+        double v = 0.0;
+        for (int w = 0; w < 256 / kWave; w++) v += s[w][threadIdx.x];
+        const int q = threadIdx.x;
+        if (q < 21) {
+            if (HtH) {
+                // upper-triangle index q -> (r, col)
+                int r = 0, k = q;
+                while (k >= 6 - r) {
+                    k -= 6 - r;
+                    r++;
+                }
+                const int col = r + k;
+                HtH[(int64_t)c * 36 + r * 6 + col] = v;
+                HtH[(int64_t)c * 36 + col * 6 + r] = v;
+            }
+        } else if (q < 27) {
+            if (Htz) Htz[(int64_t)c * 6 + (q - 21)] = v;
+        } else if (zz) {
+            zz[c] = v;
+        }
+    }
+}
+
 // waves per tile for each tile size
 template <int TS>
 struct Waves {
@@ -749,6 +1004,23 @@ void launch_render_fused(const RenderArgs &a, int variant, int num_cus, hipStrea
 void launch_order_by_length(const uint32_t *ranges, int64_t T, uint32_t *order, hipStream_t s)
 {
     if (T > 0) hipLaunchKernelGGL(k_order_by_length, dim3(1), dim3(1024), 0, s, ranges, T, order);
+}
+
+void launch_render_jvp(const RenderArgs &a, hipStream_t s)
+{
+    if (a.T_total == 0) return;
+    switch (a.o.tile) {
+        case 8: hipLaunchKernelGGL((k_render_jvp<8, 1>), dim3((unsigned)a.T_total), dim3(64), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_render_jvp<16, 4>), dim3((unsigned)a.T_total), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_render_jvp<32, 8>), dim3((unsigned)a.T_total), dim3(512), 0, s, a); break;
+    }
+}
+
+void launch_normal_reduce(const double *nrm_part, const DevCam *cams, int C, double *HtH, double *Htz, double *zz,
+                          hipStream_t s)
+{
+    if (C == 0) return;
+    hipLaunchKernelGGL(k_normal_reduce, dim3((unsigned)C), dim3(256), 0, s, nrm_part, cams, HtH, Htz, zz);
 }
 
 void launch_reduce_f64(const double *part, int64_t n, double *out, hipStream_t s)

@@ -168,9 +168,13 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid)
 }
 
 // Digit histogram of one 4096-key block, digit-major output hist[d * nb + block].
+// With `drop`, keys equal to kDropKey are left out (the first pass of a sort
+// that also compacts).
+constexpr uint32_t kDropKey = 0xffffffffu;
+
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__restrict__ keys, int64_t n_max,
                                                           const int64_t *__restrict__ d_n, int shift,
-                                                          uint32_t *__restrict__ hist, int64_t nb)
+                                                          uint32_t *__restrict__ hist, int64_t nb, bool drop)
 {
     __shared__ uint32_t s_cnt[kSortThreads / kWave][256];
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
@@ -180,8 +184,9 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__rest
     const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wv * (kSortTile / (kSortThreads / kWave));
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
-        const bool valid = j < n;
-        const uint32_t d = valid ? (keys[j] >> shift) & 0xffu : 0u;
+        const uint32_t kj = j < n ? keys[j] : kDropKey;
+        const bool valid = j < n && !(drop && kj == kDropKey);
+        const uint32_t d = valid ? (kj >> shift) & 0xffu : 0u;
         const uint64_t peers = digit_peers(d, valid);
         if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) s_cnt[wv][d] += __popcll(peers);
     }
@@ -198,7 +203,8 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
                                                              const uint32_t *__restrict__ vin,
                                                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                              int64_t n_max, const int64_t *__restrict__ d_n, int shift,
-                                                             const uint32_t *__restrict__ hist_off, int64_t nb)
+                                                             const uint32_t *__restrict__ hist_off, int64_t nb,
+                                                             bool drop)
 {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t s_cnt[NW][256];   // per-wave running digit counts, then wave bases
@@ -206,6 +212,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     __shared__ uint32_t s_glob[256];      // global first position of each digit for this block
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_nloc;           // keys of this block that are kept
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < NW * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
     __syncthreads();
@@ -216,8 +223,8 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
-        const bool valid = j < n;
-        key[r] = valid ? kin[j] : 0xffffffffu;
+        key[r] = j < n ? kin[j] : kDropKey;
+        const bool valid = j < n && !(drop && key[r] == kDropKey);
         val[r] = valid ? vin[j] : 0u;
         const uint32_t d = (key[r] >> shift) & 0xffu;
         const uint64_t peers = digit_peers(d, valid);
@@ -257,6 +264,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
             s_loc[lane * 4 + k] = run;
             run += t[k];
         }
+        if (lane == kWave - 1) s_nloc = run;
     }
     __syncthreads();
     for (int r = 0; r < kSortItems; r++) {
@@ -267,8 +275,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
         s_val[pos] = val[r];
     }
     __syncthreads();
-    const int64_t nloc64 = n - block_base;
-    const int nloc = nloc64 < kSortTile ? (int)nloc64 : kSortTile;
+    const int nloc = (int)s_nloc;
     for (int p = threadIdx.x; p < nloc; p += kSortThreads) {
         const uint32_t k = s_key[p];
         const uint32_t d = (k >> shift) & 0xffu;
@@ -289,95 +296,76 @@ __global__ void k_depth_keys(const gsl_splat *__restrict__ splats, const int32_t
     vals[m] = (uint32_t)m;
 }
 
+// Positions at or beyond the number of kept records (*d_V) get 0.
 __global__ void k_gather_counts(const uint32_t *__restrict__ order, const int32_t *__restrict__ tiles, int64_t M,
-                                uint32_t *__restrict__ counts)
+                                const int64_t *__restrict__ d_V, uint32_t *__restrict__ counts)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
-    counts[j] = (uint32_t)tiles[order[j]];
+    counts[j] = j < *d_V ? (uint32_t)tiles[order[j]] : 0u;
 }
 
-// Tiles a splat's alpha_min ellipse reaches, with the quarter-row band mask of
-// each (bit q: rows [q*T/4, (q+1)*T/4) of the tile).
-__device__ __forceinline__ bool tile_hit(const EllipseTest &e, const DevCam &cam, int tile, int tx, int ty,
+// Extreme dy (sgn = +1: largest, -1: smallest) of the ellipse
+// |L d|^2 <= kq on the vertical line dx = const: the roots of
+// (l12^2 + l22^2) dy^2 + 2 l11 l12 dx dy + l11^2 dx^2 - kq = 0.
+__device__ __forceinline__ float ellipse_dy_on_line(const EllipseTest &e, float dx, float sgn)
+{
+    const float cc = fmaf(e.l12, e.l12, e.l22 * e.l22);
+    const float u = e.l22 * e.l11 * dx;
+    const float disc = fmaxf(fmaf(cc, e.kq, -u * u), 0.f);
+    return (fmaf(sgn, sqrtf(disc), -e.l11 * e.l12 * dx)) / cc;
+}
+
+// Does the splat's alpha_min ellipse reach tile (tx, ty), and which
+// quarter-row bands of it (bit q: rows [q*T/4, (q+1)*T/4) of the tile)?
+// The ellipse and the tile's column strip are convex, so the rows their
+// intersection reaches form one interval [lo, hi]: its top is the
+// ellipse's topmost point (dy = sqrt(kq) / l22 at dx = kh dy) when that lies
+// within the strip, else the top of the ellipse on the strip edge nearest to
+// it; likewise the bottom.  A band is marked when it overlaps [lo, hi].
+__device__ __forceinline__ bool tile_hit(const EllipseTest &e, int W, int H, int tile, int tx, int ty,
                                          uint32_t *bands)
 {
     float rx0, rx1, ry0, ry1;
-    tile_rect(tx, ty, tile, cam.W, cam.H, rx0, rx1, ry0, ry1);
+    tile_rect(tx, ty, tile, W, H, rx0, rx1, ry0, ry1);
     if (!ellipse_hits_rect(e, rx0, rx1, ry0, ry1)) return false;
     if (bands) {
+        const float ux0 = rx0 - e.mx, ux1 = rx1 - e.mx;
+        const float yext = sqrtf(e.kq) / e.l22;
+        const float xt = e.kh * yext;  // dx of the topmost point; the bottommost is at -xt
+        const float hi = (xt >= ux0 && xt <= ux1) ? yext : ellipse_dy_on_line(e, fminf(fmaxf(xt, ux0), ux1), 1.f);
+        const float lo =
+            (-xt >= ux0 && -xt <= ux1) ? -yext : ellipse_dy_on_line(e, fminf(fmaxf(-xt, ux0), ux1), -1.f);
         const int q = tile / 4;
         uint32_t b = 0;
         for (int k = 0; k < 4; k++) {
-            const float by0 = (float)(ty * tile + k * q) + 0.5f;
-            const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1);
-            if (by0 <= by1 && ellipse_hits_rect(e, rx0, rx1, by0, by1)) b |= 1u << k;
+            const float by0 = (float)(ty * tile + k * q) + 0.5f - e.my;
+            const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1) - e.my;
+            if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << k;
         }
         *bands = b;
     }
     return true;
 }
 
-// Counting and emitting share one walk over a record's bbox tiles.  A lane
-// walks its own record when the bbox spans at most kSmallTiles tiles; larger
-// records are walked by the whole wave afterwards, one at a time, lane l
-// testing tile t0 + l, with a ballot and the popcount below the lane giving
-// each hit's slot.  So a large splat neither stalls a wave nor leaves it idle
-// on small ones, and the hit decisions are the same code for both kernels.
-constexpr int kSmallTiles = 8;
-
-template <bool emit>
-__device__ __forceinline__ uint32_t lane_record_tiles(const gsl_splat &s, const DevCam &cam, int tile, float kq,
-                                                      uint32_t base, uint32_t limit, uint32_t i,
-                                                      uint32_t *tile_ids, uint32_t *gauss_ids)
-{
-    const EllipseTest e = ellipse_test(s, kq);
-    const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
-    uint32_t n = 0;
-    for (int ty = ty0; ty <= ty1; ty++)
-        for (int tx = tx0; tx <= tx1; tx++) {
-            uint32_t bands = 0;
-            if (!tile_hit(e, cam, tile, tx, ty, emit ? &bands : nullptr)) continue;
-            if (emit && n < limit) {  // never beyond the record's counted range
-                tile_ids[base + n] = (uint32_t)(cam.tile_offset + ty * cam.tiles_x + tx);
-                gauss_ids[base + n] = i | (bands << kGidBits);
-            }
-            n++;
-        }
-    return n;
-}
-
-template <bool emit>
-__device__ __forceinline__ uint32_t wave_record_tiles(const gsl_splat &s, const DevCam &cam, int tile, float kq,
-                                                      int lane, uint32_t base, uint32_t limit, uint32_t i,
-                                                      uint32_t *tile_ids, uint32_t *gauss_ids)
-{
-    const EllipseTest e = ellipse_test(s, kq);
-    const int tx0 = s.x0 / tile, tx1 = s.x1 / tile, ty0 = s.y0 / tile, ty1 = s.y1 / tile;
-    const int nx = tx1 - tx0 + 1, nt = nx * (ty1 - ty0 + 1);
-    uint32_t n = 0;
-    for (int t0 = 0; t0 < nt; t0 += kWave) {
-        const int t = t0 + lane;
-        bool hit = false;
-        int tx = 0, ty = 0;
-        uint32_t bands = 0;
-        if (t < nt) {
-            ty = ty0 + t / nx;
-            tx = tx0 + t - (ty - ty0) * nx;
-            hit = tile_hit(e, cam, tile, tx, ty, emit ? &bands : nullptr);
-        }
-        const uint64_t mask = __ballot(hit);
-        if (emit && hit) {
-            const uint32_t r = n + (uint32_t)__popcll(mask & lanemask_lt(lane));
-            if (r < limit) {  // never beyond the record's counted range
-                tile_ids[base + r] = (uint32_t)(cam.tile_offset + ty * cam.tiles_x + tx);
-                gauss_ids[base + r] = i | (bands << kGidBits);
-            }
-        }
-        n += (uint32_t)__popcll(mask);
-    }
-    return n;
-}
+// Counting and emitting share one walk.  A wave expands the bbox tiles of its
+// 64 records into one flat list (an exclusive scan of the bbox tile counts
+// gives each record its segment) and tests 64 list entries per step, lane l
+// entry t0 + l; the entry's record is found by a binary search over the
+// lanes' inclusive scan values and its parameters are read from LDS.  Every
+// lane is busy whatever the mix of small and large splats, and no step waits
+// on a global load.  Within a record the hits keep bbox order (row-major),
+// so an instance's slot is the record's hits before this step plus the hits
+// of the same record on lower lanes.
+struct alignas(16) RecTiles {
+    float mx, my, l11, l12, l22, kq, kv, kh;
+    int32_t tx0, ty0, nx, tiles_x;
+    int32_t tile_base, W, H;
+    uint32_t gid;
+    uint32_t base, limit, excl;
+    float rnx;  // 1 / nx
+};
+static_assert(sizeof(RecTiles) == 80, "RecTiles layout");
 
 __device__ __forceinline__ int bbox_tiles(const gsl_splat &s, int tile)
 {
@@ -385,40 +373,115 @@ __device__ __forceinline__ int bbox_tiles(const gsl_splat &s, int tile)
     return (s.x1 / tile - s.x0 / tile + 1) * (s.y1 / tile - s.y0 / tile + 1);
 }
 
-// tiles_touched of every record (natural order), one lane per record.
+__device__ __forceinline__ void rec_fill(RecTiles &r, const gsl_splat &s, const DevCam &cam, int tile, float kq,
+                                         uint32_t gid, uint32_t base, uint32_t limit)
+{
+    const EllipseTest e = ellipse_test(s, kq);
+    r.mx = e.mx;
+    r.my = e.my;
+    r.l11 = e.l11;
+    r.l12 = e.l12;
+    r.l22 = e.l22;
+    r.kq = e.kq;
+    r.kv = e.kv;
+    r.kh = e.kh;
+    r.tx0 = s.x0 / tile;
+    r.ty0 = s.y0 / tile;
+    r.nx = s.x1 / tile - r.tx0 + 1;
+    r.tiles_x = cam.tiles_x;
+    r.tile_base = cam.tile_offset;
+    r.W = cam.W;
+    r.H = cam.H;
+    r.gid = gid;
+    r.base = base;
+    r.limit = limit;
+    r.rnx = 1.0f / (float)r.nx;
+}
+
+// Lanes [lo, hi) of a wave, lo and hi clamped to [0, 64].
+__device__ __forceinline__ uint64_t lane_range(int64_t lo, int64_t hi)
+{
+    lo = lo < 0 ? 0 : (lo > kWave ? kWave : lo);
+    hi = hi < 0 ? 0 : (hi > kWave ? kWave : hi);
+    const uint64_t below_hi = hi >= kWave ? ~0ull : ((1ull << hi) - 1ull);
+    const uint64_t below_lo = lo >= kWave ? ~0ull : ((1ull << lo) - 1ull);
+    return below_hi & ~below_lo;
+}
+
+// Walks the flat tile list of the wave's records (rec: this wave's 64
+// entries, already visible to all its lanes).  Returns the hit count of the
+// calling lane's own record ([excl, incl) is its segment).
+template <bool emit>
+__device__ __forceinline__ uint32_t expand_tiles(const RecTiles *rec, int lane, uint32_t excl, uint32_t incl,
+                                                 uint32_t total, int tile, uint32_t *__restrict__ tile_ids,
+                                                 uint32_t *__restrict__ gauss_ids)
+{
+    uint32_t own = 0;
+    for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+        const uint32_t g = t0 + (uint32_t)lane;
+        int o = 0;  // number of lanes whose segment ends at or before g
+        for (int b = 32; b; b >>= 1)
+            if (__shfl(incl, o + b - 1, kWave) <= g) o += b;
+        bool hit = false;
+        uint32_t bands = 0, slot = 0;
+        int tx = 0, ty = 0;
+        const RecTiles &r = rec[o < kWave ? o : kWave - 1];
+        if (g < total) {
+            const uint32_t t = g - r.excl;
+            uint32_t q = (uint32_t)((float)t * r.rnx);
+            if (q * (uint32_t)r.nx > t) q--;
+            else if ((q + 1) * (uint32_t)r.nx <= t) q++;
+            ty = r.ty0 + (int)q;
+            tx = r.tx0 + (int)(t - q * (uint32_t)r.nx);
+            EllipseTest e;
+            e.mx = r.mx;
+            e.my = r.my;
+            e.l11 = r.l11;
+            e.l12 = r.l12;
+            e.l22 = r.l22;
+            e.kq = r.kq;
+            e.kv = r.kv;
+            e.kh = r.kh;
+            hit = tile_hit(e, r.W, r.H, tile, tx, ty, emit ? &bands : nullptr);
+        }
+        const uint64_t mask = __ballot(hit);
+        if (emit) {
+            const uint32_t before = __shfl(own, o < kWave ? o : kWave - 1, kWave);
+            if (hit) {
+                const uint64_t seg = lane_range((int64_t)r.excl - (int64_t)t0, lane);
+                slot = before + (uint32_t)__popcll(mask & seg);
+                if (slot < r.limit) {  // never beyond the record's counted range
+                    tile_ids[r.base + slot] = (uint32_t)(r.tile_base + ty * r.tiles_x + tx);
+                    gauss_ids[r.base + slot] = r.gid | (bands << kGidBits);
+                }
+            }
+        }
+        own += (uint32_t)__popcll(mask & lane_range((int64_t)excl - (int64_t)t0, (int64_t)incl - (int64_t)t0));
+    }
+    return own;
+}
+
+// tiles_touched of every record (natural order).
 __global__ __launch_bounds__(256) void k_count_tiles(const gsl_splat *__restrict__ splats,
                                                      const DevCam *__restrict__ cams, int N, int64_t M, int tile,
                                                      float alpha_min, int32_t *__restrict__ tiles)
 {
+    __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    gsl_splat s;
-    int nt = 0;
+    uint32_t nt = 0;
     if (m < M) {
-        s = splats[m];
-        nt = bbox_tiles(s, tile);
+        const gsl_splat s = splats[m];
+        nt = (uint32_t)bbox_tiles(s, tile);
+        if (nt) rec_fill(rec[threadIdx.x], s, cams[m / N], tile, ellipse_k(s.opacity, alpha_min), 0, 0, 0);
     }
-    const bool big = nt > kSmallTiles;
-    if (m < M && !big) {
-        uint32_t n = 0;
-        if (nt > 0) {
-            const int c = (int)(m / N);
-            n = lane_record_tiles<false>(s, cams[c], tile, ellipse_k(s.opacity, alpha_min), 0, 0, 0, nullptr,
-                                         nullptr);
-        }
-        tiles[m] = (int32_t)n;
-    }
-    uint64_t todo = __ballot(big);
-    while (todo) {
-        const int src = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const int64_t mb = __shfl(m, src, kWave);
-        const gsl_splat sb = splats[mb];
-        const int c = (int)(mb / N);
-        const uint32_t n = wave_record_tiles<false>(sb, cams[c], tile, ellipse_k(sb.opacity, alpha_min), lane, 0, 0,
-                                                    0, nullptr, nullptr);
-        if (lane == 0) tiles[mb] = (int32_t)n;
-    }
+    const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
+    rec[threadIdx.x].excl = excl;
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    __syncthreads();
+    const uint32_t n = expand_tiles<false>(rec + (threadIdx.x & ~(kWave - 1)), lane, excl, incl, total, tile,
+                                           nullptr, nullptr);
+    if (m < M) tiles[m] = (int32_t)n;
 }
 
 // One (tile, Gaussian | bands) instance per reached tile, records in depth order.
@@ -430,41 +493,29 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
                                               uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ gauss_ids,
                                               int32_t *__restrict__ d_status)
 {
+    __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t K = *d_K;
     if (j == 0) *d_status = K > capacity ? GSL_ECAPACITY : GSL_OK;
-    if (K > capacity) return;  // uniform: every lane reads the same K
-    uint32_t cnt = 0, m = 0;
-    gsl_splat s;
-    int nt = 0;
+    if (K > capacity) return;  // uniform: every thread reads the same K
+    uint32_t nt = 0;
     if (j < M) {
-        cnt = counts[j];
+        const uint32_t cnt = counts[j];
         if (cnt) {
-            m = order[j];
-            s = splats[m];
-            nt = bbox_tiles(s, tile);
+            const uint32_t m = order[j];
+            const gsl_splat s = splats[m];
+            const uint32_t c = m / (uint32_t)N;
+            nt = (uint32_t)bbox_tiles(s, tile);
+            rec_fill(rec[threadIdx.x], s, cams[c], tile, ellipse_k(s.opacity, alpha_min), m - c * (uint32_t)N,
+                     offsets[j], cnt);
         }
     }
-    const bool big = nt > kSmallTiles;
-    if (cnt && !big) {
-        const int c = (int)(m / (uint32_t)N);
-        const uint32_t i = m - (uint32_t)c * (uint32_t)N;
-        lane_record_tiles<true>(s, cams[c], tile, ellipse_k(s.opacity, alpha_min), offsets[j], cnt, i, tile_ids,
-                                gauss_ids);
-    }
-    uint64_t todo = __ballot(big);
-    while (todo) {
-        const int src = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const int64_t jb = __shfl(j, src, kWave);
-        const uint32_t mb = order[jb];
-        const gsl_splat sb = splats[mb];
-        const int c = (int)(mb / (uint32_t)N);
-        const uint32_t i = mb - (uint32_t)c * (uint32_t)N;
-        wave_record_tiles<true>(sb, cams[c], tile, ellipse_k(sb.opacity, alpha_min), lane, offsets[jb], counts[jb],
-                                i, tile_ids, gauss_ids);
-    }
+    const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
+    rec[threadIdx.x].excl = excl;
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    __syncthreads();
+    expand_tiles<true>(rec + (threadIdx.x & ~(kWave - 1)), lane, excl, incl, total, tile, tile_ids, gauss_ids);
 }
 
 __global__ void k_ranges(const uint32_t *__restrict__ tile_ids, const int64_t *__restrict__ d_K, int64_t capacity,
@@ -511,17 +562,24 @@ void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint6
 
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint64_t *partial,
-                      hipStream_t s)
+                      hipStream_t s, int64_t *d_kept)
 {
     const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
-    if (nb == 0 || bits <= 0) return 0;
+    if (nb == 0 || bits <= 0) {
+        if (d_kept) launch_fill_f64(reinterpret_cast<double *>(d_kept), 0.0, 1, s);  // all-zero bits == int64 0
+        return 0;
+    }
     uint32_t *kin = keys, *vin = vals, *kout = keys2, *vout = vals2;
     int where = 0;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, n_max, d_n, shift, hist, nb);
-        launch_scan_u32(hist, hist_off, 256 * nb, partial, nullptr, s);
+        // with d_kept the first pass drops kDropKey keys and counts the rest
+        const bool drop = d_kept && shift == 0;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, n_max, d_n, shift, hist, nb,
+                           drop);
+        launch_scan_u32(hist, hist_off, 256 * nb, partial, drop ? d_kept : nullptr, s);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_max,
-                           d_n, shift, hist_off, nb);
+                           d_n, shift, hist_off, nb, drop);
+        if (drop) d_n = d_kept;
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout;
         kout = tk; vout = tv;
@@ -538,10 +596,11 @@ void launch_depth_keys(const gsl_splat *splats, const int32_t *tiles, int64_t M,
                            vals);
 }
 
-void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, uint32_t *counts, hipStream_t s)
+void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, const int64_t *d_V,
+                          uint32_t *counts, hipStream_t s)
 {
     if (M > 0)
-        hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, order, tiles, M,
+        hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, order, tiles, M, d_V,
                            counts);
 }
 

@@ -284,6 +284,83 @@ def render_stats(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, b
     return tuple(int(x) for x in counts.cpu().tolist())
 
 
+# ---------------------------------------------------------------- pose Jacobians (IESKF visual update)
+
+@dataclass
+class PoseJacobian:
+    """Outputs of gsl_pose_jacobian: image (3 P_total), jac (18, P_total) with
+    plane 6 ch + j = dI_ch/dxi_j, and per camera HtH (C,6,6), Htz (C,6),
+    zz (C,) (None where not requested)."""
+    image: Optional[torch.Tensor]
+    jac: Optional[torch.Tensor]
+    HtH: Optional[torch.Tensor]
+    Htz: Optional[torch.Tensor]
+    zz: Optional[torch.Tensor]
+
+
+def pose_jacobian(ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, proj: Proj, bins: Bins,
+                  target: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None,
+                  want_image: bool = False, want_jac: bool = False) -> PoseJacobian:
+    """Per-pixel twist Jacobians of the rendered colour and, with a target
+    image, the per-camera normal equations of the photometric model."""
+    dev = ctx.device
+    image = torch.empty(3 * cams.P_total, dtype=torch.float32, device=dev) if want_image else None
+    jac = torch.empty(18, cams.P_total, dtype=torch.float32, device=dev) if want_jac else None
+    HtH = Htz = zz = None
+    if target is not None:
+        HtH = torch.empty(cams.C, 6, 6, dtype=torch.float64, device=dev)
+        Htz = torch.empty(cams.C, 6, dtype=torch.float64, device=dev)
+        zz = torch.empty(cams.C, dtype=torch.float64, device=dev)
+        target = target.contiguous()
+    if weight is not None:
+        weight = weight.contiguous()
+    n = C.c_size_t()
+    A.check(A.lib().gsl_pose_jacobian_workspace_size(ctx.h, cams.arr, cams.C, g.N, C.byref(o), bins.capacity,
+                                                     C.byref(n)))
+    ws = ctx.workspace(int(n.value))
+    gs, ps, bs = g.struct(), proj.struct(), bins.struct()
+    A.check(A.lib().gsl_pose_jacobian(ctx.h, C.byref(gs), cams.arr, cams.C, C.byref(o), C.byref(ps), C.byref(bs),
+                                      _p(target), _p(weight), _p(image), _p(jac), _p(HtH), _p(Htz), _p(zz), _p(ws),
+                                      ws.numel(), _stream()))
+    return PoseJacobian(image, jac, HtH, Htz, zz)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def imu_to_camera_twist(R_CI, t_CI, R_CW) -> np.ndarray:
+    """A (6,6) with xi_cam = A xi_imu (gsl_imu_to_camera_twist)."""
+    R_CI = np.ascontiguousarray(R_CI, np.float64).reshape(9)
+    t_CI = np.ascontiguousarray(t_CI, np.float64).reshape(3)
+    R_CW = np.ascontiguousarray(R_CW, np.float64).reshape(9)
+    out = np.zeros(36)
+    A.check(A.lib().gsl_imu_to_camera_twist(_dptr(R_CI), _dptr(t_CI), _dptr(R_CW), _dptr(out)))
+    return out.reshape(6, 6)
+
+
+def ieskf_pose_update(HtRH, HtRz, P, dx_prior=None):
+    """(delta (6,), P_post (6,6)) of one IESKF update (gsl_ieskf_pose_update)."""
+    HtRH = np.ascontiguousarray(HtRH, np.float64).reshape(36)
+    HtRz = np.ascontiguousarray(HtRz, np.float64).reshape(6)
+    P = np.ascontiguousarray(P, np.float64).reshape(36)
+    dx = None if dx_prior is None else np.ascontiguousarray(dx_prior, np.float64).reshape(6)
+    delta, Pn = np.zeros(6), np.zeros(36)
+    A.check(A.lib().gsl_ieskf_pose_update(_dptr(HtRH), _dptr(HtRz), _dptr(P), None if dx is None else _dptr(dx),
+                                          _dptr(delta), _dptr(Pn)))
+    return delta, Pn.reshape(6, 6)
+
+
+def ieskf_visual_update(HtH_cam, Htz_cam, A_imu, P, dx_prior=None, noise_var: float = 1.0):
+    """IESKF update of the IMU pose from one camera's photometric normal
+    equations: H_imu = H_cam A, R = noise_var I (the per-pixel weights, if
+    any, already applied)."""
+    HtH_cam = np.asarray(HtH_cam, np.float64)
+    Htz_cam = np.asarray(Htz_cam, np.float64)
+    A_imu = np.asarray(A_imu, np.float64)
+    return ieskf_pose_update(A_imu.T @ HtH_cam @ A_imu / noise_var, A_imu.T @ Htz_cam / noise_var, P, dx_prior)
+
+
 # ---------------------------------------------------------------- window
 
 class Window:

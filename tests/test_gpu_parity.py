@@ -208,6 +208,96 @@ def test_bin_sort_bit_exact(oracle, tile):
     assert nboundary <= 2
 
 
+@pytest.mark.parametrize("tile", [8, 32])
+def test_bin_sort_large_splats(tile):
+    """Splats that span thousands of tiles among many small ones, on a
+    1280x1024 and a 320x200 camera: the wave-wide tile expansion runs over many
+    steps with records straddling steps.  The count equals the emitted
+    instances, the order is bit-exact, and the tile sets of the largest
+    splats (and a sample of the rest) equal the float32 recount."""
+    cams = [_rot_cam(1280, 1024, 1000.0, 21), _rot_cam(320, 200, 260.0, 22)]
+    big = S.random_scene(24, cams[0], 5, zmin=1.0, zmax=3.0, smin=0.3, smax=1.5)
+    small = S.random_scene(20000, cams[0], 6, zmin=1.0, zmax=6.0, smin=0.002, smax=0.05)
+    sc = S.Scene(np.concatenate([big.mean, small.mean]), np.concatenate([big.scale, small.scale]),
+                 np.concatenate([big.quat, small.quat]), np.concatenate([big.opacity, small.opacity]),
+                 np.concatenate([big.color, small.color]), cams)
+    st = gpu_forward(sc, sc.cams, tile=tile)
+    f = st["proj"].fields()
+    b = st["bins"]
+    K = b.K
+    assert int(b.d_status.item()) == 0
+    assert K == int(f["tiles_touched"].sum())
+    tid, gid = _gpu_instances(st)
+    tiles_x, tiles_y, toff = _tile_layout(sc.cams, tile)
+    cam_of = np.searchsorted(toff, tid, "right") - 1
+    dbits = np.array(f["depth"][cam_of, gid].view(np.uint32), np.int64)
+    order = np.lexsort((gid, dbits, tid))
+    np.testing.assert_array_equal(order, np.arange(K))
+    amin = F32(1.0 / 255.0)
+    rng = np.random.default_rng(3)
+    nbig = 0
+    for c, cam in enumerate(sc.cams):
+        sel = cam_of == c
+        tsel, gsel = tid[sel] - toff[c], gid[sel]
+        tt = f["tiles_touched"][c]
+        cand = np.nonzero(tt)[0]
+        pick = np.concatenate([cand[cand < 24], rng.choice(cand[cand >= 24], 40, replace=False)])
+        for i in pick:
+            got = set(tsel[gsel == i].tolist())
+            assert len(got) == tt[i]
+            bb = f["bbox"][c, i]
+            kq = F32(2.0 * np.log(np.float64(f["opacity"][c, i]) / np.float64(amin)) + 0.01)
+            tys, txs = np.mgrid[bb[1] // tile:bb[3] // tile + 1, bb[0] // tile:bb[2] // tile + 1]
+            txs, tys = txs.ravel(), tys.ravel()
+            nbig = max(nbig, len(txs))
+            x0 = (txs * tile).astype(F32) + F32(0.5)
+            x1 = np.minimum((txs + 1) * tile, cam.width).astype(F32) - F32(0.5)
+            y0 = (tys * tile).astype(F32) + F32(0.5)
+            y1 = np.minimum((tys + 1) * tile, cam.height).astype(F32) - F32(0.5)
+            hit, best = _ellipse_hits_f32(f["mx"][c, i], f["my"][c, i], f["l11"][c, i], f["l12"][c, i],
+                                          f["l22"][c, i], kq, x0, x1, y0, y1)
+            want = {int(ty * tiles_x[c] + tx) for tx, ty, h in zip(txs, tys, hit) if h}
+            edge = {int(ty * tiles_x[c] + tx) for tx, ty, bq in zip(txs, tys, best)
+                    if abs(float(bq) - float(kq)) <= 1e-5 * float(kq)}
+            assert (want ^ got) <= edge, (c, i)
+    assert nbig > 64 * 16  # some record spans many expansion steps
+
+
+def test_size_limits_rejected():
+    """Limits the host checks before any launch: N < 2^28 (the instance id
+    keeps 4 band bits), C*N < 2^32, 1 <= C <= 1024, image sides <= 32767,
+    tile in {8, 16, 32}, capacity < 2^32; the largest accepted sizes pass."""
+    O = ops()
+    A = O.A
+    ctx = context()
+    cams = O.CameraSet([S.Camera(100, 100, 64, 48, 128, 96, np.eye(3), np.zeros(3))])
+    o = O.opts(16)
+
+    def code(fn):
+        with pytest.raises(A.GslError) as e:
+            fn()
+        return e.value.code
+
+    assert O.workspace_size(ctx, cams, (1 << 28) - 1, o, 0) > 0
+    assert code(lambda: O.workspace_size(ctx, cams, 1 << 28, o, 0)) == A.GSL_EINVAL
+    assert code(lambda: O.workspace_size(ctx, cams, -1, o, 0)) == A.GSL_EINVAL
+    assert code(lambda: O.workspace_size(ctx, cams, 100, o, 1 << 32)) == A.GSL_EINVAL
+    many = O.CameraSet([S.Camera(100, 100, 64, 48, 128, 96, np.eye(3), np.zeros(3))] * 17)
+    assert code(lambda: O.workspace_size(ctx, many, (1 << 28) - 1, o, 0)) == A.GSL_EINVAL  # C*N >= 2^32
+    too_many = O.CameraSet([S.Camera(100, 100, 4, 4, 8, 8, np.eye(3), np.zeros(3))] * 1025)
+    assert code(lambda: O.workspace_size(ctx, too_many, 10, o, 0)) == A.GSL_ENOTSUP
+    wide = O.CameraSet([S.Camera(100, 100, 64, 48, 32768, 8, np.eye(3), np.zeros(3))])
+    assert code(lambda: O.workspace_size(ctx, wide, 10, o, 0)) == A.GSL_EINVAL
+    widest = O.CameraSet([S.Camera(100, 100, 64, 48, 32767, 8, np.eye(3), np.zeros(3))])
+    assert O.workspace_size(ctx, widest, 10, o, 0) > 0
+    bad = O.opts(16)
+    bad.tile = 12
+    assert code(lambda: O.workspace_size(ctx, cams, 10, bad, 0)) == A.GSL_ENOTSUP
+    bad = O.opts(16)
+    bad.alpha_min = 0.995
+    assert code(lambda: O.workspace_size(ctx, cams, 10, bad, 0)) == A.GSL_EINVAL
+
+
 def test_bin_sort_capacity_overflow():
     O = ops()
     sc = _scene_multi(4000, 3)
@@ -443,7 +533,8 @@ def test_window_graph_replay_and_variants():
         assert torch.equal(w.image, ref[3])
         assert abs(float(w.d_loss.item()) - float(ref[2].item())) <= 1e-9 * abs(float(ref[2].item()))
         torch.testing.assert_close(w.grads.mean, ref[0], rtol=1e-5, atol=1e-6 * float(ref[0].abs().max()))
-        torch.testing.assert_close(w.grads.pose, ref[1], rtol=1e-6, atol=1e-9)
+        # float32 atomics add the 2D gradients in a different order on every run
+        torch.testing.assert_close(w.grads.pose, ref[1], rtol=1e-5, atol=1e-6 * float(ref[1].abs().max()))
         # eager work between replays
         _ = (w.target * 2).sum().item()
     tile, times = w.tune()
