@@ -101,9 +101,23 @@ typedef struct {
 } gsl_splat;
 
 /* Output of gsl_project for C cameras x N Gaussians (device). */
+/* Binning record of one projected Gaussian in one camera (32 bytes, 32-byte
+ * aligned): the splat's mean and conic factor as in gsl_splat, kq such that
+ * alpha >= alpha_min only inside the ellipse |L (x - mu)|^2 <= kq
+ * (kq = 2 ln(opacity / alpha_min) + 0.01), and the same bbox.  gsl_project
+ * writes it; gsl_bin_sort reads it in depth order, so its size is what that
+ * gather moves. */
+typedef struct {
+    float mx, my;
+    float l11, l12;
+    float l22, kq;
+    int16_t x0, y0, x1, y1;
+} gsl_binrec;
+
 typedef struct {
     gsl_splat *splats;      /* [C][N] */
-    int32_t *tiles_touched; /* [C][N] number of tiles the bbox overlaps */
+    int32_t *tiles_touched; /* [C][N] number of tiles the alpha_min ellipse reaches */
+    gsl_binrec *binrecs;    /* [C][N], 32-byte aligned */
 } gsl_proj;
 
 /* Tile bins (device).  After gsl_bin_sort, instances [0, K) are ordered by

@@ -238,7 +238,8 @@ int check_gauss(const gsl_gaussians *g, bool need_all)
 int check_proj(const gsl_proj *p, const Layout &L)
 {
     if (!p) return fail(GSL_EINVAL, "proj is NULL");
-    if (L.M > 0 && (!p->splats || !p->tiles_touched)) return fail(GSL_EINVAL, "proj buffer is NULL");
+    if (L.M > 0 && (!p->splats || !p->tiles_touched || !p->binrecs)) return fail(GSL_EINVAL, "proj buffer is NULL");
+    if (reinterpret_cast<uintptr_t>(p->binrecs) % 32 != 0) return fail(GSL_EINVAL, "binrecs not 32-byte aligned");
     return GSL_OK;
 }
 
@@ -259,7 +260,7 @@ void do_upload(const Prepared &p, void *ws, hipStream_t s)
 
 void do_project(const Prepared &p, const gsl_gaussians *g, gsl_proj *out, void *ws, hipStream_t s)
 {
-    launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->tiles_touched, s);
+    launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->binrecs, out->tiles_touched, s);
 }
 
 void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *ws, hipStream_t s)
@@ -285,8 +286,8 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     uint32_t *ek = bins->tile_ids, *ev = bins->gauss_ids;
     uint32_t *ak = at<uint32_t>(ws, W.ikey2), *av = at<uint32_t>(ws, W.ival2);
     if (passes & 1) std::swap(ek, ak), std::swap(ev, av);
-    launch_emit(order, offsets, counts, proj->splats, at<DevCam>(ws, W.cams), L, p.o.alpha_min, bins->d_K,
-                bins->capacity_K, ek, ev, bins->d_status, s);
+    launch_emit(order, offsets, counts, proj->binrecs, at<DevCam>(ws, W.cams), L, bins->d_K, bins->capacity_K, ek, ev,
+                bins->d_status, s);
     launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, partial, s);
     // 4. per-tile ranges
     launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);
@@ -599,7 +600,7 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
     gk.v.push_back(loss);
     auto ptr = [&](const void *q) { gk.v.push_back((int64_t)(uintptr_t)q); };
     ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color);
-    ptr(target); ptr(proj->splats); ptr(proj->tiles_touched);
+    ptr(target); ptr(proj->splats); ptr(proj->tiles_touched); ptr(proj->binrecs);
     ptr(bins->tile_ids); ptr(bins->gauss_ids); ptr(bins->ranges); ptr(bins->d_K); ptr(bins->d_status);
     gk.v.push_back(bins->capacity_K);
     ptr(image); ptr(d_loss); ptr(grads->g_mean); ptr(grads->g_scale); ptr(grads->g_quat);

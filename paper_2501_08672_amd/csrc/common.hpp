@@ -24,6 +24,7 @@ struct DevCam {
     int64_t pix_offset;   // first pixel of this camera in the packed layout
 };
 static_assert(sizeof(DevCam) == 96, "DevCam layout");
+static_assert(sizeof(gsl_binrec) == 32, "gsl_binrec layout");
 
 // Constants of one call, passed by value.
 struct DevOpts {
@@ -43,6 +44,7 @@ constexpr int kG2 = 9;
 // top of 2 ln(sigma / alpha_min) that covers the float32 evaluation of the
 // power in the renderer.  Computed in float64 and rounded once, so every
 // kernel that needs it gets the same float.
+// kq of the alpha_min ellipse (binning record), in float64 then rounded once.
 __device__ __forceinline__ float ellipse_k(float opacity, float alpha_min)
 {
     return (float)(2.0 * log((double)opacity / (double)alpha_min) + 0.01);
@@ -63,7 +65,7 @@ struct EllipseTest {
     float kh;  // -l12 / l11
 };
 
-__device__ __forceinline__ EllipseTest ellipse_test(const gsl_splat &s, float kq)
+__device__ __forceinline__ EllipseTest ellipse_test(const gsl_binrec &s)
 {
     EllipseTest e;
     e.mx = s.mx;
@@ -71,7 +73,7 @@ __device__ __forceinline__ EllipseTest ellipse_test(const gsl_splat &s, float kq
     e.l11 = s.l11;
     e.l12 = s.l12;
     e.l22 = s.l22;
-    e.kq = kq;
+    e.kq = s.kq;
     const float cc = s.l12 * s.l12 + s.l22 * s.l22;
     e.kv = -(s.l11 * s.l12) / cc;
     e.kh = -s.l12 / s.l11;
@@ -158,7 +160,7 @@ constexpr int kPoseThreads = 256;
 // project.hip
 void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t s);
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
-                    gsl_splat *splats, int32_t *tiles_touched, hipStream_t s);
+                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, hipStream_t s);
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                         const float *g2d, const gsl_grads &out, int accumulate, double *pose_part,
                         int pose_blocks, hipStream_t s);
@@ -190,11 +192,11 @@ void launch_depth_keys(const gsl_splat *splats, const int32_t *tiles, int64_t M,
 void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, const int64_t *d_V,
                           uint32_t *counts, hipStream_t s);
 // tiles_touched of every (camera, Gaussian) record under the binning rule
-void launch_count_tiles(const gsl_splat *splats, const DevCam *cams, const Layout &L, float alpha_min,
-                        int32_t *tiles_touched, hipStream_t s);
-void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_splat *splats,
-                 const DevCam *cams, const Layout &L, float alpha_min, const int64_t *d_K, int64_t capacity,
-                 uint32_t *tile_ids, uint32_t *gauss_ids, int32_t *d_status, hipStream_t s);
+void launch_count_tiles(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
+                        hipStream_t s);
+void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
+                 const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
+                 uint32_t *gauss_ids, int32_t *d_status, hipStream_t s);
 void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,
                    uint32_t *ranges, hipStream_t s);
 

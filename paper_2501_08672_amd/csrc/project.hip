@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                                                  const float *__restrict__ opacity,
                                                  const float *__restrict__ color, int N, int64_t M,
                                                  const DevCam *__restrict__ cams, DevOpts o,
-                                                 gsl_splat *__restrict__ out)
+                                                 gsl_splat *__restrict__ out, gsl_binrec *__restrict__ bout)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
@@ -167,6 +167,18 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
         }
     }
     out[m] = sp;
+    gsl_binrec br;
+    br.mx = sp.mx;
+    br.my = sp.my;
+    br.l11 = sp.l11;
+    br.l12 = sp.l12;
+    br.l22 = sp.l22;
+    br.kq = kept ? ellipse_k(sp.opacity, o.alpha_min) : 0.f;
+    br.x0 = sp.x0;
+    br.y0 = sp.y0;
+    br.x1 = sp.x1;
+    br.y1 = sp.y1;
+    bout[m] = br;
 }
 
 // ------------------------------------------------------------------ pose tangents
@@ -442,13 +454,13 @@ void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t
 }
 
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
-                    gsl_splat *splats, int32_t *tiles_touched, hipStream_t s)
+                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, hipStream_t s)
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
-                       g.color, g.N, L.M, cams, o, splats);
-    launch_count_tiles(splats, cams, L, o.alpha_min, tiles_touched, s);
+                       g.color, g.N, L.M, cams, o, splats, binrecs);
+    launch_count_tiles(binrecs, cams, L, tiles_touched, s);
 }
 
 void launch_project_tangent(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,

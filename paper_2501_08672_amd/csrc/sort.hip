@@ -367,16 +367,16 @@ struct alignas(16) RecTiles {
 };
 static_assert(sizeof(RecTiles) == 80, "RecTiles layout");
 
-__device__ __forceinline__ int bbox_tiles(const gsl_splat &s, int tile)
+__device__ __forceinline__ int bbox_tiles(const gsl_binrec &s, int tile)
 {
     if (s.x0 > s.x1) return 0;
     return (s.x1 / tile - s.x0 / tile + 1) * (s.y1 / tile - s.y0 / tile + 1);
 }
 
-__device__ __forceinline__ void rec_fill(RecTiles &r, const gsl_splat &s, const DevCam &cam, int tile, float kq,
+__device__ __forceinline__ void rec_fill(RecTiles &r, const gsl_binrec &s, const DevCam &cam, int tile,
                                          uint32_t gid, uint32_t base, uint32_t limit)
 {
-    const EllipseTest e = ellipse_test(s, kq);
+    const EllipseTest e = ellipse_test(s);
     r.mx = e.mx;
     r.my = e.my;
     r.l11 = e.l11;
@@ -462,18 +462,18 @@ __device__ __forceinline__ uint32_t expand_tiles(const RecTiles *rec, int lane, 
 }
 
 // tiles_touched of every record (natural order).
-__global__ __launch_bounds__(256) void k_count_tiles(const gsl_splat *__restrict__ splats,
+__global__ __launch_bounds__(256) void k_count_tiles(const gsl_binrec *__restrict__ binrecs,
                                                      const DevCam *__restrict__ cams, int N, int64_t M, int tile,
-                                                     float alpha_min, int32_t *__restrict__ tiles)
+                                                     int32_t *__restrict__ tiles)
 {
     __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t nt = 0;
     if (m < M) {
-        const gsl_splat s = splats[m];
+        const gsl_binrec s = binrecs[m];
         nt = (uint32_t)bbox_tiles(s, tile);
-        if (nt) rec_fill(rec[threadIdx.x], s, cams[m / N], tile, ellipse_k(s.opacity, alpha_min), 0, 0, 0);
+        if (nt) rec_fill(rec[threadIdx.x], s, cams[m / N], tile, 0, 0, 0);
     }
     const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
     rec[threadIdx.x].excl = excl;
@@ -487,8 +487,8 @@ __global__ __launch_bounds__(256) void k_count_tiles(const gsl_splat *__restrict
 // One (tile, Gaussian | bands) instance per reached tile, records in depth order.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
                                               const uint32_t *__restrict__ counts,
-                                              const gsl_splat *__restrict__ splats, const DevCam *__restrict__ cams,
-                                              int N, int64_t M, int tile, float alpha_min,
+                                              const gsl_binrec *__restrict__ binrecs,
+                                              const DevCam *__restrict__ cams, int N, int64_t M, int tile,
                                               const int64_t *__restrict__ d_K, int64_t capacity,
                                               uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ gauss_ids,
                                               int32_t *__restrict__ d_status)
@@ -504,11 +504,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
         const uint32_t cnt = counts[j];
         if (cnt) {
             const uint32_t m = order[j];
-            const gsl_splat s = splats[m];
+            const gsl_binrec s = binrecs[m];
             const uint32_t c = m / (uint32_t)N;
             nt = (uint32_t)bbox_tiles(s, tile);
-            rec_fill(rec[threadIdx.x], s, cams[c], tile, ellipse_k(s.opacity, alpha_min), m - c * (uint32_t)N,
-                     offsets[j], cnt);
+            rec_fill(rec[threadIdx.x], s, cams[c], tile, m - c * (uint32_t)N, offsets[j], cnt);
         }
     }
     const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
@@ -604,22 +603,22 @@ void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M
                            counts);
 }
 
-void launch_count_tiles(const gsl_splat *splats, const DevCam *cams, const Layout &L, float alpha_min,
-                        int32_t *tiles_touched, hipStream_t s)
+void launch_count_tiles(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
+                        hipStream_t s)
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
-    hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)blocks), dim3(256), 0, s, splats, cams, L.N, L.M, L.tile,
-                       alpha_min, tiles_touched);
+    hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)blocks), dim3(256), 0, s, binrecs, cams, L.N, L.M, L.tile,
+                       tiles_touched);
 }
 
-void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_splat *splats,
-                 const DevCam *cams, const Layout &L, float alpha_min, const int64_t *d_K, int64_t capacity,
-                 uint32_t *tile_ids, uint32_t *gauss_ids, int32_t *d_status, hipStream_t s)
+void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
+                 const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
+                 uint32_t *gauss_ids, int32_t *d_status, hipStream_t s)
 {
     const int64_t blocks = L.M > 0 ? (L.M + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, counts, splats, cams, L.N,
-                       L.M, L.tile, alpha_min, d_K, capacity, tile_ids, gauss_ids, d_status);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, counts, binrecs, cams, L.N,
+                       L.M, L.tile, d_K, capacity, tile_ids, gauss_ids, d_status);
 }
 
 void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,

@@ -142,15 +142,18 @@ class Gaussians:
 
 
 class Proj:
-    """gsl_project output: splats (C, N, 48 B) and tiles_touched (C, N)."""
+    """gsl_project output: splats (C, N, 48 B), tiles_touched (C, N) and the
+    binning records (C, N, 32 B; torch allocations are 256-byte aligned)."""
 
     def __init__(self, C_: int, N: int, device):
         self.splats = torch.empty((C_, N, A.SPLAT_BYTES), dtype=torch.uint8, device=device)
         self.tiles_touched = torch.empty((C_, N), dtype=torch.int32, device=device)
+        self.binrecs = torch.empty((C_, N, 32), dtype=torch.uint8, device=device)
 
     def struct(self) -> A.Proj:
         p = A.Proj()
         p.splats, p.tiles_touched = self.splats.data_ptr(), self.tiles_touched.data_ptr()
+        p.binrecs = self.binrecs.data_ptr()
         return p
 
     def fields(self):
