@@ -211,7 +211,9 @@ GSL_API int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camer
 /* Work counts of the compositing on these bins (for throughput accounting):
  * d_counts[0] = (pixel, Gaussian) pairs the forward walk evaluates, up to
  * and including the one that stops it; d_counts[1] = contributing pairs;
- * d_counts[2] = pairs the backward walk evaluates (the sum of walk lengths).
+ * d_counts[2] = pairs the backward walk evaluates (per pixel, the list
+ * positions up to its last contributor whose splat reaches the pixel's row
+ * band).
  * d_counts is device uint64[3], overwritten. */
 GSL_API int gsl_render_stats(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
                              const gsl_proj *proj, const gsl_bins *bins, uint64_t *d_counts, void *workspace,

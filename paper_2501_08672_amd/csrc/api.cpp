@@ -190,6 +190,7 @@ WsLayout ws_layout(const Layout &L, int64_t capacity)
     w.pose_part = take(8 * (size_t)std::max<int64_t>(1, (int64_t)w.pose_blocks * L.C * 6));
     w.loss_part = take(8 * (size_t)std::max<int64_t>(1, L.T_total));
     w.order = take(4 * (size_t)std::max<int64_t>(1, L.T_total));
+    w.big = take(4 * (size_t)std::max<int64_t>(1, M));
     w.misc = take(256);
     w.total = o;
     return w;
@@ -260,7 +261,8 @@ void do_upload(const Prepared &p, void *ws, hipStream_t s)
 
 void do_project(const Prepared &p, const gsl_gaussians *g, gsl_proj *out, void *ws, hipStream_t s)
 {
-    launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->binrecs, out->tiles_touched, s);
+    launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->binrecs, out->tiles_touched,
+                   at<uint32_t>(ws, p.W.big), at<uint32_t>(ws, p.W.misc + 128), s);
 }
 
 void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *ws, hipStream_t s)
@@ -287,7 +289,7 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     uint32_t *ak = at<uint32_t>(ws, W.ikey2), *av = at<uint32_t>(ws, W.ival2);
     if (passes & 1) std::swap(ek, ak), std::swap(ev, av);
     launch_emit(order, offsets, counts, proj->binrecs, at<DevCam>(ws, W.cams), L, bins->d_K, bins->capacity_K, ek, ev,
-                bins->d_status, s);
+                bins->d_status, at<uint32_t>(ws, W.big), at<uint32_t>(ws, W.misc + 128), s);
     launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, partial, s);
     // 4. per-tile ranges
     launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);

@@ -140,7 +140,9 @@ struct WsLayout {
     size_t pose_part = 0;   // double[pose_blocks][C][6]
     size_t loss_part = 0;   // double[T_total]
     size_t order = 0;       // u32[T_total] work order of the fused kernel
-    size_t misc = 0;        // small scalars: work-queue counter (byte 0), kept-record count (byte 64)
+    size_t big = 0;         // u32[M] list of records spanning more than kBigTiles tiles
+    size_t misc = 0;        // small scalars: work-queue counter (byte 0), kept-record count (byte 64),
+                            // big-record list length (byte 128)
     size_t total = 0;
     int64_t sort_blocks = 0;
     int64_t scan_partials = 0;
@@ -160,7 +162,8 @@ constexpr int kPoseThreads = 256;
 // project.hip
 void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t s);
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
-                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, hipStream_t s);
+                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, uint32_t *big_list,
+                    uint32_t *big_n, hipStream_t s);
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                         const float *g2d, const gsl_grads &out, int accumulate, double *pose_part,
                         int pose_blocks, hipStream_t s);
@@ -193,10 +196,10 @@ void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M
                           uint32_t *counts, hipStream_t s);
 // tiles_touched of every (camera, Gaussian) record under the binning rule
 void launch_count_tiles(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
-                        hipStream_t s);
+                        uint32_t *big_list, uint32_t *big_n, hipStream_t s);
 void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
                  const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
-                 uint32_t *gauss_ids, int32_t *d_status, hipStream_t s);
+                 uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, hipStream_t s);
 void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,
                    uint32_t *ranges, hipStream_t s);
 

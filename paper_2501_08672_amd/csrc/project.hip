@@ -454,13 +454,14 @@ void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t
 }
 
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
-                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, hipStream_t s)
+                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, uint32_t *big_list,
+                    uint32_t *big_n, hipStream_t s)
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
                        g.color, g.N, L.M, cams, o, splats, binrecs);
-    launch_count_tiles(binrecs, cams, L, tiles_touched, s);
+    launch_count_tiles(binrecs, cams, L, tiles_touched, big_list, big_n, s);
 }
 
 void launch_project_tangent(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,

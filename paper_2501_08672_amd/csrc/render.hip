@@ -252,14 +252,26 @@ struct PixState {
 };
 
 // Work counters of the forward walk (only the counting kernel uses them).
+// `bwd` counts, per pixel, the in-band list positions up to its last
+// contributor: the pairs the backward walk has to evaluate.
 struct NoCount {
-    __device__ void eval(bool) {}
-    __device__ void contrib(bool) {}
+    __device__ void eval(int, bool) {}
+    __device__ void contrib(int, bool) {}
 };
+template <int PPL>
 struct Count {
     uint32_t evald = 0, ncontrib = 0;
-    __device__ void eval(bool b) { evald += b ? 1u : 0u; }
-    __device__ void contrib(bool b) { ncontrib += b ? 1u : 0u; }
+    uint32_t seen[PPL] = {}, bwd[PPL] = {};
+    __device__ void eval(int k, bool b)
+    {
+        evald += b ? 1u : 0u;
+        seen[k] += b ? 1u : 0u;
+    }
+    __device__ void contrib(int k, bool b)
+    {
+        ncontrib += b ? 1u : 0u;
+        bwd[k] = b ? seen[k] : bwd[k];
+    }
 };
 
 // Per-wave record of the list positions where at least one pixel of the wave
@@ -327,11 +339,11 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const bool live = !done[k];
                 const bool hit = live && e.alpha >= amin;
-                cnt.eval(live);
+                cnt.eval(k, live);
                 const float Tn = ps.T[k] * (1.f - e.alpha);
                 const bool stop = hit && Tn < Tmin;
                 const bool acc = hit && !stop;
-                cnt.contrib(acc);
+                cnt.contrib(k, acc);
                 done[k] = done[k] || stop;
                 const float w = acc ? e.alpha * ps.T[k] : 0.f;
                 ps.C0[k] = fmaf(w, p1.z, ps.C0[k]);
@@ -620,11 +632,12 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_count(RenderArgs a
     using G = Geo<TS, NW>;
     __shared__ Stage<G::CH> st;
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, (int)blockIdx.x);
-    Count cnt;
+    Count<G::PPL> cnt;
     const PixState<G::PPL> ps = fwd_walk<TS, NW>(a, ti, st, cnt);
+    (void)ps;
     uint32_t nw = 0;
 #pragma unroll
-    for (int k = 0; k < G::PPL; k++) nw += ps.nwalk[k];
+    for (int k = 0; k < G::PPL; k++) nw += cnt.bwd[k];
     const uint32_t e = wave_total_u32(cnt.evald), c = wave_total_u32(cnt.ncontrib), w = wave_total_u32(nw);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         atomicAdd(&counts[0], (unsigned long long)e);

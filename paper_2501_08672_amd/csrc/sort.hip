@@ -461,19 +461,40 @@ __device__ __forceinline__ uint32_t expand_tiles(const RecTiles *rec, int lane, 
     return own;
 }
 
+// Records whose bbox spans more than kBigTiles tiles leave the wave-wide walk
+// for a list that a second kernel takes one record per workgroup.  In depth
+// order the largest splats (the nearest) are contiguous: left in the flat
+// walk they would load a few waves with most of the work while the rest of
+// the chip idles.
+constexpr uint32_t kBigTiles = 256;
+constexpr int kBigBlocks = 1024;  // workgroups of the per-record kernels (grid-stride over the list)
+
+__device__ __forceinline__ void push_big(uint32_t *__restrict__ list, uint32_t *__restrict__ n, uint32_t v)
+{
+    list[atomicAdd(n, 1u)] = v;
+}
+
 // tiles_touched of every record (natural order).
 __global__ __launch_bounds__(256) void k_count_tiles(const gsl_binrec *__restrict__ binrecs,
                                                      const DevCam *__restrict__ cams, int N, int64_t M, int tile,
-                                                     int32_t *__restrict__ tiles)
+                                                     int32_t *__restrict__ tiles, uint32_t *__restrict__ big_list,
+                                                     uint32_t *__restrict__ big_n)
 {
     __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t nt = 0;
+    bool big = false;
     if (m < M) {
         const gsl_binrec s = binrecs[m];
         nt = (uint32_t)bbox_tiles(s, tile);
-        if (nt) rec_fill(rec[threadIdx.x], s, cams[m / N], tile, 0, 0, 0);
+        if (nt > kBigTiles) {
+            push_big(big_list, big_n, (uint32_t)m);
+            big = true;
+            nt = 0;
+        } else if (nt) {
+            rec_fill(rec[threadIdx.x], s, cams[m / N], tile, 0, 0, 0);
+        }
     }
     const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
     rec[threadIdx.x].excl = excl;
@@ -481,7 +502,72 @@ __global__ __launch_bounds__(256) void k_count_tiles(const gsl_binrec *__restric
     __syncthreads();
     const uint32_t n = expand_tiles<false>(rec + (threadIdx.x & ~(kWave - 1)), lane, excl, incl, total, tile,
                                            nullptr, nullptr);
-    if (m < M) tiles[m] = (int32_t)n;
+    if (m < M && !big) tiles[m] = (int32_t)n;
+}
+
+// The listed records, one per workgroup of 256 lanes (grid-stride over the
+// list): 256 bbox tiles per step in row-major order, a hit's slot from the
+// ballots of the four waves, so the instances come out exactly as the
+// wave-wide walk would write them.  Counting: list entries are record
+// indices m.  Emitting: list entries are depth-order positions j.
+template <bool emit>
+__global__ __launch_bounds__(256) void k_tiles_big(const gsl_binrec *__restrict__ binrecs,
+                                                   const DevCam *__restrict__ cams, int N, int tile,
+                                                   const uint32_t *__restrict__ big_list,
+                                                   const uint32_t *__restrict__ big_n, int32_t *__restrict__ tiles,
+                                                   const uint32_t *__restrict__ order,
+                                                   const uint32_t *__restrict__ offsets,
+                                                   const uint32_t *__restrict__ counts,
+                                                   const int64_t *__restrict__ d_K, int64_t capacity,
+                                                   uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ gauss_ids)
+{
+    __shared__ uint32_t s_cnt[4];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    if (emit && *d_K > capacity) return;  // uniform: nothing was counted into place
+    const uint32_t nbig = *big_n;
+    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const uint32_t entry = big_list[b];
+        const uint32_t m = emit ? order[entry] : entry;
+        const uint32_t base = emit ? offsets[entry] : 0u, limit = emit ? counts[entry] : 0u;
+        const gsl_binrec s = binrecs[m];
+        const uint32_t c = m / (uint32_t)N;
+        const uint32_t gid = m - c * (uint32_t)N;
+        const DevCam &cam = cams[c];
+        const EllipseTest e = ellipse_test(s);
+        const int tx0 = s.x0 / tile, ty0 = s.y0 / tile;
+        const int nx = s.x1 / tile - tx0 + 1;
+        const uint32_t nt = (uint32_t)bbox_tiles(s, tile);
+        uint32_t run = 0;
+        for (uint32_t t0 = 0; t0 < nt; t0 += 256) {
+            const uint32_t t = t0 + threadIdx.x;
+            bool hit = false;
+            uint32_t bands = 0;
+            int tx = 0, ty = 0;
+            if (t < nt) {
+                ty = ty0 + (int)(t / (uint32_t)nx);
+                tx = tx0 + (int)(t - (uint32_t)(ty - ty0) * (uint32_t)nx);
+                hit = tile_hit(e, cam.W, cam.H, tile, tx, ty, emit ? &bands : nullptr);
+            }
+            const uint64_t mask = __ballot(hit);
+            if (lane == 0) s_cnt[wv] = (uint32_t)__popcll(mask);
+            __syncthreads();
+            uint32_t before = run, tot = 0;
+            for (int k = 0; k < 4; k++) {
+                before += k < wv ? s_cnt[k] : 0u;
+                tot += s_cnt[k];
+            }
+            if (emit && hit) {
+                const uint32_t slot = before + (uint32_t)__popcll(mask & lanemask_lt(lane));
+                if (slot < limit) {  // never beyond the record's counted range
+                    tile_ids[base + slot] = (uint32_t)(cam.tile_offset + ty * cam.tiles_x + tx);
+                    gauss_ids[base + slot] = gid | (bands << kGidBits);
+                }
+            }
+            run += tot;
+            __syncthreads();
+        }
+        if (!emit && threadIdx.x == 0) tiles[m] = (int32_t)run;
+    }
 }
 
 // One (tile, Gaussian | bands) instance per reached tile, records in depth order.
@@ -491,7 +577,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
                                               const DevCam *__restrict__ cams, int N, int64_t M, int tile,
                                               const int64_t *__restrict__ d_K, int64_t capacity,
                                               uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ gauss_ids,
-                                              int32_t *__restrict__ d_status)
+                                              int32_t *__restrict__ d_status, uint32_t *__restrict__ big_list,
+                                              uint32_t *__restrict__ big_n)
 {
     __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
@@ -507,7 +594,12 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
             const gsl_binrec s = binrecs[m];
             const uint32_t c = m / (uint32_t)N;
             nt = (uint32_t)bbox_tiles(s, tile);
-            rec_fill(rec[threadIdx.x], s, cams[c], tile, m - c * (uint32_t)N, offsets[j], cnt);
+            if (nt > kBigTiles) {
+                push_big(big_list, big_n, (uint32_t)j);
+                nt = 0;
+            } else {
+                rec_fill(rec[threadIdx.x], s, cams[c], tile, m - c * (uint32_t)N, offsets[j], cnt);
+            }
         }
     }
     const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
@@ -604,21 +696,28 @@ void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M
 }
 
 void launch_count_tiles(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
-                        hipStream_t s)
+                        uint32_t *big_list, uint32_t *big_n, hipStream_t s)
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
+    launch_fill_u32(big_n, 0u, 1, s);
     hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)blocks), dim3(256), 0, s, binrecs, cams, L.N, L.M, L.tile,
-                       tiles_touched);
+                       tiles_touched, big_list, big_n);
+    hipLaunchKernelGGL((k_tiles_big<false>), dim3(kBigBlocks), dim3(256), 0, s, binrecs, cams, L.N, L.tile, big_list,
+                       big_n, tiles_touched, nullptr, nullptr, nullptr, nullptr, (int64_t)0, nullptr, nullptr);
 }
 
 void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
                  const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
-                 uint32_t *gauss_ids, int32_t *d_status, hipStream_t s)
+                 uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, hipStream_t s)
 {
     const int64_t blocks = L.M > 0 ? (L.M + 255) / 256 : 1;
+    launch_fill_u32(big_n, 0u, 1, s);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, counts, binrecs, cams, L.N,
-                       L.M, L.tile, d_K, capacity, tile_ids, gauss_ids, d_status);
+                       L.M, L.tile, d_K, capacity, tile_ids, gauss_ids, d_status, big_list, big_n);
+    if (L.M > 0)
+        hipLaunchKernelGGL((k_tiles_big<true>), dim3(kBigBlocks), dim3(256), 0, s, binrecs, cams, L.N, L.tile,
+                           big_list, big_n, nullptr, order, offsets, counts, d_K, capacity, tile_ids, gauss_ids);
 }
 
 void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,

@@ -392,6 +392,22 @@ def test_render_config2_sampled(oracle):
     assert np.isinf(tl).sum() <= 0.01 * len(tl)
 
 
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_render_stats_counts(oracle, tile):
+    """gsl_render_stats: the contributing pairs are the oracle's contributor
+    counts summed over pixels (threshold-ambiguous pixels may differ by one
+    each); contributors <= backward pairs <= forward pairs evaluated."""
+    O = ops()
+    sc = S.config1()
+    st = gpu_forward(sc, sc.cams, tile=tile)
+    ev_f, n_c, ev_b = O.render_stats(st["ctx"], st["cams"], sc.n, st["opts"], st["proj"], st["bins"])
+    r = oracle.render_image(sc, sc.cams[0], oracle.Opts())
+    amb = int((r["flags"] != 0).sum())
+    assert abs(n_c - int(r["n"].sum())) <= amb
+    assert n_c <= ev_b <= ev_f
+    assert ev_f <= st["bins"].K * tile * tile
+
+
 def test_render_empty_and_degenerate():
     O = ops()
     # all Gaussians behind the camera: background everywhere, K = 0
