@@ -128,8 +128,10 @@ typedef struct {
 typedef struct {
     uint32_t *tile_ids;  /* [capacity_K] */
     uint32_t *gauss_ids; /* [capacity_K] low 28 bits: Gaussian index i of the instance;
-                            top 4 bits: bit q set when the splat can reach rows
-                            [q*tile/4, (q+1)*tile/4) of the tile */
+                            top 4 bits: the tile parts the splat can reach: for
+                            32x32 tiles the 16x16 quadrants (bit 2 * row half +
+                            column half), for 16x16 tiles the quarter-row bands
+                            (bit q: rows [4q, 4q + 4)), for 8x8 tiles 0 */
     uint32_t *ranges;    /* [T_total][2] */
     int64_t *d_K;        /* device scalar: instance count K (even when K > capacity) */
     int32_t *d_status;   /* device scalar: GSL_OK or GSL_ECAPACITY */
@@ -274,7 +276,7 @@ GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
 GSL_API int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,
                                              const gsl_opts *opts, int64_t capacity_K, size_t *bytes);
 
-/* Photometric measurement model of the visual update (Sec. III-D, eq.
+/* Photometric measurement model of the visual update (Sec. II-D, eq.
  * eq:minimization; Appendix A): the Jacobian of the rendered colour with
  * respect to each camera's twist xi = (dphi, dt) of the left perturbation
  * T_CW <- Exp(xi) T_CW, by forward-mode differentiation through the

@@ -111,8 +111,9 @@ __device__ __forceinline__ void tile_rect(int tx, int ty, int T, int W, int H, f
 }
 
 // Instance payload: the Gaussian index in the low 28 bits and, in the top 4
-// bits, which quarter-row bands of the tile the alpha_min ellipse reaches
-// (bit q: rows [q*T/4, (q+1)*T/4) of the tile).
+// bits, which parts of the tile the alpha_min ellipse reaches (32x32 tiles:
+// the 16x16 quadrants, bit 2 * row half + column half; 16x16 tiles: the
+// quarter-row bands of 4 rows; 8x8 tiles: none).
 constexpr uint32_t kGidBits = 28;
 constexpr uint32_t kGidMask = (1u << kGidBits) - 1u;
 

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
 
 // Derivatives of one splat's 2D mean and conic along the six twist
 // directions (dphi, dt) of the left perturbation T_CW <- Exp(dphi, dt) T_CW
-// (Sec. III-D and Appendix A, the chains of eqs. eqn:grad_meani_rcw ...
+// (Sec. II-D and Appendix A, the chains of eqs. eqn:grad_meani_rcw ...
 // eqn:grad_covi_tcw taken forward): to first order p_C moves by
 // dphi x p_C + dt and W by dphi^ W.  With M = J W and P = M Rg diag(s),
 //   dmu = J dp_C,  dM = dJ(dp_C) W + J dW,  dP = dM Rg diag(s),

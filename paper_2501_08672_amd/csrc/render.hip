@@ -44,20 +44,45 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Where the pixels of a workgroup are.  Wave w owns a region of CW columns
+// by ROWS rows of the TS x TS tile: with four waves on a 32x32 tile each
+// takes a 16x16 quadrant (QUAD), otherwise a full-width strip of TS/NW rows.
+// Lane l holds column l % CW of the region and rows l / CW + k * RSTEP,
+// k < PPL.
+//
+// Each instance carries a 4-bit mask of the tile parts its alpha_min ellipse
+// reaches: for 32x32 tiles the quadrants (bit 2 * row half + column half),
+// for 16x16 tiles the quarter-row bands of 4 rows, none for 8x8.  need(w, k)
+// is the set of bits covering pixel slot k of wave w: an instance with none
+// of them set has alpha < alpha_min on every pixel of the slot.
 template <int TS, int NW>
 struct Geo {
-    static constexpr int BS = kWave * NW;          // lanes per workgroup
-    static constexpr int ROWS = TS / NW;           // tile rows per wave
-    static constexpr int PPL = TS * ROWS / kWave;  // pixels per lane
-    static constexpr int RSTEP = kWave / TS;       // row stride between a lane's pixels
-    static constexpr int CH = BS;                  // splats staged per chunk
-    // pixel slot k of every lane of wave w lies in the quarter-row band
-    // (w * ROWS + k * RSTEP) / (TS / 4) when the RSTEP rows it spans fit in a band
-    static constexpr bool BANDS = RSTEP <= TS / 4;
-    static_assert(TS * ROWS % kWave == 0 && PPL >= 1, "tile/wave layout");
-    __device__ static int band(int w, int k) { return (w * ROWS + k * RSTEP) / (TS / 4); }
-    // all pixel slots of a wave lie in one band: the band test is per splat
-    static constexpr bool ONE_BAND = BANDS && ROWS <= TS / 4 && (TS / 4) % ROWS == 0;
+    static constexpr int BS = kWave * NW;                // lanes per workgroup
+    static constexpr bool QUAD = TS == 32 && NW == 4;     // 16x16 quadrant per wave
+    static constexpr int CW = QUAD ? 16 : TS;             // columns per wave region
+    static constexpr int ROWS = QUAD ? 16 : TS / NW;      // rows per wave region
+    static constexpr int PPL = CW * ROWS / kWave;         // pixels per lane
+    static constexpr int RSTEP = kWave / CW;              // row stride between a lane's pixels
+    static constexpr int CH = BS;                         // splats staged per chunk
+    static constexpr bool MASKED = TS >= 16;
+    static_assert(CW * ROWS % kWave == 0 && PPL >= 1 && ROWS * (QUAD ? 2 : NW) == TS, "tile/wave layout");
+    __device__ static int col0(int w) { return QUAD ? (w & 1) * 16 : 0; }
+    __device__ static int row0(int w) { return QUAD ? (w >> 1) * 16 : w * ROWS; }
+    __device__ static uint32_t need(int w, int k)
+    {
+        const int r0 = row0(w) + k * RSTEP, r1 = r0 + RSTEP - 1;  // rows of the slot
+        if (TS == 32) {
+            const uint32_t cols = CW == 16 ? 1u << (col0(w) / 16) : 3u;  // column halves of the region
+            uint32_t m = 0;
+            for (int h = r0 / 16; h <= r1 / 16; h++) m |= cols << (2 * h);
+            return m;
+        }
+        uint32_t m = 0;
+        for (int b = r0 / 4; b <= r1 / 4; b++) m |= 1u << b;
+        return m;
+    }
+    // the slots of a wave need the same bits: the test is per splat
+    static constexpr bool ONE_BAND = MASKED && (TS == 32 ? ROWS <= 16 : ROWS <= 4);
 };
 
 // DPP sum of a wave: the total lands in lane 63.
@@ -182,8 +207,8 @@ __device__ __forceinline__ TileInfo<TS, NW> tile_info(const RenderArgs &a, int t
     const int local = t - cam.tile_offset;
     const int ty = local / cam.tiles_x, tx = local - ty * cam.tiles_x;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    ti.px = tx * TS + lane % TS;
-    ti.py0 = ty * TS + w * G::ROWS + lane / TS;
+    ti.px = tx * TS + G::col0(w) + lane % G::CW;
+    ti.py0 = ty * TS + G::row0(w) + lane / G::CW;
     ti.rs = a.ranges[2 * (int64_t)t];
     ti.re = a.ranges[2 * (int64_t)t + 1];
     ti.npix = (int64_t)ti.W * ti.H;
@@ -218,8 +243,8 @@ __device__ __forceinline__ void stage_load(Stage<CH> &st, const RenderArgs &a, c
 template <int TS, int NW>
 __device__ __forceinline__ bool in_band(uint32_t val, int w, int k)
 {
-    if (!Geo<TS, NW>::BANDS) return true;
-    return (val >> (kGidBits + Geo<TS, NW>::band(w, k))) & 1u;
+    if (!Geo<TS, NW>::MASKED) return true;
+    return ((val >> kGidBits) & Geo<TS, NW>::need(w, k)) != 0u;
 }
 
 // Alpha of one (pixel, splat) pair.  Every walk (forward, backward,
@@ -691,7 +716,7 @@ __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ p
 
 // ------------------------------------------------------------------ pose Jacobian
 
-// Forward-mode walk for the IESKF visual update (Sec. III-D, Appendix A):
+// Forward-mode walk for the IESKF visual update (Sec. II-D, Appendix A):
 // per pixel, alongside T and the colour, the six tangents dT and the 3 x 6
 // tangents of the colour with respect to the camera twist, with every
 // threshold decision taken exactly as in the forward walk (same alpha

@@ -316,13 +316,26 @@ __device__ __forceinline__ float ellipse_dy_on_line(const EllipseTest &e, float 
     return (fmaf(sgn, sqrtf(disc), -e.l11 * e.l12 * dx)) / cc;
 }
 
-// Does the splat's alpha_min ellipse reach tile (tx, ty), and which
-// quarter-row bands of it (bit q: rows [q*T/4, (q+1)*T/4) of the tile)?
-// The ellipse and the tile's column strip are convex, so the rows their
-// intersection reaches form one interval [lo, hi]: its top is the
+// The rows (relative to the mean) that the ellipse reaches within the
+// column strip [ux0, ux1] (relative to the mean): the ellipse and the strip
+// are convex, so these form one interval [lo, hi].  Its top is the
 // ellipse's topmost point (dy = sqrt(kq) / l22 at dx = kh dy) when that lies
 // within the strip, else the top of the ellipse on the strip edge nearest to
-// it; likewise the bottom.  A band is marked when it overlaps [lo, hi].
+// it; likewise the bottom.
+__device__ __forceinline__ void ellipse_rows_in_strip(const EllipseTest &e, float ux0, float ux1, float &lo,
+                                                      float &hi)
+{
+    const float yext = sqrtf(e.kq) / e.l22;
+    const float xt = e.kh * yext;  // dx of the topmost point; the bottommost is at -xt
+    hi = (xt >= ux0 && xt <= ux1) ? yext : ellipse_dy_on_line(e, fminf(fmaxf(xt, ux0), ux1), 1.f);
+    lo = (-xt >= ux0 && -xt <= ux1) ? -yext : ellipse_dy_on_line(e, fminf(fmaxf(-xt, ux0), ux1), -1.f);
+}
+
+// Does the splat's alpha_min ellipse reach tile (tx, ty), and which parts of
+// it?  For 32x32 tiles the parts are the quadrants (bit 2 * row half +
+// column half), for 16x16 tiles the quarter-row bands (bit q: rows
+// [4q, 4q + 4)), for 8x8 tiles none; a part is marked when the rows the
+// ellipse reaches within the part's columns overlap the part's rows.
 __device__ __forceinline__ bool tile_hit(const EllipseTest &e, int W, int H, int tile, int tx, int ty,
                                          uint32_t *bands)
 {
@@ -330,18 +343,29 @@ __device__ __forceinline__ bool tile_hit(const EllipseTest &e, int W, int H, int
     tile_rect(tx, ty, tile, W, H, rx0, rx1, ry0, ry1);
     if (!ellipse_hits_rect(e, rx0, rx1, ry0, ry1)) return false;
     if (bands) {
-        const float ux0 = rx0 - e.mx, ux1 = rx1 - e.mx;
-        const float yext = sqrtf(e.kq) / e.l22;
-        const float xt = e.kh * yext;  // dx of the topmost point; the bottommost is at -xt
-        const float hi = (xt >= ux0 && xt <= ux1) ? yext : ellipse_dy_on_line(e, fminf(fmaxf(xt, ux0), ux1), 1.f);
-        const float lo =
-            (-xt >= ux0 && -xt <= ux1) ? -yext : ellipse_dy_on_line(e, fminf(fmaxf(-xt, ux0), ux1), -1.f);
-        const int q = tile / 4;
         uint32_t b = 0;
-        for (int k = 0; k < 4; k++) {
-            const float by0 = (float)(ty * tile + k * q) + 0.5f - e.my;
-            const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1) - e.my;
-            if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << k;
+        if (tile == 32) {
+            for (int ch = 0; ch < 2; ch++) {
+                const float cx0 = (float)(tx * 32 + ch * 16) + 0.5f;
+                const float cx1 = fminf((float)(tx * 32 + ch * 16 + 16) - 0.5f, rx1);
+                if (cx0 > cx1) continue;  // the half lies beyond the image
+                float lo, hi;
+                ellipse_rows_in_strip(e, cx0 - e.mx, cx1 - e.mx, lo, hi);
+                for (int rh = 0; rh < 2; rh++) {
+                    const float by0 = (float)(ty * 32 + rh * 16) + 0.5f - e.my;
+                    const float by1 = fminf((float)(ty * 32 + rh * 16 + 16) - 0.5f, ry1) - e.my;
+                    if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << (2 * rh + ch);
+                }
+            }
+        } else if (tile == 16) {
+            float lo, hi;
+            ellipse_rows_in_strip(e, rx0 - e.mx, rx1 - e.mx, lo, hi);
+            const int q = tile / 4;
+            for (int k = 0; k < 4; k++) {
+                const float by0 = (float)(ty * tile + k * q) + 0.5f - e.my;
+                const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1) - e.my;
+                if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << k;
+            }
         }
         *bands = b;
     }

@@ -201,10 +201,18 @@ def test_bin_sort_bit_exact(oracle, tile):
             hv, hu = np.nonzero(a >= o.alpha_min * (1 - 1e-6))
             need = {int((y // tile) * tiles_x[c] + x // tile) for y, x in zip(hv, hu)}
             assert need <= got[i], (c, i, need - got[i])
-            # ... and its row band within that tile is marked
+            # ... and its part of that tile is marked: the 16x16 quadrant of a
+            # 32x32 tile (bit 2 * row half + column half), the 4-row band of a
+            # 16x16 tile; 8x8 tiles carry no mask
             for y, x in zip(hv, hu):
                 t = int((y // tile) * tiles_x[c] + x // tile)
-                assert band_of[(int(i), t)] >> int((y % tile) // (tile // 4)) & 1, (c, i, t, y)
+                bm = band_of[(int(i), t)]
+                if tile == 32:
+                    assert bm >> int(2 * ((y % 32) // 16) + (x % 32) // 16) & 1, (c, i, t, y, x)
+                elif tile == 16:
+                    assert bm >> int((y % 16) // 4) & 1, (c, i, t, y)
+                else:
+                    assert bm == 0
     assert nboundary <= 2
 
 
