@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-jac", action="store_true", help="skip the pose-Jacobian measurement")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line: window step time vs N in {20k, 100k, 500k, 2M} at "
+                         "640x512 and 1280x1024 (8 keyframes), one JSON line per point")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration runs)")
     return ap.parse_args()
@@ -156,8 +159,68 @@ def pose_jacobian_bench(ctx, ops, S, torch, reps=5):
             "residual_rms": round(float(np.sqrt(pj.zz.sum().item() / (3 * P))), 5)}
 
 
+def sweep(args):
+    import torch
+
+    import scenegen as S
+    from paper_2501_08672_amd import ops
+
+    ctx = ops.Context(0)
+    for (W, H) in ((640, 512), (1280, 1024)):
+        for n in (20_000, 100_000, 500_000, 2_000_000):
+            sc, tgt_sc = S.config3(per_plane=n // 50, width=W, height=H, f=0.78125 * W)
+            cs = ops.CameraSet(sc.cams)
+            g, gt = ops.Gaussians.from_scene(sc), ops.Gaussians.from_scene(tgt_sc)
+            o = ops.opts(16)
+            pt = ops.project(ctx, gt, cs, o)
+            bt = ops.bin_sort(ctx, cs, gt.N, o, pt)
+            target, _, _ = ops.render_fwd(ctx, cs, gt.N, o, pt, bt)
+            del pt, bt, gt
+            win = ops.Window(ctx, g, cs, o, target, loss="l1")
+            tile, _ = win.tune()
+            for _ in range(3):
+                win.step(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                win.step(True)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / args.steps
+            print(json.dumps({"gaussians": n, "frames": cs.C, "width": W, "height": H, "tile": tile,
+                              "instances_K": win.bins.K, "ms_per_step": round(t * 1e3, 4),
+                              "mpix_s": round(cs.P_total / t / 1e6, 2)}), flush=True)
+            del win, g, target
+            torch.cuda.empty_cache()
+    # the uneven batch: 2M surfels, 16 cameras from 320x256 to 1920x1080
+    sc, tgt_sc = S.config5()
+    cs = ops.CameraSet(sc.cams)
+    g, gt = ops.Gaussians.from_scene(sc), ops.Gaussians.from_scene(tgt_sc)
+    o = ops.opts(16)
+    pt = ops.project(ctx, gt, cs, o)
+    bt = ops.bin_sort(ctx, cs, gt.N, o, pt)
+    target, _, _ = ops.render_fwd(ctx, cs, gt.N, o, pt, bt)
+    del pt, bt, gt
+    win = ops.Window(ctx, g, cs, o, target, loss="l1")
+    tile, _ = win.tune()
+    for _ in range(3):
+        win.step(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        win.step(True)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"gaussians": sc.n, "frames": cs.C, "sizes": "uneven, 320x256 ... 1920x1080",
+                      "pixels": cs.P_total, "tile": tile, "instances_K": win.bins.K,
+                      "ms_per_step": round(t * 1e3, 4), "mpix_s": round(cs.P_total / t / 1e6, 2)}), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.sweep:
+        sweep(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path is built)"}))
         sys.exit(2)
@@ -213,6 +276,17 @@ def main():
     P = cs.P_total
     mpix = P / t_win / 1e6
     log(f"window step {t_win * 1e3:.3f} ms, {mpix:.1f} Mpix/s, K={K}, loss={float(win.d_loss.item()):.6f}")
+    # per-step distribution (HIP events around each replay, outside the timed region above)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    for k in range(args.steps):
+        evs[2 * k].record()
+        win.step(use_graph)
+        evs[2 * k + 1].record()
+    torch.cuda.synchronize()
+    per_step = np.array([evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(args.steps)])
+    step_pct = {"p10": round(float(np.percentile(per_step, 10)), 4), "p50": round(float(np.median(per_step)), 4),
+                "p90": round(float(np.percentile(per_step, 90)), 4)}
+    log(f"per-step ms p10/p50/p90: {step_pct}")
 
     # stage times of eager steps (HIP events on the launch stream)
     stages = np.array([win.profiled_step() for _ in range(5)])
@@ -295,6 +369,7 @@ def main():
                                "L1 loss, fwd+bwd to all Gaussian parameters and the 8 poses",
                    "gaussians": sc.n, "frames": cs.C, "width": 1280, "height": 1024, "tile": tile,
                    "instances_K": K, "hip_graph": use_graph},
+        "step_ms_events": step_pct,
         "fwd_ms_per_frame": round(fwd_ms / cs.C, 4),
         "per_frame": per_frame,
         "stage_ms": {"project": round(st_ms[0], 4), "bin_sort": round(st_ms[1], 4),
