@@ -118,6 +118,7 @@ typedef struct {
     gsl_splat *splats;      /* [C][N] */
     int32_t *tiles_touched; /* [C][N] number of tiles the alpha_min ellipse reaches */
     gsl_binrec *binrecs;    /* [C][N], 32-byte aligned */
+    uint32_t *depth_keys;   /* [C][N] bits of the float depth (0xFFFFFFFF when culled): the depth-sort key */
 } gsl_proj;
 
 /* Tile bins (device).  After gsl_bin_sort, instances [0, K) are ordered by

@@ -55,7 +55,8 @@ class Gaussians(C.Structure):
 
 
 class Proj(C.Structure):
-    _fields_ = [("splats", C.c_void_p), ("tiles_touched", C.c_void_p), ("binrecs", C.c_void_p)]
+    _fields_ = [("splats", C.c_void_p), ("tiles_touched", C.c_void_p), ("binrecs", C.c_void_p),
+                ("depth_keys", C.c_void_p)]
 
 
 class Bins(C.Structure):

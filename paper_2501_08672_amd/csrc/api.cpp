@@ -239,7 +239,8 @@ int check_gauss(const gsl_gaussians *g, bool need_all)
 int check_proj(const gsl_proj *p, const Layout &L)
 {
     if (!p) return fail(GSL_EINVAL, "proj is NULL");
-    if (L.M > 0 && (!p->splats || !p->tiles_touched || !p->binrecs)) return fail(GSL_EINVAL, "proj buffer is NULL");
+    if (L.M > 0 && (!p->splats || !p->tiles_touched || !p->binrecs || !p->depth_keys))
+        return fail(GSL_EINVAL, "proj buffer is NULL");
     if (reinterpret_cast<uintptr_t>(p->binrecs) % 32 != 0) return fail(GSL_EINVAL, "binrecs not 32-byte aligned");
     return GSL_OK;
 }
@@ -261,7 +262,8 @@ void do_upload(const Prepared &p, void *ws, hipStream_t s)
 
 void do_project(const Prepared &p, const gsl_gaussians *g, gsl_proj *out, void *ws, hipStream_t s)
 {
-    launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->binrecs, out->tiles_touched,
+    launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->binrecs, out->depth_keys,
+                   out->tiles_touched,
                    at<uint32_t>(ws, p.W.big), at<uint32_t>(ws, p.W.misc + 128), s);
 }
 
@@ -276,7 +278,7 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     // 1. depth order of the records that reach a tile (ties by record index =
     // Gaussian index per camera); the first pass drops the others
     int64_t *d_V = at<int64_t>(ws, W.misc + 64);
-    launch_depth_keys(proj->splats, proj->tiles_touched, L.M, dkey, dval, s);
+    launch_depth_keys(proj->depth_keys, proj->tiles_touched, L.M, dkey, dval, s);
     int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, partial, s, d_V);
     const uint32_t *order = where ? dval2 : dval;
     // 2. instance offsets in that order
@@ -602,7 +604,7 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
     gk.v.push_back(loss);
     auto ptr = [&](const void *q) { gk.v.push_back((int64_t)(uintptr_t)q); };
     ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color);
-    ptr(target); ptr(proj->splats); ptr(proj->tiles_touched); ptr(proj->binrecs);
+    ptr(target); ptr(proj->splats); ptr(proj->tiles_touched); ptr(proj->binrecs); ptr(proj->depth_keys);
     ptr(bins->tile_ids); ptr(bins->gauss_ids); ptr(bins->ranges); ptr(bins->d_K); ptr(bins->d_status);
     gk.v.push_back(bins->capacity_K);
     ptr(image); ptr(d_loss); ptr(grads->g_mean); ptr(grads->g_scale); ptr(grads->g_quat);

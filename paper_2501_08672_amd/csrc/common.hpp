@@ -163,8 +163,8 @@ constexpr int kPoseThreads = 256;
 // project.hip
 void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t s);
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
-                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, uint32_t *big_list,
-                    uint32_t *big_n, hipStream_t s);
+                    gsl_splat *splats, gsl_binrec *binrecs, uint32_t *depth_keys, int32_t *tiles_touched,
+                    uint32_t *big_list, uint32_t *big_n, hipStream_t s);
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                         const float *g2d, const gsl_grads &out, int accumulate, double *pose_part,
                         int pose_blocks, hipStream_t s);
@@ -191,7 +191,7 @@ void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint6
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint64_t *partial,
                       hipStream_t s, int64_t *d_kept = nullptr);
-void launch_depth_keys(const gsl_splat *splats, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
+void launch_depth_keys(const uint32_t *depth_keys, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
                        hipStream_t s);
 void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, const int64_t *d_V,
                           uint32_t *counts, hipStream_t s);

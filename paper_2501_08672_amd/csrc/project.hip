@@ -113,7 +113,8 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                                                  const float *__restrict__ opacity,
                                                  const float *__restrict__ color, int N, int64_t M,
                                                  const DevCam *__restrict__ cams, DevOpts o,
-                                                 gsl_splat *__restrict__ out, gsl_binrec *__restrict__ bout)
+                                                 gsl_splat *__restrict__ out, gsl_binrec *__restrict__ bout,
+                                                 uint32_t *__restrict__ kout)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
     br.x1 = sp.x1;
     br.y1 = sp.y1;
     bout[m] = br;
+    kout[m] = kept ? __float_as_uint(sp.depth) : 0xffffffffu;
 }
 
 // ------------------------------------------------------------------ pose tangents
@@ -454,13 +456,13 @@ void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t
 }
 
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
-                    gsl_splat *splats, gsl_binrec *binrecs, int32_t *tiles_touched, uint32_t *big_list,
-                    uint32_t *big_n, hipStream_t s)
+                    gsl_splat *splats, gsl_binrec *binrecs, uint32_t *depth_keys, int32_t *tiles_touched,
+                    uint32_t *big_list, uint32_t *big_n, hipStream_t s)
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
-                       g.color, g.N, L.M, cams, o, splats, binrecs);
+                       g.color, g.N, L.M, cams, o, splats, binrecs, depth_keys);
     launch_count_tiles(binrecs, cams, L, tiles_touched, big_list, big_n, s);
 }
 

@@ -155,11 +155,10 @@ __device__ __forceinline__ int64_t live_count(const int64_t *d_n, int64_t n_max)
 }
 
 // Mask of the lanes of this wave whose digit equals this lane's digit.
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid)
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int db)
 {
     uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; b++) {
+    for (int b = 0; b < db; b++) {
         const bool bit = (d >> b) & 1u;
         const uint64_t m = __ballot(bit);
         peers &= bit ? m : ~m;
@@ -173,25 +172,26 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid)
 constexpr uint32_t kDropKey = 0xffffffffu;
 
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__restrict__ keys, int64_t n_max,
-                                                          const int64_t *__restrict__ d_n, int shift,
+                                                          const int64_t *__restrict__ d_n, int shift, int db,
                                                           uint32_t *__restrict__ hist, int64_t nb, bool drop)
 {
     __shared__ uint32_t s_cnt[kSortThreads / kWave][256];
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < (kSortThreads / kWave) * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
     __syncthreads();
+    const uint32_t dmask = (1u << db) - 1u;
     const int64_t n = live_count(d_n, n_max);
     const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wv * (kSortTile / (kSortThreads / kWave));
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
         const uint32_t kj = j < n ? keys[j] : kDropKey;
         const bool valid = j < n && !(drop && kj == kDropKey);
-        const uint32_t d = valid ? (kj >> shift) & 0xffu : 0u;
-        const uint64_t peers = digit_peers(d, valid);
+        const uint32_t d = valid ? (kj >> shift) & dmask : 0u;
+        const uint64_t peers = digit_peers(d, valid, db);
         if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) s_cnt[wv][d] += __popcll(peers);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += kSortThreads) {
+    for (int d = threadIdx.x; d < (1 << db); d += kSortThreads) {
         uint32_t t = 0;
         for (int w = 0; w < kSortThreads / kWave; w++) t += s_cnt[w][d];
         hist[(int64_t)d * nb + blockIdx.x] = t;
@@ -203,9 +203,10 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
                                                              const uint32_t *__restrict__ vin,
                                                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                              int64_t n_max, const int64_t *__restrict__ d_n, int shift,
-                                                             const uint32_t *__restrict__ hist_off, int64_t nb,
+                                                             int db, const uint32_t *__restrict__ hist_off, int64_t nb,
                                                              bool drop)
 {
+    const uint32_t dmask = (1u << db) - 1u;
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t s_cnt[NW][256];   // per-wave running digit counts, then wave bases
     __shared__ uint32_t s_loc[256];       // block-local first position of each digit
@@ -226,8 +227,8 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
         key[r] = j < n ? kin[j] : kDropKey;
         const bool valid = j < n && !(drop && key[r] == kDropKey);
         val[r] = valid ? vin[j] : 0u;
-        const uint32_t d = (key[r] >> shift) & 0xffu;
-        const uint64_t peers = digit_peers(d, valid);
+        const uint32_t d = (key[r] >> shift) & dmask;
+        const uint64_t peers = digit_peers(d, valid, db);
         const uint32_t before = valid ? s_cnt[wv][d] : 0u;
         rank[r] = before + (uint32_t)__popcll(peers & lanemask_lt(lane));
         if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) s_cnt[wv][d] = before + __popcll(peers);
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
             run += c;
         }
         s_loc[d] = run;  // total of digit d in this block (scanned below)
-        s_glob[d] = hist_off[(int64_t)d * nb + blockIdx.x];
+        s_glob[d] = d <= (int)dmask ? hist_off[(int64_t)d * nb + blockIdx.x] : 0u;
     }
     __syncthreads();
     if (threadIdx.x < kWave) {
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     __syncthreads();
     for (int r = 0; r < kSortItems; r++) {
         if (rank[r] == 0xffffffffu) continue;
-        const uint32_t d = (key[r] >> shift) & 0xffu;
+        const uint32_t d = (key[r] >> shift) & dmask;
         const uint32_t pos = s_loc[d] + s_cnt[wv][d] + rank[r];
         s_key[pos] = key[r];
         s_val[pos] = val[r];
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     const int nloc = (int)s_nloc;
     for (int p = threadIdx.x; p < nloc; p += kSortThreads) {
         const uint32_t k = s_key[p];
-        const uint32_t d = (k >> shift) & 0xffu;
+        const uint32_t d = (k >> shift) & dmask;
         const uint32_t dst = s_glob[d] + (uint32_t)p - s_loc[d];
         kout[dst] = k;
         vout[dst] = s_val[p];
@@ -287,12 +288,12 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
 
 // ------------------------------------------------------------------ binning
 
-__global__ void k_depth_keys(const gsl_splat *__restrict__ splats, const int32_t *__restrict__ tiles, int64_t M,
+__global__ void k_depth_keys(const uint32_t *__restrict__ depth_keys, const int32_t *__restrict__ tiles, int64_t M,
                              uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
-    keys[m] = tiles[m] > 0 ? __float_as_uint(splats[m].depth) : 0xffffffffu;
+    keys[m] = tiles[m] > 0 ? depth_keys[m] : 0xffffffffu;
     vals[m] = (uint32_t)m;
 }
 
@@ -686,14 +687,17 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
     }
     uint32_t *kin = keys, *vin = vals, *kout = keys2, *vout = vals2;
     int where = 0;
-    for (int shift = 0; shift < bits; shift += 8) {
+    // as few passes of at most 8 bits as cover `bits`, the digits split evenly
+    // (fewer buckets per pass write longer runs)
+    const int passes = (bits + 7) / 8, db = (bits + passes - 1) / passes;
+    for (int shift = 0; shift < bits; shift += db) {
         // with d_kept the first pass drops kDropKey keys and counts the rest
         const bool drop = d_kept && shift == 0;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, n_max, d_n, shift, hist, nb,
-                           drop);
-        launch_scan_u32(hist, hist_off, 256 * nb, partial, drop ? d_kept : nullptr, s);
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, n_max, d_n, shift, db, hist,
+                           nb, drop);
+        launch_scan_u32(hist, hist_off, (int64_t)(1 << db) * nb, partial, drop ? d_kept : nullptr, s);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_max,
-                           d_n, shift, hist_off, nb, drop);
+                           d_n, shift, db, hist_off, nb, drop);
         if (drop) d_n = d_kept;
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout;
@@ -703,11 +707,11 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
     return where;
 }
 
-void launch_depth_keys(const gsl_splat *splats, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
+void launch_depth_keys(const uint32_t *depth_keys, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
                        hipStream_t s)
 {
     if (M > 0)
-        hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, splats, tiles, M, keys,
+        hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, depth_keys, tiles, M, keys,
                            vals);
 }
 

@@ -142,18 +142,20 @@ class Gaussians:
 
 
 class Proj:
-    """gsl_project output: splats (C, N, 48 B), tiles_touched (C, N) and the
-    binning records (C, N, 32 B; torch allocations are 256-byte aligned)."""
+    """gsl_project output: splats (C, N, 48 B), tiles_touched (C, N), the
+    binning records (C, N, 32 B; torch allocations are 256-byte aligned) and
+    the depth-sort keys (C, N)."""
 
     def __init__(self, C_: int, N: int, device):
         self.splats = torch.empty((C_, N, A.SPLAT_BYTES), dtype=torch.uint8, device=device)
         self.tiles_touched = torch.empty((C_, N), dtype=torch.int32, device=device)
         self.binrecs = torch.empty((C_, N, 32), dtype=torch.uint8, device=device)
+        self.depth_keys = torch.empty((C_, N), dtype=torch.int32, device=device)
 
     def struct(self) -> A.Proj:
         p = A.Proj()
         p.splats, p.tiles_touched = self.splats.data_ptr(), self.tiles_touched.data_ptr()
-        p.binrecs = self.binrecs.data_ptr()
+        p.binrecs, p.depth_keys = self.binrecs.data_ptr(), self.depth_keys.data_ptr()
         return p
 
     def fields(self):
