@@ -1,0 +1,221 @@
+// Binning walk shared by the projection (which counts the tiles each splat
+// reaches) and the emission of instances (sort.hip): the exact ellipse-tile
+// test, the tile-part masks, and the wave-wide flat expansion of a wave's
+// records over their bbox tiles.  Both kernels run this same code, so the
+// emitted instances are exactly the counted ones.
+#pragma once
+#include "common.hpp"
+
+namespace gsl {
+
+namespace {
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (lane == 0) ? 0ull : (~0ull >> (64 - lane)); }
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane)
+{
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t o = __shfl_up(v, off, kWave);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Extreme dy (sgn = +1: largest, -1: smallest) of the ellipse
+// |L d|^2 <= kq on the vertical line dx = const: the roots of
+// (l12^2 + l22^2) dy^2 + 2 l11 l12 dx dy + l11^2 dx^2 - kq = 0.
+__device__ __forceinline__ float ellipse_dy_on_line(const EllipseTest &e, float dx, float sgn)
+{
+    const float cc = fmaf(e.l12, e.l12, e.l22 * e.l22);
+    const float u = e.l22 * e.l11 * dx;
+    const float disc = fmaxf(fmaf(cc, e.kq, -u * u), 0.f);
+    // approximate reciprocal: the band test only has to be conservative, and
+    // the +0.01 in kq leaves far more room than its error
+    return (fmaf(sgn, sqrtf(disc), -e.l11 * e.l12 * dx)) * __builtin_amdgcn_rcpf(cc);
+}
+
+// The rows (relative to the mean) that the ellipse reaches within the
+// column strip [ux0, ux1] (relative to the mean): the ellipse and the strip
+// are convex, so these form one interval [lo, hi].  Its top is the
+// ellipse's topmost point (dy = sqrt(kq) / l22 at dx = kh dy) when that lies
+// within the strip, else the top of the ellipse on the strip edge nearest to
+// it; likewise the bottom.
+__device__ __forceinline__ void ellipse_rows_in_strip(const EllipseTest &e, float ux0, float ux1, float &lo,
+                                                      float &hi)
+{
+    const float yext = sqrtf(e.kq) * __builtin_amdgcn_rcpf(e.l22);
+    const float xt = e.kh * yext;  // dx of the topmost point; the bottommost is at -xt
+    hi = (xt >= ux0 && xt <= ux1) ? yext : ellipse_dy_on_line(e, fminf(fmaxf(xt, ux0), ux1), 1.f);
+    lo = (-xt >= ux0 && -xt <= ux1) ? -yext : ellipse_dy_on_line(e, fminf(fmaxf(-xt, ux0), ux1), -1.f);
+}
+
+// Does the splat's alpha_min ellipse reach tile (tx, ty), and which parts of
+// it?  For 32x32 tiles the parts are the quadrants (bit 2 * row half +
+// column half), for 16x16 tiles the quarter-row bands (bit q: rows
+// [4q, 4q + 4)), for 8x8 tiles none; a part is marked when the rows the
+// ellipse reaches within the part's columns overlap the part's rows.
+__device__ __forceinline__ bool tile_hit(const EllipseTest &e, int W, int H, int tile, int tx, int ty,
+                                         uint32_t *bands)
+{
+    float rx0, rx1, ry0, ry1;
+    tile_rect(tx, ty, tile, W, H, rx0, rx1, ry0, ry1);
+    if (!ellipse_hits_rect(e, rx0, rx1, ry0, ry1)) return false;
+    if (bands) {
+        uint32_t b = 0;
+        if (tile == 32) {
+            for (int ch = 0; ch < 2; ch++) {
+                const float cx0 = (float)(tx * 32 + ch * 16) + 0.5f;
+                const float cx1 = fminf((float)(tx * 32 + ch * 16 + 16) - 0.5f, rx1);
+                if (cx0 > cx1) continue;  // the half lies beyond the image
+                float lo, hi;
+                ellipse_rows_in_strip(e, cx0 - e.mx, cx1 - e.mx, lo, hi);
+                for (int rh = 0; rh < 2; rh++) {
+                    const float by0 = (float)(ty * 32 + rh * 16) + 0.5f - e.my;
+                    const float by1 = fminf((float)(ty * 32 + rh * 16 + 16) - 0.5f, ry1) - e.my;
+                    if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << (2 * rh + ch);
+                }
+            }
+        } else if (tile == 16) {
+            float lo, hi;
+            ellipse_rows_in_strip(e, rx0 - e.mx, rx1 - e.mx, lo, hi);
+            const int q = tile / 4;
+            for (int k = 0; k < 4; k++) {
+                const float by0 = (float)(ty * tile + k * q) + 0.5f - e.my;
+                const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1) - e.my;
+                if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << k;
+            }
+        }
+        *bands = b;
+    }
+    return true;
+}
+
+// Counting and emitting share one walk.  A wave expands the bbox tiles of its
+// 64 records into one flat list (an exclusive scan of the bbox tile counts
+// gives each record its segment) and tests 64 list entries per step, lane l
+// entry t0 + l; the entry's record is found by a binary search over the
+// lanes' inclusive scan values and its parameters are read from LDS.  Every
+// lane is busy whatever the mix of small and large splats, and no step waits
+// on a global load.  Within a record the hits keep bbox order (row-major),
+// so an instance's slot is the record's hits before this step plus the hits
+// of the same record on lower lanes.
+struct alignas(16) RecTiles {
+    float mx, my, l11, l12, l22, kq, kv, kh;
+    int32_t tx0, ty0, nx, tiles_x;
+    int32_t tile_base, W, H;
+    uint32_t gid;
+    uint32_t base, limit, excl;
+    float rnx;  // 1 / nx
+};
+static_assert(sizeof(RecTiles) == 80, "RecTiles layout");
+
+__device__ __forceinline__ int bbox_tiles(const gsl_binrec &s, int tile)
+{
+    if (s.x0 > s.x1) return 0;
+    return (s.x1 / tile - s.x0 / tile + 1) * (s.y1 / tile - s.y0 / tile + 1);
+}
+
+__device__ __forceinline__ void rec_fill(RecTiles &r, const gsl_binrec &s, const DevCam &cam, int tile,
+                                         uint32_t gid, uint32_t base, uint32_t limit)
+{
+    const EllipseTest e = ellipse_test(s);
+    r.mx = e.mx;
+    r.my = e.my;
+    r.l11 = e.l11;
+    r.l12 = e.l12;
+    r.l22 = e.l22;
+    r.kq = e.kq;
+    r.kv = e.kv;
+    r.kh = e.kh;
+    r.tx0 = s.x0 / tile;
+    r.ty0 = s.y0 / tile;
+    r.nx = s.x1 / tile - r.tx0 + 1;
+    r.tiles_x = cam.tiles_x;
+    r.tile_base = cam.tile_offset;
+    r.W = cam.W;
+    r.H = cam.H;
+    r.gid = gid;
+    r.base = base;
+    r.limit = limit;
+    r.rnx = 1.0f / (float)r.nx;
+}
+
+// Lanes [lo, hi) of a wave, lo and hi clamped to [0, 64].
+__device__ __forceinline__ uint64_t lane_range(int64_t lo, int64_t hi)
+{
+    lo = lo < 0 ? 0 : (lo > kWave ? kWave : lo);
+    hi = hi < 0 ? 0 : (hi > kWave ? kWave : hi);
+    const uint64_t below_hi = hi >= kWave ? ~0ull : ((1ull << hi) - 1ull);
+    const uint64_t below_lo = lo >= kWave ? ~0ull : ((1ull << lo) - 1ull);
+    return below_hi & ~below_lo;
+}
+
+// Walks the flat tile list of the wave's records (rec: this wave's 64
+// entries, already visible to all its lanes).  Returns the hit count of the
+// calling lane's own record ([excl, incl) is its segment).
+template <bool emit>
+__device__ __forceinline__ uint32_t expand_tiles(const RecTiles *rec, int lane, uint32_t excl, uint32_t incl,
+                                                 uint32_t total, int tile, uint32_t *__restrict__ tile_ids,
+                                                 uint32_t *__restrict__ gauss_ids)
+{
+    uint32_t own = 0;
+    for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+        const uint32_t g = t0 + (uint32_t)lane;
+        int o = 0;  // number of lanes whose segment ends at or before g
+        for (int b = 32; b; b >>= 1)
+            if (__shfl(incl, o + b - 1, kWave) <= g) o += b;
+        bool hit = false;
+        uint32_t bands = 0, slot = 0;
+        int tx = 0, ty = 0;
+        const RecTiles &r = rec[o < kWave ? o : kWave - 1];
+        if (g < total) {
+            const uint32_t t = g - r.excl;
+            uint32_t q = (uint32_t)((float)t * r.rnx);
+            if (q * (uint32_t)r.nx > t) q--;
+            else if ((q + 1) * (uint32_t)r.nx <= t) q++;
+            ty = r.ty0 + (int)q;
+            tx = r.tx0 + (int)(t - q * (uint32_t)r.nx);
+            EllipseTest e;
+            e.mx = r.mx;
+            e.my = r.my;
+            e.l11 = r.l11;
+            e.l12 = r.l12;
+            e.l22 = r.l22;
+            e.kq = r.kq;
+            e.kv = r.kv;
+            e.kh = r.kh;
+            hit = tile_hit(e, r.W, r.H, tile, tx, ty, emit ? &bands : nullptr);
+        }
+        const uint64_t mask = __ballot(hit);
+        if (emit) {
+            const uint32_t before = __shfl(own, o < kWave ? o : kWave - 1, kWave);
+            if (hit) {
+                const uint64_t seg = lane_range((int64_t)r.excl - (int64_t)t0, lane);
+                slot = before + (uint32_t)__popcll(mask & seg);
+                if (slot < r.limit) {  // never beyond the record's counted range
+                    tile_ids[r.base + slot] = (uint32_t)(r.tile_base + ty * r.tiles_x + tx);
+                    gauss_ids[r.base + slot] = r.gid | (bands << kGidBits);
+                }
+            }
+        }
+        own += (uint32_t)__popcll(mask & lane_range((int64_t)excl - (int64_t)t0, (int64_t)incl - (int64_t)t0));
+    }
+    return own;
+}
+
+// Records whose bbox spans more than kBigTiles tiles leave the wave-wide walk
+// for a list that a second kernel takes one record per workgroup.  In depth
+// order the largest splats (the nearest) are contiguous: left in the flat
+// walk they would load a few waves with most of the work while the rest of
+// the chip idles.
+constexpr uint32_t kBigTiles = 256;
+constexpr int kBigBlocks = 1024;  // workgroups of the per-record kernels (grid-stride over the list)
+
+__device__ __forceinline__ void push_big(uint32_t *__restrict__ list, uint32_t *__restrict__ n, uint32_t v)
+{
+    list[atomicAdd(n, 1u)] = v;
+}
+
+}  // namespace
+
+}  // namespace gsl

@@ -196,8 +196,9 @@ void launch_depth_keys(const uint32_t *depth_keys, const int32_t *tiles, int64_t
 void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, const int64_t *d_V,
                           uint32_t *counts, hipStream_t s);
 // tiles_touched of every (camera, Gaussian) record under the binning rule
-void launch_count_tiles(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
-                        uint32_t *big_list, uint32_t *big_n, hipStream_t s);
+// the records k_project put on the big-record list (tiles_touched of each)
+void launch_count_big(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
+                      uint32_t *big_list, uint32_t *big_n, hipStream_t s);
 void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
                  const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
                  uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, hipStream_t s);

@@ -19,7 +19,7 @@
 // T_CW: dL/ddt = sum_i dL/dp_C,i and dL/ddphi = sum_i p_C,i x dL/dp_C,i plus
 // the term of Sigma2D's dependence on W.  Per-workgroup pose partials are
 // summed by a second kernel, so the pose gradient is deterministic.
-#include "common.hpp"
+#include "binning.hpp"
 
 namespace gsl {
 
@@ -108,79 +108,103 @@ __device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, con
     return true;
 }
 
+// Also counts the tiles each splat's alpha_min ellipse reaches (tiles_touched)
+// with the binning walk of the emission, from the record still in registers;
+// records spanning more than kBigTiles tiles go to big_list for a second kernel.
 __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean, const float *__restrict__ scale,
                                                  const float *__restrict__ quat,
                                                  const float *__restrict__ opacity,
                                                  const float *__restrict__ color, int N, int64_t M,
                                                  const DevCam *__restrict__ cams, DevOpts o,
                                                  gsl_splat *__restrict__ out, gsl_binrec *__restrict__ bout,
-                                                 uint32_t *__restrict__ kout)
+                                                 uint32_t *__restrict__ kout, int32_t *__restrict__ tiles,
+                                                 uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_n)
 {
+    __shared__ RecTiles rec[256];
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const int c = (int)(m / N);
-    const int i = (int)(m - (int64_t)c * N);
-    const DevCam cam = cams[c];
+    uint32_t nt = 0;
+    bool big = false;
+    if (m < M) {
+        const int c = (int)(m / N);
+        const int i = (int)(m - (int64_t)c * N);
+        const DevCam cam = cams[c];
 
-    gsl_splat sp;
-    sp.mx = sp.my = sp.l11 = sp.l12 = sp.l22 = 0.f;
-    sp.opacity = opacity[i];
-    sp.r = color[i];
-    sp.g = color[N + i];
-    sp.b = color[2 * N + i];
-    sp.depth = 0.f;
-    sp.x0 = 0; sp.y0 = 0; sp.x1 = -1; sp.y1 = -1;
+        gsl_splat sp;
+        sp.mx = sp.my = sp.l11 = sp.l12 = sp.l22 = 0.f;
+        sp.opacity = opacity[i];
+        sp.r = color[i];
+        sp.g = color[N + i];
+        sp.b = color[2 * N + i];
+        sp.depth = 0.f;
+        sp.x0 = 0; sp.y0 = 0; sp.x1 = -1; sp.y1 = -1;
 
-    Proj p;
-    bool kept = compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
-    if (kept) {
-        const double W = cam.W, H = cam.H, g = o.guard;
-        if (p.mx < -g * W || p.mx > (1.0 + g) * W || p.my < -g * H || p.my > (1.0 + g) * H) kept = false;
-        if (!(p.det > 0.0)) kept = false;
-        const double sigma = sp.opacity;
-        if (!(sigma >= (double)o.alpha_min)) kept = false;
+        Proj p;
+        bool kept = compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
         if (kept) {
-            // |L d|^2 <= k  <=>  sigma G(d) >= alpha_min;  the bbox of that
-            // ellipse is |dx| <= sqrt(k a), |dy| <= sqrt(k c).  The margin
-            // covers float32 evaluation of the power in the renderer.
-            const double k = 2.0 * log(sigma / (double)o.alpha_min) + 0.01;
-            const double hx = sqrt(k * p.a) + 0.01, hy = sqrt(k * p.c) + 0.01;
-            double x0 = ceil(p.mx - hx - 0.5), x1 = floor(p.mx + hx - 0.5);
-            double y0 = ceil(p.my - hy - 0.5), y1 = floor(p.my + hy - 0.5);
-            x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
-            x1 = fmin(x1, W - 1.0); y1 = fmin(y1, H - 1.0);
-            if (x0 > x1 || y0 > y1) {
-                kept = false;
-            } else {
-                const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
-                sp.x0 = (int16_t)ix0; sp.x1 = (int16_t)ix1;
-                sp.y0 = (int16_t)iy0; sp.y1 = (int16_t)iy1;
-                const double l22 = 1.0 / sqrt(p.c);
-                const double l11 = sqrt(p.c / p.det);
-                const double l12 = -p.b / sqrt(p.c * p.det);
-                sp.mx = (float)p.mx;
-                sp.my = (float)p.my;
-                sp.l11 = (float)l11;
-                sp.l12 = (float)l12;
-                sp.l22 = (float)l22;
-                sp.depth = (float)p.z;
+            const double W = cam.W, H = cam.H, g = o.guard;
+            if (p.mx < -g * W || p.mx > (1.0 + g) * W || p.my < -g * H || p.my > (1.0 + g) * H) kept = false;
+            if (!(p.det > 0.0)) kept = false;
+            const double sigma = sp.opacity;
+            if (!(sigma >= (double)o.alpha_min)) kept = false;
+            if (kept) {
+                // |L d|^2 <= k  <=>  sigma G(d) >= alpha_min;  the bbox of that
+                // ellipse is |dx| <= sqrt(k a), |dy| <= sqrt(k c).  The margin
+                // covers float32 evaluation of the power in the renderer.
+                const double k = 2.0 * log(sigma / (double)o.alpha_min) + 0.01;
+                const double hx = sqrt(k * p.a) + 0.01, hy = sqrt(k * p.c) + 0.01;
+                double x0 = ceil(p.mx - hx - 0.5), x1 = floor(p.mx + hx - 0.5);
+                double y0 = ceil(p.my - hy - 0.5), y1 = floor(p.my + hy - 0.5);
+                x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+                x1 = fmin(x1, W - 1.0); y1 = fmin(y1, H - 1.0);
+                if (x0 > x1 || y0 > y1) {
+                    kept = false;
+                } else {
+                    const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
+                    sp.x0 = (int16_t)ix0; sp.x1 = (int16_t)ix1;
+                    sp.y0 = (int16_t)iy0; sp.y1 = (int16_t)iy1;
+                    const double l22 = 1.0 / sqrt(p.c);
+                    const double l11 = sqrt(p.c / p.det);
+                    const double l12 = -p.b / sqrt(p.c * p.det);
+                    sp.mx = (float)p.mx;
+                    sp.my = (float)p.my;
+                    sp.l11 = (float)l11;
+                    sp.l12 = (float)l12;
+                    sp.l22 = (float)l22;
+                    sp.depth = (float)p.z;
+                }
             }
         }
+        out[m] = sp;
+        gsl_binrec br;
+        br.mx = sp.mx;
+        br.my = sp.my;
+        br.l11 = sp.l11;
+        br.l12 = sp.l12;
+        br.l22 = sp.l22;
+        br.kq = kept ? ellipse_k(sp.opacity, o.alpha_min) : 0.f;
+        br.x0 = sp.x0;
+        br.y0 = sp.y0;
+        br.x1 = sp.x1;
+        br.y1 = sp.y1;
+        bout[m] = br;
+        kout[m] = kept ? __float_as_uint(sp.depth) : 0xffffffffu;
+        nt = (uint32_t)bbox_tiles(br, o.tile);
+        if (nt > kBigTiles) {
+            push_big(big_list, big_n, (uint32_t)m);
+            big = true;
+            nt = 0;
+        } else if (nt) {
+            rec_fill(rec[threadIdx.x], br, cam, o.tile, 0, 0, 0);
+        }
     }
-    out[m] = sp;
-    gsl_binrec br;
-    br.mx = sp.mx;
-    br.my = sp.my;
-    br.l11 = sp.l11;
-    br.l12 = sp.l12;
-    br.l22 = sp.l22;
-    br.kq = kept ? ellipse_k(sp.opacity, o.alpha_min) : 0.f;
-    br.x0 = sp.x0;
-    br.y0 = sp.y0;
-    br.x1 = sp.x1;
-    br.y1 = sp.y1;
-    bout[m] = br;
-    kout[m] = kept ? __float_as_uint(sp.depth) : 0xffffffffu;
+    const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
+    rec[threadIdx.x].excl = excl;
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    __syncthreads();
+    const uint32_t n = expand_tiles<false>(rec + (threadIdx.x & ~(kWave - 1)), lane, excl, incl, total, o.tile,
+                                           nullptr, nullptr);
+    if (m < M && !big) tiles[m] = (int32_t)n;
 }
 
 // ------------------------------------------------------------------ pose tangents
@@ -461,9 +485,10 @@ void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L,
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
+    launch_fill_u32(big_n, 0u, 1, s);
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
-                       g.color, g.N, L.M, cams, o, splats, binrecs, depth_keys);
-    launch_count_tiles(binrecs, cams, L, tiles_touched, big_list, big_n, s);
+                       g.color, g.N, L.M, cams, o, splats, binrecs, depth_keys, tiles_touched, big_list, big_n);
+    launch_count_big(binrecs, cams, L, tiles_touched, big_list, big_n, s);
 }
 
 void launch_project_tangent(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
