@@ -286,3 +286,48 @@ def ieskf_pose_update(HtRH, HtRz, P_prior, x_minus_prior=None):
     dx = np.zeros(n) if x_minus_prior is None else np.asarray(x_minus_prior, np.float64)
     delta = -Kz - (np.eye(n) - KH) @ dx
     return delta, (np.eye(n) - KH) @ P
+
+
+# ---------------------------------------------------------------- Adam over the map parameters
+
+# Raw (optimised) parameters, 14 rows per Gaussian: mean (3), log-scale (3),
+# quaternion (4), opacity logit (1), colour (3).  The renderer takes the
+# activated values: scale = exp(log-scale), opacity = sigmoid(logit); mean,
+# quaternion and colour pass unchanged.
+RAW_ROWS = {"mean": (0, 3), "scale": (3, 6), "quat": (6, 10), "opacity": (10, 11), "color": (11, 14)}
+
+
+def activate(raw):
+    """raw (14, N) -> dict of activated parameters, each (k, N)."""
+    raw = np.asarray(raw, np.float64)
+    return {"mean": raw[0:3], "scale": np.exp(raw[3:6]), "quat": raw[6:10],
+            "opacity": 1.0 / (1.0 + np.exp(-raw[10:11])), "color": raw[11:14]}
+
+
+def raw_gradient(raw, g_act):
+    """Chain rule from the activated parameters' gradients (dict of (k, N)) to
+    the raw rows: d exp(u)/du = exp(u), d sigmoid(u)/du = s (1 - s)."""
+    a = activate(raw)
+    g = np.zeros_like(np.asarray(raw, np.float64))
+    g[0:3] = g_act["mean"]
+    g[3:6] = g_act["scale"] * a["scale"]
+    g[6:10] = g_act["quat"]
+    s = a["opacity"]
+    g[10:11] = g_act["opacity"] * s * (1.0 - s)
+    g[11:14] = g_act["color"]
+    return g
+
+
+def adam_step(raw, m, v, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step (Kingma and Ba) at step number t >= 1 with a learning
+    rate per row (lr: (14,) or scalar):
+    m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+    x <- x - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+    Returns (raw, m, v), new arrays."""
+    raw, m, v, grad = (np.asarray(a, np.float64) for a in (raw, m, v, grad))
+    lr = np.asarray(lr, np.float64).reshape(-1, 1) if np.ndim(lr) else float(lr)
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return raw - lr * mh / (np.sqrt(vh) + eps), m, v

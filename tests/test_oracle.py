@@ -551,3 +551,57 @@ def test_ieskf_update_matches_gain_form(oracle):
     ws = np.repeat(w, 3)
     np.testing.assert_allclose(A, sum(ws[i] * np.outer(Hs[i], Hs[i]) for i in range(len(ws))), rtol=1e-12)
     np.testing.assert_allclose(b, sum(ws[i] * Hs[i] * res.reshape(-1)[i] for i in range(len(ws))), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- Adam
+
+def test_adam_constant_gradient_closed_form(oracle):
+    """For a gradient that stays g, the bias-corrected moments are exactly g
+    and g^2, so every step moves by -lr g / (|g| + eps); the first step of any
+    gradient sequence is the same."""
+    rng = np.random.default_rng(2)
+    raw = rng.normal(size=(14, 7))
+    g = rng.normal(size=(14, 7))
+    lr = np.linspace(1e-3, 1e-2, 14)
+    m = np.zeros_like(raw)
+    v = np.zeros_like(raw)
+    x = raw.copy()
+    for t in range(1, 6):
+        x, m, v = oracle.adam_step(x, m, v, g, t, lr, eps=1e-8)
+        want = raw - t * lr[:, None] * g / (np.abs(g) + 1e-8)
+        np.testing.assert_allclose(x, want, rtol=1e-12, atol=1e-12)
+
+
+def test_adam_matches_scalar_recursion(oracle):
+    """A changing gradient, against the recursion written for one scalar."""
+    rng = np.random.default_rng(3)
+    gs = rng.normal(size=12)
+    x, m, v = 0.5, 0.0, 0.0
+    X, M, V = np.full((14, 1), 0.5), np.zeros((14, 1)), np.zeros((14, 1))
+    for t, g in enumerate(gs, 1):
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g * g
+        x = x - 0.01 * (m / (1 - 0.9 ** t)) / (np.sqrt(v / (1 - 0.999 ** t)) + 1e-15)
+        X, M, V = oracle.adam_step(X, M, V, np.full((14, 1), g), t, 0.01)
+    np.testing.assert_allclose(X[:, 0], x, rtol=1e-13)
+
+
+def test_activation_chain_matches_differences(oracle):
+    """raw_gradient against central differences of a linear functional of the
+    activated parameters."""
+    rng = np.random.default_rng(4)
+    raw = rng.normal(size=(14, 5))
+    W = {k: rng.normal(size=(b - a, 5)) for k, (a, b) in oracle.RAW_ROWS.items()}
+
+    def f(r):
+        act = oracle.activate(r)
+        return sum(float((W[k] * act[k]).sum()) for k in W)
+
+    g = oracle.raw_gradient(raw, W)
+    h = 1e-6
+    fd = np.zeros_like(raw)
+    for idx in np.ndindex(*raw.shape):
+        e = np.zeros_like(raw)
+        e[idx] = h
+        fd[idx] = (f(raw + e) - f(raw - e)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)  # central-difference rounding at h = 1e-6
