@@ -346,6 +346,25 @@ def main():
         log(f"per-frame plain launches {t_pf * 1e3:.3f} ms per window ({P / t_pf / 1e6:.1f} Mpix/s)")
         del frames
 
+    # the optimisation loop of one keyframe: 10 iterations of window step +
+    # Adam recorded as one graph (run last: it moves the Gaussians)
+    st = ops.AdamState.from_gaussians(g)
+    ops.adam_activate(ctx, st, g)
+    hp = ops.adam_hparams()
+    win.optimize(st, hp, iters=10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        losses = win.optimize(st, hp, iters=10)
+    torch.cuda.synchronize()
+    t_opt = (time.perf_counter() - t1) / reps
+    assert win.status() == 0, "instance capacity exceeded during the optimisation loop"
+    optimize = {"iters": 10, "ms": round(t_opt * 1e3, 4), "ms_per_iter": round(t_opt * 1e3 / 10, 4),
+                "last_losses": [round(float(x), 6) for x in losses[[0, -1]].cpu().tolist()],
+                "how": "gsl_window_optimize: 10 x (window step + Adam step over the 500k raw parameters), one graph"}
+    log(f"optimise 10 iterations: {optimize}")
+
     pose_jac = None
     if not args.no_jac:
         pose_jac = pose_jacobian_bench(ctx, ops, S, torch)
@@ -386,6 +405,7 @@ def main():
         "window_hbm": {"algorithmic_bytes": int(step_bytes),
                        "frac": round(step_bytes / t_win / 1e9 / HBM_PEAK_GBS, 4)},
     }
+    result["optimize"] = optimize
     if pose_jac is not None:
         result["pose_jacobian"] = pose_jac
     if tune_times is not None:

@@ -269,6 +269,49 @@ GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
                     gsl_grads *grads, void *workspace, size_t workspace_bytes, float *times_ms, int32_t ntimes,
                     void *stream);
 
+/* ---- Adam over the map parameters ----------------------------------------- */
+
+/* The map is refined with Adam (Sec. II-B, eq. eq:gaussian_optimization).
+ * The optimiser keeps raw parameters: 14 rows of N floats, row-major [14][N]:
+ * mean (3), log-scale (3), quaternion (4), opacity logit (1), colour (3).  The
+ * renderer takes the activated values (scale = exp(log-scale), opacity =
+ * sigmoid(logit), the rest unchanged), which the optimiser writes into the
+ * arrays of a gsl_gaussians (its pointers are written through). */
+typedef struct {
+    float lr[5];  /* learning rates: mean, log-scale, quaternion, opacity logit, colour */
+    float beta1, beta2, eps;
+} gsl_adam;
+
+typedef struct {
+    float *raw;      /* [14][N] raw parameters */
+    float *m, *v;    /* [14][N] first and second moments (zero before the first step) */
+    int32_t *d_step; /* device: steps taken (0 before the first step), advanced by each step */
+    int32_t N;
+} gsl_adam_state;
+
+/* act <- activation(raw).  No optimiser step. */
+GSL_API int gsl_adam_activate(gsl_ctx *ctx, const gsl_adam_state *st, gsl_gaussians *act, void *stream);
+
+/* One Adam step at step number t = *d_step + 1: the gradients of the
+ * activated values (grads, as gsl_render_bwd / gsl_window_step write them)
+ * are chained to the raw rows, m <- b1 m + (1 - b1) g,
+ * v <- b2 v + (1 - b2) g^2, raw <- raw - lr (m / (1 - b1^t)) /
+ * (sqrt(v / (1 - b2^t)) + eps); then act <- activation(raw) and *d_step += 1. */
+GSL_API int gsl_adam_step(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, const gsl_grads *grads,
+                          gsl_gaussians *act, void *stream);
+
+/* `iters` optimisation iterations of the window (the paper runs 10 per
+ * keyframe): each is gsl_window_step on act followed by gsl_adam_step, the
+ * loss of iteration k going to d_losses[k] (device float64 [iters]).  act must
+ * hold activation(raw) on entry (gsl_adam_activate).  With use_graph != 0 the
+ * whole sequence is recorded once into a HIP graph per (shapes, buffers,
+ * options, camera poses, iters) and replayed. */
+GSL_API int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gsl_gaussians *act,
+                                const gsl_camera *cams, int32_t C, const gsl_opts *opts, const float *target,
+                                int loss, gsl_proj *proj, gsl_bins *bins, double *d_losses, gsl_grads *grads,
+                                int32_t iters, void *workspace, size_t workspace_bytes, int use_graph,
+                                void *stream);
+
 /* ---- pose Jacobians for the IESKF visual update -------------------------- */
 
 /* Workspace bytes for gsl_pose_jacobian: the bytes gsl_workspace_size gives

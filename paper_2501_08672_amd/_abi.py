@@ -30,7 +30,7 @@ EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "g
            "gsl_project", "gsl_bin_sort", "gsl_render_fwd", "gsl_render_bwd", "gsl_render_stats", "gsl_window_step",
            "gsl_window_tune", "gsl_window_variant", "gsl_profile", "gsl_profile_read",
            "gsl_pose_jacobian_workspace_size", "gsl_pose_jacobian", "gsl_imu_to_camera_twist",
-           "gsl_ieskf_pose_update"]
+           "gsl_ieskf_pose_update", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize"]
 
 
 class GslError(RuntimeError):
@@ -57,6 +57,15 @@ class Gaussians(C.Structure):
 class Proj(C.Structure):
     _fields_ = [("splats", C.c_void_p), ("tiles_touched", C.c_void_p), ("binrecs", C.c_void_p),
                 ("depth_keys", C.c_void_p)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float * 5), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+class AdamState(C.Structure):
+    _fields_ = [("raw", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("d_step", C.c_void_p),
+                ("N", C.c_int32)]
 
 
 class Bins(C.Structure):
@@ -110,6 +119,11 @@ def lib() -> C.CDLL:
     L.gsl_pose_jacobian.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, P, P, P, P, P, C.c_size_t, P]
     L.gsl_imu_to_camera_twist.argtypes = [P, P, P, P]
     L.gsl_ieskf_pose_update.argtypes = [P, P, P, P, P, P]
+    pa, ps = C.POINTER(Adam), C.POINTER(AdamState)
+    L.gsl_adam_activate.argtypes = [P, ps, pg, P]
+    L.gsl_adam_step.argtypes = [P, ps, pa, pgr, pg, P]
+    L.gsl_window_optimize.argtypes = [P, ps, pa, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, pgr, C.c_int32, P,
+                                      C.c_size_t, C.c_int, P]
     for name in EXPORTS:
         if name not in ("gsl_last_error", "gsl_default_opts"):
             getattr(L, name).restype = C.c_int

@@ -375,6 +375,97 @@ VariantKey window_key(const Layout &L, const gsl_camera *cams)
     return k;
 }
 
+// Records the work `enqueue(stream)` launches into a HIP graph cached under
+// `key` (first call) and launches the graph on `s`.
+template <typename F>
+int graph_run(gsl_ctx *ctx, const VariantKey &key, hipStream_t s, F &&enqueue)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        GraphEntry e;
+        hipStream_t cs = ctx->cap_stream;
+        GSL_TRY(check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"));
+        enqueue(cs);
+        hipError_t le = hipGetLastError();
+        hipError_t ce = hipStreamEndCapture(cs, &e.graph);
+        if (le != hipSuccess) return fail(GSL_EHIP, "launch during capture: %s", hipGetErrorString(le));
+        GSL_TRY(check_hip(ce, "hipStreamEndCapture"));
+        hipError_t ie = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(e.graph);
+            return fail(GSL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        }
+        if (ctx->graphs.size() > 64) {  // bound the cache
+            for (auto &kv : ctx->graphs) {
+                (void)hipGraphExecDestroy(kv.second.exec);
+                (void)hipGraphDestroy(kv.second.graph);
+            }
+            ctx->graphs.clear();
+        }
+        it = ctx->graphs.emplace(key, e).first;
+    }
+    return check_hip(hipGraphLaunch(it->second.exec, s), "hipGraphLaunch");
+}
+
+// Graph key of a window pass: shapes, variant, loss, every pointer, options
+// and camera contents.
+VariantKey window_graph_key(const VariantKey &vk, int variant, int loss, const gsl_gaussians *g, const float *target,
+                            const gsl_proj *proj, const gsl_bins *bins, const float *image, const double *d_loss,
+                            const gsl_grads *grads, const void *workspace, const gsl_opts *opts,
+                            const gsl_camera *cams, int32_t C)
+{
+    VariantKey gk = vk;
+    gk.v.push_back(variant);
+    gk.v.push_back(loss);
+    auto ptr = [&](const void *q) { gk.v.push_back((int64_t)(uintptr_t)q); };
+    ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color);
+    ptr(target); ptr(proj->splats); ptr(proj->tiles_touched); ptr(proj->binrecs); ptr(proj->depth_keys);
+    ptr(bins->tile_ids); ptr(bins->gauss_ids); ptr(bins->ranges); ptr(bins->d_K); ptr(bins->d_status);
+    gk.v.push_back(bins->capacity_K);
+    ptr(image); ptr(d_loss); ptr(grads->g_mean); ptr(grads->g_scale); ptr(grads->g_quat);
+    ptr(grads->g_opacity); ptr(grads->g_color); ptr(grads->g_pose); ptr(workspace);
+    const int32_t *ow = reinterpret_cast<const int32_t *>(opts);
+    for (size_t k = 0; k < sizeof(gsl_opts) / 4; k++) gk.v.push_back(ow[k]);
+    for (int c = 0; c < C; c++) {
+        const int32_t *cw = reinterpret_cast<const int32_t *>(&cams[c]);
+        for (size_t k = 0; k < sizeof(gsl_camera) / 4; k++) gk.v.push_back(cw[k]);
+    }
+    return gk;
+}
+
+int check_adam(const gsl_adam_state *st, const gsl_adam *hp)
+{
+    if (!st) return fail(GSL_EINVAL, "adam state is NULL");
+    if (st->N < 0) return fail(GSL_EINVAL, "negative Gaussian count");
+    if (st->N > 0 && (!st->raw || !st->m || !st->v || !st->d_step)) return fail(GSL_EINVAL, "adam buffer is NULL");
+    if (hp) {
+        if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f))
+            return fail(GSL_EINVAL, "need 0 <= beta < 1");
+        if (!(hp->eps > 0.f)) return fail(GSL_EINVAL, "need eps > 0");
+        for (int k = 0; k < 5; k++)
+            if (!(hp->lr[k] >= 0.f)) return fail(GSL_EINVAL, "learning rates must be >= 0");
+    }
+    return GSL_OK;
+}
+
+void act_arrays(gsl_gaussians *act, float *out[5])
+{
+    out[0] = const_cast<float *>(act->mean);
+    out[1] = const_cast<float *>(act->scale);
+    out[2] = const_cast<float *>(act->quat);
+    out[3] = const_cast<float *>(act->opacity);
+    out[4] = const_cast<float *>(act->color);
+}
+
+void do_adam(gsl_adam_state *st, const gsl_adam *hp, const gsl_grads *grads, gsl_gaussians *act, hipStream_t s)
+{
+    const float *g[5] = {grads->g_mean, grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_color};
+    float *a[5];
+    act_arrays(act, a);
+    launch_adam(g, a, st->raw, st->m, st->v, st->d_step, hp->lr, hp->beta1, hp->beta2, hp->eps, st->N, true, s);
+}
+
 // Bytes gsl_pose_jacobian needs past the common workspace: per-record
 // tangents, then per-item normal-equation partials.
 size_t jvp_tangent_bytes(const Layout &L) { return align_up(4 * (size_t)kTangent * (size_t)L.M); }
@@ -598,52 +689,11 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
         do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, s, ctx->profile);
         return check_launch("gsl_window_step");
     }
-    // graph key: shapes, variant, every pointer, options and camera contents
-    VariantKey gk = vk;
-    gk.v.push_back(variant);
-    gk.v.push_back(loss);
-    auto ptr = [&](const void *q) { gk.v.push_back((int64_t)(uintptr_t)q); };
-    ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color);
-    ptr(target); ptr(proj->splats); ptr(proj->tiles_touched); ptr(proj->binrecs); ptr(proj->depth_keys);
-    ptr(bins->tile_ids); ptr(bins->gauss_ids); ptr(bins->ranges); ptr(bins->d_K); ptr(bins->d_status);
-    gk.v.push_back(bins->capacity_K);
-    ptr(image); ptr(d_loss); ptr(grads->g_mean); ptr(grads->g_scale); ptr(grads->g_quat);
-    ptr(grads->g_opacity); ptr(grads->g_color); ptr(grads->g_pose); ptr(workspace);
-    {
-        const int32_t *ow = reinterpret_cast<const int32_t *>(opts);
-        for (size_t k = 0; k < sizeof(gsl_opts) / 4; k++) gk.v.push_back(ow[k]);
-        for (int c = 0; c < C; c++) {
-            const int32_t *cw = reinterpret_cast<const int32_t *>(&cams[c]);
-            for (size_t k = 0; k < sizeof(gsl_camera) / 4; k++) gk.v.push_back(cw[k]);
-        }
-    }
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    auto it = ctx->graphs.find(gk);
-    if (it == ctx->graphs.end()) {
-        GraphEntry e;
-        hipStream_t cs = ctx->cap_stream;
-        GSL_TRY(check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"));
+    const VariantKey gk =
+        window_graph_key(vk, variant, loss, g, target, proj, bins, image, d_loss, grads, workspace, opts, cams, C);
+    return graph_run(ctx, gk, s, [&](hipStream_t cs) {
         do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, cs);
-        hipError_t le = hipGetLastError();
-        hipError_t ce = hipStreamEndCapture(cs, &e.graph);
-        if (le != hipSuccess) return fail(GSL_EHIP, "launch during capture: %s", hipGetErrorString(le));
-        GSL_TRY(check_hip(ce, "hipStreamEndCapture"));
-        hipError_t ie = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
-            (void)hipGraphDestroy(e.graph);
-            return fail(GSL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
-        }
-        if (ctx->graphs.size() > 64) {  // bound the cache
-            for (auto &kv : ctx->graphs) {
-                (void)hipGraphExecDestroy(kv.second.exec);
-                (void)hipGraphDestroy(kv.second.graph);
-            }
-            ctx->graphs.clear();
-        }
-        it = ctx->graphs.emplace(gk, e).first;
-    }
-    GSL_TRY(check_hip(hipGraphLaunch(it->second.exec, s), "hipGraphLaunch"));
-    return GSL_OK;
+    });
 }
 
 int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, int32_t variant)
@@ -747,6 +797,79 @@ int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
     if (rc != GSL_OK) return rc;
     opts_inout->tile = best_tile;
     return check_launch("gsl_window_tune");
+}
+
+int gsl_adam_activate(gsl_ctx *ctx, const gsl_adam_state *st, gsl_gaussians *act, void *stream)
+{
+    if (!ctx || !act) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_adam(st, nullptr));
+    if (act->N != st->N) return fail(GSL_EINVAL, "act.N %d != state N %d", act->N, st->N);
+    GSL_TRY(check_gauss(act, true));
+    float *a[5];
+    act_arrays(act, a);
+    launch_adam(nullptr, a, st->raw, nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, 1.f, st->N, false,
+                (hipStream_t)stream);
+    return check_launch("gsl_adam_activate");
+}
+
+int gsl_adam_step(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, const gsl_grads *grads, gsl_gaussians *act,
+                  void *stream)
+{
+    if (!ctx || !act || !hp || !grads) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_adam(st, hp));
+    if (act->N != st->N) return fail(GSL_EINVAL, "act.N %d != state N %d", act->N, st->N);
+    GSL_TRY(check_gauss(act, true));
+    if (st->N > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_color))
+        return fail(GSL_EINVAL, "gradient buffer is NULL");
+    do_adam(st, hp, grads, act, (hipStream_t)stream);
+    return check_launch("gsl_adam_step");
+}
+
+int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gsl_gaussians *act,
+                        const gsl_camera *cams, int32_t C, const gsl_opts *opts, const float *target, int loss,
+                        gsl_proj *proj, gsl_bins *bins, double *d_losses, gsl_grads *grads, int32_t iters,
+                        void *workspace, size_t workspace_bytes, int use_graph, void *stream)
+{
+    if (!act || !hp) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_adam(st, hp));
+    GSL_TRY(check_gauss(act, true));
+    if (act->N != st->N) return fail(GSL_EINVAL, "act.N %d != state N %d", act->N, st->N);
+    GSL_TRY(check_bins(bins));
+    if (!grads || !target || !d_losses) return fail(GSL_EINVAL, "NULL argument");
+    if (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_color)
+        return fail(GSL_EINVAL, "gradient buffer is NULL");
+    if (loss != GSL_LOSS_L1 && loss != GSL_LOSS_L2) return fail(GSL_EINVAL, "unknown loss %d", loss);
+    if (iters < 1 || iters > 1000) return fail(GSL_EINVAL, "iters %d not in [1, 1000]", iters);
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, act->N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    hipStream_t s = (hipStream_t)stream;
+    const VariantKey vk = window_key(p.L, cams);
+    int variant = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->variant.find(vk);
+        if (it != ctx->variant.end()) variant = it->second;
+    }
+    auto enqueue = [&](hipStream_t q) {
+        for (int k = 0; k < iters; k++) {
+            do_window(ctx, p, act, target, loss, proj, bins, nullptr, d_losses + k, grads, workspace, variant, q);
+            do_adam(st, hp, grads, act, q);
+        }
+    };
+    if (!use_graph) {
+        enqueue(s);
+        return check_launch("gsl_window_optimize");
+    }
+    VariantKey gk = window_graph_key(vk, variant, loss, act, target, proj, bins, nullptr, d_losses, grads,
+                                     workspace, opts, cams, C);
+    gk.v.push_back(-1);  // a separator from the single-step keys
+    gk.v.push_back(iters);
+    for (const void *q : {(const void *)st->raw, (const void *)st->m, (const void *)st->v, (const void *)st->d_step})
+        gk.v.push_back((int64_t)(uintptr_t)q);
+    const int32_t *hw = reinterpret_cast<const int32_t *>(hp);
+    for (size_t k = 0; k < sizeof(gsl_adam) / 4; k++) gk.v.push_back(hw[k]);
+    return graph_run(ctx, gk, s, enqueue);
 }
 
 int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,

@@ -159,6 +159,12 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kPoseThreads = 256;
 
+// optim.hip: Adam over raw parameters [14][N]; with update == false only the
+// activated values are written.  g / act: mean, scale, quaternion, opacity,
+// colour arrays in the gsl_gaussians layout.
+void launch_adam(const float *const g[5], float *const act[5], float *raw, float *m, float *v, const int32_t *d_step,
+                 const float lr[5], float beta1, float beta2, float eps, int N, bool update, hipStream_t s);
+
 // ---------------------------------------------------------------- launchers
 // project.hip
 void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t s);

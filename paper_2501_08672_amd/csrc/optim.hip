@@ -1,0 +1,97 @@
+// Adam over the map parameters (Sec. II-B: the Gaussian map is refined with
+// the Adam optimiser on the photometric loss of eq. eq:gaussian_optimization).
+//
+// The optimiser owns the raw parameters, 14 rows of N floats: mean (3),
+// log-scale (3), quaternion (4), opacity logit (1), colour (3); the renderer
+// takes the activated values, scale = exp(log-scale) and opacity =
+// sigmoid(logit), the other rows unchanged.  One lane per Gaussian: the
+// gradients of the activated values are chained to the raw rows, the moments
+// and the raw values are updated, and the new activated values are written
+// for the next pass.  The step count lives in device memory and is advanced by
+// a second one-lane kernel, so a captured graph of several iterations (or its
+// replays) uses the right bias corrections.
+#include "common.hpp"
+
+namespace gsl {
+
+namespace {
+
+struct AdamArgs {
+    const float *g[5];      // gradients of the activated mean, scale, quaternion, opacity, colour
+    float *act[5];          // activated outputs, same layout
+    float *raw, *m, *v;     // [14][N]
+    const int32_t *d_step;  // steps taken so far
+    float lr[5];
+    float beta1, beta2, eps;
+    int N;
+    bool update;            // false: only write the activated values of raw
+};
+
+constexpr int kRowGroup[14] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4};
+constexpr int kRowInGroup[14] = {0, 1, 2, 0, 1, 2, 0, 1, 2, 3, 0, 0, 1, 2};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const int64_t N = a.N;
+    float bc1 = 1.f, bc2 = 1.f;
+    if (a.update) {
+        const float t = (float)(*a.d_step + 1);
+        bc1 = 1.f - powf(a.beta1, t);
+        bc2 = 1.f - powf(a.beta2, t);
+    }
+#pragma unroll
+    for (int r = 0; r < 14; r++) {
+        const int grp = kRowGroup[r], k = kRowInGroup[r];
+        float x = a.raw[r * N + i];
+        if (a.update) {
+            float g = a.g[grp][k * N + i];
+            if (grp == 1) {
+                g *= expf(x);  // d exp(u) / du
+            } else if (grp == 3) {
+                const float s = 1.f / (1.f + expf(-x));
+                g *= s * (1.f - s);  // d sigmoid(u) / du
+            }
+            const float m = fmaf(a.beta1, a.m[r * N + i], (1.f - a.beta1) * g);
+            const float v = fmaf(a.beta2, a.v[r * N + i], (1.f - a.beta2) * g * g);
+            a.m[r * N + i] = m;
+            a.v[r * N + i] = v;
+            x -= a.lr[grp] * (m / bc1) / (sqrtf(v / bc2) + a.eps);
+            a.raw[r * N + i] = x;
+        }
+        float y = x;
+        if (grp == 1) y = expf(x);
+        else if (grp == 3) y = 1.f / (1.f + expf(-x));
+        a.act[grp][k * N + i] = y;
+    }
+}
+
+__global__ void k_step_advance(int32_t *d_step) { *d_step += 1; }
+
+}  // namespace
+
+void launch_adam(const float *const g[5], float *const act[5], float *raw, float *m, float *v, const int32_t *d_step,
+                 const float lr[5], float beta1, float beta2, float eps, int N, bool update, hipStream_t s)
+{
+    if (N == 0) return;
+    AdamArgs a;
+    for (int k = 0; k < 5; k++) {
+        a.g[k] = g ? g[k] : nullptr;
+        a.act[k] = act[k];
+        a.lr[k] = lr ? lr[k] : 0.f;
+    }
+    a.raw = raw;
+    a.m = m;
+    a.v = v;
+    a.d_step = d_step;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.N = N;
+    a.update = update;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a);
+    if (update) hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, const_cast<int32_t *>(d_step));
+}
+
+}  // namespace gsl

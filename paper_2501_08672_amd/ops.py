@@ -289,6 +289,59 @@ def render_stats(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, b
     return tuple(int(x) for x in counts.cpu().tolist())
 
 
+# ---------------------------------------------------------------- Adam over the map parameters
+
+class AdamState:
+    """gsl_adam_state: raw parameters (14, N) — mean 3, log-scale 3,
+    quaternion 4, opacity logit 1, colour 3 — their Adam moments and the
+    device step counter."""
+
+    def __init__(self, raw: torch.Tensor):
+        if raw.dtype != torch.float32 or raw.dim() != 2 or raw.shape[0] != 14:
+            raise ValueError("raw parameters must be a float32 (14, N) tensor")
+        self.raw = raw.contiguous()
+        self.m = torch.zeros_like(self.raw)
+        self.v = torch.zeros_like(self.raw)
+        self.d_step = torch.zeros(1, dtype=torch.int32, device=raw.device)
+
+    @property
+    def N(self) -> int:
+        return int(self.raw.shape[1])
+
+    @staticmethod
+    def from_gaussians(g: "Gaussians") -> "AdamState":
+        """Raw parameters of activated ones (initialisation, outside the step)."""
+        raw = torch.cat([g.mean, torch.log(g.scale), g.quat, torch.logit(g.opacity)[None], g.color], 0)
+        return AdamState(raw.float())
+
+    def struct(self) -> A.AdamState:
+        st = A.AdamState()
+        st.raw, st.m, st.v, st.d_step = (t.data_ptr() for t in (self.raw, self.m, self.v, self.d_step))
+        st.N = self.N
+        return st
+
+
+def adam_hparams(lr=(1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3), beta1=0.9, beta2=0.999, eps=1e-15) -> A.Adam:
+    """Learning rates per group: mean, log-scale, quaternion, opacity logit, colour."""
+    hp = A.Adam()
+    for k in range(5):
+        hp.lr[k] = float(lr[k])
+    hp.beta1, hp.beta2, hp.eps = float(beta1), float(beta2), float(eps)
+    return hp
+
+
+def adam_activate(ctx: Context, st: AdamState, g: "Gaussians"):
+    """g <- activation(st.raw)."""
+    ss, gs = st.struct(), g.struct()
+    A.check(A.lib().gsl_adam_activate(ctx.h, C.byref(ss), C.byref(gs), _stream()))
+
+
+def adam_step(ctx: Context, st: AdamState, hp: A.Adam, grads: "Grads", g: "Gaussians"):
+    """One Adam step from the gradients of the activated parameters; writes g."""
+    ss, gs, gr = st.struct(), g.struct(), grads.struct()
+    A.check(A.lib().gsl_adam_step(ctx.h, C.byref(ss), C.byref(hp), C.byref(gr), C.byref(gs), _stream()))
+
+
 # ---------------------------------------------------------------- pose Jacobians (IESKF visual update)
 
 @dataclass
@@ -405,6 +458,24 @@ class Window:
                                         _p(self.target), self.loss, C.byref(ps), C.byref(bs), _p(self.image),
                                         _p(self.d_loss), C.byref(gr), _p(self.ws), self.ws.numel(),
                                         int(bool(use_graph)), _stream()))
+
+    def optimize(self, st: AdamState, hp: A.Adam, iters: int = 10, use_graph: bool = True) -> torch.Tensor:
+        """`iters` window steps each followed by an Adam step (gsl_window_optimize);
+        self.g must hold activation(st.raw) (adam_activate) and is updated.
+        Returns the per-iteration losses (device float64)."""
+        if st.N != self.g.N:
+            raise ValueError("optimiser and window hold different Gaussian counts")
+        key = (iters, id(st))
+        if getattr(self, "_losses_key", None) != key:
+            self._losses = torch.zeros(iters, dtype=torch.float64, device=self.ctx.device)
+            self._losses_key = key
+        gs, ps, bs, gr, ss = (self.g.struct(), self.proj.struct(), self.bins.struct(), self.grads.struct(),
+                              st.struct())
+        A.check(A.lib().gsl_window_optimize(self.ctx.h, C.byref(ss), C.byref(hp), C.byref(gs), self.cams.arr,
+                                            self.cams.C, C.byref(self.opts), _p(self.target), self.loss, C.byref(ps),
+                                            C.byref(bs), _p(self._losses), C.byref(gr), int(iters), _p(self.ws),
+                                            self.ws.numel(), int(bool(use_graph)), _stream()))
+        return self._losses
 
     def profiled_step(self):
         """One eager step with HIP events between its stages; returns the
