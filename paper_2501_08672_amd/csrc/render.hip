@@ -64,6 +64,10 @@ struct Geo {
     static constexpr int PPL = CW * ROWS / kWave;         // pixels per lane
     static constexpr int RSTEP = kWave / CW;              // row stride between a lane's pixels
     static constexpr int CH = BS;                         // splats staged per chunk
+    // workgroups per CU the compositing kernels ask the compiler to fit: four
+    // waves per workgroup, eight workgroups = eight waves per SIMD (64 VGPRs);
+    // measured faster than fewer, larger-register waves
+    static constexpr int MIN_WG = BS == 256 ? 8 : 1;
     static constexpr bool MASKED = TS >= 16;
     static_assert(CW * ROWS % kWave == 0 && PPL >= 1 && ROWS * (QUAD ? 2 : NW) == TS, "tile/wave layout");
     __device__ static int col0(int w) { return QUAD ? (w & 1) * 16 : 0; }
@@ -504,7 +508,7 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
 }
 
 template <int TS, int NW>
-__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fwd(RenderArgs a)
+__global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_render_fwd(RenderArgs a)
 {
     using G = Geo<TS, NW>;
     __shared__ Stage<G::CH> st;
@@ -617,7 +621,7 @@ __device__ __forceinline__ int item_of_block(const RenderArgs &a, uint32_t b, bo
 }
 
 template <int TS, int NW, bool XCD>
-__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused(RenderArgs a)
+__global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_render_fused(RenderArgs a)
 {
     __shared__ Stage<Geo<TS, NW>::CH> st;
     __shared__ uint32_t s_max;
@@ -629,7 +633,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused(RenderArgs a
 }
 
 template <int TS, int NW>
-__global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_fused_persistent(RenderArgs a)
+__global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_render_fused_persistent(RenderArgs a)
 {
     __shared__ Stage<Geo<TS, NW>::CH> st;
     __shared__ uint32_t s_max;
