@@ -331,3 +331,83 @@ def adam_step(raw, m, v, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-15):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     return raw - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------- sliding-window maintenance
+
+KEY_BITS = 21            # bits per axis of a packed voxel key
+KEY_BIAS = 1 << 20       # axis index i is stored as i + 2^20, so i in [-2^20, 2^20)
+
+
+def voxel_key(points, voxel_size):
+    """Root-voxel hash key of each point (Sec. II-A, eq. HashKey): the integer
+    voxel index floor(p / v_s) per axis, computed in fp64 (p widened from
+    float32, v_s from float32).  The three indices are packed into one uint64
+    as ((ix + 2^20) << 42) | ((iy + 2^20) << 21) | (iz + 2^20).  A point with
+    an index outside [-2^20, 2^20) on any axis, or a non-finite coordinate,
+    has no key.  Returns (keys uint64 [P], valid bool [P]); invalid keys are 0."""
+    p = np.asarray(points, np.float32).astype(np.float64).reshape(-1, 3)
+    vs = float(np.float32(voxel_size))
+    keys = np.zeros(len(p), np.uint64)
+    valid = np.zeros(len(p), bool)
+    for j in range(len(p)):
+        if not np.all(np.isfinite(p[j])):
+            continue
+        idx = [int(np.floor(p[j, a] / vs)) for a in range(3)]
+        if any(i < -KEY_BIAS or i >= KEY_BIAS for i in idx):
+            continue
+        keys[j] = ((idx[0] + KEY_BIAS) << (2 * KEY_BITS)) | ((idx[1] + KEY_BIAS) << KEY_BITS) | (idx[2] + KEY_BIAS)
+        valid[j] = True
+    return keys, valid
+
+
+def window_classify(win_keys, point_keys, point_valid):
+    """Steps 1 and 3 of the incremental window update (Sec. II-C): the field
+    of view is the set of keys of the current LiDAR frame's points.  A window
+    Gaussian whose voxel key is not in it is DELETE; a key of the frame that no
+    window Gaussian carries is ADD.  Returns (delete bool [n], add_keys uint64)
+    with the ADD keys listed once each, in the order of their first point."""
+    win_keys = [int(k) for k in np.asarray(win_keys)]
+    fov = set(int(k) for k, ok in zip(np.asarray(point_keys), np.asarray(point_valid)) if ok)
+    delete = np.array([k not in fov for k in win_keys], bool)
+    in_window = set(win_keys)
+    add, seen = [], set()
+    for k, ok in zip(np.asarray(point_keys), np.asarray(point_valid)):
+        k = int(k)
+        if ok and k not in in_window and k not in seen:
+            seen.add(k)
+            add.append(k)
+    return delete, np.array(add, np.uint64)
+
+
+def window_maintain(keys, rows, fov_keys, add_keys, add_rows):
+    """Incremental update of the Gaussian window (Sec. II-C, steps 1, 2, 4),
+    written element by element.
+
+    keys (n,) voxel keys of the window; rows (R, n) its parameters;
+    fov_keys: the voxel keys of the current field of view.
+    Step 1: a Gaussian whose key is not in fov_keys is DELETE; its key and
+    parameters go to the evicted lists, in window order.
+    Step 2: with D deletions, each DELETE slot before n - D is filled by the
+    next kept Gaussian from [n - D, n), in order (swap with the rear); the
+    window is then [0, n - D).
+    Step 4: add_keys / add_rows are appended.
+    Returns keys_out, rows_out, evicted_keys, evicted_rows."""
+    keys = np.asarray(keys)
+    rows = np.asarray(rows)
+    fov = set(int(k) for k in np.asarray(fov_keys))
+    n = len(keys)
+    delete = [int(k) not in fov for k in keys]
+    D = sum(delete)
+    ev = [i for i in range(n) if delete[i]]
+    holes = [i for i in range(n - D) if delete[i]]
+    rear = [i for i in range(n - D, n) if not delete[i]]
+    assert len(holes) == len(rear)
+    out_keys = keys[: n - D].copy()
+    out_rows = rows[:, : n - D].copy()
+    for h, r in zip(holes, rear):
+        out_keys[h] = keys[r]
+        out_rows[:, h] = rows[:, r]
+    out_keys = np.concatenate([out_keys, np.asarray(add_keys, keys.dtype)])
+    out_rows = np.concatenate([out_rows, np.asarray(add_rows, rows.dtype).reshape(rows.shape[0], -1)], 1)
+    return out_keys, out_rows, keys[ev], rows[:, ev]

@@ -605,3 +605,112 @@ def test_activation_chain_matches_differences(oracle):
         e[idx] = h
         fd[idx] = (f(raw + e) - f(raw - e)) / (2 * h)
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)  # central-difference rounding at h = 1e-6
+
+
+# ---------------------------------------------------------------- window maintenance
+
+def test_window_maintain_worked_example(oracle):
+    """Eight Gaussians, keys 10..17, field of view {10, 12, 13, 15, 16, 17, 99}:
+    11 and 14 are deleted (D = 2); the holes before n - D = 6 are slots 1 and 4,
+    filled by the kept Gaussians of the rear [6, 8) in order (16 -> 1, 17 -> 4);
+    then 20 and 21 are appended."""
+    keys = np.arange(10, 18, dtype=np.uint64)
+    rows = np.stack([keys.astype(np.float32), -keys.astype(np.float32)])
+    k, r, ek, er = oracle.window_maintain(keys, rows, [10, 12, 13, 15, 16, 17, 99], np.array([20, 21], np.uint64),
+                                          np.array([[20, 21], [-20, -21]], np.float32))
+    assert k.tolist() == [10, 16, 12, 13, 17, 15, 20, 21]
+    assert r[0].tolist() == [10, 16, 12, 13, 17, 15, 20, 21] and r[1].tolist() == [-x for x in r[0].tolist()]
+    assert ek.tolist() == [11, 14] and er[0].tolist() == [11, 14]
+
+
+def test_window_maintain_invariants(oracle):
+    """Random windows: the kept keys are exactly the window keys in the field
+    of view, front Gaussians that are kept do not move, every Gaussian keeps
+    its own parameters, evicted are the rest in window order."""
+    rng = np.random.default_rng(8)
+    for trial in range(20):
+        n = int(rng.integers(0, 200))
+        keys = rng.permutation(10_000)[:n].astype(np.uint64)
+        rows = rng.normal(size=(3, n)).astype(np.float32)
+        rows[0] = keys
+        fov = rng.choice(10_000, 5000, replace=False)
+        add = np.arange(20_000, 20_000 + int(rng.integers(0, 30)), dtype=np.uint64)
+        add_rows = np.stack([add.astype(np.float32), np.zeros(len(add), np.float32), np.ones(len(add), np.float32)])
+        k, r, ek, er = oracle.window_maintain(keys, rows, fov, add, add_rows)
+        inf = np.isin(keys, fov)
+        D = int((~inf).sum())
+        assert sorted(k[: n - D].tolist()) == sorted(keys[inf].tolist())
+        assert k[n - D:].tolist() == add.tolist()
+        front_kept = np.nonzero(inf[: n - D])[0]
+        assert np.array_equal(k[front_kept], keys[front_kept])
+        np.testing.assert_array_equal(r[0], k.astype(np.float32))
+        assert ek.tolist() == keys[~inf].tolist()
+        np.testing.assert_array_equal(er, rows[:, ~inf])
+
+
+def _unpack(key):
+    m = (1 << 21) - 1
+    return ((int(key) >> 42) & m) - (1 << 20), ((int(key) >> 21) & m) - (1 << 20), (int(key) & m) - (1 << 20)
+
+
+def test_voxel_key_floor_and_packing(oracle):
+    """floor, not truncation, on negative coordinates; a coordinate exactly on
+    a voxel face belongs to the voxel above; the packed fields decode to the
+    indices; out-of-range and non-finite points have no key."""
+    pts = np.array([[0.26, -0.1, 1.0], [-0.5, 0.0, 0.49], [6.0e5, 0, 0], [np.nan, 0, 0]], np.float32)  # 6e5 / 0.5 >= 2^20
+    k, ok = oracle.voxel_key(pts, 0.5)
+    assert ok.tolist() == [True, True, False, False]
+    assert _unpack(k[0]) == (0, -1, 2)
+    assert _unpack(k[1]) == (-1, 0, 0)
+    assert int(k[0]) == (1 << 62) | ((1 << 20) - 1 << 21) | ((1 << 20) + 2)
+    assert k[2] == 0 and k[3] == 0
+
+
+def test_voxel_key_cell_contains_point(oracle):
+    """The voxel a key names contains the point: i v_s <= p < (i + 1) v_s per
+    axis, exactly (float32 inputs make fp64 products and the quotient's floor
+    exact), and two points share a key iff they share every index."""
+    rng = np.random.default_rng(3)
+    pts = (rng.normal(size=(400, 3)) * 40).astype(np.float32)
+    pts[:50] = np.round(pts[:50] / 0.4) * np.float32(0.4)  # near voxel faces
+    for vs in (0.4, 1.0, 0.25):
+        k, ok = oracle.voxel_key(pts, vs)
+        assert ok.all()
+        v = float(np.float32(vs))
+        for j in range(len(pts)):
+            idx = _unpack(k[j])
+            for a in range(3):
+                assert idx[a] * v <= float(pts[j, a]) < (idx[a] + 1) * v
+        i_all = np.floor(pts.astype(np.float64) / v).astype(np.int64)
+        same_key = k[:, None] == k[None, :]
+        same_idx = (i_all[:, None, :] == i_all[None, :, :]).all(-1)
+        assert np.array_equal(same_key, same_idx)
+
+
+def test_window_classify_worked_example(oracle):
+    """Window keys [5, 7, 5, 9, 11]; frame keys [7, 3, 7, 12, 5, 3, x(invalid)]:
+    the field of view is {3, 5, 7, 12}; 9 and 11 are DELETE; ADD is 3 then 12
+    (order of first appearance), each once."""
+    d, add = oracle.window_classify(np.array([5, 7, 5, 9, 11], np.uint64),
+                                    np.array([7, 3, 7, 12, 5, 3, 9], np.uint64),
+                                    np.array([1, 1, 1, 1, 1, 1, 0], bool))
+    assert d.tolist() == [False, False, False, True, True]
+    assert add.tolist() == [3, 12]
+
+
+def test_window_classify_set_identities(oracle):
+    """ADD and the kept window keys partition the field of view; ADD keys are
+    unique, absent from the window, and ordered by first appearance."""
+    rng = np.random.default_rng(5)
+    for trial in range(10):
+        win = rng.integers(0, 300, int(rng.integers(0, 400))).astype(np.uint64)
+        pk = rng.integers(100, 500, int(rng.integers(0, 600))).astype(np.uint64)
+        ok = rng.random(len(pk)) > 0.1
+        d, add = oracle.window_classify(win, pk, ok)
+        fov = set(pk[ok].tolist())
+        kept = set(win[~d].tolist())
+        assert kept <= fov and set(win[d].tolist()).isdisjoint(fov)
+        assert len(set(add.tolist())) == len(add) and set(add.tolist()).isdisjoint(set(win.tolist()))
+        assert kept | set(add.tolist()) == fov
+        first = [int(np.nonzero((pk == a) & ok)[0][0]) for a in add]
+        assert first == sorted(first)
