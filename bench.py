@@ -18,6 +18,8 @@ Prints one JSON line; besides the metric it carries
   cpu_baseline      the FP64 oracle, forward + backward, on a pixel sample
   pose_jacobian     the IESKF measurement model (per-pixel twist Jacobians and
                     normal equations) on 32 perturbed poses of a 640x512 view
+  window_update     the incremental sliding-window update (hash classification
+                    of a LiDAR frame's voxels, in-place compaction) at 500k
 """
 import argparse
 import hashlib
@@ -57,6 +59,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-jac", action="store_true", help="skip the pose-Jacobian measurement")
+    ap.add_argument("--no-window-update", action="store_true", help="skip the window-update measurement")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line: window step time vs N in {20k, 100k, 500k, 2M} at "
                          "640x512 and 1280x1024 (8 keyframes), one JSON line per point")
@@ -157,6 +160,64 @@ def pose_jacobian_bench(ctx, ops, S, torch, reps=5):
                     "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
                     "pairs": {"evaluated": ev_f, "contributors": n_contrib}},
             "residual_rms": round(float(np.sqrt(pj.zz.sum().item() / (3 * P))), 5)}
+
+
+def window_update_bench(ctx, ops, S, torch, frames=8):
+    """The incremental window update (Sec. II-C) on a synthetic LiDAR stream:
+    a 500k-Gaussian window (42 rows: raw parameters and Adam moments) at a
+    capacity of 2^20, 100k points per frame, root voxels of 0.5 m, the sensor
+    moving 1 m per frame.  Per frame: gsl_window_classify, the host read of
+    (D, A), and gsl_window_compact appending as many Gaussians per ADD voxel
+    as the window holds per voxel on average (rows resident on the device)."""
+    n, P, cap, vs, R = 500_000, 100_000, 1 << 20, 0.5, 42
+    pts_np, means = S.lidar_stream(71, frames + 1, P, n)
+    pts = [torch.from_numpy(p).cuda() for p in pts_np]
+    sw = ops.SlidingWindow(ctx, cap, vs)
+    sw.keys[:n] = ops.voxel_keys(ctx, torch.from_numpy(means).cuda(), vs)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    sw.block.normal_(generator=gen)
+    sw.n = n
+    per_voxel = max(1, round(n / int(torch.unique(sw.keys[:n]).numel())))
+    pool = torch.randn(R, cap, generator=gen, device="cuda")
+    ws = ops.window_workspace(ctx, cap, P)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    rows = []
+    for f in range(frames + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        counts, addv = ops.window_classify(ctx, pts[f], vs, sw.keys, sw.n, ws)
+        ev[1].record()
+        D, A = (int(x) for x in counts.cpu())
+        akeys = addv[:A].repeat_interleave(per_voxel)
+        arows = pool[:, :akeys.shape[0]].contiguous()
+        ev[2].record()
+        _, _, status = ops.window_compact(ctx, sw.keys, sw.block, sw.n, D, akeys, arows, ws)
+        ev[3].record()
+        torch.cuda.synchronize()
+        t_frame = time.perf_counter() - t0
+        assert int(status.item()) == 0
+        n_before = sw.n
+        sw.n = sw.n - D + int(akeys.shape[0])
+        if f == 0:
+            continue  # warm-up frame
+        rows.append((n_before, D, A, int(akeys.shape[0]), ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]),
+                     t_frame * 1e3))
+    a = np.array(rows, dtype=np.float64)
+    n_m, D_m, Av_m, Ag_m, cls_ms, cmp_ms, frame_ms = (float(x) for x in a.mean(0))
+    rec = 8 + 4 * R
+    cls_bytes = 12 * P + 8 * n_m + 8 * Av_m
+    cmp_bytes = 2 * D_m * rec + 2 * D_m * rec + 2 * Ag_m * rec  # evict, move (<= D), append
+    return {"workload": "sliding-window update: 500k Gaussians x 42 rows (raw + Adam moments), capacity 2^20, "
+                        "100k LiDAR points per frame, 0.5 m root voxels, sensor moving 1 m per frame",
+            "frames": frames, "window": round(n_m), "deleted": round(D_m), "add_voxels": round(Av_m),
+            "appended": round(Ag_m), "classify_ms": round(cls_ms, 4), "compact_ms": round(cmp_ms, 4),
+            "frame_ms": round(frame_ms, 4),
+            "hbm": {"classify_bytes": int(cls_bytes), "compact_bytes_max": int(cmp_bytes),
+                    "classify_gbs": round(cls_bytes / (cls_ms * 1e-3) / 1e9, 1),
+                    "compact_gbs": round(cmp_bytes / (cmp_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS},
+            "how": "HIP events around each call; frame_ms adds the host read of (D, A) and the appended rows' "
+                   "staging, the per-frame synchronisation the host-side global map needs"}
 
 
 def sweep(args):
@@ -365,6 +426,11 @@ def main():
                 "how": "gsl_window_optimize: 10 x (window step + Adam step over the 500k raw parameters), one graph"}
     log(f"optimise 10 iterations: {optimize}")
 
+    win_upd = None
+    if not args.no_window_update:
+        win_upd = window_update_bench(ctx, ops, S, torch)
+        log(f"window update: {win_upd}")
+
     pose_jac = None
     if not args.no_jac:
         pose_jac = pose_jacobian_bench(ctx, ops, S, torch)
@@ -408,6 +474,8 @@ def main():
     result["optimize"] = optimize
     if pose_jac is not None:
         result["pose_jacobian"] = pose_jac
+    if win_upd is not None:
+        result["window_update"] = win_upd
     if tune_times is not None:
         result["autotune_ms"] = [round(t, 3) for t in tune_times]
     if not args.no_cpu:

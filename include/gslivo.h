@@ -272,7 +272,7 @@ GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
 /* ---- Adam over the map parameters ----------------------------------------- */
 
 /* The map is refined with Adam (Sec. II-B, eq. eq:gaussian_optimization).
- * The optimiser keeps raw parameters: 14 rows of N floats, row-major [14][N]:
+ * The optimiser keeps raw parameters: 14 rows of N floats at a row stride ld:
  * mean (3), log-scale (3), quaternion (4), opacity logit (1), colour (3).  The
  * renderer takes the activated values (scale = exp(log-scale), opacity =
  * sigmoid(logit), the rest unchanged), which the optimiser writes into the
@@ -283,10 +283,12 @@ typedef struct {
 } gsl_adam;
 
 typedef struct {
-    float *raw;      /* [14][N] raw parameters */
-    float *m, *v;    /* [14][N] first and second moments (zero before the first step) */
+    float *raw;      /* [14][ld] raw parameters: row r of Gaussian i at raw[r * ld + i] */
+    float *m, *v;    /* [14][ld] first and second moments (zero before the first step) */
     int32_t *d_step; /* device: steps taken (0 before the first step), advanced by each step */
-    int32_t N;
+    int32_t N;       /* Gaussians in the window */
+    int32_t ld;      /* row stride in floats, >= N (0: N).  A window kept at a fixed
+                      * capacity (gsl_window_compact) uses its capacity here. */
 } gsl_adam_state;
 
 /* act <- activation(raw).  No optimiser step. */
@@ -311,6 +313,69 @@ GSL_API int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam
                                 int loss, gsl_proj *proj, gsl_bins *bins, double *d_losses, gsl_grads *grads,
                                 int32_t iters, void *workspace, size_t workspace_bytes, int use_graph,
                                 void *stream);
+
+/* ---- sliding-window maintenance ------------------------------------------ */
+
+/* The window of Gaussians is kept contiguous on the device and updated
+ * incrementally from frame to frame (Sec. II-C, Steps 1-4).  Each Gaussian
+ * carries the 64-bit key of the root voxel it belongs to (Sec. II-A, eq.
+ * HashKey): with i = floor(p / v_s) per axis, computed in float64,
+ *   key = ((ix + 2^20) << 42) | ((iy + 2^20) << 21) | (iz + 2^20),
+ * defined for indices in [-2^20, 2^20).  Its parameters are R rows of 4-byte
+ * words at a row stride ld (a capacity): row r of Gaussian i at
+ * rows[r * ld + i].  Raw parameters and Adam moments allocated as one
+ * [42][ld] block (raw, m, v of a gsl_adam_state with that ld) are moved by
+ * one call. */
+
+/* keys[i] <- the voxel key of point i, whose coordinates are
+ * xyz[i * point_stride + a * axis_stride], a = 0, 1, 2 (device float; [P][3]
+ * interleaved: strides 3, 1; component-major [3][P] like gsl_gaussians.mean:
+ * strides 1, P).  A point without a key (non-finite, or an index outside
+ * [-2^20, 2^20)) gets 0xFFFFFFFFFFFFFFFF, which no window Gaussian may carry
+ * and stay in the window.  For keying new Gaussians at insertion. */
+GSL_API int gsl_voxel_keys(gsl_ctx *ctx, const float *xyz, int32_t P, int64_t point_stride, int64_t axis_stride,
+                           float voxel_size, uint64_t *keys, void *stream);
+
+/* Workspace bytes for gsl_window_classify / gsl_window_compact with a window
+ * of n Gaussians and a frame of P points: a hash table of 16 B per slot
+ * (the smallest power of two >= max(1024, 2P)), 12 B per point, 12 B per
+ * window Gaussian and the scan partials. */
+GSL_API int gsl_window_workspace_size(int32_t n, int32_t P, size_t *bytes);
+
+/* Steps 1 and 3.  points: device float [P][3] world coordinates of the
+ * current LiDAR frame (interleaved x, y, z); voxel_size v_s > 0; keys: device
+ * uint64 [n] of the window.  The field of view is the set of keys of the
+ * frame's points (points without a key are ignored).  Writes, on the device:
+ *   counts  int32[2]: D, the window Gaussians whose key is not in the field
+ *           of view (DELETE), and A, the keys of the frame that no window
+ *           Gaussian carries (ADD);
+ *   add_keys uint64[P] (may be NULL): entries [0, A) are the ADD keys, each
+ *           once, in the order of their first point.
+ * The workspace keeps the classification for gsl_window_compact; it must not
+ * be reused before that call has been enqueued. */
+GSL_API int gsl_window_classify(gsl_ctx *ctx, const float *points, int32_t P, float voxel_size,
+                                const uint64_t *keys, int32_t n, int32_t *counts, uint64_t *add_keys,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Steps 2 and 4, in place, after gsl_window_classify on the same workspace
+ * with the same n.  D is the DELETE count that call wrote (read back by the
+ * caller).  In stream order:
+ *   1. the DELETE Gaussians are gathered, in window order, into
+ *      evicted_keys uint64[D] and evicted_rows float[R][D] (row stride D);
+ *      either may be NULL (not written);
+ *   2. with n' = n - D, the k-th DELETE slot below n' receives the k-th kept
+ *      Gaussian of [n', n) (keys and rows); kept Gaussians below n' keep
+ *      their slot;
+ *   3. the A new Gaussians add_keys uint64[A], add_rows float[R][A] (row
+ *      stride A) are written to slots [n', n' + A).
+ * Afterwards the window holds n - D + A Gaussians.  Host checks: n - D + A <=
+ * ld, 0 <= D <= n.  If n or D differ from what the classification found on
+ * the device, nothing is written and *status (device int32, may be NULL)
+ * is set to 1; otherwise to 0. */
+GSL_API int gsl_window_compact(gsl_ctx *ctx, uint64_t *keys, float *rows, int32_t R, int64_t ld, int32_t n,
+                               int32_t D, const uint64_t *add_keys, const float *add_rows, int32_t A,
+                               uint64_t *evicted_keys, float *evicted_rows, const void *workspace,
+                               size_t workspace_bytes, int32_t *status, void *stream);
 
 /* ---- pose Jacobians for the IESKF visual update -------------------------- */
 

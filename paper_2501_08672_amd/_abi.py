@@ -30,7 +30,8 @@ EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "g
            "gsl_project", "gsl_bin_sort", "gsl_render_fwd", "gsl_render_bwd", "gsl_render_stats", "gsl_window_step",
            "gsl_window_tune", "gsl_window_variant", "gsl_profile", "gsl_profile_read",
            "gsl_pose_jacobian_workspace_size", "gsl_pose_jacobian", "gsl_imu_to_camera_twist",
-           "gsl_ieskf_pose_update", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize"]
+           "gsl_ieskf_pose_update", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
+           "gsl_voxel_keys", "gsl_window_workspace_size", "gsl_window_classify", "gsl_window_compact"]
 
 
 class GslError(RuntimeError):
@@ -65,7 +66,7 @@ class Adam(C.Structure):
 
 class AdamState(C.Structure):
     _fields_ = [("raw", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("d_step", C.c_void_p),
-                ("N", C.c_int32)]
+                ("N", C.c_int32), ("ld", C.c_int32)]
 
 
 class Bins(C.Structure):
@@ -124,6 +125,11 @@ def lib() -> C.CDLL:
     L.gsl_adam_step.argtypes = [P, ps, pa, pgr, pg, P]
     L.gsl_window_optimize.argtypes = [P, ps, pa, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, pgr, C.c_int32, P,
                                       C.c_size_t, C.c_int, P]
+    L.gsl_voxel_keys.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, C.c_float, P, P]
+    L.gsl_window_workspace_size.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+    L.gsl_window_classify.argtypes = [P, P, C.c_int32, C.c_float, P, C.c_int32, P, P, P, C.c_size_t, P]
+    L.gsl_window_compact.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, C.c_int32, P, P, C.c_int32, P, P, P,
+                                     C.c_size_t, P, P]
     for name in EXPORTS:
         if name not in ("gsl_last_error", "gsl_default_opts"):
             getattr(L, name).restype = C.c_int

@@ -439,6 +439,7 @@ int check_adam(const gsl_adam_state *st, const gsl_adam *hp)
     if (!st) return fail(GSL_EINVAL, "adam state is NULL");
     if (st->N < 0) return fail(GSL_EINVAL, "negative Gaussian count");
     if (st->N > 0 && (!st->raw || !st->m || !st->v || !st->d_step)) return fail(GSL_EINVAL, "adam buffer is NULL");
+    if (st->ld != 0 && st->ld < st->N) return fail(GSL_EINVAL, "adam row stride %d < N %d", st->ld, st->N);
     if (hp) {
         if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f))
             return fail(GSL_EINVAL, "need 0 <= beta < 1");
@@ -448,6 +449,8 @@ int check_adam(const gsl_adam_state *st, const gsl_adam *hp)
     }
     return GSL_OK;
 }
+
+int64_t adam_ld(const gsl_adam_state *st) { return st->ld ? st->ld : st->N; }
 
 void act_arrays(gsl_gaussians *act, float *out[5])
 {
@@ -463,7 +466,8 @@ void do_adam(gsl_adam_state *st, const gsl_adam *hp, const gsl_grads *grads, gsl
     const float *g[5] = {grads->g_mean, grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_color};
     float *a[5];
     act_arrays(act, a);
-    launch_adam(g, a, st->raw, st->m, st->v, st->d_step, hp->lr, hp->beta1, hp->beta2, hp->eps, st->N, true, s);
+    launch_adam(g, a, st->raw, st->m, st->v, st->d_step, hp->lr, hp->beta1, hp->beta2, hp->eps, st->N, adam_ld(st),
+                true, s);
 }
 
 // Bytes gsl_pose_jacobian needs past the common workspace: per-record
@@ -500,6 +504,69 @@ bool invert6(const double *A, double *X)
     for (int r = 0; r < 6; r++)
         for (int c = 0; c < 6; c++) X[6 * r + c] = M[r][6 + c];
     return true;
+}
+
+// Window-maintenance workspace: the header and the per-Gaussian arrays come
+// first (their offsets depend on n only, so gsl_window_compact can find them
+// without P), then the scan partials, the per-point arrays and the table.
+constexpr int64_t kWinMaxPoints = (int64_t)1 << 28;
+
+struct WinLayout {
+    size_t hdr = 0, del = 0, drank = 0, evpos = 0, compact_end = 0;
+    size_t partial = 0, pslot = 0, addf = 0, arank = 0, table = 0, total = 0;
+    uint64_t slots = 0;
+};
+
+WinLayout win_layout(int64_t n, int64_t P)
+{
+    WinLayout w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    w.hdr = take(64);
+    w.del = take(4 * (size_t)n);
+    w.drank = take(4 * (size_t)n);
+    w.evpos = take(4 * (size_t)n);
+    w.compact_end = o;
+    const int64_t nb = (std::max(n, P) + kScanTile - 1) / kScanTile;
+    w.partial = take(8 * (size_t)std::max<int64_t>(nb, 1));
+    w.pslot = take(4 * (size_t)P);
+    w.addf = take(4 * (size_t)P);
+    w.arank = take(4 * (size_t)P);
+    w.slots = window_table_slots(P);
+    w.table = take(16 * (size_t)w.slots);
+    w.total = o;
+    return w;
+}
+
+WinWs win_ws(void *ws, const WinLayout &l)
+{
+    char *b = static_cast<char *>(ws);
+    WinWs w;
+    w.hdr = reinterpret_cast<int64_t *>(b + l.hdr);
+    w.del = reinterpret_cast<uint32_t *>(b + l.del);
+    w.drank = reinterpret_cast<uint32_t *>(b + l.drank);
+    w.evpos = reinterpret_cast<uint32_t *>(b + l.evpos);
+    if (l.total) {
+        w.partial = reinterpret_cast<uint64_t *>(b + l.partial);
+        w.pslot = reinterpret_cast<uint32_t *>(b + l.pslot);
+        w.addf = reinterpret_cast<uint32_t *>(b + l.addf);
+        w.arank = reinterpret_cast<uint32_t *>(b + l.arank);
+        w.table = b + l.table;
+        w.slots = l.slots;
+    }
+    return w;
+}
+
+int check_device(gsl_ctx *ctx)
+{
+    int cur = -1;
+    GSL_TRY(check_hip(hipGetDevice(&cur), "hipGetDevice"));
+    if (cur != ctx->device) return fail(GSL_ESTATE, "current device %d is not the context's device %d", cur, ctx->device);
+    return GSL_OK;
 }
 
 }  // namespace
@@ -807,7 +874,7 @@ int gsl_adam_activate(gsl_ctx *ctx, const gsl_adam_state *st, gsl_gaussians *act
     GSL_TRY(check_gauss(act, true));
     float *a[5];
     act_arrays(act, a);
-    launch_adam(nullptr, a, st->raw, nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, 1.f, st->N, false,
+    launch_adam(nullptr, a, st->raw, nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, 1.f, st->N, adam_ld(st), false,
                 (hipStream_t)stream);
     return check_launch("gsl_adam_activate");
 }
@@ -867,9 +934,75 @@ int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gs
     gk.v.push_back(iters);
     for (const void *q : {(const void *)st->raw, (const void *)st->m, (const void *)st->v, (const void *)st->d_step})
         gk.v.push_back((int64_t)(uintptr_t)q);
+    gk.v.push_back(adam_ld(st));
     const int32_t *hw = reinterpret_cast<const int32_t *>(hp);
     for (size_t k = 0; k < sizeof(gsl_adam) / 4; k++) gk.v.push_back(hw[k]);
     return graph_run(ctx, gk, s, enqueue);
+}
+
+int gsl_window_workspace_size(int32_t n, int32_t P, size_t *bytes)
+{
+    if (!bytes) return fail(GSL_EINVAL, "NULL argument");
+    if (n < 0 || P < 0 || P > kWinMaxPoints) return fail(GSL_EINVAL, "need n >= 0 and 0 <= P <= 2^28");
+    *bytes = win_layout(n, P).total;
+    return GSL_OK;
+}
+
+int gsl_voxel_keys(gsl_ctx *ctx, const float *xyz, int32_t P, int64_t point_stride, int64_t axis_stride,
+                   float voxel_size, uint64_t *keys, void *stream)
+{
+    if (!ctx) return fail(GSL_EINVAL, "NULL argument");
+    if (P < 0) return fail(GSL_EINVAL, "negative point count");
+    if (P > 0 && (!xyz || !keys)) return fail(GSL_EINVAL, "NULL argument");
+    if (point_stride < 0 || axis_stride < 0) return fail(GSL_EINVAL, "negative stride");
+    if (!(voxel_size > 0.f) || !std::isfinite(voxel_size)) return fail(GSL_EINVAL, "voxel_size must be finite and > 0");
+    GSL_TRY(check_device(ctx));
+    launch_voxel_keys(xyz, P, point_stride, axis_stride, voxel_size, keys, (hipStream_t)stream);
+    return check_launch("gsl_voxel_keys");
+}
+
+int gsl_window_classify(gsl_ctx *ctx, const float *points, int32_t P, float voxel_size, const uint64_t *keys,
+                        int32_t n, int32_t *counts, uint64_t *add_keys, void *workspace, size_t workspace_bytes,
+                        void *stream)
+{
+    if (!ctx || !counts || !workspace) return fail(GSL_EINVAL, "NULL argument");
+    if (n < 0 || P < 0 || P > kWinMaxPoints) return fail(GSL_EINVAL, "need n >= 0 and 0 <= P <= 2^28");
+    if (P > 0 && !points) return fail(GSL_EINVAL, "points is NULL");
+    if (n > 0 && !keys) return fail(GSL_EINVAL, "keys is NULL");
+    if (!(voxel_size > 0.f) || !std::isfinite(voxel_size)) return fail(GSL_EINVAL, "voxel_size must be finite and > 0");
+    if ((uintptr_t)workspace % 256) return fail(GSL_EINVAL, "workspace must be 256-byte aligned");
+    const WinLayout l = win_layout(n, P);
+    if (workspace_bytes < l.total)
+        return fail(GSL_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes, l.total);
+    GSL_TRY(check_device(ctx));
+    launch_window_classify(points, P, voxel_size, keys, n, win_ws(workspace, l), counts, add_keys,
+                           (hipStream_t)stream);
+    return check_launch("gsl_window_classify");
+}
+
+int gsl_window_compact(gsl_ctx *ctx, uint64_t *keys, float *rows, int32_t R, int64_t ld, int32_t n, int32_t D,
+                       const uint64_t *add_keys, const float *add_rows, int32_t A, uint64_t *evicted_keys,
+                       float *evicted_rows, const void *workspace, size_t workspace_bytes, int32_t *status,
+                       void *stream)
+{
+    if (!ctx || !workspace) return fail(GSL_EINVAL, "NULL argument");
+    if (R < 0 || n < 0 || A < 0) return fail(GSL_EINVAL, "negative size");
+    if (D < 0 || D > n) return fail(GSL_EINVAL, "D %d not in [0, n = %d]", D, n);
+    if (ld < (int64_t)n || (int64_t)n - D + A > ld)
+        return fail(GSL_EINVAL, "row stride %lld too small for n = %d, n - D + A = %lld", (long long)ld, n,
+                    (long long)n - D + A);
+    if ((n > 0 || A > 0) && !keys) return fail(GSL_EINVAL, "keys is NULL");
+    if (R > 0 && (n > 0 || A > 0) && !rows) return fail(GSL_EINVAL, "rows is NULL");
+    if (A > 0 && (!add_keys || (R > 0 && !add_rows))) return fail(GSL_EINVAL, "added Gaussians are NULL");
+    if ((uintptr_t)workspace % 256) return fail(GSL_EINVAL, "workspace must be 256-byte aligned");
+    WinLayout l = win_layout(n, 0);
+    if (workspace_bytes < l.compact_end)
+        return fail(GSL_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes, l.compact_end);
+    l.total = 0;  // only the header and the per-Gaussian arrays are used
+    GSL_TRY(check_device(ctx));
+    launch_window_compact(keys, rows, R, ld, n, D, add_keys, add_rows, A, evicted_keys, evicted_rows,
+                          win_ws(const_cast<void *>(workspace), l), status, (hipStream_t)stream);
+    return check_launch("gsl_window_compact");
 }
 
 int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,

@@ -159,11 +159,33 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kPoseThreads = 256;
 
-// optim.hip: Adam over raw parameters [14][N]; with update == false only the
+// optim.hip: Adam over raw parameters [14][ld]; with update == false only the
 // activated values are written.  g / act: mean, scale, quaternion, opacity,
-// colour arrays in the gsl_gaussians layout.
+// colour arrays in the gsl_gaussians layout (row stride N).
 void launch_adam(const float *const g[5], float *const act[5], float *raw, float *m, float *v, const int32_t *d_step,
-                 const float lr[5], float beta1, float beta2, float eps, int N, bool update, hipStream_t s);
+                 const float lr[5], float beta1, float beta2, float eps, int N, int64_t ld, bool update,
+                 hipStream_t s);
+
+// window.hip: maintenance of the sliding window (hash set of the frame's
+// voxel keys, DELETE / ADD classification, in-place compaction).
+struct WinWs {
+    void *table = nullptr;      // 16-byte slots
+    uint64_t slots = 0;         // power of two, >= 2 P
+    int64_t *hdr = nullptr;     // D, A, n, P of the last classification, a marker
+    uint32_t *pslot = nullptr;  // [P] slot of each point's key
+    uint32_t *addf = nullptr, *arank = nullptr;  // [P]
+    uint32_t *del = nullptr, *drank = nullptr, *evpos = nullptr;  // [n]
+    uint64_t *partial = nullptr;  // scan partial sums
+};
+uint64_t window_table_slots(int64_t P);
+// key of point i from xyz[i * ps + a * as], a = 0..2 (~0 where it has none)
+void launch_voxel_keys(const float *xyz, int64_t P, int64_t ps, int64_t as, float voxel_size, uint64_t *keys,
+                       hipStream_t s);
+void launch_window_classify(const float *pts, int64_t P, float voxel_size, const uint64_t *keys, int64_t n,
+                            const WinWs &w, int32_t *counts, uint64_t *add_keys, hipStream_t s);
+void launch_window_compact(uint64_t *keys, float *rows, int R, int64_t ld, int64_t n, int64_t D,
+                           const uint64_t *add_keys, const float *add_rows, int64_t A, uint64_t *evicted_keys,
+                           float *evicted_rows, const WinWs &w, int32_t *status, hipStream_t s);
 
 // ---------------------------------------------------------------- launchers
 // project.hip

@@ -1,7 +1,8 @@
 // Adam over the map parameters (Sec. II-B: the Gaussian map is refined with
 // the Adam optimiser on the photometric loss of eq. eq:gaussian_optimization).
 //
-// The optimiser owns the raw parameters, 14 rows of N floats: mean (3),
+// The optimiser owns the raw parameters, 14 rows of N floats at a row stride
+// ld (a window kept at a fixed capacity uses the capacity): mean (3),
 // log-scale (3), quaternion (4), opacity logit (1), colour (3); the renderer
 // takes the activated values, scale = exp(log-scale) and opacity =
 // sigmoid(logit), the other rows unchanged.  One lane per Gaussian: the
@@ -19,11 +20,12 @@ namespace {
 struct AdamArgs {
     const float *g[5];      // gradients of the activated mean, scale, quaternion, opacity, colour
     float *act[5];          // activated outputs, same layout
-    float *raw, *m, *v;     // [14][N]
+    float *raw, *m, *v;     // [14][ld]
     const int32_t *d_step;  // steps taken so far
     float lr[5];
     float beta1, beta2, eps;
     int N;
+    int64_t ld;
     bool update;            // false: only write the activated values of raw
 };
 
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    const int64_t N = a.N;
+    const int64_t N = a.N, ld = a.ld;
     float bc1 = 1.f, bc2 = 1.f;
     if (a.update) {
         const float t = (float)(*a.d_step + 1);
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a)
 #pragma unroll
     for (int r = 0; r < 14; r++) {
         const int grp = kRowGroup[r], k = kRowInGroup[r];
-        float x = a.raw[r * N + i];
+        float x = a.raw[r * ld + i];
         if (a.update) {
             float g = a.g[grp][k * N + i];
             if (grp == 1) {
@@ -53,12 +55,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a)
                 const float s = 1.f / (1.f + expf(-x));
                 g *= s * (1.f - s);  // d sigmoid(u) / du
             }
-            const float m = fmaf(a.beta1, a.m[r * N + i], (1.f - a.beta1) * g);
-            const float v = fmaf(a.beta2, a.v[r * N + i], (1.f - a.beta2) * g * g);
-            a.m[r * N + i] = m;
-            a.v[r * N + i] = v;
+            const float m = fmaf(a.beta1, a.m[r * ld + i], (1.f - a.beta1) * g);
+            const float v = fmaf(a.beta2, a.v[r * ld + i], (1.f - a.beta2) * g * g);
+            a.m[r * ld + i] = m;
+            a.v[r * ld + i] = v;
             x -= a.lr[grp] * (m / bc1) / (sqrtf(v / bc2) + a.eps);
-            a.raw[r * N + i] = x;
+            a.raw[r * ld + i] = x;
         }
         float y = x;
         if (grp == 1) y = expf(x);
@@ -72,7 +74,8 @@ __global__ void k_step_advance(int32_t *d_step) { *d_step += 1; }
 }  // namespace
 
 void launch_adam(const float *const g[5], float *const act[5], float *raw, float *m, float *v, const int32_t *d_step,
-                 const float lr[5], float beta1, float beta2, float eps, int N, bool update, hipStream_t s)
+                 const float lr[5], float beta1, float beta2, float eps, int N, int64_t ld, bool update,
+                 hipStream_t s)
 {
     if (N == 0) return;
     AdamArgs a;
@@ -89,6 +92,7 @@ void launch_adam(const float *const g[5], float *const act[5], float *raw, float
     a.beta2 = beta2;
     a.eps = eps;
     a.N = N;
+    a.ld = ld;
     a.update = update;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a);
     if (update) hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, const_cast<int32_t *>(d_step));

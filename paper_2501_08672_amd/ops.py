@@ -292,21 +292,29 @@ def render_stats(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, b
 # ---------------------------------------------------------------- Adam over the map parameters
 
 class AdamState:
-    """gsl_adam_state: raw parameters (14, N) — mean 3, log-scale 3,
+    """gsl_adam_state: raw parameters (14, ld) — mean 3, log-scale 3,
     quaternion 4, opacity logit 1, colour 3 — their Adam moments and the
-    device step counter."""
+    device step counter.  The first n columns are live (n = ld unless given),
+    so a window kept at a fixed capacity can hand in views of its block."""
 
-    def __init__(self, raw: torch.Tensor):
+    def __init__(self, raw: torch.Tensor, m: Optional[torch.Tensor] = None, v: Optional[torch.Tensor] = None,
+                 d_step: Optional[torch.Tensor] = None, n: Optional[int] = None):
         if raw.dtype != torch.float32 or raw.dim() != 2 or raw.shape[0] != 14:
-            raise ValueError("raw parameters must be a float32 (14, N) tensor")
-        self.raw = raw.contiguous()
-        self.m = torch.zeros_like(self.raw)
-        self.v = torch.zeros_like(self.raw)
-        self.d_step = torch.zeros(1, dtype=torch.int32, device=raw.device)
+            raise ValueError("raw parameters must be a float32 (14, ld) tensor")
+        self.raw = raw if raw.stride(1) == 1 else raw.contiguous()
+        self.m = torch.zeros_like(self.raw) if m is None else m
+        self.v = torch.zeros_like(self.raw) if v is None else v
+        for t in (self.m, self.v):
+            if t.shape != self.raw.shape or t.stride() != self.raw.stride() or t.dtype != torch.float32:
+                raise ValueError("moments must have the raw parameters' shape and strides")
+        self.d_step = torch.zeros(1, dtype=torch.int32, device=raw.device) if d_step is None else d_step
+        self.n = int(self.raw.shape[1]) if n is None else int(n)
+        if not 0 <= self.n <= self.raw.shape[1]:
+            raise ValueError("live count exceeds the row length")
 
     @property
     def N(self) -> int:
-        return int(self.raw.shape[1])
+        return self.n
 
     @staticmethod
     def from_gaussians(g: "Gaussians") -> "AdamState":
@@ -317,7 +325,8 @@ class AdamState:
     def struct(self) -> A.AdamState:
         st = A.AdamState()
         st.raw, st.m, st.v, st.d_step = (t.data_ptr() for t in (self.raw, self.m, self.v, self.d_step))
-        st.N = self.N
+        st.N = self.n
+        st.ld = int(self.raw.stride(0))
         return st
 
 
@@ -340,6 +349,112 @@ def adam_step(ctx: Context, st: AdamState, hp: A.Adam, grads: "Grads", g: "Gauss
     """One Adam step from the gradients of the activated parameters; writes g."""
     ss, gs, gr = st.struct(), g.struct(), grads.struct()
     A.check(A.lib().gsl_adam_step(ctx.h, C.byref(ss), C.byref(hp), C.byref(gr), C.byref(gs), _stream()))
+
+
+# ---------------------------------------------------------------- sliding-window maintenance
+
+def voxel_keys(ctx: Context, xyz: torch.Tensor, voxel_size: float, component_major: bool = False) -> torch.Tensor:
+    """Voxel keys (int64 tensor holding the uint64 bits; -1 = no key) of
+    points given as (P, 3), or (3, P) with component_major (gsl_voxel_keys)."""
+    if xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[0 if component_major else 1] != 3:
+        raise ValueError("points must be a float32 (P, 3) tensor, or (3, P) when component-major")
+    if component_major:
+        P, ps, as_ = xyz.shape[1], xyz.stride(1), xyz.stride(0)
+    else:
+        P, ps, as_ = xyz.shape[0], xyz.stride(0), xyz.stride(1)
+    keys = torch.empty(P, dtype=torch.int64, device=xyz.device)
+    A.check(A.lib().gsl_voxel_keys(ctx.h, _p(xyz), P, ps, as_, float(voxel_size), _p(keys), _stream()))
+    return keys
+
+
+def window_workspace(ctx: Context, n: int, P: int) -> torch.Tensor:
+    """A workspace of its own for one classify + compact pair (n Gaussians, P points)."""
+    nb = C.c_size_t()
+    A.check(A.lib().gsl_window_workspace_size(int(n), int(P), C.byref(nb)))
+    return torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=ctx.device)
+
+
+def window_classify(ctx: Context, points: torch.Tensor, voxel_size: float, keys: torch.Tensor, n: int,
+                    ws: torch.Tensor):
+    """Steps 1 and 3 (gsl_window_classify).  points (P, 3) float32; keys:
+    the window's keys (first n used).  Returns (counts int32[2] = (D, A) and
+    add_keys int64[P], both on the device; the first A add keys are valid)."""
+    points = points.contiguous()
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be a float32 (P, 3) tensor")
+    P = points.shape[0]
+    counts = torch.zeros(2, dtype=torch.int32, device=points.device)
+    add_keys = torch.empty(max(P, 1), dtype=torch.int64, device=points.device)
+    A.check(A.lib().gsl_window_classify(ctx.h, _p(points), P, float(voxel_size), _p(keys), int(n), _p(counts),
+                                        _p(add_keys), _p(ws), ws.numel(), _stream()))
+    return counts, add_keys
+
+
+def window_compact(ctx: Context, keys: torch.Tensor, rows: Optional[torch.Tensor], n: int, D: int,
+                   add_keys: torch.Tensor, add_rows: Optional[torch.Tensor], ws: torch.Tensor, evict: bool = True):
+    """Steps 2 and 4 in place (gsl_window_compact).  keys int64 (ld,), rows
+    float32 (R, ld) (or None); add_keys (A,), add_rows (R, A).  Returns
+    (evicted_keys (D,), evicted_rows (R, D), status int32[1]) on the device."""
+    ld = keys.shape[0]
+    R = 0 if rows is None else rows.shape[0]
+    if rows is not None and (rows.dtype != torch.float32 or rows.shape[1] != ld or rows.stride(1) != 1
+                             or rows.stride(0) != ld):
+        raise ValueError("rows must be a float32 (R, ld) row-major tensor with the keys' length")
+    Aadd = int(add_keys.shape[0])
+    add_keys = add_keys.contiguous()
+    if R and Aadd:
+        add_rows = add_rows.contiguous()
+        if add_rows.shape != (R, Aadd) or add_rows.dtype != torch.float32:
+            raise ValueError("add_rows must be float32 (R, A)")
+    dev = keys.device
+    ek = torch.empty(int(D), dtype=torch.int64, device=dev) if evict else None
+    er = torch.empty(R, int(D), dtype=torch.float32, device=dev) if evict and R else None
+    status = torch.empty(1, dtype=torch.int32, device=dev)  # always written
+    A.check(A.lib().gsl_window_compact(ctx.h, _p(keys), _p(rows), R, ld, int(n), int(D), _p(add_keys),
+                                       _p(add_rows) if R and Aadd else None, Aadd, _p(ek), _p(er), _p(ws),
+                                       ws.numel(), _p(status), _stream()))
+    return ek, er, status
+
+
+class SlidingWindow:
+    """The window of Gaussians at a fixed capacity on the device (Sec. II-C):
+    one float32 block (42, capacity) — raw parameters (rows 0-13), Adam
+    first (14-27) and second (28-41) moments — and the voxel keys; the first
+    n columns are live.  `update` runs one frame's incremental update."""
+
+    ROWS = 42
+
+    def __init__(self, ctx: Context, capacity: int, voxel_size: float):
+        self.ctx, self.capacity, self.voxel_size = ctx, int(capacity), float(voxel_size)
+        dev = ctx.device
+        self.block = torch.zeros(self.ROWS, self.capacity, dtype=torch.float32, device=dev)
+        self.keys = torch.full((self.capacity,), -1, dtype=torch.int64, device=dev)
+        self.d_step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.n = 0
+
+    def adam_state(self) -> AdamState:
+        b = self.block
+        return AdamState(b[0:14], b[14:28], b[28:42], self.d_step, n=self.n)
+
+    def update(self, points: torch.Tensor, fetch, ws: Optional[torch.Tensor] = None):
+        """One frame: classify against the frame's points, then call
+        fetch(add_keys int64 (A_vox,) on the host) -> (keys (A,), rows (42, A)),
+        the Gaussians to append (from the global map or newly initialised;
+        moments zero), and compact.  Returns (evicted_keys, evicted_rows) on
+        the device, for the global map."""
+        ws = window_workspace(self.ctx, self.n, points.shape[0]) if ws is None else ws
+        counts, add_vox = window_classify(self.ctx, points, self.voxel_size, self.keys, self.n, ws)
+        D, A_vox = (int(x) for x in counts.cpu())
+        akeys, arows = fetch(add_vox[:A_vox].cpu())
+        akeys = torch.as_tensor(akeys, dtype=torch.int64).to(self.keys.device)
+        arows = torch.as_tensor(arows, dtype=torch.float32).to(self.keys.device).reshape(self.ROWS, -1)
+        if self.n - D + akeys.shape[0] > self.capacity:
+            raise ValueError("window capacity exceeded")
+        ek, er, status = window_compact(self.ctx, self.keys, self.block, self.n, D, akeys, arows, ws)
+        if int(status.item()) != 0:
+            raise RuntimeError("window compaction rejected: stale classification")
+        self.n = self.n - D + int(akeys.shape[0])
+        return ek, er
 
 
 # ---------------------------------------------------------------- pose Jacobians (IESKF visual update)

@@ -15,6 +15,7 @@ from .scenes import (  # noqa: F401
     look_camera,
     camera_from_pose,
     trajectory_cameras,
+    lidar_stream,
     perturb_camera,
     so3_exp,
     config1,

@@ -307,6 +307,40 @@ def trajectory_cameras(n, width, height, f, seed, step=0.3, turn_deg=5.0):
     return cams
 
 
+def lidar_stream(seed, frames, points_per_frame, n_window, extent=80.0, n_planes=600, patch=6.0,
+                 range_m=20.0, step=1.0, nan_frac=0.01, mean_sigma=0.05):
+    """A synthetic LiDAR stream for the sliding-window update (Sec. II-C).
+
+    The world is a corridor of planar patches (centres uniform in
+    [0, extent] x [-8, 8] x [-3, 3] m, normals uniform on the sphere, side
+    `patch` m), densely sampled once.  The sensor moves along +x by `step`
+    metres per frame starting at x = range_m; frame k holds points_per_frame
+    samples (with replacement) of the surface points within range_m of the
+    sensor, a `nan_frac` share of them replaced by NaN returns.  The initial
+    window is n_window Gaussian means: samples of frame 0's points with
+    N(0, mean_sigma) offsets.  Returns (list of (P, 3) float32 arrays,
+    (n_window, 3) float32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    per = 8000
+    cloud = np.empty((n_planes * per, 3))
+    for p in range(n_planes):
+        c = np.array([rng.uniform(0, extent), rng.uniform(-8, 8), rng.uniform(-3, 3)])
+        a, b, _ = _plane_frame(rng.normal(size=3))
+        uv = rng.uniform(-patch / 2, patch / 2, (per, 2))
+        cloud[p * per:(p + 1) * per] = c + uv[:, :1] * a + uv[:, 1:] * b
+    out = []
+    for k in range(frames):
+        sensor = np.array([range_m + k * step, 0.0, 0.0])
+        near = cloud[np.sum((cloud - sensor) ** 2, 1) <= range_m ** 2]
+        pts = near[rng.integers(0, len(near), points_per_frame)]
+        bad = rng.random(points_per_frame) < nan_frac
+        pts[bad] = np.nan
+        out.append(pts.astype(F32))
+    first = out[0][np.all(np.isfinite(out[0]), 1)].astype(np.float64)
+    means = first[rng.integers(0, len(first), n_window)] + rng.normal(0.0, mean_sigma, (n_window, 3))
+    return out, means.astype(F32)
+
+
 # ----------------------------------------------------------------------------
 # the five benchmark workloads
 # ----------------------------------------------------------------------------

@@ -40,15 +40,16 @@ def test_exports_match_header(abi):
 def test_struct_layouts_match_header(abi, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gslivo.h"\nint main(void){'
-                   'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gsl_camera), sizeof(gsl_opts), '
-                   'sizeof(gsl_gaussians), sizeof(gsl_splat), sizeof(gsl_proj), sizeof(gsl_bins), sizeof(gsl_grads), '
-                   'offsetof(gsl_camera, t_cw), offsetof(gsl_bins, capacity_K), sizeof(gsl_binrec)); return 0;}')
+                   'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gsl_camera), '
+                   'sizeof(gsl_opts), sizeof(gsl_gaussians), sizeof(gsl_splat), sizeof(gsl_proj), sizeof(gsl_bins), '
+                   'sizeof(gsl_grads), offsetof(gsl_camera, t_cw), offsetof(gsl_bins, capacity_K), sizeof(gsl_binrec), '
+                   'sizeof(gsl_adam), sizeof(gsl_adam_state), offsetof(gsl_adam_state, ld)); return 0;}')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(abi.Camera), C.sizeof(abi.Opts), C.sizeof(abi.Gaussians), abi.SPLAT_BYTES,
             C.sizeof(abi.Proj), C.sizeof(abi.Bins), C.sizeof(abi.Grads), abi.Camera.t_cw.offset,
-            abi.Bins.capacity_K.offset, 32]
+            abi.Bins.capacity_K.offset, 32, C.sizeof(abi.Adam), C.sizeof(abi.AdamState), abi.AdamState.ld.offset]
     assert got == want
 
 
