@@ -124,8 +124,158 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
-def _params(scene):
-    return (_d(scene.mean), _d(scene.scale), _d(scene.quat), _d(scene.opacity), _d(scene.color))
+def _params(scene, cam=None):
+    """Parameters as float64 arrays; with SH coefficients the colour is the
+    one seen from `cam`."""
+    colour = _d(scene.color) if getattr(scene, "sh", None) is None else _d(sh_colour(scene, cam))
+    return (_d(scene.mean), _d(scene.scale), _d(scene.quat), _d(scene.opacity), colour)
+
+
+# ---------------------------------------------------------------- view-dependent colour (spherical harmonics)
+
+_Y00 = 0.5 / np.sqrt(np.pi)
+
+
+def sh_basis(u, degree):
+    """Real orthonormal spherical harmonics Y_lm of degrees l = 1..degree at
+    the points u (..., 3) (unit vectors), each divided by Y_00 = 1/(2 sqrt(pi)),
+    so that a colour is c(u) = k_0 + sum_k k_k B_k(u) and the degree-0
+    coefficient k_0 is the colour itself (the map's SH coefficients, Sec. II-B).
+    Order: l = 1..degree, m = -l..l.  Written as the usual Cartesian
+    polynomials of the real basis (no Condon-Shortley sign):
+      l = 1: c1 (y, z, x),                         c1 = sqrt(3 / (4 pi))
+      l = 2: c2 xy, c2 yz, c20 (3z^2 - 1), c2 xz, c2/2 (x^2 - y^2),
+             c2 = sqrt(15 / pi) / 2, c20 = sqrt(5 / pi) / 4
+      l = 3: a y(3x^2 - y^2), b xyz, c y(5z^2 - 1), e (5z^3 - 3z),
+             c x(5z^2 - 1), b/2 (x^2 - y^2) z, a x(x^2 - 3y^2),
+             a = sqrt(35 / (2 pi)) / 4, b = sqrt(105 / pi) / 2,
+             c = sqrt(21 / (2 pi)) / 4, e = sqrt(7 / pi) / 4.
+    Returns (..., K), K = (degree + 1)^2 - 1."""
+    u = np.asarray(u, np.float64)
+    x, y, z = u[..., 0], u[..., 1], u[..., 2]
+    out = []
+    if degree >= 1:
+        c1 = np.sqrt(3.0 / (4.0 * np.pi))
+        out += [c1 * y, c1 * z, c1 * x]
+    if degree >= 2:
+        c2, c20 = np.sqrt(15.0 / np.pi) / 2.0, np.sqrt(5.0 / np.pi) / 4.0
+        out += [c2 * x * y, c2 * y * z, c20 * (3.0 * z * z - 1.0), c2 * x * z, 0.5 * c2 * (x * x - y * y)]
+    if degree >= 3:
+        a, b = np.sqrt(35.0 / (2.0 * np.pi)) / 4.0, np.sqrt(105.0 / np.pi) / 2.0
+        c, e = np.sqrt(21.0 / (2.0 * np.pi)) / 4.0, np.sqrt(7.0 / np.pi) / 4.0
+        out += [a * y * (3.0 * x * x - y * y), b * x * y * z, c * y * (5.0 * z * z - 1.0),
+                e * (5.0 * z ** 3 - 3.0 * z), c * x * (5.0 * z * z - 1.0), 0.5 * b * (x * x - y * y) * z,
+                a * x * (x * x - 3.0 * y * y)]
+    if not out:
+        return np.zeros(u.shape[:-1] + (0,))
+    return np.stack(out, -1) / _Y00
+
+
+def sh_basis_grad(u, degree):
+    """Partial derivatives of the polynomials of sh_basis with respect to
+    (x, y, z): (..., K, 3)."""
+    u = np.asarray(u, np.float64)
+    x, y, z = u[..., 0], u[..., 1], u[..., 2]
+    o, l = np.zeros_like(x), np.ones_like(x)
+    rows = []
+    if degree >= 1:
+        c1 = np.sqrt(3.0 / (4.0 * np.pi))
+        rows += [(o, c1 * l, o), (o, o, c1 * l), (c1 * l, o, o)]
+    if degree >= 2:
+        c2, c20 = np.sqrt(15.0 / np.pi) / 2.0, np.sqrt(5.0 / np.pi) / 4.0
+        rows += [(c2 * y, c2 * x, o), (o, c2 * z, c2 * y), (o, o, 6.0 * c20 * z), (c2 * z, o, c2 * x),
+                 (c2 * x, -c2 * y, o)]
+    if degree >= 3:
+        a, b = np.sqrt(35.0 / (2.0 * np.pi)) / 4.0, np.sqrt(105.0 / np.pi) / 2.0
+        c, e = np.sqrt(21.0 / (2.0 * np.pi)) / 4.0, np.sqrt(7.0 / np.pi) / 4.0
+        rows += [(6.0 * a * x * y, a * (3.0 * x * x - 3.0 * y * y), o),
+                 (b * y * z, b * x * z, b * x * y),
+                 (o, c * (5.0 * z * z - 1.0), 10.0 * c * y * z),
+                 (o, o, e * (15.0 * z * z - 3.0)),
+                 (c * (5.0 * z * z - 1.0), o, 10.0 * c * x * z),
+                 (b * x * z, -b * y * z, 0.5 * b * (x * x - y * y)),
+                 (a * (3.0 * x * x - 3.0 * y * y), -6.0 * a * x * y, o)]
+    if not rows:
+        return np.zeros(u.shape[:-1] + (0, 3))
+    return np.stack([np.stack(r, -1) for r in rows], -2) / _Y00
+
+
+def bilinear_colour(means, cam, image, near_z=0.2):
+    """Initial colour of new Gaussians (Sec. II-B, eq. c(mu_I)): the mean is
+    projected into the camera, mu_I = (fx x/z + cx, fy y/z + cy), and the
+    colour is the bilinear interpolation of the image there: pixel (i, j) has
+    its centre at (i + 1/2, j + 1/2); with s = mu_I - 1/2 clamped to the
+    centres' range [0, W-1] x [0, H-1], the four surrounding pixels are
+    weighted by the areas of the opposite sub-rectangles, c = sum_j c_j A_j.
+    A mean with z <= near_z or outside [0, W) x [0, H) gets no colour.
+    means (n, 3); image planar (3, H, W).  Returns colour (n, 3) (zero where
+    invalid) and valid (n,) bool.  All in float64."""
+    means = np.asarray(means, np.float64).reshape(-1, 3)
+    img = np.asarray(image, np.float64)
+    H, W = img.shape[1], img.shape[2]
+    R = np.asarray(cam.R_cw, np.float64).reshape(3, 3)
+    t = np.asarray(cam.t_cw, np.float64).reshape(3)
+    out = np.zeros((len(means), 3))
+    valid = np.zeros(len(means), bool)
+    for n in range(len(means)):
+        pc = R @ means[n] + t
+        if not pc[2] > near_z:
+            continue
+        u = cam.fx * pc[0] / pc[2] + cam.cx
+        v = cam.fy * pc[1] / pc[2] + cam.cy
+        if not (0.0 <= u < W and 0.0 <= v < H):
+            continue
+        sx = min(max(u - 0.5, 0.0), W - 1.0)
+        sy = min(max(v - 0.5, 0.0), H - 1.0)
+        i0, j0 = min(int(np.floor(sx)), max(W - 2, 0)), min(int(np.floor(sy)), max(H - 2, 0))
+        a, b = sx - i0, sy - j0
+        i1, j1 = min(i0 + 1, W - 1), min(j0 + 1, H - 1)
+        out[n] = ((1 - a) * (1 - b) * img[:, j0, i0] + a * (1 - b) * img[:, j0, i1]
+                  + (1 - a) * b * img[:, j1, i0] + a * b * img[:, j1, i1])
+        valid[n] = True
+    return out, valid
+
+
+def camera_centre(cam):
+    """World position of the camera: o = -R_cw^T t_cw."""
+    R = np.asarray(cam.R_cw, np.float64).reshape(3, 3)
+    return -R.T @ np.asarray(cam.t_cw, np.float64).reshape(3)
+
+
+def _view_dirs(scene, cam):
+    d = np.asarray(scene.mean, np.float64) - camera_centre(cam)
+    r = np.linalg.norm(d, axis=1)
+    return d / r[:, None], r
+
+
+def sh_colour(scene, cam):
+    """Colour of every Gaussian seen from `cam`: c = k_0 + sum_k k_k B_k(u)
+    with u the unit direction from the camera centre to the mean, in world
+    coordinates.  No clamp (the degree-0 colour is used directly, as without
+    SH).  (N, 3) float64."""
+    col = np.asarray(scene.color, np.float64)
+    if getattr(scene, "sh", None) is None:
+        return col
+    u, _ = _view_dirs(scene, cam)
+    B = sh_basis(u, scene.sh_degree)
+    return col + np.einsum("nk,nkc->nc", B, np.asarray(scene.sh, np.float64))
+
+
+def sh_colour_vjp(scene, cam, g_c):
+    """Adjoint of sh_colour for a cotangent g_c (N, 3): returns g_color (N,3),
+    g_sh (N,K,3), g_mean (N,3) and g_dt (3,), the gradient with respect to the
+    translation of the left twist of T_CW (the camera centre moves by
+    -R_cw^T dt; a rotation of the twist leaves it in place)."""
+    g_c = np.asarray(g_c, np.float64)
+    u, r = _view_dirs(scene, cam)
+    sh = np.asarray(scene.sh, np.float64)
+    B = sh_basis(u, scene.sh_degree)
+    dB = sh_basis_grad(u, scene.sh_degree)
+    g_sh = B[:, :, None] * g_c[:, None, :]
+    g_u = np.einsum("nc,nkc,nkj->nj", g_c, sh, dB)
+    g_d = (g_u - u * np.sum(u * g_u, 1, keepdims=True)) / r[:, None]
+    R = np.asarray(cam.R_cw, np.float64).reshape(3, 3)
+    return g_c.copy(), g_sh, g_d, R @ g_d.sum(0)
 
 
 def all_pixels(cam) -> np.ndarray:
@@ -137,7 +287,7 @@ def project(scene, cam, opts: Opts = Opts()):
     """Per-Gaussian projection into `cam`: p_cam (N,3), mean2d (N,2),
     cov2d (N,3: xx, xy, yy incl. dilation), conic (N,3: A, B, C), status (N,)."""
     N = scene.n
-    m, s, q, _, _ = _params(scene)
+    m, s, q, _, _ = _params(scene, cam)
     out = {k: np.zeros((N, w)) for k, w in (("p_cam", 3), ("mean2d", 2), ("cov2d", 3), ("conic", 3))}
     out["status"] = np.zeros(N, np.int32)
     co, oo = _cam(cam), opts.c()
@@ -153,7 +303,7 @@ def render(scene, cam, opts: Opts = Opts(), pixels=None):
     last contributor (-1 if none) and flags (P,) ambiguity bits."""
     pix = all_pixels(cam) if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
     P = pix.shape[0]
-    m, s, q, o, c = _params(scene)
+    m, s, q, o, c = _params(scene, cam)
     rgb = np.zeros((P, 3))
     T = np.zeros(P)
     n = np.zeros(P, np.int32)
@@ -181,9 +331,11 @@ def render_bwd(scene, cams, vs, opts: Opts = Opts(), pixels=None, want_g2d=False
     scale (N,3), quat (N,4), opacity (N,), color (N,3), pose (C,6) as
     (dphi, dt) of a left perturbation of each T_CW, and g2d (C,N,9) if asked."""
     N = scene.n
-    m, s, q, o, c = _params(scene)
+    has_sh = getattr(scene, "sh", None) is not None
     g = {"mean": np.zeros((N, 3)), "scale": np.zeros((N, 3)), "quat": np.zeros((N, 4)),
          "opacity": np.zeros(N), "color": np.zeros((N, 3)), "pose": np.zeros((len(cams), 6))}
+    if has_sh:
+        g["sh"] = np.zeros(scene.sh.shape)
     if want_g2d:
         g["g2d"] = np.zeros((len(cams), N, 9))
     oo = opts.c()
@@ -200,9 +352,17 @@ def render_bwd(scene, cams, vs, opts: Opts = Opts(), pixels=None, want_g2d=False
         pose = np.zeros(6)
         g2 = np.zeros((N, 9)) if want_g2d else None
         co = _cam(cam)
+        m, s, q, o, c = _params(scene, cam)
+        gcol = np.zeros((N, 3)) if has_sh else g["color"]
         lib().orc_render_bwd(N, _p(m), _p(s), _p(q), _p(o), _p(c), C.byref(co), C.byref(oo), pix.shape[0],
                              _p(pix), _p(v), _p(g["mean"]), _p(g["scale"]), _p(g["quat"]), _p(g["opacity"]),
-                             _p(g["color"]), _p(pose), _p(g2))
+                             _p(gcol), _p(pose), _p(g2))
+        if has_sh:  # chain the per-camera colour gradient through the SH colour
+            gc0, gsh, gm, gdt = sh_colour_vjp(scene, cam, gcol)
+            g["color"] += gc0
+            g["sh"] += gsh
+            g["mean"] += gm
+            pose[3:] += gdt
         g["pose"][ci] = pose
         if want_g2d:
             g["g2d"][ci] = g2
@@ -210,7 +370,7 @@ def render_bwd(scene, cams, vs, opts: Opts = Opts(), pixels=None, want_g2d=False
 
 
 def pixel_trace(scene, cam, u, v, opts: Opts = Opts(), cap=100000):
-    m, s, q, o, c = _params(scene)
+    m, s, q, o, c = _params(scene, cam)
     ids = np.zeros(cap, np.int64)
     al = np.zeros(cap)
     Ts = np.zeros(cap)
@@ -228,7 +388,9 @@ def render_jvp(scene, cam, opts: Opts = Opts(), pixels=None):
     (contributor sets held fixed).  Returns rgb (P,3), jac (P,3,6), pixels."""
     pix = all_pixels(cam) if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
     P = pix.shape[0]
-    m, s, q, o, c = _params(scene)
+    if getattr(scene, "sh", None) is not None:
+        raise NotImplementedError("pose Jacobians are defined here for degree-0 colour only")
+    m, s, q, o, c = _params(scene, cam)
     rgb = np.zeros((P, 3))
     jac = np.zeros((P, 3, 6))
     co, oo = _cam(cam), opts.c()

@@ -16,6 +16,7 @@ from .scenes import (  # noqa: F401
     camera_from_pose,
     trajectory_cameras,
     lidar_stream,
+    with_sh,
     perturb_camera,
     so3_exp,
     config1,

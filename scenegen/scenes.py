@@ -21,7 +21,7 @@ Conventions shared by all consumers:
 from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
-from typing import List
+from typing import List, Optional
 
 import numpy as np
 
@@ -63,6 +63,7 @@ class Scene:
     color: np.ndarray
     cams: List[Camera] = field(default_factory=list)
     name: str = ""
+    sh: Optional[np.ndarray] = None  # (N, K, 3) higher-order SH coefficients, K = (degree + 1)^2 - 1
 
     def __post_init__(self):
         self.mean = np.ascontiguousarray(self.mean, dtype=F32)
@@ -74,6 +75,14 @@ class Scene:
         assert self.mean.shape == (n, 3) and self.scale.shape == (n, 3)
         assert self.quat.shape == (n, 4) and self.opacity.shape == (n,)
         assert self.color.shape == (n, 3)
+        if self.sh is not None:
+            self.sh = np.ascontiguousarray(self.sh, dtype=F32)
+            assert self.sh.ndim == 3 and self.sh.shape[0] == n and self.sh.shape[2] == 3
+            assert self.sh.shape[1] in (3, 8, 15)
+
+    @property
+    def sh_degree(self) -> int:
+        return 0 if self.sh is None else {3: 1, 8: 2, 15: 3}[self.sh.shape[1]]
 
     @property
     def n(self) -> int:
@@ -82,7 +91,8 @@ class Scene:
     def subset(self, idx) -> "Scene":
         idx = np.asarray(idx)
         return replace(self, mean=self.mean[idx], scale=self.scale[idx], quat=self.quat[idx],
-                       opacity=self.opacity[idx], color=self.color[idx])
+                       opacity=self.opacity[idx], color=self.color[idx],
+                       sh=None if self.sh is None else self.sh[idx])
 
     def permuted(self, perm) -> "Scene":
         return self.subset(perm)
@@ -92,6 +102,8 @@ class Scene:
         h = hashlib.sha1()
         for a in (self.mean, self.scale, self.quat, self.opacity, self.color):
             h.update(np.ascontiguousarray(a).tobytes())
+        if self.sh is not None:
+            h.update(self.sh.tobytes())
         for c in self.cams:
             h.update(np.array([c.fx, c.fy, c.cx, c.cy, c.width, c.height], np.float64).tobytes())
             h.update(c.R_cw.tobytes())
@@ -305,6 +317,19 @@ def trajectory_cameras(n, width, height, f, seed, step=0.3, turn_deg=5.0):
     for R, c in zip(Rwc, C):
         cams.append(camera_from_pose(R0.T @ R, R0.T @ (c - C0), width, height, f))
     return cams
+
+
+def with_sh(scene: Scene, degree: int, seed, sigma=0.15) -> Scene:
+    """The scene with view-dependent colour: higher-order SH coefficients of
+    degrees 1..degree drawn N(0, sigma / l) per channel (degree l), the
+    degree-0 coefficient being the scene's colour."""
+    if degree == 0:
+        return replace(scene, sh=None)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K = (degree + 1) ** 2 - 1
+    lvl = np.array([l for l in range(1, degree + 1) for _ in range(2 * l + 1)], np.float64)
+    sh = rng.normal(size=(scene.n, K, 3)) * (sigma / lvl)[None, :, None]
+    return replace(scene, sh=sh.astype(F32), name=scene.name + f"+sh{degree}")
 
 
 def lidar_stream(seed, frames, points_per_frame, n_window, extent=80.0, n_planes=600, patch=6.0,

@@ -12,6 +12,8 @@ import pytest
 from scipy.spatial.transform import Rotation
 
 import scenegen as S
+from dataclasses import replace
+
 from scenegen import Camera, Scene
 
 pytestmark = pytest.mark.filterwarnings("ignore")
@@ -714,3 +716,202 @@ def test_window_classify_set_identities(oracle):
         assert kept | set(add.tolist()) == fov
         first = [int(np.nonzero((pk == a) & ok)[0][0]) for a in add]
         assert first == sorted(first)
+
+
+# ---------------------------------------------------------------- view-dependent colour
+
+def _real_sh_scipy(l, m, u):
+    """Real orthonormal Y_lm from scipy's complex harmonics (with the
+    Condon-Shortley phase), made real as sqrt(2) (-1)^m Re / Im."""
+    from scipy.special import sph_harm_y
+    theta = np.arccos(np.clip(u[:, 2], -1, 1))
+    phi = np.arctan2(u[:, 1], u[:, 0])
+    if m == 0:
+        return sph_harm_y(l, 0, theta, phi).real
+    Y = sph_harm_y(l, abs(m), theta, phi)
+    return np.sqrt(2.0) * (-1) ** m * (Y.real if m > 0 else Y.imag)
+
+
+def _unit(rng, n):
+    u = rng.normal(size=(n, 3))
+    return u / np.linalg.norm(u, axis=1, keepdims=True)
+
+
+def test_sh_basis_matches_scipy(oracle):
+    """The Cartesian polynomials against scipy's spherical harmonics, every
+    (l, m) up to degree 3, times Y_00 = 1 / (2 sqrt(pi))."""
+    u = _unit(np.random.default_rng(1), 200)
+    B = oracle.sh_basis(u, 3) * (0.5 / np.sqrt(np.pi))
+    k = 0
+    for l in range(1, 4):
+        for m in range(-l, l + 1):
+            np.testing.assert_allclose(B[:, k], _real_sh_scipy(l, m, u), atol=1e-12, err_msg=f"l={l} m={m}")
+            k += 1
+    assert oracle.sh_basis(u, 1).shape == (200, 3) and oracle.sh_basis(u, 2).shape == (200, 8)
+
+
+def test_sh_basis_orthogonal_on_sphere(oracle):
+    """Gauss-Legendre in cos(theta) x uniform phi (exact for these degrees):
+    the integral of B_i B_j over the sphere is 4 pi delta_ij, and of B_i is 0."""
+    xg, wg = np.polynomial.legendre.leggauss(10)
+    nphi = 16
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    u = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    w = (wg[:, None] * np.full(nphi, 2 * np.pi / nphi)[None, :]).reshape(-1)
+    B = oracle.sh_basis(u, 3)
+    G = (B * w[:, None]).T @ B
+    np.testing.assert_allclose(G, 4 * np.pi * np.eye(15), atol=1e-11)
+    np.testing.assert_allclose(w @ B, np.zeros(15), atol=1e-11)
+
+
+def test_sh_basis_grad_matches_differences(oracle):
+    rng = np.random.default_rng(2)
+    u = rng.normal(size=(50, 3))
+    g = oracle.sh_basis_grad(u, 3)
+    h = 1e-6
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd = (oracle.sh_basis(u + e, 3) - oracle.sh_basis(u - e, 3)) / (2 * h)
+        np.testing.assert_allclose(g[:, :, a], fd, rtol=1e-7, atol=1e-8)
+
+
+def _sh_scene(seed, degree, n=6, W=20, H=16):
+    sc, cam = _fd_scene(seed, n=n, W=W, H=H)
+    return S.with_sh(sc, degree, seed + 100, sigma=0.3), cam
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_sh_colour_vjp_matches_differences(oracle, degree):
+    """The adjoint of the view-dependent colour against central differences
+    in the coefficients, the means and the camera translation."""
+    sc, cam = _sh_scene(5, degree)
+    Rc = Rotation.from_rotvec([0.2, -0.1, 0.3]).as_matrix()
+    cam = Cam64(cam, Rc, [0.3, -0.2, 0.1])
+    rng = np.random.default_rng(6)
+    gc = rng.normal(size=(sc.n, 3))
+    gcol, gsh, gm, gdt = oracle.sh_colour_vjp(sc, cam, gc)
+    f = lambda s, c: float(np.sum(oracle.sh_colour(s, c) * gc))
+    base = {k: np.asarray(getattr(sc, k), np.float64).copy() for k in ("mean", "color", "sh")}
+    h = 1e-6
+    for name, an in (("mean", gm), ("color", gcol), ("sh", gsh)):
+        fd = np.zeros_like(base[name])
+        for idx in np.ndindex(base[name].shape):
+            vals = []
+            for sgn in (1, -1):
+                s2 = replace(sc)
+                for k in base:
+                    setattr(s2, k, base[k].copy())
+                getattr(s2, name)[idx] += sgn * h
+                vals.append(f(s2, cam))
+            fd[idx] = (vals[0] - vals[1]) / (2 * h)
+        np.testing.assert_allclose(an, fd, rtol=1e-6, atol=1e-8, err_msg=name)
+    s64 = replace(sc)
+    for k in base:
+        setattr(s64, k, base[k].copy())
+    fd = np.zeros(3)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd[a] = (f(s64, Cam64(cam, cam.R_cw, cam.t_cw + e)) - f(s64, Cam64(cam, cam.R_cw, cam.t_cw - e))) / (2 * h)
+    np.testing.assert_allclose(gdt, fd, rtol=1e-6, atol=1e-8)
+    # a rotation about the camera centre leaves the view directions unchanged
+    E = _rodrigues([1e-3, -2e-3, 5e-4])
+    np.testing.assert_allclose(oracle.sh_colour(s64, Cam64(cam, E @ cam.R_cw, E @ cam.t_cw)),
+                               oracle.sh_colour(s64, cam), atol=1e-12)
+
+
+def test_sh_render_gradients_match_differences(oracle):
+    """Through the whole render: the SH coefficients, the means (whose colour
+    now depends on the view direction) and the pose translation."""
+    sc, cam0 = _sh_scene(7, 2, n=5)
+    Rc = Rotation.from_rotvec([0.05, -0.1, 0.02]).as_matrix()
+    cam = Cam64(cam0, Rc, [0.05, -0.02, 0.1])
+    o = oracle.Opts(bg=(0.2, 0.1, 0.3))
+    rng = np.random.default_rng(8)
+    Wimg = rng.normal(size=(3, cam.height, cam.width))
+    Wimg[:, oracle.render_image(sc, cam, o)["flags"] != 0] = 0
+    g = oracle.render_bwd(sc, [cam], [Wimg], o)
+    base = {k: np.asarray(getattr(sc, k), np.float64).copy() for k in ("mean", "scale", "quat", "opacity", "color",
+                                                                       "sh")}
+
+    def L(params, c=cam):
+        s2 = replace(sc)
+        for k in params:
+            setattr(s2, k, params[k])
+        return _loss(oracle, s2, [c], [Wimg], o)
+
+    h = 1e-6
+    for name in ("sh", "mean", "color"):
+        fd = np.zeros_like(base[name])
+        for idx in np.ndindex(base[name].shape):
+            vals = []
+            for sgn in (1, -1):
+                p = {k: v.copy() for k, v in base.items()}
+                p[name][idx] += sgn * h
+                vals.append(L(p))
+            fd[idx] = (vals[0] - vals[1]) / (2 * h)
+        np.testing.assert_allclose(g[name], fd, atol=2e-6 * np.abs(fd).max() + 1e-9, rtol=2e-5, err_msg=name)
+    fd = np.zeros(6)
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        cams = []
+        for sgn in (1, -1):
+            E = _rodrigues(sgn * e[:3])
+            cams.append(Cam64(cam, E @ cam.R_cw, E @ cam.t_cw + sgn * e[3:]))
+        fd[k] = (L(base, cams[0]) - L(base, cams[1])) / (2 * h)
+    np.testing.assert_allclose(g["pose"][0], fd, rtol=2e-5, atol=1e-6 * np.abs(fd).max())
+
+
+def _backproject(cam, u, v, z):
+    """World points that project to pixel coordinates (u, v) at depth z."""
+    pc = np.stack([(u - cam.cx) / cam.fx * z, (v - cam.cy) / cam.fy * z, z], -1)
+    R = np.asarray(cam.R_cw, np.float64)
+    return (pc - np.asarray(cam.t_cw, np.float64)) @ R
+
+
+def test_bilinear_colour_pixel_centres_and_affine_images(oracle):
+    """At a pixel centre the colour is that pixel; an image affine in (u, v)
+    per channel is reproduced exactly anywhere between centres; the midpoint
+    of four centres gives their mean."""
+    rng = np.random.default_rng(9)
+    Rc = Rotation.from_rotvec([0.1, 0.2, -0.1]).as_matrix()
+    cam = Cam64(_cam(W=17, H=11, f=20.0), Rc, [0.1, 0.0, -0.2])
+    img = rng.uniform(size=(3, 11, 17))
+    ii, jj = rng.integers(0, 17, 30), rng.integers(0, 11, 30)
+    pts = _backproject(cam, ii + 0.5, jj + 0.5, rng.uniform(1, 5, 30))
+    c, ok = oracle.bilinear_colour(pts, cam, img)
+    assert ok.all()
+    np.testing.assert_allclose(c, img[:, jj, ii].T, atol=1e-12)
+    # affine image: c_ch(u, v) = a_ch + b_ch (u - 1/2) + d_ch (v - 1/2) at the pixel centres
+    a, b, d = rng.normal(size=3), rng.normal(size=3), rng.normal(size=3)
+    V, U = np.mgrid[0:11, 0:17]
+    aff = a[:, None, None] + b[:, None, None] * U + d[:, None, None] * V
+    u = rng.uniform(0.5, 16.5, 200)
+    v = rng.uniform(0.5, 10.5, 200)
+    c, ok = oracle.bilinear_colour(_backproject(cam, u, v, rng.uniform(1, 5, 200)), cam, aff)
+    assert ok.all()
+    want = a[None] + b[None] * (u - 0.5)[:, None] + d[None] * (v - 0.5)[:, None]
+    np.testing.assert_allclose(c, want, atol=1e-9)
+    # midpoint of the centres of (3, 4), (4, 4), (3, 5), (4, 5)
+    c, _ = oracle.bilinear_colour(_backproject(cam, np.array([4.0]), np.array([5.0]), np.array([2.0])), cam, img)
+    np.testing.assert_allclose(c[0], img[:, 4:6, 3:5].mean((1, 2)), atol=1e-12)
+
+
+def test_bilinear_colour_borders_and_invalid(oracle):
+    """Between the image border and the outer pixel centres the edge pixel
+    value holds (clamp); behind the near plane or outside the image nothing."""
+    cam = _cam(W=8, H=6, f=10.0)
+    rng = np.random.default_rng(10)
+    img = rng.uniform(size=(3, 6, 8))
+    pts = _backproject(cam, np.array([0.2, 7.9, 0.1, 4.0]), np.array([0.3, 5.9, 3.0, -0.5]), np.array([2.0] * 4))
+    c, ok = oracle.bilinear_colour(pts, cam, img)
+    assert ok.tolist() == [True, True, True, False]
+    np.testing.assert_allclose(c[0], img[:, 0, 0], atol=1e-12)
+    np.testing.assert_allclose(c[1], img[:, 5, 7], atol=1e-12)
+    np.testing.assert_allclose(c[2], 0.5 * (img[:, 2, 0] + img[:, 3, 0]), atol=1e-12)
+    behind = _backproject(cam, np.array([4.0]), np.array([3.0]), np.array([0.1]))
+    assert not oracle.bilinear_colour(behind, cam, img)[1][0]
