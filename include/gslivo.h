@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define GSL_ABI_VERSION 1
+#define GSL_ABI_VERSION 2
 
 #ifndef GSL_API
 #define GSL_API __attribute__((visibility("default")))
@@ -76,7 +76,17 @@ typedef struct {
     int32_t tile;    /* tile edge in pixels: 8, 16 or 32 */
 } gsl_opts;
 
-/* Gaussians of the window (SoA, component-major, device). */
+/* Gaussians of the window (SoA, component-major, device).
+ *
+ * View-dependent colour (the map's spherical-harmonic coefficients, Sec.
+ * II-B): with sh_degree D in 1..3 the colour of Gaussian i seen from a camera
+ * centred at o is c = color_i + sum_k sh_k,i B_k(u), u = (mean_i - o) /
+ * |mean_i - o| in world coordinates, where B_k are the real orthonormal
+ * harmonics of degrees 1..D (order l = 1..D, m = -l..l; Cartesian forms
+ * without the Condon-Shortley sign: B_1 = c1 (y, z, x), ...) divided by
+ * Y_00 = 1 / (2 sqrt(pi)), so the degree-0 coefficient is `color` itself.
+ * K = (D + 1)^2 - 1 coefficients per channel, stored sh[(k * 3 + ch) * N + i].
+ * No clamp.  sh_degree 0 (sh may be NULL): the colour is `color`. */
 typedef struct {
     const float *mean;    /* [3][N] world position (m) */
     const float *scale;   /* [3][N] per-axis standard deviation (m), activated */
@@ -84,6 +94,8 @@ typedef struct {
     const float *opacity; /* [N] in (0, 1), activated */
     const float *color;   /* [3][N] degree-0 RGB */
     int32_t N;
+    int32_t sh_degree;    /* 0..3 */
+    const float *sh;      /* [K][3][N] higher-order SH coefficients (sh_degree > 0) */
 } gsl_gaussians;
 
 /* One projected Gaussian in one camera (48 bytes, 16-byte aligned).  The 2D
@@ -149,6 +161,7 @@ typedef struct {
     float *g_opacity; /* [N] */
     float *g_color;   /* [3][N] */
     double *g_pose;   /* [C][6] */
+    float *g_sh;      /* [K][3][N], with SH colour (sh_degree > 0) */
 } gsl_grads;
 
 /* ---- context ---------------------------------------------------------- */
@@ -273,22 +286,27 @@ GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
 
 /* The map is refined with Adam (Sec. II-B, eq. eq:gaussian_optimization).
  * The optimiser keeps raw parameters: 14 rows of N floats at a row stride ld:
- * mean (3), log-scale (3), quaternion (4), opacity logit (1), colour (3).  The
+ * mean (3), log-scale (3), quaternion (4), opacity logit (1), colour (3), then
+ * with SH colour the 3K higher-order coefficients.  The
  * renderer takes the activated values (scale = exp(log-scale), opacity =
  * sigmoid(logit), the rest unchanged), which the optimiser writes into the
  * arrays of a gsl_gaussians (its pointers are written through). */
 typedef struct {
     float lr[5];  /* learning rates: mean, log-scale, quaternion, opacity logit, colour */
     float beta1, beta2, eps;
+    float lr_sh;  /* learning rate of the higher-order SH coefficients */
 } gsl_adam;
 
 typedef struct {
-    float *raw;      /* [14][ld] raw parameters: row r of Gaussian i at raw[r * ld + i] */
-    float *m, *v;    /* [14][ld] first and second moments (zero before the first step) */
+    float *raw;      /* [14 + 3K][ld] raw parameters: row r of Gaussian i at raw[r * ld + i] */
+    float *m, *v;    /* [14 + 3K][ld] first and second moments (zero before the first step) */
     int32_t *d_step; /* device: steps taken (0 before the first step), advanced by each step */
     int32_t N;       /* Gaussians in the window */
     int32_t ld;      /* row stride in floats, >= N (0: N).  A window kept at a fixed
                       * capacity (gsl_window_compact) uses its capacity here. */
+    int32_t sh_degree; /* rows 14 .. 14 + 3K - 1 are the SH coefficients in the
+                        * gsl_gaussians.sh order (identity activation); must equal
+                        * the activated Gaussians' sh_degree */
 } gsl_adam_state;
 
 /* act <- activation(raw).  No optimiser step. */
@@ -313,6 +331,20 @@ GSL_API int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam
                                 int loss, gsl_proj *proj, gsl_bins *bins, double *d_losses, gsl_grads *grads,
                                 int32_t iters, void *workspace, size_t workspace_bytes, int use_graph,
                                 void *stream);
+
+/* Initial colour of new Gaussians (Sec. II-B, eq. c(mu_I)): each mean
+ * (device float mean[a * mean_ld + i], a = 0..2) is projected into the
+ * camera in float64; the colour is the bilinear interpolation of the image
+ * (device float, planar [3][H][W]) there.  Pixel (c, r) has its centre at
+ * (c + 1/2, r + 1/2); the projected point minus 1/2 is clamped to the range
+ * of the centres and the four surrounding pixels are weighted by the areas
+ * of the opposite sub-rectangles.  Writes color[ch * color_ld + i] for the
+ * means in front of opts->near_z that project into [0, W) x [0, H) and
+ * valid[i] (may be NULL) = 1 for those, 0 otherwise (colour untouched).
+ * The higher-order SH coefficients of new Gaussians start at zero. */
+GSL_API int gsl_color_init(gsl_ctx *ctx, const float *mean, int64_t mean_ld, int32_t n, const gsl_camera *cam,
+                           const float *image, const gsl_opts *opts, float *color, int64_t color_ld,
+                           uint8_t *valid, void *stream);
 
 /* ---- sliding-window maintenance ------------------------------------------ */
 

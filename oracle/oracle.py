@@ -460,10 +460,14 @@ RAW_ROWS = {"mean": (0, 3), "scale": (3, 6), "quat": (6, 10), "opacity": (10, 11
 
 
 def activate(raw):
-    """raw (14, N) -> dict of activated parameters, each (k, N)."""
+    """raw (14 + 3K, N) -> dict of activated parameters, each (k, N); the
+    rows after the colour are SH coefficients, used as they are ("sh")."""
     raw = np.asarray(raw, np.float64)
-    return {"mean": raw[0:3], "scale": np.exp(raw[3:6]), "quat": raw[6:10],
-            "opacity": 1.0 / (1.0 + np.exp(-raw[10:11])), "color": raw[11:14]}
+    out = {"mean": raw[0:3], "scale": np.exp(raw[3:6]), "quat": raw[6:10],
+           "opacity": 1.0 / (1.0 + np.exp(-raw[10:11])), "color": raw[11:14]}
+    if raw.shape[0] > 14:
+        out["sh"] = raw[14:]
+    return out
 
 
 def raw_gradient(raw, g_act):
@@ -477,6 +481,8 @@ def raw_gradient(raw, g_act):
     s = a["opacity"]
     g[10:11] = g_act["opacity"] * s * (1.0 - s)
     g[11:14] = g_act["color"]
+    if g.shape[0] > 14:
+        g[14:] = g_act["sh"]
     return g
 
 

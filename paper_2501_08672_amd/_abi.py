@@ -31,7 +31,8 @@ EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "g
            "gsl_window_tune", "gsl_window_variant", "gsl_profile", "gsl_profile_read",
            "gsl_pose_jacobian_workspace_size", "gsl_pose_jacobian", "gsl_imu_to_camera_twist",
            "gsl_ieskf_pose_update", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
-           "gsl_voxel_keys", "gsl_window_workspace_size", "gsl_window_classify", "gsl_window_compact"]
+           "gsl_voxel_keys", "gsl_window_workspace_size", "gsl_window_classify", "gsl_window_compact",
+           "gsl_color_init"]
 
 
 class GslError(RuntimeError):
@@ -52,7 +53,7 @@ class Opts(C.Structure):
 
 class Gaussians(C.Structure):
     _fields_ = [("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p), ("opacity", C.c_void_p),
-                ("color", C.c_void_p), ("N", C.c_int32)]
+                ("color", C.c_void_p), ("N", C.c_int32), ("sh_degree", C.c_int32), ("sh", C.c_void_p)]
 
 
 class Proj(C.Structure):
@@ -61,12 +62,13 @@ class Proj(C.Structure):
 
 
 class Adam(C.Structure):
-    _fields_ = [("lr", C.c_float * 5), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+    _fields_ = [("lr", C.c_float * 5), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("lr_sh", C.c_float)]
 
 
 class AdamState(C.Structure):
     _fields_ = [("raw", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("d_step", C.c_void_p),
-                ("N", C.c_int32), ("ld", C.c_int32)]
+                ("N", C.c_int32), ("ld", C.c_int32), ("sh_degree", C.c_int32)]
 
 
 class Bins(C.Structure):
@@ -76,7 +78,7 @@ class Bins(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [("g_mean", C.c_void_p), ("g_scale", C.c_void_p), ("g_quat", C.c_void_p), ("g_opacity", C.c_void_p),
-                ("g_color", C.c_void_p), ("g_pose", C.c_void_p)]
+                ("g_color", C.c_void_p), ("g_pose", C.c_void_p), ("g_sh", C.c_void_p)]
 
 
 SPLAT_BYTES = 48
@@ -125,6 +127,7 @@ def lib() -> C.CDLL:
     L.gsl_adam_step.argtypes = [P, ps, pa, pgr, pg, P]
     L.gsl_window_optimize.argtypes = [P, ps, pa, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, pgr, C.c_int32, P,
                                       C.c_size_t, C.c_int, P]
+    L.gsl_color_init.argtypes = [P, P, C.c_int64, C.c_int32, pc, P, po, P, C.c_int64, P, P]
     L.gsl_voxel_keys.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, C.c_float, P, P]
     L.gsl_window_workspace_size.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
     L.gsl_window_classify.argtypes = [P, P, C.c_int32, C.c_float, P, C.c_int32, P, P, P, C.c_size_t, P]

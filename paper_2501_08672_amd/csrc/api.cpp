@@ -188,6 +188,7 @@ WsLayout ws_layout(const Layout &L, int64_t capacity)
     w.g2d = take(4 * (size_t)M * kG2);
     w.pose_blocks = (int32_t)((L.N + kPoseThreads - 1) / kPoseThreads);
     w.pose_part = take(8 * (size_t)std::max<int64_t>(1, (int64_t)w.pose_blocks * L.C * 6));
+    w.pose_part_sh = take(8 * (size_t)std::max<int64_t>(1, (int64_t)w.pose_blocks * L.C * 6));
     w.loss_part = take(8 * (size_t)std::max<int64_t>(1, L.T_total));
     w.order = take(4 * (size_t)std::max<int64_t>(1, L.T_total));
     w.big = take(4 * (size_t)std::max<int64_t>(1, M));
@@ -233,6 +234,8 @@ int check_gauss(const gsl_gaussians *g, bool need_all)
     if (g->N < 0) return fail(GSL_EINVAL, "negative Gaussian count");
     if (g->N > 0 && (!g->mean || !g->scale || !g->quat || (need_all && (!g->opacity || !g->color))))
         return fail(GSL_EINVAL, "Gaussian parameter pointer is NULL");
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(GSL_EINVAL, "sh_degree %d not in [0, 3]", g->sh_degree);
+    if (g->sh_degree > 0 && g->N > 0 && need_all && !g->sh) return fail(GSL_EINVAL, "sh is NULL");
     return GSL_OK;
 }
 
@@ -319,13 +322,16 @@ void do_project_bwd(const Prepared &p, const gsl_gaussians *g, gsl_grads *grads,
                     hipStream_t s)
 {
     double *pose_part = at<double>(ws, p.W.pose_part);
+    double *pose_part_sh = g->sh_degree > 0 ? at<double>(ws, p.W.pose_part_sh) : nullptr;
     launch_project_bwd(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, at<float>(ws, p.W.g2d), *grads, accumulate,
                        pose_part, p.W.pose_blocks, s);
+    launch_sh_bwd(*g, at<DevCam>(ws, p.W.cams), p.L, at<float>(ws, p.W.g2d), grads->g_sh, grads->g_mean, accumulate,
+                  pose_part_sh, p.W.pose_blocks, s);
     if (grads->g_pose) {
         if (p.L.N == 0) {
             if (!accumulate) launch_fill_f64(grads->g_pose, 0.0, 6 * (int64_t)p.L.C, s);
         } else {
-            launch_pose_reduce(pose_part, p.W.pose_blocks, p.L.C, grads->g_pose, accumulate, s);
+            launch_pose_reduce(pose_part, pose_part_sh, p.W.pose_blocks, p.L.C, grads->g_pose, accumulate, s);
         }
     }
 }
@@ -419,12 +425,13 @@ VariantKey window_graph_key(const VariantKey &vk, int variant, int loss, const g
     gk.v.push_back(variant);
     gk.v.push_back(loss);
     auto ptr = [&](const void *q) { gk.v.push_back((int64_t)(uintptr_t)q); };
-    ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color);
+    ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color); ptr(g->sh);
+    gk.v.push_back(g->sh_degree);
     ptr(target); ptr(proj->splats); ptr(proj->tiles_touched); ptr(proj->binrecs); ptr(proj->depth_keys);
     ptr(bins->tile_ids); ptr(bins->gauss_ids); ptr(bins->ranges); ptr(bins->d_K); ptr(bins->d_status);
     gk.v.push_back(bins->capacity_K);
     ptr(image); ptr(d_loss); ptr(grads->g_mean); ptr(grads->g_scale); ptr(grads->g_quat);
-    ptr(grads->g_opacity); ptr(grads->g_color); ptr(grads->g_pose); ptr(workspace);
+    ptr(grads->g_opacity); ptr(grads->g_color); ptr(grads->g_pose); ptr(grads->g_sh); ptr(workspace);
     const int32_t *ow = reinterpret_cast<const int32_t *>(opts);
     for (size_t k = 0; k < sizeof(gsl_opts) / 4; k++) gk.v.push_back(ow[k]);
     for (int c = 0; c < C; c++) {
@@ -440,34 +447,52 @@ int check_adam(const gsl_adam_state *st, const gsl_adam *hp)
     if (st->N < 0) return fail(GSL_EINVAL, "negative Gaussian count");
     if (st->N > 0 && (!st->raw || !st->m || !st->v || !st->d_step)) return fail(GSL_EINVAL, "adam buffer is NULL");
     if (st->ld != 0 && st->ld < st->N) return fail(GSL_EINVAL, "adam row stride %d < N %d", st->ld, st->N);
+    if (st->sh_degree < 0 || st->sh_degree > 3) return fail(GSL_EINVAL, "sh_degree %d not in [0, 3]", st->sh_degree);
     if (hp) {
         if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f))
             return fail(GSL_EINVAL, "need 0 <= beta < 1");
         if (!(hp->eps > 0.f)) return fail(GSL_EINVAL, "need eps > 0");
         for (int k = 0; k < 5; k++)
             if (!(hp->lr[k] >= 0.f)) return fail(GSL_EINVAL, "learning rates must be >= 0");
+        if (!(hp->lr_sh >= 0.f)) return fail(GSL_EINVAL, "learning rates must be >= 0");
     }
     return GSL_OK;
 }
 
 int64_t adam_ld(const gsl_adam_state *st) { return st->ld ? st->ld : st->N; }
 
-void act_arrays(gsl_gaussians *act, float *out[5])
+void act_arrays(gsl_gaussians *act, float *out[6])
 {
     out[0] = const_cast<float *>(act->mean);
     out[1] = const_cast<float *>(act->scale);
     out[2] = const_cast<float *>(act->quat);
     out[3] = const_cast<float *>(act->opacity);
     out[4] = const_cast<float *>(act->color);
+    out[5] = const_cast<float *>(act->sh);
 }
 
 void do_adam(gsl_adam_state *st, const gsl_adam *hp, const gsl_grads *grads, gsl_gaussians *act, hipStream_t s)
 {
-    const float *g[5] = {grads->g_mean, grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_color};
-    float *a[5];
+    const float *g[6] = {grads->g_mean, grads->g_scale, grads->g_quat, grads->g_opacity, grads->g_color,
+                         grads->g_sh};
+    float *a[6];
     act_arrays(act, a);
-    launch_adam(g, a, st->raw, st->m, st->v, st->d_step, hp->lr, hp->beta1, hp->beta2, hp->eps, st->N, adam_ld(st),
-                true, s);
+    const float lr[6] = {hp->lr[0], hp->lr[1], hp->lr[2], hp->lr[3], hp->lr[4], hp->lr_sh};
+    launch_adam(g, a, st->raw, st->m, st->v, st->d_step, lr, hp->beta1, hp->beta2, hp->eps, st->N, st->sh_degree,
+                adam_ld(st), true, s);
+}
+
+// The optimiser state and the activated Gaussians describe the same window.
+int check_adam_act(const gsl_adam_state *st, const gsl_gaussians *act, const gsl_grads *grads)
+{
+    if (act->N != st->N) return fail(GSL_EINVAL, "act.N %d != state N %d", act->N, st->N);
+    if (act->sh_degree != st->sh_degree)
+        return fail(GSL_EINVAL, "act.sh_degree %d != state sh_degree %d", act->sh_degree, st->sh_degree);
+    if (grads && st->N > 0 &&
+        (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_color ||
+         (st->sh_degree > 0 && !grads->g_sh)))
+        return fail(GSL_EINVAL, "gradient buffer is NULL");
+    return GSL_OK;
 }
 
 // Bytes gsl_pose_jacobian needs past the common workspace: per-record
@@ -870,12 +895,12 @@ int gsl_adam_activate(gsl_ctx *ctx, const gsl_adam_state *st, gsl_gaussians *act
 {
     if (!ctx || !act) return fail(GSL_EINVAL, "NULL argument");
     GSL_TRY(check_adam(st, nullptr));
-    if (act->N != st->N) return fail(GSL_EINVAL, "act.N %d != state N %d", act->N, st->N);
+    GSL_TRY(check_adam_act(st, act, nullptr));
     GSL_TRY(check_gauss(act, true));
-    float *a[5];
+    float *a[6];
     act_arrays(act, a);
-    launch_adam(nullptr, a, st->raw, nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, 1.f, st->N, adam_ld(st), false,
-                (hipStream_t)stream);
+    launch_adam(nullptr, a, st->raw, nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, 1.f, st->N, st->sh_degree,
+                adam_ld(st), false, (hipStream_t)stream);
     return check_launch("gsl_adam_activate");
 }
 
@@ -884,10 +909,8 @@ int gsl_adam_step(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, const gs
 {
     if (!ctx || !act || !hp || !grads) return fail(GSL_EINVAL, "NULL argument");
     GSL_TRY(check_adam(st, hp));
-    if (act->N != st->N) return fail(GSL_EINVAL, "act.N %d != state N %d", act->N, st->N);
+    GSL_TRY(check_adam_act(st, act, grads));
     GSL_TRY(check_gauss(act, true));
-    if (st->N > 0 && (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_color))
-        return fail(GSL_EINVAL, "gradient buffer is NULL");
     do_adam(st, hp, grads, act, (hipStream_t)stream);
     return check_launch("gsl_adam_step");
 }
@@ -900,9 +923,9 @@ int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gs
     if (!act || !hp) return fail(GSL_EINVAL, "NULL argument");
     GSL_TRY(check_adam(st, hp));
     GSL_TRY(check_gauss(act, true));
-    if (act->N != st->N) return fail(GSL_EINVAL, "act.N %d != state N %d", act->N, st->N);
     GSL_TRY(check_bins(bins));
     if (!grads || !target || !d_losses) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_adam_act(st, act, grads));
     if (!grads->g_mean || !grads->g_scale || !grads->g_quat || !grads->g_opacity || !grads->g_color)
         return fail(GSL_EINVAL, "gradient buffer is NULL");
     if (loss != GSL_LOSS_L1 && loss != GSL_LOSS_L2) return fail(GSL_EINVAL, "unknown loss %d", loss);
@@ -935,6 +958,7 @@ int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gs
     for (const void *q : {(const void *)st->raw, (const void *)st->m, (const void *)st->v, (const void *)st->d_step})
         gk.v.push_back((int64_t)(uintptr_t)q);
     gk.v.push_back(adam_ld(st));
+    gk.v.push_back(st->sh_degree);
     const int32_t *hw = reinterpret_cast<const int32_t *>(hp);
     for (size_t k = 0; k < sizeof(gsl_adam) / 4; k++) gk.v.push_back(hw[k]);
     return graph_run(ctx, gk, s, enqueue);
@@ -946,6 +970,21 @@ int gsl_window_workspace_size(int32_t n, int32_t P, size_t *bytes)
     if (n < 0 || P < 0 || P > kWinMaxPoints) return fail(GSL_EINVAL, "need n >= 0 and 0 <= P <= 2^28");
     *bytes = win_layout(n, P).total;
     return GSL_OK;
+}
+
+int gsl_color_init(gsl_ctx *ctx, const float *mean, int64_t mean_ld, int32_t n, const gsl_camera *cam,
+                   const float *image, const gsl_opts *opts, float *color, int64_t color_ld, uint8_t *valid,
+                   void *stream)
+{
+    if (!ctx || !cam) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_opts(opts));
+    if (n < 0) return fail(GSL_EINVAL, "negative count");
+    if (n > 0 && (!mean || !image || !color)) return fail(GSL_EINVAL, "NULL argument");
+    if (mean_ld < n || color_ld < n) return fail(GSL_EINVAL, "row strides must be >= n");
+    if (cam->width <= 0 || cam->height <= 0) return fail(GSL_EINVAL, "empty image");
+    GSL_TRY(check_device(ctx));
+    launch_color_init(mean, mean_ld, n, *cam, opts->near_z, image, color, color_ld, valid, (hipStream_t)stream);
+    return check_launch("gsl_color_init");
 }
 
 int gsl_voxel_keys(gsl_ctx *ctx, const float *xyz, int32_t P, int64_t point_stride, int64_t axis_stride,
@@ -1023,6 +1062,8 @@ int gsl_pose_jacobian(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *ca
                       size_t workspace_bytes, void *stream)
 {
     GSL_TRY(check_gauss(g, false));
+    if (g->sh_degree > 0)
+        return fail(GSL_ENOTSUP, "pose Jacobians are built for degree-0 colour (sh_degree %d)", g->sh_degree);
     GSL_TRY(check_bins(bins));
     Prepared p;
     GSL_TRY(prepare(ctx, cams, C, g->N, opts, bins->capacity_K, workspace, workspace_bytes, p));

@@ -139,6 +139,7 @@ struct WsLayout {
     size_t partial = 0;     // u64[...] scan partial sums
     size_t g2d = 0;         // float[C][N][kG2]
     size_t pose_part = 0;   // double[pose_blocks][C][6]
+    size_t pose_part_sh = 0;  // the same for the SH colour's camera-centre term
     size_t loss_part = 0;   // double[T_total]
     size_t order = 0;       // u32[T_total] work order of the fused kernel
     size_t big = 0;         // u32[M] list of records spanning more than kBigTiles tiles
@@ -161,10 +162,10 @@ constexpr int kPoseThreads = 256;
 
 // optim.hip: Adam over raw parameters [14][ld]; with update == false only the
 // activated values are written.  g / act: mean, scale, quaternion, opacity,
-// colour arrays in the gsl_gaussians layout (row stride N).
-void launch_adam(const float *const g[5], float *const act[5], float *raw, float *m, float *v, const int32_t *d_step,
-                 const float lr[5], float beta1, float beta2, float eps, int N, int64_t ld, bool update,
-                 hipStream_t s);
+// colour and SH arrays in the gsl_gaussians layout (row stride N).
+void launch_adam(const float *const g[6], float *const act[6], float *raw, float *m, float *v, const int32_t *d_step,
+                 const float lr[6], float beta1, float beta2, float eps, int N, int sh_degree, int64_t ld,
+                 bool update, hipStream_t s);
 
 // window.hip: maintenance of the sliding window (hash set of the frame's
 // voxel keys, DELETE / ADD classification, in-place compaction).
@@ -281,7 +282,15 @@ void launch_order_by_length(const uint32_t *ranges, int64_t T, uint32_t *order, 
 // counts[3] (device, accumulated): forward pairs evaluated, contributors, backward pairs
 void launch_render_count(const RenderArgs &a, unsigned long long *counts, hipStream_t s);
 void launch_reduce_f64(const double *part, int64_t n, double *out, hipStream_t s);
-void launch_pose_reduce(const double *pose_part, int blocks, int C, double *g_pose, int accumulate,
-                        hipStream_t s);
+// sh.hip: bilinear colour of new Gaussians from a camera image
+void launch_color_init(const float *mean, int64_t mean_ld, int n, const gsl_camera &c, float near_z,
+                       const float *image, float *color, int64_t color_ld, uint8_t *valid, hipStream_t s);
+// sums pose_part (and pose_part2 when not null), [blocks][C][6] each
+void launch_pose_reduce(const double *pose_part, const double *pose_part2, int blocks, int C, double *g_pose,
+                        int accumulate, hipStream_t s);
+// adjoint of the SH colour (no-op at sh_degree 0): g_sh written or
+// accumulated, the view-direction term added to g_mean, pose dt partials
+void launch_sh_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const float *g2d, float *g_sh,
+                   float *g_mean, int accumulate, double *pose_part, int pose_blocks, hipStream_t s);
 
 }  // namespace gsl

@@ -3,7 +3,8 @@
 //
 // The optimiser owns the raw parameters, 14 rows of N floats at a row stride
 // ld (a window kept at a fixed capacity uses the capacity): mean (3),
-// log-scale (3), quaternion (4), opacity logit (1), colour (3); the renderer
+// log-scale (3), quaternion (4), opacity logit (1), colour (3), then the 3K
+// higher-order SH coefficients of a view-dependent colour; the renderer
 // takes the activated values, scale = exp(log-scale) and opacity =
 // sigmoid(logit), the other rows unchanged.  One lane per Gaussian: the
 // gradients of the activated values are chained to the raw rows, the moments
@@ -11,26 +12,31 @@
 // for the next pass.  The step count lives in device memory and is advanced by
 // a second one-lane kernel, so a captured graph of several iterations (or its
 // replays) uses the right bias corrections.
-#include "common.hpp"
+#include "sh.hpp"
 
 namespace gsl {
 
 namespace {
 
 struct AdamArgs {
-    const float *g[5];      // gradients of the activated mean, scale, quaternion, opacity, colour
-    float *act[5];          // activated outputs, same layout
-    float *raw, *m, *v;     // [14][ld]
+    const float *g[6];      // gradients of the activated mean, scale, quaternion, opacity, colour, SH
+    float *act[6];          // activated outputs, same layout
+    float *raw, *m, *v;     // [14 + 3K][ld]
     const int32_t *d_step;  // steps taken so far
-    float lr[5];
+    float lr[6];
     float beta1, beta2, eps;
     int N;
+    int rows;               // 14 + 3K
     int64_t ld;
     bool update;            // false: only write the activated values of raw
 };
 
+constexpr int kBaseRows = 14;
+constexpr int kMaxRows = kBaseRows + 3 * kShMaxK;
 constexpr int kRowGroup[14] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4};
 constexpr int kRowInGroup[14] = {0, 1, 2, 0, 1, 2, 0, 1, 2, 3, 0, 0, 1, 2};
+__host__ __device__ constexpr int row_group(int r) { return r < kBaseRows ? kRowGroup[r] : 5; }
+__host__ __device__ constexpr int row_in_group(int r) { return r < kBaseRows ? kRowInGroup[r] : r - kBaseRows; }
 
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a)
 {
@@ -44,8 +50,9 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a)
         bc2 = 1.f - powf(a.beta2, t);
     }
 #pragma unroll
-    for (int r = 0; r < 14; r++) {
-        const int grp = kRowGroup[r], k = kRowInGroup[r];
+    for (int r = 0; r < kMaxRows; r++) {
+        if (r >= a.rows) break;
+        const int grp = row_group(r), k = row_in_group(r);
         float x = a.raw[r * ld + i];
         if (a.update) {
             float g = a.g[grp][k * N + i];
@@ -73,17 +80,18 @@ __global__ void k_step_advance(int32_t *d_step) { *d_step += 1; }
 
 }  // namespace
 
-void launch_adam(const float *const g[5], float *const act[5], float *raw, float *m, float *v, const int32_t *d_step,
-                 const float lr[5], float beta1, float beta2, float eps, int N, int64_t ld, bool update,
-                 hipStream_t s)
+void launch_adam(const float *const g[6], float *const act[6], float *raw, float *m, float *v, const int32_t *d_step,
+                 const float lr[6], float beta1, float beta2, float eps, int N, int sh_degree, int64_t ld,
+                 bool update, hipStream_t s)
 {
     if (N == 0) return;
     AdamArgs a;
-    for (int k = 0; k < 5; k++) {
+    for (int k = 0; k < 6; k++) {
         a.g[k] = g ? g[k] : nullptr;
         a.act[k] = act[k];
         a.lr[k] = lr ? lr[k] : 0.f;
     }
+    a.rows = kBaseRows + 3 * sh_count(sh_degree);
     a.raw = raw;
     a.m = m;
     a.v = v;

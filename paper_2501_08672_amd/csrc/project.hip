@@ -20,6 +20,7 @@
 // the term of Sigma2D's dependence on W.  Per-workgroup pose partials are
 // summed by a second kernel, so the pose gradient is deterministic.
 #include "binning.hpp"
+#include "sh.hpp"
 
 namespace gsl {
 
@@ -111,10 +112,12 @@ __device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, con
 // Also counts the tiles each splat's alpha_min ellipse reaches (tiles_touched)
 // with the binning walk of the emission, from the record still in registers;
 // records spanning more than kBigTiles tiles go to big_list for a second kernel.
+template <bool SH>
 __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean, const float *__restrict__ scale,
                                                  const float *__restrict__ quat,
                                                  const float *__restrict__ opacity,
-                                                 const float *__restrict__ color, int N, int64_t M,
+                                                 const float *__restrict__ color,
+                                                 const float *__restrict__ sh, int shd, int N, int64_t M,
                                                  const DevCam *__restrict__ cams, DevOpts o,
                                                  gsl_splat *__restrict__ out, gsl_binrec *__restrict__ bout,
                                                  uint32_t *__restrict__ kout, int32_t *__restrict__ tiles,
@@ -172,6 +175,24 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                     sp.l12 = (float)l12;
                     sp.l22 = (float)l22;
                     sp.depth = (float)p.z;
+                    if (SH) {
+                        // view-dependent colour from the camera centre
+                        double u[3];
+                        view_dir(cam, mean[i], mean[N + i], mean[2 * N + i], u);
+                        const int K = sh_count(shd);
+                        double rgb[3] = {sp.r, sp.g, sp.b};
+#pragma unroll
+                        for (int k = 0; k < kShMaxK; k++) {
+                            if (k < K) {
+                                const double bk = sh_b(k, u[0], u[1], u[2]);
+                                for (int ch = 0; ch < 3; ch++)
+                                    rgb[ch] += bk * (double)sh[((int64_t)k * 3 + ch) * N + i];
+                            }
+                        }
+                        sp.r = (float)rgb[0];
+                        sp.g = (float)rgb[1];
+                        sp.b = (float)rgb[2];
+                    }
                 }
             }
         }
@@ -444,14 +465,122 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
     put(out.g_opacity, i, gop);
 }
 
-__global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ part, int blocks, int C,
+// Adjoint of the view-dependent colour (SH degree > 0), after k_project_bwd:
+// one lane per Gaussian looping over the cameras.  From the colour gradient
+// g_c of each (camera, Gaussian) record: dL/dsh_k = sum_c g_c B_k(u_c); the
+// colour's dependence on the view direction u = (mu - o) / r adds
+// (I - u u^T) g_u / r to the mean gradient, with g_u = sum_ch g_c,ch
+// sum_k sh_k,ch dB_k/du; the camera centre o = -R^T t moves by -R^T dt under
+// the left twist (a rotation leaves it in place), so the twist's dt gets
+// R (I - u u^T) g_u / r, written as per-workgroup partials (the dphi slots
+// zero) for the pose reduction.
+__global__ __launch_bounds__(kPoseThreads) void k_sh_bwd(const float *__restrict__ mean, const float *__restrict__ sh,
+                                                         int shd, int N, int C, const DevCam *__restrict__ cams,
+                                                         const float *__restrict__ g2d, float *__restrict__ g_sh,
+                                                         float *__restrict__ g_mean, int accumulate,
+                                                         double *__restrict__ pose_part)
+{
+    __shared__ double s_red[kPoseThreads / kWave][3];
+    const int i = blockIdx.x * kPoseThreads + threadIdx.x;
+    const bool valid = i < N;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int K = sh_count(shd);
+    float acc[3 * kShMaxK];
+#pragma unroll
+    for (int k = 0; k < 3 * kShMaxK; k++) acc[k] = 0.f;
+    double gm[3] = {0, 0, 0};
+    double px = 0, py = 0, pz = 0;
+    if (valid) {
+        px = mean[i];
+        py = mean[N + i];
+        pz = mean[2 * N + i];
+    }
+    for (int c = 0; c < C; c++) {
+        double gt[3] = {0, 0, 0};
+        float gc[3] = {0.f, 0.f, 0.f};
+        if (valid) {
+            const float *src = g2d + ((int64_t)c * N + i) * kG2 + 6;
+            gc[0] = src[0];
+            gc[1] = src[1];
+            gc[2] = src[2];
+        }
+        const bool any = gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f;
+        if (any) {
+            const DevCam cam = cams[c];
+            double u[3];
+            const double r = view_dir(cam, px, py, pz, u);
+            double gu[3] = {0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < kShMaxK; k++) {
+                if (k < K) {
+                    const double bk = sh_b(k, u[0], u[1], u[2]);
+                    double dx, dy, dz;
+                    sh_db(k, u[0], u[1], u[2], dx, dy, dz);
+                    double w = 0;
+                    for (int ch = 0; ch < 3; ch++) {
+                        acc[3 * k + ch] += (float)((double)gc[ch] * bk);
+                        w += (double)gc[ch] * (double)sh[((int64_t)k * 3 + ch) * N + i];
+                    }
+                    gu[0] += w * dx;
+                    gu[1] += w * dy;
+                    gu[2] += w * dz;
+                }
+            }
+            const double ug = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2];
+            const double ir = 1.0 / r;
+            double gd[3];
+            for (int j = 0; j < 3; j++) {
+                gd[j] = (gu[j] - u[j] * ug) * ir;
+                gm[j] += gd[j];
+            }
+            for (int j = 0; j < 3; j++)
+                gt[j] = cam.R[3 * j] * gd[0] + cam.R[3 * j + 1] * gd[1] + cam.R[3 * j + 2] * gd[2];
+        }
+        if (__syncthreads_or(any)) {
+            for (int k = 0; k < 3; k++) {
+                const double v = wave_sum_f64(gt[k]);
+                if (lane == 0) s_red[wv][k] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x < 6) {
+                double v = 0;
+                if (threadIdx.x >= 3)
+                    for (int w = 0; w < kPoseThreads / kWave; w++) v += s_red[w][threadIdx.x - 3];
+                pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = v;
+            }
+            __syncthreads();
+        } else if (threadIdx.x < 6) {
+            pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = 0.0;
+        }
+    }
+    if (!valid) return;
+    if (g_mean)
+        for (int k = 0; k < 3; k++) g_mean[(int64_t)k * N + i] += (float)gm[k];
+    if (g_sh) {
+#pragma unroll
+        for (int k = 0; k < 3 * kShMaxK; k++) {
+            if (k < 3 * K) {
+                float *dst = g_sh + (int64_t)k * N + i;
+                if (accumulate) *dst += acc[k];
+                else *dst = acc[k];
+            }
+        }
+    }
+}
+
+// Sums the per-workgroup pose partials (and a second set, when given).
+__global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ part,
+                                                     const double *__restrict__ part2, int blocks, int C,
                                                      double *__restrict__ g_pose, int accumulate)
 {
     __shared__ double s_red[256 / kWave][6];
     const int c = blockIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < blocks; b += 256)
-        for (int k = 0; k < 6; k++) acc[k] += part[((int64_t)b * C + c) * 6 + k];
+        for (int k = 0; k < 6; k++) {
+            acc[k] += part[((int64_t)b * C + c) * 6 + k];
+            if (part2) acc[k] += part2[((int64_t)b * C + c) * 6 + k];
+        }
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     for (int k = 0; k < 6; k++) {
         const double v = wave_sum_f64(acc[k]);
@@ -486,8 +615,14 @@ void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L,
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
     launch_fill_u32(big_n, 0u, 1, s);
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.opacity,
-                       g.color, g.N, L.M, cams, o, splats, binrecs, depth_keys, tiles_touched, big_list, big_n);
+    if (g.sh_degree > 0)
+        hipLaunchKernelGGL(k_project<true>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat,
+                           g.opacity, g.color, g.sh, g.sh_degree, g.N, L.M, cams, o, splats, binrecs, depth_keys,
+                           tiles_touched, big_list, big_n);
+    else
+        hipLaunchKernelGGL(k_project<false>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat,
+                           g.opacity, g.color, g.sh, 0, g.N, L.M, cams, o, splats, binrecs, depth_keys,
+                           tiles_touched, big_list, big_n);
     launch_count_big(binrecs, cams, L, tiles_touched, big_list, big_n, s);
 }
 
@@ -509,10 +644,20 @@ void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout
                        L.C, cams, o, g2d, out, accumulate, pose_part);
 }
 
-void launch_pose_reduce(const double *pose_part, int blocks, int C, double *g_pose, int accumulate, hipStream_t s)
+void launch_pose_reduce(const double *pose_part, const double *pose_part2, int blocks, int C, double *g_pose,
+                        int accumulate, hipStream_t s)
 {
     if (!g_pose || C == 0) return;
-    hipLaunchKernelGGL(k_pose_reduce, dim3(C), dim3(256), 0, s, pose_part, blocks, C, g_pose, accumulate);
+    hipLaunchKernelGGL(k_pose_reduce, dim3(C), dim3(256), 0, s, pose_part, pose_part2, blocks, C, g_pose,
+                       accumulate);
+}
+
+void launch_sh_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const float *g2d, float *g_sh,
+                   float *g_mean, int accumulate, double *pose_part, int pose_blocks, hipStream_t s)
+{
+    if (L.N == 0 || pose_blocks == 0 || g.sh_degree <= 0) return;
+    hipLaunchKernelGGL(k_sh_bwd, dim3(pose_blocks), dim3(kPoseThreads), 0, s, g.mean, g.sh, g.sh_degree, g.N, L.C,
+                       cams, g2d, g_sh, g_mean, accumulate, pose_part);
 }
 
 }  // namespace gsl

@@ -107,38 +107,68 @@ class CameraSet:
         return torch.cat([im.reshape(-1) for im in images]).contiguous()
 
 
+def sh_count(degree: int) -> int:
+    """Higher-order SH coefficients per channel: (degree + 1)^2 - 1."""
+    return (degree + 1) ** 2 - 1
+
+
+def sh_degree_of(rows: int) -> int:
+    """SH degree of 3K coefficient rows."""
+    for d in range(4):
+        if 3 * sh_count(d) == rows:
+            return d
+    raise ValueError(f"{rows} SH rows is not 3 ((D + 1)^2 - 1) for D in 0..3")
+
+
 @dataclass
 class Gaussians:
+    """The window's Gaussians, component-major (gsl_gaussians); `sh` holds the
+    higher-order SH coefficients as (3K, N) rows, row k * 3 + ch, or None."""
     mean: torch.Tensor
     scale: torch.Tensor
     quat: torch.Tensor
     opacity: torch.Tensor
     color: torch.Tensor
+    sh: Optional[torch.Tensor] = None
 
     @property
     def N(self) -> int:
         return int(self.opacity.shape[0])
 
+    @property
+    def sh_degree(self) -> int:
+        return 0 if self.sh is None else sh_degree_of(int(self.sh.shape[0]))
+
     @staticmethod
     def from_scene(scene, device="cuda") -> "Gaussians":
         def soa(a):
             return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32).T)).to(device)
+        sh = None
+        if getattr(scene, "sh", None) is not None:
+            a = np.asarray(scene.sh, np.float32)  # (N, K, 3) -> rows k * 3 + ch
+            sh = torch.from_numpy(np.ascontiguousarray(a.transpose(1, 2, 0).reshape(-1, a.shape[0]))).to(device)
         return Gaussians(soa(scene.mean), soa(scene.scale), soa(scene.quat),
                          torch.from_numpy(np.ascontiguousarray(scene.opacity, np.float32)).to(device),
-                         soa(scene.color))
+                         soa(scene.color), sh)
+
+    def tensors(self):
+        return [t for t in (self.mean, self.scale, self.quat, self.opacity, self.color, self.sh) if t is not None]
 
     def struct(self) -> A.Gaussians:
-        for t in (self.mean, self.scale, self.quat, self.opacity, self.color):
+        for t in self.tensors():
             if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
                 raise ValueError("Gaussian parameters must be contiguous float32 device tensors")
         g = A.Gaussians()
         g.mean, g.scale, g.quat = self.mean.data_ptr(), self.scale.data_ptr(), self.quat.data_ptr()
         g.opacity, g.color = self.opacity.data_ptr(), self.color.data_ptr()
         g.N = self.N
+        g.sh_degree = self.sh_degree
+        g.sh = self.sh.data_ptr() if self.sh is not None else None
         return g
 
     def zeros_like(self) -> "Gaussians":
-        return Gaussians(*(torch.zeros_like(t) for t in (self.mean, self.scale, self.quat, self.opacity, self.color)))
+        return Gaussians(*(torch.zeros_like(t) for t in (self.mean, self.scale, self.quat, self.opacity, self.color)),
+                         None if self.sh is None else torch.zeros_like(self.sh))
 
 
 class Proj:
@@ -193,18 +223,21 @@ class Bins:
 
 
 class Grads:
-    def __init__(self, N: int, C_: int, device):
+    def __init__(self, N: int, C_: int, device, sh_degree: int = 0):
         self.mean = torch.empty((3, N), dtype=torch.float32, device=device)
         self.scale = torch.empty((3, N), dtype=torch.float32, device=device)
         self.quat = torch.empty((4, N), dtype=torch.float32, device=device)
         self.opacity = torch.empty((N,), dtype=torch.float32, device=device)
         self.color = torch.empty((3, N), dtype=torch.float32, device=device)
         self.pose = torch.empty((C_, 6), dtype=torch.float64, device=device)
+        self.sh = (torch.empty((3 * sh_count(sh_degree), N), dtype=torch.float32, device=device)
+                   if sh_degree > 0 else None)
 
     def struct(self) -> A.Grads:
         g = A.Grads()
         g.g_mean, g.g_scale, g.g_quat = self.mean.data_ptr(), self.scale.data_ptr(), self.quat.data_ptr()
         g.g_opacity, g.g_color, g.g_pose = self.opacity.data_ptr(), self.color.data_ptr(), self.pose.data_ptr()
+        g.g_sh = self.sh.data_ptr() if self.sh is not None else None
         return g
 
 
@@ -267,7 +300,7 @@ def render_fwd(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, bin
 
 def render_bwd(ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, proj: Proj, bins: Bins, T_final, n_walk,
                dL_dimage: torch.Tensor, accumulate: bool = False, out: Optional[Grads] = None) -> Grads:
-    out = out or Grads(g.N, cams.C, ctx.device)
+    out = out or Grads(g.N, cams.C, ctx.device, g.sh_degree)
     nb = workspace_size(ctx, cams, g.N, o, bins.capacity)
     ws = ctx.workspace(nb)
     gs, ps, bs, gr = g.struct(), proj.struct(), bins.struct(), out.struct()
@@ -292,15 +325,16 @@ def render_stats(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, b
 # ---------------------------------------------------------------- Adam over the map parameters
 
 class AdamState:
-    """gsl_adam_state: raw parameters (14, ld) — mean 3, log-scale 3,
-    quaternion 4, opacity logit 1, colour 3 — their Adam moments and the
+    """gsl_adam_state: raw parameters (14 + 3K, ld) — mean 3, log-scale 3,
+    quaternion 4, opacity logit 1, colour 3, SH 3K — their Adam moments and the
     device step counter.  The first n columns are live (n = ld unless given),
     so a window kept at a fixed capacity can hand in views of its block."""
 
     def __init__(self, raw: torch.Tensor, m: Optional[torch.Tensor] = None, v: Optional[torch.Tensor] = None,
                  d_step: Optional[torch.Tensor] = None, n: Optional[int] = None):
-        if raw.dtype != torch.float32 or raw.dim() != 2 or raw.shape[0] != 14:
-            raise ValueError("raw parameters must be a float32 (14, ld) tensor")
+        if raw.dtype != torch.float32 or raw.dim() != 2 or raw.shape[0] < 14:
+            raise ValueError("raw parameters must be a float32 (14 + 3K, ld) tensor")
+        self.sh_degree = sh_degree_of(int(raw.shape[0]) - 14)
         self.raw = raw if raw.stride(1) == 1 else raw.contiguous()
         self.m = torch.zeros_like(self.raw) if m is None else m
         self.v = torch.zeros_like(self.raw) if v is None else v
@@ -319,23 +353,29 @@ class AdamState:
     @staticmethod
     def from_gaussians(g: "Gaussians") -> "AdamState":
         """Raw parameters of activated ones (initialisation, outside the step)."""
-        raw = torch.cat([g.mean, torch.log(g.scale), g.quat, torch.logit(g.opacity)[None], g.color], 0)
-        return AdamState(raw.float())
+        rows = [g.mean, torch.log(g.scale), g.quat, torch.logit(g.opacity)[None], g.color]
+        if g.sh is not None:
+            rows.append(g.sh)
+        return AdamState(torch.cat(rows, 0).float())
 
     def struct(self) -> A.AdamState:
         st = A.AdamState()
         st.raw, st.m, st.v, st.d_step = (t.data_ptr() for t in (self.raw, self.m, self.v, self.d_step))
         st.N = self.n
         st.ld = int(self.raw.stride(0))
+        st.sh_degree = self.sh_degree
         return st
 
 
-def adam_hparams(lr=(1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3), beta1=0.9, beta2=0.999, eps=1e-15) -> A.Adam:
-    """Learning rates per group: mean, log-scale, quaternion, opacity logit, colour."""
+def adam_hparams(lr=(1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3), beta1=0.9, beta2=0.999, eps=1e-15,
+                 lr_sh=1.25e-4) -> A.Adam:
+    """Learning rates per group: mean, log-scale, quaternion, opacity logit,
+    colour; lr_sh for the higher-order SH coefficients."""
     hp = A.Adam()
     for k in range(5):
         hp.lr[k] = float(lr[k])
     hp.beta1, hp.beta2, hp.eps = float(beta1), float(beta2), float(eps)
+    hp.lr_sh = float(lr_sh)
     return hp
 
 
@@ -352,6 +392,24 @@ def adam_step(ctx: Context, st: AdamState, hp: A.Adam, grads: "Grads", g: "Gauss
 
 
 # ---------------------------------------------------------------- sliding-window maintenance
+
+def color_init(ctx: Context, mean: torch.Tensor, cam, image: torch.Tensor, o: A.Opts,
+               color: Optional[torch.Tensor] = None):
+    """Bilinear colour of Gaussians (mean (3, n), rows may be strided) from a
+    camera image (3, H, W) (gsl_color_init).  Returns (color (3, n), valid
+    uint8 (n,)); colour rows of invalid Gaussians are left as they were."""
+    n = int(mean.shape[1])
+    if mean.stride(1) != 1 or mean.dtype != torch.float32:
+        raise ValueError("mean must be float32 (3, n) with unit column stride")
+    image = image.contiguous()
+    if color is None:
+        color = torch.zeros(3, n, dtype=torch.float32, device=mean.device)
+    valid = torch.empty(max(n, 1), dtype=torch.uint8, device=mean.device)
+    c = A.camera_array([cam])
+    A.check(A.lib().gsl_color_init(ctx.h, _p(mean), int(mean.stride(0)), n, c, _p(image), C.byref(o),
+                                   _p(color), int(color.stride(0)), _p(valid), _stream()))
+    return color, valid[:n]
+
 
 def voxel_keys(ctx: Context, xyz: torch.Tensor, voxel_size: float, component_major: bool = False) -> torch.Tensor:
     """Voxel keys (int64 tensor holding the uint64 bits; -1 = no key) of
@@ -418,14 +476,14 @@ def window_compact(ctx: Context, keys: torch.Tensor, rows: Optional[torch.Tensor
 
 class SlidingWindow:
     """The window of Gaussians at a fixed capacity on the device (Sec. II-C):
-    one float32 block (42, capacity) — raw parameters (rows 0-13), Adam
-    first (14-27) and second (28-41) moments — and the voxel keys; the first
-    n columns are live.  `update` runs one frame's incremental update."""
+    one float32 block (3R, capacity) — R = 14 + 3K raw parameter rows, then
+    the Adam first and second moments — and the voxel keys; the first n
+    columns are live.  `update` runs one frame's incremental update."""
 
-    ROWS = 42
-
-    def __init__(self, ctx: Context, capacity: int, voxel_size: float):
+    def __init__(self, ctx: Context, capacity: int, voxel_size: float, sh_degree: int = 0):
         self.ctx, self.capacity, self.voxel_size = ctx, int(capacity), float(voxel_size)
+        self.params = 14 + 3 * sh_count(sh_degree)
+        self.ROWS = 3 * self.params
         dev = ctx.device
         self.block = torch.zeros(self.ROWS, self.capacity, dtype=torch.float32, device=dev)
         self.keys = torch.full((self.capacity,), -1, dtype=torch.int64, device=dev)
@@ -433,12 +491,12 @@ class SlidingWindow:
         self.n = 0
 
     def adam_state(self) -> AdamState:
-        b = self.block
-        return AdamState(b[0:14], b[14:28], b[28:42], self.d_step, n=self.n)
+        b, R = self.block, self.params
+        return AdamState(b[0:R], b[R:2 * R], b[2 * R:3 * R], self.d_step, n=self.n)
 
     def update(self, points: torch.Tensor, fetch, ws: Optional[torch.Tensor] = None):
         """One frame: classify against the frame's points, then call
-        fetch(add_keys int64 (A_vox,) on the host) -> (keys (A,), rows (42, A)),
+        fetch(add_keys int64 (A_vox,) on the host) -> (keys (A,), rows (3R, A)),
         the Gaussians to append (from the global map or newly initialised;
         moments zero), and compact.  Returns (evicted_keys, evicted_rows) on
         the device, for the global map."""
@@ -550,7 +608,7 @@ class Window:
         self.loss = LOSS[loss]
         self.keep_image = keep_image
         self.headroom = headroom
-        self.grads = Grads(g.N, cams.C, ctx.device)
+        self.grads = Grads(g.N, cams.C, ctx.device, g.sh_degree)
         self.d_loss = torch.zeros(1, dtype=torch.float64, device=ctx.device)
         self.image = torch.empty(3 * cams.P_total, dtype=torch.float32, device=ctx.device) if keep_image else None
         self._alloc(capacity)

@@ -55,9 +55,13 @@ def gpu_backward(state, v_packed, accumulate=False):
     gr = O.render_bwd(s["ctx"], s["g"], s["cams"], s["opts"], s["proj"], s["bins"], s["T"], s["n_walk"],
                       v_packed, accumulate=accumulate)
     torch.cuda.synchronize()
-    return {"mean": gr.mean.cpu().numpy().T.astype(np.float64), "scale": gr.scale.cpu().numpy().T.astype(np.float64),
-            "quat": gr.quat.cpu().numpy().T.astype(np.float64), "opacity": gr.opacity.cpu().numpy().astype(np.float64),
-            "color": gr.color.cpu().numpy().T.astype(np.float64), "pose": gr.pose.cpu().numpy()}
+    out = {"mean": gr.mean.cpu().numpy().T.astype(np.float64), "scale": gr.scale.cpu().numpy().T.astype(np.float64),
+           "quat": gr.quat.cpu().numpy().T.astype(np.float64), "opacity": gr.opacity.cpu().numpy().astype(np.float64),
+           "color": gr.color.cpu().numpy().T.astype(np.float64), "pose": gr.pose.cpu().numpy()}
+    if gr.sh is not None:  # rows k * 3 + ch -> (N, K, 3) like the scene's
+        a = gr.sh.cpu().numpy().astype(np.float64)
+        out["sh"] = a.reshape(-1, 3, a.shape[1]).transpose(2, 0, 1)
+    return out
 
 
 def oracle_opts(O_oracle, **kw):
@@ -77,9 +81,9 @@ def pixel_tolerance(flags, tol=IMG_TOL, bg=0.0, cmax=1.0):
     return np.where((flags & 1) != 0, np.inf, t)
 
 
-def compare_images(gpu_img, orc_img, flags, tol=IMG_TOL, max_flag_frac=0.02, name="", bg=0.0):
+def compare_images(gpu_img, orc_img, flags, tol=IMG_TOL, max_flag_frac=0.02, name="", bg=0.0, cmax=1.0):
     """gpu_img, orc_img: (3, H, W); flags (H, W).  Returns (max error, excluded count)."""
-    tl = pixel_tolerance(flags, tol, bg=max(abs(b) for b in np.atleast_1d(bg)))
+    tl = pixel_tolerance(flags, tol, bg=max(abs(b) for b in np.atleast_1d(bg)), cmax=cmax)
     err = np.abs(gpu_img.astype(np.float64) - orc_img).max(0)
     bad = err > tl
     assert not bad.any(), f"{name}: {int(bad.sum())} pixels beyond tolerance, worst {float((err - tl)[bad].max()):.3g}"

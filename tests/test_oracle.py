@@ -588,12 +588,15 @@ def test_adam_matches_scalar_recursion(oracle):
     np.testing.assert_allclose(X[:, 0], x, rtol=1e-13)
 
 
-def test_activation_chain_matches_differences(oracle):
+@pytest.mark.parametrize("rows", [14, 14 + 9])
+def test_activation_chain_matches_differences(oracle, rows):
     """raw_gradient against central differences of a linear functional of the
-    activated parameters."""
+    activated parameters (with SH coefficient rows after the colour)."""
     rng = np.random.default_rng(4)
-    raw = rng.normal(size=(14, 5))
+    raw = rng.normal(size=(rows, 5))
     W = {k: rng.normal(size=(b - a, 5)) for k, (a, b) in oracle.RAW_ROWS.items()}
+    if rows > 14:
+        W["sh"] = rng.normal(size=(rows - 14, 5))
 
     def f(r):
         act = oracle.activate(r)
