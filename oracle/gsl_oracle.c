@@ -650,12 +650,14 @@ static void project_tangent(const proj_t *p, const orc_camera *cam, double dmu[1
 /* dI/dxi of one pixel (jac[3][6], channel-major), with the contributor set
  * held fixed: along the walk T_{k+1} = T_k (1 - a_k), so
  * dT_{k+1} = dT_k (1 - a_k) - T_k da_k and the pixel gains
- * c_k (T_k da_k + a_k dT_k); the background adds bg dT_final.  A clamped
- * alpha has da = 0; otherwise da = a dpower with
+ * c_k (T_k da_k + a_k dT_k), plus a_k T_k dc_k when the colour itself
+ * depends on the pose (dcol_all, N x 3 x 6, may be NULL); the background
+ * adds bg dT_final.  A clamped alpha has da = 0; otherwise da = a dpower with
  * dpower = (Q d) . dmu - 1/2 d^T dQ d, d = x - mu. */
 static void pixel_tangent(double px, double py, int64_t M, const int64_t *order, const proj_t *proj,
                           const double *opacity, const double *color, const orc_opts *o, const double *dmu_all,
-                          const double *dQ_all, contrib_t *list, double rgb[3], double jac[18])
+                          const double *dQ_all, const double *dcol_all, contrib_t *list, double rgb[3],
+                          double jac[18])
 {
     int32_t n;
     composite_pixel(px, py, M, order, proj, opacity, color, o, 0.0, rgb, &n, NULL, NULL, list);
@@ -677,7 +679,10 @@ static void pixel_tangent(double px, double py, int64_t M, const int64_t *order,
             }
         }
         for (int j = 0; j < 6; j++) {
-            for (int ch = 0; ch < 3; ch++) jac[6 * ch + j] += c[ch] * (e->T * da[j] + e->alpha * dT[j]);
+            for (int ch = 0; ch < 3; ch++) {
+                jac[6 * ch + j] += c[ch] * (e->T * da[j] + e->alpha * dT[j]);
+                if (dcol_all) jac[6 * ch + j] += e->alpha * e->T * dcol_all[18 * i + 6 * ch + j];
+            }
             dT[j] = dT[j] * (1.0 - e->alpha) - e->T * da[j];
         }
     }
@@ -687,10 +692,12 @@ static void pixel_tangent(double px, double py, int64_t M, const int64_t *order,
 
 /* Per-pixel Jacobian of the rendered colour with respect to the camera twist
  * (dphi, dt) of the left perturbation of T_CW, for the listed pixels:
- * jac (npix x 3 x 6), and the colour itself in rgb (npix x 3). */
+ * jac (npix x 3 x 6), and the colour itself in rgb (npix x 3).  dcol
+ * (N x 3 x 6, may be NULL) is the derivative of each Gaussian's colour with
+ * respect to the twist (a view-dependent colour). */
 int orc_render_jvp(int64_t N, const double *mean, const double *scale, const double *quat,
-                   const double *opacity, const double *color, const orc_camera *cam, const orc_opts *o,
-                   int64_t npix, const int32_t *pix, double *rgb, double *jac)
+                   const double *opacity, const double *color, const double *dcol, const orc_camera *cam,
+                   const orc_opts *o, int64_t npix, const int32_t *pix, double *rgb, double *jac)
 {
     proj_t *proj;
     int64_t *order;
@@ -705,8 +712,8 @@ int orc_render_jvp(int64_t N, const double *mean, const double *scale, const dou
         contrib_t *list = (contrib_t *)malloc(sizeof(contrib_t) * (size_t)(M > 0 ? M : 1));
         #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < npix; p++)
-            pixel_tangent(pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5, M, order, proj, opacity, color, o, dmu, dQ, list,
-                          rgb + 3 * p, jac + 18 * p);
+            pixel_tangent(pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5, M, order, proj, opacity, color, o, dmu, dQ, dcol,
+                          list, rgb + 3 * p, jac + 18 * p);
         free(list);
     }
     free(dmu);

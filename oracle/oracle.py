@@ -89,7 +89,7 @@ def lib():
         L.orc_pixel_trace.argtypes = [C.c_int64, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
                                       C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.orc_pixel_trace.restype = C.c_int32
-        L.orc_render_jvp.argtypes = [C.c_int64, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
+        L.orc_render_jvp.argtypes = [C.c_int64, P, P, P, P, P, P, C.POINTER(_Cam), C.POINTER(_Opts),
                                      C.c_int64, P, P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
@@ -198,6 +198,23 @@ def sh_basis_grad(u, degree):
     if not rows:
         return np.zeros(u.shape[:-1] + (0, 3))
     return np.stack([np.stack(r, -1) for r in rows], -2) / _Y00
+
+
+def sh_colour_twist_tangent(scene, cam):
+    """Derivative of each Gaussian's colour with respect to the left twist
+    (dphi, dt) of T_CW: (N, 3, 6).  A rotation leaves the camera centre in
+    place (zero); dt moves the view vector d = mu - o by R^T dt, so
+    dc/ddt = dc/du (I - u u^T) / r R^T."""
+    u, r = _view_dirs(scene, cam)
+    sh = np.asarray(scene.sh, np.float64)
+    dB = sh_basis_grad(u, scene.sh_degree)
+    dc_du = np.einsum("nkc,nkj->ncj", sh, dB)
+    proj = np.eye(3)[None] - u[:, :, None] * u[:, None, :]
+    dc_dd = np.einsum("ncj,njl->ncl", dc_du, proj) / r[:, None, None]
+    R = np.asarray(cam.R_cw, np.float64).reshape(3, 3)
+    out = np.zeros((scene.n, 3, 6))
+    out[:, :, 3:] = dc_dd @ R.T
+    return out
 
 
 def bilinear_colour(means, cam, image, near_z=0.2):
@@ -388,14 +405,13 @@ def render_jvp(scene, cam, opts: Opts = Opts(), pixels=None):
     (contributor sets held fixed).  Returns rgb (P,3), jac (P,3,6), pixels."""
     pix = all_pixels(cam) if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
     P = pix.shape[0]
-    if getattr(scene, "sh", None) is not None:
-        raise NotImplementedError("pose Jacobians are defined here for degree-0 colour only")
     m, s, q, o, c = _params(scene, cam)
+    dcol = None if getattr(scene, "sh", None) is None else _d(sh_colour_twist_tangent(scene, cam))
     rgb = np.zeros((P, 3))
     jac = np.zeros((P, 3, 6))
     co, oo = _cam(cam), opts.c()
-    lib().orc_render_jvp(scene.n, _p(m), _p(s), _p(q), _p(o), _p(c), C.byref(co), C.byref(oo), P, _p(pix),
-                         _p(rgb), _p(jac))
+    lib().orc_render_jvp(scene.n, _p(m), _p(s), _p(q), _p(o), _p(c), _p(dcol), C.byref(co), C.byref(oo), P,
+                         _p(pix), _p(rgb), _p(jac))
     return {"rgb": rgb, "jac": jac, "pixels": pix}
 
 

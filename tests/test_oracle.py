@@ -446,11 +446,14 @@ def _twist_scene(seed):
     return sc, cam0
 
 
-def test_pose_jvp_matches_twist_differences(oracle):
+@pytest.mark.parametrize("degree", [0, 3])
+def test_pose_jvp_matches_twist_differences(oracle, degree):
     """Per-pixel dI/d(dphi, dt) against central differences of the rendered
     colour under T_CW <- Exp(dphi, dt) T_CW (exponential from scipy), on the
-    pixels where the steps h and 2h agree (no threshold crossed)."""
+    pixels where the steps h and 2h agree (no threshold crossed); with SH
+    colour the camera centre's motion changes the colours too."""
     sc, cam0 = _twist_scene(9)
+    sc = S.with_sh(sc, degree, 19, sigma=0.3)
     o = oracle.Opts(bg=(0.2, 0.1, 0.3))
     J = oracle.render_jvp(sc, cam0, o)
     flags = oracle.render(sc, cam0, o)["flags"]
@@ -473,8 +476,8 @@ def test_pose_jvp_matches_twist_differences(oracle):
     assert checked > 0.8 * 6 * cam0.width * cam0.height
 
 
-@pytest.mark.parametrize("seed", [3, 17])
-def test_pose_jvp_adjoint_identity(oracle, seed):
+@pytest.mark.parametrize("seed,degree", [(3, 0), (17, 0), (23, 2)])
+def test_pose_jvp_adjoint_identity(oracle, seed, degree):
     """Forward and reverse mode are two separate derivations of one Jacobian:
     sum_p <v_p, dI_p/dxi> equals the pose gradient of L = sum_p <v_p, I_p>
     for any cotangent v, with background, clamped alphas and cut-off walks."""
@@ -483,6 +486,7 @@ def test_pose_jvp_adjoint_identity(oracle, seed):
     cam = Cam64(Camera(30.0, 33.0, 16.0, 12.0, 32, 24, Rc, [0, 0, 0]), Rc, rng.normal(0, 0.2, 3))
     sc = S.random_scene(120, cam, seed=seed, zmin=1.0, zmax=3.0, smin=0.05, smax=0.3, unnormalised_quats=True)
     sc.opacity[:20] = 0.999  # clamped at 0.99 near their centres
+    sc = S.with_sh(sc, degree, seed + 1, sigma=0.3)
     o = oracle.Opts(bg=(0.3, 0.6, 0.1))
     J = oracle.render_jvp(sc, cam, o)
     r = oracle.render(sc, cam, o)
