@@ -412,8 +412,9 @@ GSL_API int gsl_window_compact(gsl_ctx *ctx, uint64_t *keys, float *rows, int32_
 /* ---- pose Jacobians for the IESKF visual update -------------------------- */
 
 /* Workspace bytes for gsl_pose_jacobian: the bytes gsl_workspace_size gives
- * for the same arguments, plus 128 B per (camera, Gaussian) record for its
- * twist tangents and 224 B per tile for the per-tile partial sums. */
+ * for the same arguments, plus 160 B per (camera, Gaussian) record for its
+ * twist tangents (those of the 2D mean and conic, and of the colour when it
+ * is view-dependent) and 224 B per tile for the per-tile partial sums. */
 GSL_API int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,
                                              const gsl_opts *opts, int64_t capacity_K, size_t *bytes);
 
@@ -423,7 +424,9 @@ GSL_API int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cam
  * T_CW <- Exp(xi) T_CW, by forward-mode differentiation through the
  * projection (eqs. eqn:grad_meani_rcw ... eqn:grad_covi_tcw) and the same
  * front-to-back walk as gsl_render_fwd (same contributors; the thresholds
- * are held fixed).  Needs gsl_project and gsl_bin_sort outputs for these
+ * are held fixed).  With SH colour (sh_degree > 0) the colours' own
+ * dependence on the camera centre (the translation of the twist) is
+ * included.  Needs gsl_project and gsl_bin_sort outputs for these
  * Gaussians and cameras.  Device outputs, each may be NULL:
  *   image  float[3 * P_total]  the rendered colour, packed as gsl_render_fwd;
  *   jac    float[18 * P_total] plane 6 * ch + j holds dI_ch/dxi_j of every

@@ -497,7 +497,7 @@ int check_adam_act(const gsl_adam_state *st, const gsl_gaussians *act, const gsl
 
 // Bytes gsl_pose_jacobian needs past the common workspace: per-record
 // tangents, then per-item normal-equation partials.
-size_t jvp_tangent_bytes(const Layout &L) { return align_up(4 * (size_t)kTangent * (size_t)L.M); }
+size_t jvp_tangent_bytes(const Layout &L) { return align_up(4 * (size_t)kTangentSH * (size_t)L.M); }
 size_t jvp_extra_bytes(const Layout &L)
 {
     return jvp_tangent_bytes(L) + align_up(8 * (size_t)kNrm * (size_t)std::max<int64_t>(1, L.T_total));
@@ -1062,8 +1062,7 @@ int gsl_pose_jacobian(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *ca
                       size_t workspace_bytes, void *stream)
 {
     GSL_TRY(check_gauss(g, false));
-    if (g->sh_degree > 0)
-        return fail(GSL_ENOTSUP, "pose Jacobians are built for degree-0 colour (sh_degree %d)", g->sh_degree);
+    if (g->sh_degree > 0 && g->N > 0 && !g->sh) return fail(GSL_EINVAL, "sh is NULL");
     GSL_TRY(check_bins(bins));
     Prepared p;
     GSL_TRY(prepare(ctx, cams, C, g->N, opts, bins->capacity_K, workspace, workspace_bytes, p));
@@ -1084,6 +1083,7 @@ int gsl_pose_jacobian(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *ca
     a.weight = weight;
     a.jac = jac;
     a.tangent = tangent;
+    a.sh_colour = g->sh_degree > 0;
     a.P_total = p.L.P_total;
     a.nrm_part = normal ? part : nullptr;
     launch_render_jvp(a, s);

@@ -200,6 +200,9 @@ void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout
 // Per-record derivatives of the 2D mean and conic along the camera twist,
 // kTangent floats per record (records that reach no tile are not written).
 constexpr int kTangent = 32;
+// With a view-dependent colour the record also holds dc/d(dt) (3 channels x
+// 3 translation directions) at floats 30..38: 40 floats.
+constexpr int kTangentSH = 40;
 void launch_project_tangent(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                             const int32_t *tiles_touched, float *tangent, hipStream_t s);
 
@@ -258,7 +261,8 @@ struct RenderArgs {
     const uint32_t *order;
     uint32_t *queue;
     // pose Jacobian (forward mode)
-    const float *tangent;   // [M][kTangent]
+    const float *tangent;   // [M][kTangent], or [M][kTangentSH] with sh_colour
+    int sh_colour;          // the tangents carry colour derivatives
     const float *weight;    // per-pixel R^-1 weight or NULL (1)
     int64_t P_total;        // pixels of all cameras (plane stride of jac)
     float *jac;             // [18][P_total] dI_ch/dxi_j planes (plane 6 ch + j) or NULL

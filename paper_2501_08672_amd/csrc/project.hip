@@ -240,13 +240,16 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
 // Record m gets kTangent floats: dmx[6], dmy[6], dA[6], dB[6], dC[6] of the
 // conic (A, B, C) = Sigma2D^{-1}, then two unused.  Only records that reach a
 // tile are written (no other record is ever read).
+template <bool SH>
 __global__ __launch_bounds__(256) void k_project_tangent(const float *__restrict__ mean,
                                                          const float *__restrict__ scale,
-                                                         const float *__restrict__ quat, int N, int64_t M,
+                                                         const float *__restrict__ quat,
+                                                         const float *__restrict__ sh, int shd, int N, int64_t M,
                                                          const DevCam *__restrict__ cams, DevOpts o,
                                                          const int32_t *__restrict__ tiles_touched,
                                                          float *__restrict__ tangent)
 {
+    constexpr int STRIDE = SH ? kTangentSH : kTangent;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || tiles_touched[m] <= 0) return;
     const int c = (int)(m / N);
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(256) void k_project_tangent(const float *__restrict
     const double J00 = fx * iz, J02 = -fx * p.x * iz * iz, J11 = fy * iz, J12 = -fy * p.y * iz * iz;
     const double id = 1.0 / p.det;
     const double QA = p.c * id, QB = -p.b * id, QC = p.a * id;
-    float *out = tangent + m * kTangent;
+    float *out = tangent + m * STRIDE;
     for (int k = 0; k < 6; k++) {
         double dp[3] = {0.0, 0.0, 0.0};
         double E[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // [e]x for a rotation direction
@@ -303,8 +306,39 @@ __global__ __launch_bounds__(256) void k_project_tangent(const float *__restrict
         out[18 + k] = (float)(-(t00 * QB + t01 * QC));
         out[24 + k] = (float)(-(t10 * QB + t11 * QC));
     }
-    out[30] = 0.f;
-    out[31] = 0.f;
+    if (!SH) {
+        out[30] = 0.f;
+        out[31] = 0.f;
+        return;
+    }
+    // colour along the twist: a rotation keeps the camera centre; dt moves
+    // the view vector d = mu - o by R^T dt, so dc/ddt = dc/du (I - u u^T) / r R^T
+    double u[3];
+    const double r = view_dir(cam, mean[i], mean[N + i], mean[2 * N + i], u);
+    const int K = sh_count(shd);
+    double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // [channel][axis]
+#pragma unroll
+    for (int k = 0; k < kShMaxK; k++) {
+        if (k < K) {
+            double dx, dy, dz;
+            sh_db(k, u[0], u[1], u[2], dx, dy, dz);
+            for (int ch = 0; ch < 3; ch++) {
+                const double w = sh[((int64_t)k * 3 + ch) * N + i];
+                du[ch][0] += w * dx;
+                du[ch][1] += w * dy;
+                du[ch][2] += w * dz;
+            }
+        }
+    }
+    const double ir = 1.0 / r;
+    for (int ch = 0; ch < 3; ch++) {
+        const double ug = u[0] * du[ch][0] + u[1] * du[ch][1] + u[2] * du[ch][2];
+        double dd[3];
+        for (int a = 0; a < 3; a++) dd[a] = (du[ch][a] - u[a] * ug) * ir;
+        for (int j = 0; j < 3; j++)
+            out[30 + 3 * ch + j] = (float)(p.W[3 * j] * dd[0] + p.W[3 * j + 1] * dd[1] + p.W[3 * j + 2] * dd[2]);
+    }
+    out[39] = 0.f;
 }
 
 // ------------------------------------------------------------------ backward
@@ -631,8 +665,12 @@ void launch_project_tangent(const gsl_gaussians &g, const DevCam *cams, const La
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
-    hipLaunchKernelGGL(k_project_tangent, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat, g.N, L.M,
-                       cams, o, tiles_touched, tangent);
+    if (g.sh_degree > 0)
+        hipLaunchKernelGGL(k_project_tangent<true>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat,
+                           g.sh, g.sh_degree, g.N, L.M, cams, o, tiles_touched, tangent);
+    else
+        hipLaunchKernelGGL(k_project_tangent<false>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale,
+                           g.quat, g.sh, 0, g.N, L.M, cams, o, tiles_touched, tangent);
 }
 
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,

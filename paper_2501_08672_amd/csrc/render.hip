@@ -733,27 +733,28 @@ __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ p
 // H^T R^-1 H (21), H^T R^-1 z (6) and z^T R^-1 z, R^-1 a per-pixel weight.
 // One pixel per lane for 8x8 and 16x16 tiles, two for 32x32; the splats and
 // their tangent records are staged in chunks of up to 256.
-template <int CH>
+template <int CH, int NQ>
 struct TanStage {
     float4 p0[CH];
     float4 p1[CH];
     float p2[CH];
     uint32_t gid[CH];
-    float4 t[kTangent / 4][CH];
+    float4 t[NQ][CH];
 };
 
-template <int TS, int NW>
+template <int TS, int NW, bool SHC>
 __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
 {
     using G = Geo<TS, NW>;
     constexpr int PPL = G::PPL;
     constexpr int CH = G::BS < 256 ? G::BS : 256;
-    __shared__ TanStage<CH> st;
+    constexpr int STRIDE = SHC ? kTangentSH : kTangent;
+    __shared__ TanStage<CH, STRIDE / 4> st;
     __shared__ double s_nrm[NW][kNrm];
     const int t = (int)blockIdx.x;
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, t);
     const gsl_splat *rec = a.splats + (int64_t)ti.c * a.N;
-    const float *tan = a.tangent + (int64_t)ti.c * a.N * kTangent;
+    const float *tan = a.tangent + (int64_t)ti.c * a.N * STRIDE;
     const float fx = ti.px + 0.5f;
     const float amin = a.o.alpha_min, amax = a.o.alpha_max, Tmin = a.o.T_min;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -788,9 +789,9 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
             st.p1[threadIdx.x] = r4[1];
             st.p2[threadIdx.x] = r4[2].x;
             st.gid[threadIdx.x] = val;
-            const float4 *t4 = reinterpret_cast<const float4 *>(tan + (int64_t)gi * kTangent);
+            const float4 *t4 = reinterpret_cast<const float4 *>(tan + (int64_t)gi * STRIDE);
 #pragma unroll
-            for (int q = 0; q < kTangent / 4; q++) st.t[q][threadIdx.x] = t4[q];
+            for (int q = 0; q < STRIDE / 4; q++) st.t[q][threadIdx.x] = t4[q];
         }
         __syncthreads();
         const int n = (int)min((uint32_t)CH, ti.re - start);
@@ -847,6 +848,14 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
                     dT[k][q] = fmaf(dT[k][q], 1.f - al, -Tk * da[q]);
                 }
                 const float wgt = al * Tk;
+                if (SHC) {  // the colour's own derivative along dt: + alpha T dc
+                    const float4 c0 = st.t[7][j], c1 = st.t[8][j], c2 = st.t[9][j];
+                    const float dc[9] = {c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x, c2.y, c2.z};
+#pragma unroll
+                    for (int ch = 0; ch < 3; ch++)
+#pragma unroll
+                        for (int q = 0; q < 3; q++) dC[k][ch][3 + q] = fmaf(wgt, dc[3 * ch + q], dC[k][ch][3 + q]);
+                }
                 C0[k] = fmaf(wgt, p1.z, C0[k]);
                 C1[k] = fmaf(wgt, p1.w, C1[k]);
                 C2[k] = fmaf(wgt, cb, C2[k]);
@@ -1052,9 +1061,18 @@ void launch_render_jvp(const RenderArgs &a, hipStream_t s)
 {
     if (a.T_total == 0) return;
     switch (a.o.tile) {
-        case 8: hipLaunchKernelGGL((k_render_jvp<8, 1>), dim3((unsigned)a.T_total), dim3(64), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((k_render_jvp<16, 4>), dim3((unsigned)a.T_total), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_render_jvp<32, 8>), dim3((unsigned)a.T_total), dim3(512), 0, s, a); break;
+        case 8:
+            if (a.sh_colour) hipLaunchKernelGGL((k_render_jvp<8, 1, true>), dim3((unsigned)a.T_total), dim3(64), 0, s, a);
+            else hipLaunchKernelGGL((k_render_jvp<8, 1, false>), dim3((unsigned)a.T_total), dim3(64), 0, s, a);
+            break;
+        case 16:
+            if (a.sh_colour) hipLaunchKernelGGL((k_render_jvp<16, 4, true>), dim3((unsigned)a.T_total), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_render_jvp<16, 4, false>), dim3((unsigned)a.T_total), dim3(256), 0, s, a);
+            break;
+        default:
+            if (a.sh_colour) hipLaunchKernelGGL((k_render_jvp<32, 8, true>), dim3((unsigned)a.T_total), dim3(512), 0, s, a);
+            else hipLaunchKernelGGL((k_render_jvp<32, 8, false>), dim3((unsigned)a.T_total), dim3(512), 0, s, a);
+            break;
     }
 }
 

@@ -53,12 +53,13 @@ def _jac_per_camera(st, pj):
     return out
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_pose_jacobian_matches_oracle(oracle, tile):
+@pytest.mark.parametrize("tile,degree", [(8, 0), (16, 0), (32, 0), (16, 3), (32, 2)])
+def test_pose_jacobian_matches_oracle(oracle, tile, degree):
     """Per pixel, per twist direction: |GPU - oracle| <= 1e-3 max |oracle| on
     the pixels the oracle does not flag; the colour equals gsl_render_fwd's
-    bit for bit (same walk, same decisions)."""
-    sc = _scene(3)
+    bit for bit (same walk, same decisions).  With SH colour the colours'
+    dependence on the camera centre is part of the Jacobian."""
+    sc = S.with_sh(_scene(3), degree, 33, sigma=0.2)
     bg = (0.1, 0.2, 0.3)
     st, pj = _run(sc, tile, bg=bg)
     img_fwd = st["image"].cpu().numpy()
@@ -108,10 +109,12 @@ def test_pose_normal_equations_match_oracle(oracle, weighted):
         assert np.array_equal(g, g.T)
 
 
-def test_pose_jacobian_adjoint_identity_on_gpu():
+@pytest.mark.parametrize("degree", [0, 3])
+def test_pose_jacobian_adjoint_identity_on_gpu(degree):
     """GPU forward mode against GPU reverse mode: sum_p <v_p, dI_p/dxi> equals
-    gsl_render_bwd's pose gradient for the same cotangent v."""
-    sc = _scene(8)
+    gsl_render_bwd's pose gradient for the same cotangent v (with SH colour
+    both include the colours' dependence on the camera centre)."""
+    sc = S.with_sh(_scene(8), degree, 18, sigma=0.2)
     st, pj = _run(sc, 16)
     rng = np.random.default_rng(4)
     v = rng.normal(size=3 * st["cams"].P_total).astype(np.float32)

@@ -151,15 +151,6 @@ def test_sh_adam_rows_match_oracle(oracle):
     np.testing.assert_allclose(g.scale.cpu().numpy(), np.exp(x[3:6]), rtol=1e-5, atol=1e-7)
 
 
-def test_pose_jacobian_rejects_sh():
-    O = ops()
-    ctx = context()
-    sc = _scene(500, 51, 1)
-    st = gpu_forward(sc, sc.cams)
-    with pytest.raises(O.A.GslError):
-        O.pose_jacobian(ctx, st["g"], st["cams"], st["opts"], st["proj"], st["bins"], want_jac=True)
-
-
 @pytest.mark.parametrize("W,H", [(96, 80), (17, 11)])
 def test_color_init_matches_oracle(oracle, W, H):
     """Bilinear colours of means in front of and behind the camera, inside
