@@ -20,6 +20,7 @@ Prints one JSON line; besides the metric it carries
                     normal equations) on 32 perturbed poses of a 640x512 view
   window_update     the incremental sliding-window update (hash classification
                     of a LiDAR frame's voxels, in-place compaction) at 500k
+  sh3_window        the same window step with SH degree 3 colour
 """
 import argparse
 import hashlib
@@ -60,6 +61,8 @@ def parse():
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-jac", action="store_true", help="skip the pose-Jacobian measurement")
     ap.add_argument("--no-window-update", action="store_true", help="skip the window-update measurement")
+    ap.add_argument("--no-sh", action="store_true", help="skip the SH-colour window measurement")
+    ap.add_argument("--no-optimize", action="store_true", help="skip the 10-iteration optimisation loop")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line: window step time vs N in {20k, 100k, 500k, 2M} at "
                          "640x512 and 1280x1024 (8 keyframes), one JSON line per point")
@@ -160,6 +163,54 @@ def pose_jacobian_bench(ctx, ops, S, torch, reps=5):
                     "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
                     "pairs": {"evaluated": ev_f, "contributors": n_contrib}},
             "residual_rms": round(float(np.sqrt(pj.zz.sum().item() / (3 * P))), 5)}
+
+
+def optimize_bench(ctx, ops, torch, g, win):
+    """The optimisation loop of one keyframe: 10 iterations of window step +
+    Adam recorded as one graph (it moves the Gaussians, so it runs after the
+    window-step measurements)."""
+    st = ops.AdamState.from_gaussians(g)
+    ops.adam_activate(ctx, st, g)
+    hp = ops.adam_hparams()
+    win.optimize(st, hp, iters=10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        losses = win.optimize(st, hp, iters=10)
+    torch.cuda.synchronize()
+    t_opt = (time.perf_counter() - t1) / reps
+    assert win.status() == 0, "instance capacity exceeded during the optimisation loop"
+    return {"iters": 10, "ms": round(t_opt * 1e3, 4), "ms_per_iter": round(t_opt * 1e3 / 10, 4),
+            "last_losses": [round(float(x), 6) for x in losses[[0, -1]].cpu().tolist()],
+            "how": "gsl_window_optimize: 10 x (window step + Adam step over the 500k raw parameters), one graph"}
+
+
+def sh_window_bench(ctx, ops, S, torch, sc, cs, target, tile, steps=10):
+    """The bench window with view-dependent colour: the same 500k surfels and
+    8 keyframes with SH degree 3 (15 coefficients per channel, N(0, 0.15/l)),
+    one window step (projection with the SH colour, binning, fused render,
+    projection adjoint + SH adjoint) replayed as a graph, against the same
+    target."""
+    sc3 = S.with_sh(sc, 3, 33)
+    g = ops.Gaussians.from_scene(sc3)
+    win = ops.Window(ctx, g, cs, ops.opts(tile), target, loss="l1")
+    for _ in range(3):
+        win.step(True)
+    torch.cuda.synchronize()
+    assert win.status() == 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        win.step(True)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    st_ms = np.array([win.profiled_step() for _ in range(3)]).mean(0)
+    res = {"workload": "the bench window with SH degree 3 colour (500k surfels, 8 keyframes 1280x1024, L1)",
+           "sh_degree": 3, "ms_per_step": round(t * 1e3, 4), "mpix_s": round(cs.P_total / t / 1e6, 2),
+           "stage_ms": {"project": round(float(st_ms[0]), 4), "bin_sort": round(float(st_ms[1]), 4),
+                        "fused_render": round(float(st_ms[2]), 4), "adjoint": round(float(st_ms[3]), 4)}}
+    del win, g
+    return res
 
 
 def window_update_bench(ctx, ops, S, torch, frames=8):
@@ -407,24 +458,15 @@ def main():
         log(f"per-frame plain launches {t_pf * 1e3:.3f} ms per window ({P / t_pf / 1e6:.1f} Mpix/s)")
         del frames
 
-    # the optimisation loop of one keyframe: 10 iterations of window step +
-    # Adam recorded as one graph (run last: it moves the Gaussians)
-    st = ops.AdamState.from_gaussians(g)
-    ops.adam_activate(ctx, st, g)
-    hp = ops.adam_hparams()
-    win.optimize(st, hp, iters=10)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    reps = 3
-    for _ in range(reps):
-        losses = win.optimize(st, hp, iters=10)
-    torch.cuda.synchronize()
-    t_opt = (time.perf_counter() - t1) / reps
-    assert win.status() == 0, "instance capacity exceeded during the optimisation loop"
-    optimize = {"iters": 10, "ms": round(t_opt * 1e3, 4), "ms_per_iter": round(t_opt * 1e3 / 10, 4),
-                "last_losses": [round(float(x), 6) for x in losses[[0, -1]].cpu().tolist()],
-                "how": "gsl_window_optimize: 10 x (window step + Adam step over the 500k raw parameters), one graph"}
-    log(f"optimise 10 iterations: {optimize}")
+    optimize = None
+    if not args.no_optimize:
+        optimize = optimize_bench(ctx, ops, torch, g, win)
+        log(f"optimise 10 iterations: {optimize}")
+
+    sh3 = None
+    if not args.no_sh:
+        sh3 = sh_window_bench(ctx, ops, S, torch, sc, cs, target, tile)
+        log(f"SH degree 3 window: {sh3}")
 
     win_upd = None
     if not args.no_window_update:
@@ -471,11 +513,14 @@ def main():
         "window_hbm": {"algorithmic_bytes": int(step_bytes),
                        "frac": round(step_bytes / t_win / 1e9 / HBM_PEAK_GBS, 4)},
     }
-    result["optimize"] = optimize
+    if optimize is not None:
+        result["optimize"] = optimize
     if pose_jac is not None:
         result["pose_jacobian"] = pose_jac
     if win_upd is not None:
         result["window_update"] = win_upd
+    if sh3 is not None:
+        result["sh3_window"] = sh3
     if tune_times is not None:
         result["autotune_ms"] = [round(t, 3) for t in tune_times]
     if not args.no_cpu:
