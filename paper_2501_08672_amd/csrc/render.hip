@@ -227,6 +227,7 @@ struct Stage {
     float4 p1[CH];  // l22, opacity, r, g
     float p2[CH];   // b
     uint32_t gid[CH];  // Gaussian index | band mask << 28
+    uint8_t wl[CH / kWave][CH];  // per wave: the chunk entries that reach its region, in order
 };
 
 template <int CH>
@@ -271,6 +272,28 @@ __device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1
     e.s = p1.y * e.G;
     e.alpha = fminf(amax, e.s);
     return e;
+}
+
+// Builds this wave's list of the chunk entries that reach its region (one
+// band test per splat and wave) in Stage::wl; returns its length.  Every lane
+// of the workgroup calls it after the chunk is staged; on return the lists
+// are visible to their waves.
+template <int TS, int NW>
+__device__ __forceinline__ int wave_list(Stage<Geo<TS, NW>::CH> &st, int n, int wv, int lane)
+{
+    constexpr int CH = Geo<TS, NW>::CH;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int c = 0;
+#pragma unroll
+    for (int g = 0; g < CH; g += kWave) {
+        const int e = g + lane;
+        const bool in = e < n && in_band<TS, NW>(st.gid[e], wv, 0);
+        const uint64_t m = __ballot(in);
+        if (in) st.wl[wv][c + __popcll(m & below)] = (uint8_t)e;
+        c += __popcll(m);
+    }
+    __syncthreads();
+    return c;
 }
 
 template <int PPL>
@@ -321,14 +344,16 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
     const gsl_splat *rec = a.splats + (int64_t)ti.c * a.N;
     const float fx = ti.px + 0.5f;
     const float amin = a.o.alpha_min, amax = a.o.alpha_max, Tmin = a.o.T_min;
+    // A pixel's transmittance carries its state in the sign: T > 0 while the
+    // walk is open, -T once a Gaussian would take it below T_min.  With
+    // T_min > 0 and alpha < 1 a finished pixel has T (1 - alpha) < 0 < T_min,
+    // so the same test that finishes a pixel keeps it finished.
     PixState<PPL> ps;
-    bool done[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        ps.T[k] = 1.f;
+        ps.T[k] = ti.inside(k) ? 1.f : -1.f;
         ps.C0[k] = ps.C1[k] = ps.C2[k] = 0.f;
         ps.nwalk[k] = 0;
-        done[k] = !ti.inside(k);
     }
     float fy[PPL];
 #pragma unroll
@@ -340,7 +365,7 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
     auto open = [&]() {
         bool o = false;
 #pragma unroll
-        for (int k = 0; k < PPL; k++) o |= !done[k];
+        for (int k = 0; k < PPL; k++) o |= ps.T[k] > 0.f;
         return o;
     };
     for (uint32_t start = ti.rs; start < ti.re; start += G::CH) {
@@ -348,8 +373,13 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
         stage_load<G::CH>(st, a, rec, start + threadIdx.x, ti.re);
         __syncthreads();
         const int n = (int)min((uint32_t)G::CH, ti.re - start);
-        for (int j = 0; j < n; j++) {
+        // With one band test per wave, the wave walks only the entries that
+        // reach its region (a band the ellipse misses has alpha < alpha_min
+        // everywhere), listed in order: no skip branch in the walk.
+        const int nw_list = G::ONE_BAND ? wave_list<TS, NW>(st, n, wv, lane) : n;
+        for (int jj = 0; jj < nw_list; jj++) {
             if (!__any(open())) break;
+            const int j = G::ONE_BAND ? __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]) : jj;
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
@@ -358,27 +388,22 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
             const float ax = p0.z * dx;
             const uint32_t pos1 = start + (uint32_t)j + 1u - ti.rs;
             bool used = false;
-            // a band the ellipse does not reach has alpha < alpha_min everywhere
-            const bool wave_in = !G::ONE_BAND || in_band<TS, NW>(val, wv, 0);
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (!wave_in) break;
                 if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;
                 // predicated: every lane evaluates, selects decide what changes
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
-                const bool live = !done[k];
-                const bool hit = live && e.alpha >= amin;
-                cnt.eval(k, live);
-                const float Tn = ps.T[k] * (1.f - e.alpha);
-                const bool stop = hit && Tn < Tmin;
-                const bool acc = hit && !stop;
+                const float T = ps.T[k];
+                cnt.eval(k, T > 0.f);
+                const bool hit = e.alpha >= amin;
+                const float Tn = T * (1.f - e.alpha);
+                const bool acc = hit && Tn >= Tmin;  // false for a finished pixel
                 cnt.contrib(k, acc);
-                done[k] = done[k] || stop;
-                const float w = acc ? e.alpha * ps.T[k] : 0.f;
+                const float w = acc ? e.alpha * T : 0.f;
                 ps.C0[k] = fmaf(w, p1.z, ps.C0[k]);
                 ps.C1[k] = fmaf(w, p1.w, ps.C1[k]);
                 ps.C2[k] = fmaf(w, cb, ps.C2[k]);
-                ps.T[k] = acc ? Tn : ps.T[k];
+                ps.T[k] = acc ? Tn : (hit ? -fabsf(T) : T);
                 ps.nwalk[k] = acc ? pos1 : ps.nwalk[k];
                 used = used || acc;
             }
@@ -395,6 +420,8 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
         __syncthreads();
     }
     if (hits && lane == 0 && hword < kHitWords) hits[hword] = hbits;
+#pragma unroll
+    for (int k = 0; k < PPL; k++) ps.T[k] = fabsf(ps.T[k]);
     return ps;
 }
 
