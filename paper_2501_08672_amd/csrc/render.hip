@@ -65,9 +65,10 @@ struct Geo {
     static constexpr int RSTEP = kWave / CW;              // row stride between a lane's pixels
     static constexpr int CH = BS;                         // splats staged per chunk
     // workgroups per CU the compositing kernels ask the compiler to fit: four
-    // waves per workgroup, eight workgroups = eight waves per SIMD (64 VGPRs);
-    // measured faster than fewer, larger-register waves
-    static constexpr int MIN_WG = BS == 256 ? 8 : 1;
+    // waves per workgroup, seven workgroups = seven waves per SIMD (at most 72
+    // VGPRs, which the fused kernel fits without spilling); measured faster
+    // than eight with spills and than fewer, larger-register waves
+    static constexpr int MIN_WG = BS == 256 ? 7 : 1;
     static constexpr bool MASKED = TS >= 16;
     static_assert(CW * ROWS % kWave == 0 && PPL >= 1 && ROWS * (QUAD ? 2 : NW) == TS, "tile/wave layout");
     __device__ static int col0(int w) { return QUAD ? (w & 1) * 16 : 0; }
@@ -104,6 +105,17 @@ __device__ __forceinline__ float dpp_sum63(float v)
 __device__ __forceinline__ float wave_total(float v)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dpp_sum63(v)), 63));
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x141, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x140, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ uint32_t wave_total_u32(uint32_t v)
@@ -278,10 +290,10 @@ __device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1
 // band test per splat and wave) in Stage::wl; returns its length.  Every lane
 // of the workgroup calls it after the chunk is staged; on return the lists
 // are visible to their waves.
-template <int TS, int NW>
-__device__ __forceinline__ int wave_list(Stage<Geo<TS, NW>::CH> &st, int n, int wv, int lane)
+template <int TS, int NW, int CH, typename St>
+__device__ __forceinline__ int wave_list(St &st, int n, int wv, int lane)
 {
-    constexpr int CH = Geo<TS, NW>::CH;
+    static_assert(CH <= 256, "list entries are bytes");
     const uint64_t below = (1ull << lane) - 1ull;
     int c = 0;
 #pragma unroll
@@ -376,7 +388,7 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
         // With one band test per wave, the wave walks only the entries that
         // reach its region (a band the ellipse misses has alpha < alpha_min
         // everywhere), listed in order: no skip branch in the walk.
-        const int nw_list = G::ONE_BAND ? wave_list<TS, NW>(st, n, wv, lane) : n;
+        const int nw_list = G::ONE_BAND ? wave_list<TS, NW, G::CH>(st, n, wv, lane) : n;
         for (int jj = 0; jj < nw_list; jj++) {
             if (!__any(open())) break;
             const int j = G::ONE_BAND ? __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]) : jj;
@@ -425,6 +437,31 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
     return ps;
 }
 
+// The backward walk's list: entries that reach the wave's region, lie before
+// the wave's last contributor (pos < maxn) and, within the first 32 *
+// kHitWords positions, where the forward walk saw one of its contributors.
+template <int TS, int NW>
+__device__ __forceinline__ int wave_list_bwd(Stage<Geo<TS, NW>::CH> &st, int n, uint32_t pos0, uint32_t maxn,
+                                             const uint32_t *hits, int wv, int lane)
+{
+    constexpr int CH = Geo<TS, NW>::CH;
+    static_assert(CH <= 256, "list entries are bytes");
+    const uint64_t below = (1ull << lane) - 1ull;
+    int c = 0;
+#pragma unroll
+    for (int g = 0; g < CH; g += kWave) {
+        const int e = g + lane;
+        const uint32_t pos = pos0 + (uint32_t)e;
+        bool in = e < n && pos < maxn && (!Geo<TS, NW>::ONE_BAND || in_band<TS, NW>(st.gid[e], wv, 0));
+        if (in && hits && pos < 32u * kHitWords) in = ((hits[pos >> 5] >> (pos & 31)) & 1u) != 0u;
+        const uint64_t m = __ballot(in);
+        if (in) st.wl[wv][c + __popcll(m & below)] = (uint8_t)e;
+        c += __popcll(m);
+    }
+    __syncthreads();
+    return c;
+}
+
 // Backward walk.  Tf[k] is the final transmittance of pixel k, v its cotangent.
 template <int TS, int NW>
 __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti, Stage<Geo<TS, NW>::CH> &st,
@@ -464,21 +501,22 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
     const int slot = reduce9_slot(lane);
     const bool writer = slot >= 0 && (lane & 3) == 0;
     const int64_t lo = ti.rs;
+    // the last list position any pixel of this wave walks to
+    const uint32_t wave_max = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_max));
     for (int64_t end = lo + maxn; end > lo; end -= G::CH) {
         const int64_t start = end - G::CH > lo ? end - G::CH : lo;
         __syncthreads();
         stage_load<G::CH>(st, a, rec, (uint32_t)(start + threadIdx.x), (uint32_t)end);
         __syncthreads();
-        for (int j = (int)(end - start) - 1; j >= 0; j--) {
+        // the entries this wave has to visit, in order (walked in reverse)
+        const int nl = wave_list_bwd<TS, NW>(st, (int)(end - start), (uint32_t)(start - lo), wave_max, hits, wv, lane);
+        for (int jj = nl - 1; jj >= 0; jj--) {
+            const int j = __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]);
             const uint32_t pos = (uint32_t)(start - lo) + (uint32_t)j;
-            if (!__any(pos < lane_max)) continue;
-            // the forward walk of this item saw no contributor of this wave here
-            if (hits && pos < 32u * kHitWords && !((hits[pos >> 5] >> (pos & 31)) & 1u)) continue;
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
             const uint32_t val = __builtin_amdgcn_readfirstlane(st.gid[j]);  // same for every lane
-            if (G::ONE_BAND && !in_band<TS, NW>(val, wv, 0)) continue;
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
             // Per lane: gp = dL/dpower of each pixel; the lane's pixels share
@@ -760,13 +798,14 @@ __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ p
 // H^T R^-1 H (21), H^T R^-1 z (6) and z^T R^-1 z, R^-1 a per-pixel weight.
 // One pixel per lane for 8x8 and 16x16 tiles, two for 32x32; the splats and
 // their tangent records are staged in chunks of up to 256.
-template <int CH, int NQ>
+template <int CH, int NQ, int NWV>
 struct TanStage {
     float4 p0[CH];
     float4 p1[CH];
     float p2[CH];
     uint32_t gid[CH];
     float4 t[NQ][CH];
+    uint8_t wl[NWV][CH];  // per wave: the entries that reach its region
 };
 
 template <int TS, int NW, bool SHC>
@@ -776,7 +815,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
     constexpr int PPL = G::PPL;
     constexpr int CH = G::BS < 256 ? G::BS : 256;
     constexpr int STRIDE = SHC ? kTangentSH : kTangent;
-    __shared__ TanStage<CH, STRIDE / 4> st;
+    __shared__ TanStage<CH, STRIDE / 4, NW> st;
     __shared__ double s_nrm[NW][kNrm];
     const int t = (int)blockIdx.x;
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, t);
@@ -786,13 +825,12 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
     const float amin = a.o.alpha_min, amax = a.o.alpha_max, Tmin = a.o.T_min;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
+    // T < 0 marks a finished pixel, as in the forward walk
     float T[PPL], C0[PPL], C1[PPL], C2[PPL], fy[PPL], dT[PPL][6], dC[PPL][3][6];
-    bool done[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        T[k] = 1.f;
+        T[k] = ti.inside(k) ? 1.f : -1.f;
         C0[k] = C1[k] = C2[k] = 0.f;
-        done[k] = !ti.inside(k);
         fy[k] = (float)(ti.py0 + k * G::RSTEP) + 0.5f;
 #pragma unroll
         for (int j = 0; j < 6; j++) {
@@ -803,7 +841,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
     auto open = [&]() {
         bool o = false;
 #pragma unroll
-        for (int k = 0; k < PPL; k++) o |= !done[k];
+        for (int k = 0; k < PPL; k++) o |= T[k] > 0.f;
         return o;
     };
     for (uint32_t start = ti.rs; start < ti.re; start += CH) {
@@ -822,10 +860,11 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
         }
         __syncthreads();
         const int n = (int)min((uint32_t)CH, ti.re - start);
-        for (int j = 0; j < n; j++) {
+        const int nl = G::ONE_BAND ? wave_list<TS, NW, CH>(st, n, wv, lane) : n;
+        for (int jj = 0; jj < nl; jj++) {
             if (!__any(open())) break;
+            const int j = G::ONE_BAND ? __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]) : jj;
             const uint32_t val = __builtin_amdgcn_readfirstlane(st.gid[j]);
-            if (G::ONE_BAND && !in_band<TS, NW>(val, wv, 0)) continue;
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
@@ -837,12 +876,13 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
             for (int k = 0; k < PPL; k++) {
                 if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
-                const bool hit = !done[k] && e.alpha >= amin;
+                const bool hit = e.alpha >= amin;
                 const float Tn = T[k] * (1.f - e.alpha);
-                const bool stop = hit && Tn < Tmin;
-                const bool acc = hit && !stop;
-                done[k] = done[k] || stop;
-                if (!__any(acc)) continue;
+                const bool acc = hit && Tn >= Tmin;  // false for a finished pixel
+                if (!__any(acc)) {
+                    T[k] = hit ? -fabsf(T[k]) : T[k];
+                    continue;
+                }
                 // a contributor moves the state; others act as alpha = 0, dalpha = 0
                 const float al = acc ? e.alpha : 0.f;
                 const float sg = (acc && e.s < amax) ? e.alpha : 0.f;  // dalpha = sg * dpower
@@ -886,7 +926,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
                 C0[k] = fmaf(wgt, p1.z, C0[k]);
                 C1[k] = fmaf(wgt, p1.w, C1[k]);
                 C2[k] = fmaf(wgt, cb, C2[k]);
-                T[k] = acc ? Tn : Tk;
+                T[k] = acc ? Tn : (hit ? -fabsf(Tk) : Tk);
             }
         }
         __syncthreads();
@@ -900,7 +940,8 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
         if (!ti.inside(k)) continue;
         const int64_t off = ti.off(k);
         // the same expression as the forward kernels, so the colour matches theirs bit for bit
-        const float I[3] = {C0[k] + T[k] * a.o.bg[0], C1[k] + T[k] * a.o.bg[1], C2[k] + T[k] * a.o.bg[2]};
+        const float Tf = fabsf(T[k]);
+        const float I[3] = {C0[k] + Tf * a.o.bg[0], C1[k] + Tf * a.o.bg[1], C2[k] + Tf * a.o.bg[2]};
         float Jp[3][6];
 #pragma unroll
         for (int ch = 0; ch < 3; ch++)
