@@ -605,3 +605,50 @@ def test_rasterize_autograd():
     np.testing.assert_allclose(params[0].grad.cpu().numpy().T, gg["mean"], rtol=1e-5,
                                atol=1e-6 * np.abs(gg["mean"]).max())
     np.testing.assert_allclose(pose.grad.cpu().numpy(), gg["pose"], rtol=1e-5, atol=1e-9)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("variant", [0, 4, 2])
+def test_window_step_bins_equal_bin_sort(variant, use_graph):
+    """Whatever the fused variant, the window step leaves bins bit-identical
+    to gsl_bin_sort's for the same projection."""
+    O = ops()
+    ctx = context()
+    sc = _scene_multi(5000, 61)
+    tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda")
+    w = _window(sc, tgt, 16, "l1")
+    w.set_variant(variant)
+    for _ in range(2):
+        w.step(use_graph=use_graph)
+    torch.cuda.synchronize()
+    assert w.status() == 0
+    proj = O.project(ctx, w.g, w.cams, w.opts)
+    b = O.bin_sort(ctx, w.cams, w.g.N, w.opts, proj, capacity=w.bins.capacity, grow=False)
+    torch.cuda.synchronize()
+    K = b.K
+    assert w.bins.K == K
+    assert torch.equal(w.bins.tile_ids[:K], b.tile_ids[:K])
+    assert torch.equal(w.bins.gauss_ids[:K], b.gauss_ids[:K])
+    assert torch.equal(w.bins.ranges, b.ranges)
+
+
+def test_window_step_capacity_overflow():
+    """A capacity below the instance count: the window step reports
+    GSL_ECAPACITY through the status word and runs to the end; with enough
+    capacity the graph path succeeds."""
+    O = ops()
+    sc = _scene_multi(5000, 62)
+    tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda")
+    w = _window(sc, tgt, 16, "l1")
+    w.step(use_graph=False)
+    torch.cuda.synchronize()
+    K = w.bins.K
+    for cap in (K // 3, (2 * K) // 3, K - 1):
+        w2 = O.Window(w.ctx, w.g, w.cams, w.opts, tgt, loss="l1", capacity=max(cap, 1))
+        w2.step(use_graph=False)
+        torch.cuda.synchronize()
+        assert w2.status() == O.A.GSL_ECAPACITY, cap
+    w3 = O.Window(w.ctx, w.g, w.cams, w.opts, tgt, loss="l1", capacity=K)
+    w3.step(use_graph=True)
+    torch.cuda.synchronize()
+    assert w3.status() == 0 and w3.bins.K == K
