@@ -231,7 +231,8 @@ def test_sliding_window_update_and_adam_on_capacity_layout(oracle):
         made = {}
 
         def fetch(add_vox):
-            ak = np.repeat(add_vox.numpy().view(np.uint64), 3)
+            made["vox"] = add_vox.numpy().view(np.uint64).copy()
+            ak = np.repeat(made["vox"], 3)
             ar = rng.normal(size=(R_ROWS, len(ak))).astype(np.float32)
             ar[14:] = 0.0
             made["k"], made["r"] = ak, ar
@@ -239,8 +240,12 @@ def test_sliding_window_update_and_adam_on_capacity_layout(oracle):
 
         ek, er = sw.update(torch.from_numpy(frames[f]).cuda(), fetch)
         torch.cuda.synchronize()
+        # the oracle's own classification decides its side; the GPU's ADD list must equal it
         pk, pok = oracle.voxel_key(frames[f], vs)
-        win_keys, win_rows, ek_w, er_w = oracle.window_maintain(win_keys, win_rows, pk[pok], made["k"], made["r"])
+        _, add_o = oracle.window_classify(win_keys, pk, pok)
+        assert np.array_equal(made["vox"], add_o)
+        win_keys, win_rows, ek_w, er_w = oracle.window_maintain(win_keys, win_rows, pk[pok], np.repeat(add_o, 3),
+                                                                made["r"])
         assert sw.n == len(win_keys)
         assert np.array_equal(_u64(sw.keys[:sw.n]), win_keys)
         assert np.array_equal(sw.block[:, :sw.n].cpu().numpy().view(np.uint32), win_rows.view(np.uint32))

@@ -8,6 +8,12 @@
   the gradient of a sparse cotangent against the oracle.
 * 2M surfels, 16 cameras 320x256 .. 1920x1080: sampled pixels against the
   oracle, and the batched window step against per-camera steps.
+* the benchmark's launch configuration (500k, 8 x 1280x1024, tile 32, fused
+  window step replayed as a graph): its image equals gsl_render_fwd's bit for
+  bit and its gradients equal gsl_render_bwd's with the loss cotangent; the
+  same window with SH degree 3 colour on sampled pixels against the oracle.
+* the window update at its benchmark size (500k Gaussians, 100k points per
+  frame), two frames, bit for bit against the oracle.
 """
 import numpy as np
 import pytest
@@ -173,3 +179,87 @@ def test_uneven_batch_window_vs_per_camera(uneven):
         del w1
     assert abs(loss - float(w.d_loss.item())) <= 1e-6 * abs(loss)
     torch.testing.assert_close(tot_mean, w.grads.mean, rtol=1e-4, atol=1e-5 * float(tot_mean.abs().max()))
+
+
+def test_bench_window_step_is_the_separate_path():
+    """The fused tile-32 window step (graph) at the benchmark size: the image
+    it keeps equals gsl_render_fwd's bit for bit, and its L2-loss gradients
+    are gsl_render_bwd's for the cotangent image - target.  Both add float32
+    2D gradients with atomics in run-dependent order, up to thousands of adds
+    per record at this size: 1e-4 of each tensor's largest entry (measured
+    4e-5 on the scales), 1e-3 per large element."""
+    O = ops()
+    ctx = context()
+    sc, tgt_sc = S.config3()
+    cs = O.CameraSet(sc.cams)
+    g = O.Gaussians.from_scene(sc)
+    target = gpu_forward(tgt_sc, sc.cams, tile=32)["image"]
+    w = O.Window(ctx, g, cs, O.opts(32), target, loss="l2", keep_image=True)
+    for _ in range(2):
+        w.step(use_graph=True)
+    torch.cuda.synchronize()
+    assert w.status() == 0
+    st = gpu_forward(sc, sc.cams, tile=32)
+    assert torch.equal(w.image, st["image"])
+    gg = gpu_backward(st, (st["image"] - target).contiguous())
+    got = {"mean": w.grads.mean.cpu().numpy().T, "scale": w.grads.scale.cpu().numpy().T,
+           "quat": w.grads.quat.cpu().numpy().T, "opacity": w.grads.opacity.cpu().numpy(),
+           "color": w.grads.color.cpu().numpy().T, "pose": w.grads.pose.cpu().numpy()}
+    compare_grads(got, gg, rel=1e-4, keys=("mean", "scale", "quat", "opacity", "color", "pose"), elem_rel=1e-3,
+                  name="bench window")
+
+
+def test_bench_window_sh3_sampled(oracle):
+    """The benchmark window with SH degree 3 colour at tile 32: sampled
+    pixels of every keyframe against the oracle."""
+    sc, _ = S.config3()
+    sc = S.with_sh(sc, 3, 33)
+    st = gpu_forward(sc, sc.cams, tile=32)
+    imgs = unpack_np(st["cams"], st["image"])
+    rng = np.random.default_rng(7)
+    cm = max(float(np.abs(oracle.sh_colour(sc, c)).max()) for c in sc.cams)
+    for c, cam in enumerate(sc.cams):
+        pix = _sample(cam, 32, rng)
+        r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
+        got = imgs[c][:, pix[:, 1], pix[:, 0]].T
+        assert np.all(np.abs(got - r["rgb"]).max(1) <= pixel_tolerance(r["flags"], cmax=cm)), c
+
+
+def test_window_update_bench_size(oracle):
+    """Two frames of the benchmark's window update (500k Gaussians x 42 rows,
+    capacity 2^20, 100k points, 0.5 m voxels), bit for bit against the oracle."""
+    O = ops()
+    ctx = context()
+    n, P, cap, vs, R = 500_000, 100_000, 1 << 20, 0.5, 42
+    frames, means = S.lidar_stream(71, 3, P, n)
+    k, ok = oracle.voxel_key(means, vs)
+    win_keys = np.where(ok, k, np.uint64(0xFFFFFFFFFFFFFFFF))
+    win_rows = np.random.default_rng(72).normal(size=(R, n)).astype(np.float32)
+    sw = O.SlidingWindow(ctx, cap, vs)
+    sw.keys[:n] = O.voxel_keys(ctx, torch.from_numpy(means).cuda(), vs)
+    sw.block[:, :n] = torch.from_numpy(win_rows).cuda()
+    sw.n = n
+    for f in (1, 2):
+        rng = np.random.default_rng(100 + f)
+        made = {}
+
+        def fetch(add_vox):
+            made["vox"] = add_vox.numpy().view(np.uint64).copy()
+            ak = np.repeat(made["vox"], 15)
+            ar = rng.normal(size=(R, len(ak))).astype(np.float32)
+            made["k"], made["r"] = ak, ar
+            return torch.from_numpy(ak.view(np.int64).copy()), torch.from_numpy(ar)
+
+        ek, er = sw.update(torch.from_numpy(frames[f]).cuda(), fetch)
+        torch.cuda.synchronize()
+        # the oracle's own classification decides its side; the GPU's ADD list must equal it
+        pk, pok = oracle.voxel_key(frames[f], vs)
+        _, add_o = oracle.window_classify(win_keys, pk, pok)
+        assert np.array_equal(made["vox"], add_o)
+        win_keys, win_rows, ek_w, er_w = oracle.window_maintain(win_keys, win_rows, pk[pok], np.repeat(add_o, 15),
+                                                                made["r"])
+        assert sw.n == len(win_keys)
+        assert np.array_equal(sw.keys[:sw.n].cpu().numpy().view(np.uint64), win_keys)
+        assert np.array_equal(sw.block[:, :sw.n].cpu().numpy().view(np.uint32), win_rows.view(np.uint32))
+        assert np.array_equal(ek.cpu().numpy().view(np.uint64), ek_w)
+        assert np.array_equal(er.cpu().numpy().view(np.uint32), er_w.view(np.uint32))
