@@ -402,13 +402,14 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
 }
 
 __global__ void k_ranges(const uint32_t *__restrict__ tile_ids, const int64_t *__restrict__ d_K, int64_t capacity,
-                         uint32_t *__restrict__ ranges)
+                         int64_t T_total, uint32_t *__restrict__ ranges)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t K = *d_K;
     if (K > capacity) return;
     if (k >= K) return;
     const uint32_t t = tile_ids[k];
+    if ((int64_t)t >= T_total) return;  // never trust an id as an index
     if (k == 0 || tile_ids[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
     if (k == K - 1 || tile_ids[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
 }
@@ -517,7 +518,7 @@ void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacit
     launch_fill_u32(ranges, 0u, 2 * T_total, s);
     if (capacity > 0)
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s, tile_ids, d_K,
-                           capacity, ranges);
+                           capacity, T_total, ranges);
 }
 
 }  // namespace gsl
