@@ -356,8 +356,8 @@ GSL_API int gsl_color_init(gsl_ctx *ctx, const float *mean, int64_t mean_ld, int
  * defined for indices in [-2^20, 2^20).  Its parameters are R rows of 4-byte
  * words at a row stride ld (a capacity): row r of Gaussian i at
  * rows[r * ld + i].  Raw parameters and Adam moments allocated as one
- * [42][ld] block (raw, m, v of a gsl_adam_state with that ld) are moved by
- * one call. */
+ * [3 (14 + 3K)][ld] block (raw, m, v of a gsl_adam_state with that ld; 42
+ * rows without SH colour) are moved by one call. */
 
 /* keys[i] <- the voxel key of point i, whose coordinates are
  * xyz[i * point_stride + a * axis_stride], a = 0, 1, 2 (device float; [P][3]
@@ -369,9 +369,10 @@ GSL_API int gsl_voxel_keys(gsl_ctx *ctx, const float *xyz, int32_t P, int64_t po
                            float voxel_size, uint64_t *keys, void *stream);
 
 /* Workspace bytes for gsl_window_classify / gsl_window_compact with a window
- * of n Gaussians and a frame of P points: a hash table of 16 B per slot
- * (the smallest power of two >= max(1024, 2P)), 12 B per point, 12 B per
- * window Gaussian and the scan partials. */
+ * of n Gaussians and a frame of P points (P <= 2^28): a hash table of 16 B
+ * per slot (the smallest power of two >= max(1024, 2P)), 12 B per point,
+ * 12 B per window Gaussian and the scan partials.  The workspace must be
+ * 256-byte aligned. */
 GSL_API int gsl_window_workspace_size(int32_t n, int32_t P, size_t *bytes);
 
 /* Steps 1 and 3.  points: device float [P][3] world coordinates of the
@@ -390,8 +391,9 @@ GSL_API int gsl_window_classify(gsl_ctx *ctx, const float *points, int32_t P, fl
                                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* Steps 2 and 4, in place, after gsl_window_classify on the same workspace
- * with the same n.  D is the DELETE count that call wrote (read back by the
- * caller).  In stream order:
+ * with the same n.  keys: device uint64[ld]; rows: device float [R][ld]
+ * (R may be 0: keys only).  D is the DELETE count that call wrote (read back
+ * by the caller).  In stream order:
  *   1. the DELETE Gaussians are gathered, in window order, into
  *      evicted_keys uint64[D] and evicted_rows float[R][D] (row stride D);
  *      either may be NULL (not written);
