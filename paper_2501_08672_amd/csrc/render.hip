@@ -40,7 +40,12 @@ namespace gsl {
 
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
+// Staged splats hold L' = kPowScale L (L the Cholesky factor of the conic)
+// and log2 of the opacity, so that sigma exp(-|L d|^2 / 2) is one exp2 of
+// log2(sigma) - |L' d|^2.  kPowScale^2 = log2(e) / 2; conic terms built from
+// L' are scaled back by kPowScaleInv2 = 1 / kPowScale^2 = 2 ln 2.
+constexpr float kPowScale = 0.84932180028801904f;
+constexpr float kPowScaleInv2 = 1.3862943611198906f;
 
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -235,12 +240,24 @@ __device__ __forceinline__ TileInfo<TS, NW> tile_info(const RenderArgs &a, int t
 
 template <int CH>
 struct Stage {
-    float4 p0[CH];  // mx, my, l11, l12
-    float4 p1[CH];  // l22, opacity, r, g
+    float4 p0[CH];  // mx, my, l11', l12'  (factor scaled by kPowScale)
+    float4 p1[CH];  // l22', log2(opacity), r, g
     float p2[CH];   // b
     uint32_t gid[CH];  // Gaussian index | band mask << 28
     uint8_t wl[CH / kWave][CH];  // per wave: the chunk entries that reach its region, in order
 };
+
+// A projection record (mx, my, l11, l12 | l22, opacity, r, g | b ...) in the
+// staged form that eval_pair reads.
+__device__ __forceinline__ void stage_splat(const float4 *__restrict__ r4, float4 &p0, float4 &p1)
+{
+    p0 = r4[0];
+    p1 = r4[1];
+    p0.z *= kPowScale;
+    p0.w *= kPowScale;
+    p1.x *= kPowScale;
+    p1.y = log2f(p1.y);
+}
 
 template <int CH>
 __device__ __forceinline__ void stage_load(Stage<CH> &st, const RenderArgs &a, const gsl_splat *__restrict__ rec,
@@ -249,8 +266,7 @@ __device__ __forceinline__ void stage_load(Stage<CH> &st, const RenderArgs &a, c
     if (k < end) {
         const uint32_t val = a.gauss_ids[k];
         const float4 *r4 = reinterpret_cast<const float4 *>(rec + (val & kGidMask));
-        st.p0[threadIdx.x] = r4[0];
-        st.p1[threadIdx.x] = r4[1];
+        stage_splat(r4, st.p0[threadIdx.x], st.p1[threadIdx.x]);
         st.p2[threadIdx.x] = r4[2].x;
         st.gid[threadIdx.x] = val;
     }
@@ -269,19 +285,20 @@ __device__ __forceinline__ bool in_band(uint32_t val, int w, int k)
 // compiled without floating-point contraction and the fused multiply-adds are
 // explicit — so the backward reproduces the forward's alpha bit for bit and
 // the result does not depend on the tile size or the lane layout.
+// With the staged form (ax = l11' dx): s = sigma G = exp2(log2 sigma - t1'^2 - t2'^2),
+// t1' = l11' dx + l12' dy, t2' = l22' dy.
 struct PairEval {
-    float dy, t1, t2, G, s, alpha;
+    float dy, s, alpha;
 };
 
 __device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1, float ax, float fy, float amax)
 {
     PairEval e;
     e.dy = fy - p0.y;
-    e.t1 = fmaf(p0.w, e.dy, ax);
-    e.t2 = p1.x * e.dy;
-    const float q = fmaf(e.t1, e.t1, e.t2 * e.t2);
-    e.G = __builtin_amdgcn_exp2f(q * (-0.5f * kLog2e));
-    e.s = p1.y * e.G;
+    const float t1 = fmaf(p0.w, e.dy, ax);
+    const float t2 = p1.x * e.dy;
+    const float lg = fmaf(-t1, t1, fmaf(-t2, t2, p1.y));
+    e.s = __builtin_amdgcn_exp2f(lg);
     e.alpha = fminf(amax, e.s);
     return e;
 }
@@ -522,8 +539,9 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
             // Per lane: gp = dL/dpower of each pixel; the lane's pixels share
             // dx, so the 2D-mean and conic gradients need only P = sum gp,
             // Q = sum gp dy and R = sum gp dy^2 (t1 = l11 dx + l12 dy,
-            // t2 = l22 dy, power = -(t1^2 + t2^2) / 2).
-            float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gop = 0.f, P = 0.f, Q = 0.f, R = 0.f;
+            // t2 = l22 dy, power = -(t1^2 + t2^2) / 2).  dalpha/dsigma = G =
+            // s / sigma, so the opacity gradient is P / sigma.
+            float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, P = 0.f, Q = 0.f, R = 0.f;
             bool used = false;
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
@@ -546,7 +564,6 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
                 SV[k] = fmaf(w, vc, SV[k]);
                 // alpha is clamped where sigma G >= alpha_max: no gradient to sigma, G
                 const float gam = (hit && e.s < amax) ? ga : 0.f;
-                gop = fmaf(e.G, gam, gop);
                 const float gp = e.s * gam;
                 const float hy = gp * e.dy;
                 P += gp;
@@ -555,13 +572,13 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
             }
             if (used) {
                 float g[kG2];
-                const float u = fmaf(ax, P, p0.w * Q);  // sum of gp t1
-                g[0] = p0.z * u;
-                g[1] = fmaf(p0.w, u, p1.x * (p1.x * Q));
+                const float u = fmaf(ax, P, p0.w * Q);  // kPowScale * sum of gp t1
+                g[0] = kPowScaleInv2 * (p0.z * u);
+                g[1] = kPowScaleInv2 * fmaf(p0.w, u, p1.x * (p1.x * Q));
                 g[2] = -0.5f * (dx * dx) * P;
                 g[3] = -dx * Q;
                 g[4] = -0.5f * R;
-                g[5] = gop;
+                g[5] = P * __builtin_amdgcn_exp2f(-p1.y);
                 g[6] = gc0;
                 g[7] = gc1;
                 g[8] = gc2;
@@ -850,8 +867,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
             const uint32_t val = a.gauss_ids[start + threadIdx.x];
             const uint32_t gi = val & kGidMask;
             const float4 *r4 = reinterpret_cast<const float4 *>(rec + gi);
-            st.p0[threadIdx.x] = r4[0];
-            st.p1[threadIdx.x] = r4[1];
+            stage_splat(r4, st.p0[threadIdx.x], st.p1[threadIdx.x]);
             st.p2[threadIdx.x] = r4[2].x;
             st.gid[threadIdx.x] = val;
             const float4 *t4 = reinterpret_cast<const float4 *>(tan + (int64_t)gi * STRIDE);
@@ -870,8 +886,9 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
             const float cb = st.p2[j];
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
-            // conic (A, B, C) = L^T L from the Cholesky factor (l11, l12; 0, l22)
-            const float cA = p0.z * p0.z, cB = p0.z * p0.w, cC = fmaf(p0.w, p0.w, p1.x * p1.x);
+            // conic (A, B, C) = L^T L from the staged factor (l11', l12'; 0, l22')
+            const float cA = kPowScaleInv2 * (p0.z * p0.z), cB = kPowScaleInv2 * (p0.z * p0.w),
+                        cC = kPowScaleInv2 * fmaf(p0.w, p0.w, p1.x * p1.x);
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
                 if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;
