@@ -61,11 +61,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__
 {
     __shared__ uint64_t s[kScanThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    uint64_t acc = 0;
+    uint32_t v[kScanItems];  // all loads in flight before the first add
+#pragma unroll
     for (int k = 0; k < kScanItems; k++) {
         const int64_t j = base + (int64_t)k * kScanThreads + threadIdx.x;
-        if (j < n) acc += in[j];
+        v[k] = j < n ? in[j] : 0u;
     }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) acc += v[k];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if ((threadIdx.x & 63) == 0) s[threadIdx.x / kWave] = acc;
     __syncthreads();
@@ -173,9 +177,16 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__rest
     const uint32_t dmask = (1u << db) - 1u;
     const int64_t n = live_count(d_n, n_max);
     const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wv * (kSortTile / (kSortThreads / kWave));
+    uint32_t kk[kSortItems];  // all loads in flight before the first ballot
+#pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
-        const uint32_t kj = j < n ? keys[j] : kDropKey;
+        kk[r] = j < n ? keys[j] : kDropKey;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t j = base + (int64_t)r * kWave + lane;
+        const uint32_t kj = kk[r];
         const bool valid = j < n && !(drop && kj == kDropKey);
         const uint32_t d = valid ? (kj >> shift) & dmask : 0u;
         const uint64_t peers = digit_peers(d, valid, db);
@@ -213,11 +224,17 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     if (block_base >= n) return;
     const int64_t base = block_base + (int64_t)wv * (kSortTile / NW);
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
-    for (int r = 0; r < kSortItems; r++) {
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {  // all loads in flight before the first ballot
         const int64_t j = base + (int64_t)r * kWave + lane;
         key[r] = j < n ? kin[j] : kDropKey;
+        val[r] = j < n ? vin[j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t j = base + (int64_t)r * kWave + lane;
         const bool valid = j < n && !(drop && key[r] == kDropKey);
-        val[r] = valid ? vin[j] : 0u;
+        if (!valid) val[r] = 0u;
         const uint32_t d = (key[r] >> shift) & dmask;
         const uint64_t peers = digit_peers(d, valid, db);
         const uint32_t before = valid ? s_cnt[wv][d] : 0u;
