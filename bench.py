@@ -52,8 +52,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=320, help="oracle sample: pixels per camera")
@@ -95,6 +95,23 @@ def read_traffic():
         return None
 
 
+def copy_peak_gbs(torch, mib=1024, reps=10):
+    """HBM bandwidth a plain device copy reaches on this GPU: bytes read plus
+    written per second (HIP events around `reps` copies of `mib` MiB)."""
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def cpu_baseline(sc, cams, per_cam, seed=0):
     """The FP64 oracle, as it stands, on `per_cam` seeded pixels of every camera."""
     from oracle import oracle as O
@@ -113,8 +130,16 @@ def cpu_baseline(sc, cams, per_cam, seed=0):
     O.render_bwd(sc, cams, vs, o, pixels=pix)
     t2 = time.perf_counter()
     n = per_cam * len(cams)
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(n / (t2 - t0) / 1e6, 6), "unit": "Mpixels/s", "cores": O.num_threads(),
-            "kind": "oracle",
+            "cpu_model": cpu, "kind": "oracle",
             "sample": f"{per_cam} seeded pixels per camera x {len(cams)} cameras of the same window; forward "
                       f"{t1 - t0:.2f} s + backward (random cotangent on those pixels) {t2 - t1:.2f} s; each call "
                       f"projects and depth-orders all {sc.n} Gaussians"}
@@ -458,6 +483,9 @@ def main():
         log(f"per-frame plain launches {t_pf * 1e3:.3f} ms per window ({P / t_pf / 1e6:.1f} Mpix/s)")
         del frames
 
+    copy_gbs = copy_peak_gbs(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+
     optimize = None
     if not args.no_optimize:
         optimize = optimize_bench(ctx, ops, torch, g, win)
@@ -506,12 +534,15 @@ def main():
                      "traffic": None if traffic is None else int(traffic),
                      "kernel": "k_render_fused", "kernel_ms": round(fused_ms, 4),
                      "algorithmic_flops": int(flops),
-                     "pairs": {"fwd_evaluated": ev_f, "contributors": n_contrib, "bwd_evaluated": ev_b},
+                     "pairs": {"fwd_evaluated": ev_f, "contributors": n_contrib, "bwd_evaluated": ev_b,
+                               "fwd_per_pixel": round(ev_f / P, 2), "contributors_per_pixel": round(n_contrib / P, 2)},
                      "hbm_view": {"algorithmic_bytes": int(fused_bytes),
                                   "gbs": round(fused_bytes / (fused_ms * 1e-3) / 1e9, 1),
                                   "frac": round(fused_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
         "window_hbm": {"algorithmic_bytes": int(step_bytes),
-                       "frac": round(step_bytes / t_win / 1e9 / HBM_PEAK_GBS, 4)},
+                       "frac": round(step_bytes / t_win / 1e9 / HBM_PEAK_GBS, 4),
+                       "copy_peak_gbs": round(copy_gbs, 1),
+                       "frac_of_copy_peak": round(step_bytes / t_win / 1e9 / copy_gbs, 4)},
     }
     if optimize is not None:
         result["optimize"] = optimize
