@@ -397,9 +397,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
     if (K > capacity) return;  // uniform: every thread reads the same K
     uint32_t nt = 0;
     if (j < M) {
-        const uint32_t cnt = counts[j];
+        // three independent loads first (order[j] is only used where cnt != 0)
+        const uint32_t cnt = counts[j], m = order[j], off = offsets[j];
         if (cnt) {
-            const uint32_t m = order[j];
             const gsl_binrec s = binrecs[m];
             const uint32_t c = m / (uint32_t)N;
             nt = (uint32_t)bbox_tiles(s, tile);
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
                 push_big(big_list, big_n, (uint32_t)j);
                 nt = 0;
             } else {
-                rec_fill(rec[threadIdx.x], s, cams[c], tile, m - c * (uint32_t)N, offsets[j], cnt);
+                rec_fill(rec[threadIdx.x], s, cams[c], tile, m - c * (uint32_t)N, off, cnt);
             }
         }
     }
@@ -418,17 +418,39 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
     expand_tiles<true>(rec + (threadIdx.x & ~(kWave - 1)), lane, excl, incl, total, tile, tile_ids, gauss_ids);
 }
 
+// Four consecutive positions per thread: the ids at k0-1 .. k0+4 (a sentinel
+// outside [0, K), never equal to a valid id) mark where runs start and end.
+constexpr int kRangeItems = 4;
+
 __global__ void k_ranges(const uint32_t *__restrict__ tile_ids, const int64_t *__restrict__ d_K, int64_t capacity,
                          int64_t T_total, uint32_t *__restrict__ ranges)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t K = *d_K;
+    constexpr uint32_t kNone = 0xffffffffu;
+    const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+    const int64_t K = *d_K;
     if (K > capacity) return;
-    if (k >= K) return;
-    const uint32_t t = tile_ids[k];
-    if ((int64_t)t >= T_total) return;  // never trust an id as an index
-    if (k == 0 || tile_ids[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
-    if (k == K - 1 || tile_ids[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+    if (k0 >= K) return;
+    uint32_t t[kRangeItems + 2];
+    t[0] = k0 > 0 ? tile_ids[k0 - 1] : kNone;
+    if (k0 + kRangeItems <= K && (reinterpret_cast<uintptr_t>(tile_ids) & 15u) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(tile_ids + k0);
+        t[1] = v.x;
+        t[2] = v.y;
+        t[3] = v.z;
+        t[4] = v.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kRangeItems; q++) t[1 + q] = k0 + q < K ? tile_ids[k0 + q] : kNone;
+    }
+    t[kRangeItems + 1] = k0 + kRangeItems < K ? tile_ids[k0 + kRangeItems] : kNone;
+#pragma unroll
+    for (int q = 0; q < kRangeItems; q++) {
+        const uint32_t cur = t[1 + q];
+        if ((int64_t)cur >= T_total) continue;  // never trust an id as an index (also skips positions >= K)
+        const int64_t k = k0 + q;
+        if (t[q] != cur) ranges[2 * (int64_t)cur] = (uint32_t)k;
+        if (t[q + 2] != cur) ranges[2 * (int64_t)cur + 1] = (uint32_t)(k + 1);
+    }
 }
 
 }  // namespace
@@ -534,8 +556,8 @@ void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacit
 {
     launch_fill_u32(ranges, 0u, 2 * T_total, s);
     if (capacity > 0)
-        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s, tile_ids, d_K,
-                           capacity, T_total, ranges);
+        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((capacity + 256 * kRangeItems - 1) / (256 * kRangeItems))),
+                           dim3(256), 0, s, tile_ids, d_K, capacity, T_total, ranges);
 }
 
 }  // namespace gsl
