@@ -149,14 +149,18 @@ __device__ __forceinline__ int64_t live_count(const int64_t *d_n, int64_t n_max)
     return n < n_max ? n : n_max;
 }
 
-// Mask of the lanes of this wave whose digit equals this lane's digit.
+// Mask of the lanes of this wave whose digit equals this lane's digit: per
+// bit, the ballot of lanes with the bit set, taken as is where this lane's
+// bit is set and complemented where it is clear (xnor with the bit spread
+// over the word by a signed one-bit extract).
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int db)
 {
-    uint64_t peers = __ballot(valid);
+    uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
     for (int b = 0; b < db; b++) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);  // 0 or all ones
+        const uint64_t m = __builtin_amdgcn_ballot_w64(sb != 0u);
+        const uint64_t s2 = ((uint64_t)sb << 32) | sb;
+        peers &= ~(m ^ s2);
     }
     return peers;
 }
@@ -188,9 +192,8 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__rest
         const int64_t j = base + (int64_t)r * kWave + lane;
         const uint32_t kj = kk[r];
         const bool valid = j < n && !(drop && kj == kDropKey);
-        const uint32_t d = valid ? (kj >> shift) & dmask : 0u;
-        const uint64_t peers = digit_peers(d, valid, db);
-        if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) s_cnt[wv][d] += __popcll(peers);
+        // the counts do not depend on the order of the adds
+        if (valid) atomicAdd(&s_cnt[wv][(kj >> shift) & dmask], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < (1 << db); d += kSortThreads) {
