@@ -1,10 +1,10 @@
 // Projection of 3D Gaussians into the cameras of a window and its adjoint.
 //
 // Forward (Sec. II-B, eqs. equ:3dgs, equ:q, equ:spat): one lane per
-// (camera, Gaussian).  The arithmetic is float64 — CDNA4 runs it at half the
-// float32 rate and this kernel is bound by its 44 B in / 52 B out per lane —
-// so the float32 splat it stores carries a correctly rounded mean and conic
-// factor even for the thin, grazing surfels a LiDAR map produces.
+// (camera, Gaussian).  The arithmetic is float64 (CDNA4 issues it at the
+// rate of non-packed float32), so the float32 splat it stores carries a
+// correctly rounded mean and conic factor even for the thin, grazing
+// surfels a LiDAR map produces.
 //
 // Sigma2D is formed as P P^T + eps I with P = (J W) R diag(s), the product of
 // the pinhole Jacobian J, the camera rotation W = R_cw and the Gaussian's
@@ -67,13 +67,37 @@ __device__ __forceinline__ void quat_rot(const double q[4], double R[9])
     R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+// The camera-independent part of a Gaussian: world mean, normalised
+// quaternion and its rotation, scale.
+struct GaussLocal {
+    double px, py, pz;
+    double qn[4], qlen;
+    double Rg[9];
+    double s[3];
+};
+
+__device__ __forceinline__ void load_gauss(const float *__restrict__ mean, const float *__restrict__ scale,
+                                           const float *__restrict__ quat, int N, int i, GaussLocal &gl)
+{
+    gl.px = mean[i];
+    gl.py = mean[N + i];
+    gl.pz = mean[2 * N + i];
+    double q[4] = {quat[i], quat[N + i], quat[2 * N + i], quat[3 * N + i]};
+    gl.qlen = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double il = 1.0 / gl.qlen;
+    for (int k = 0; k < 4; k++) gl.qn[k] = q[k] * il;
+    quat_rot(gl.qn, gl.Rg);
+    gl.s[0] = scale[i];
+    gl.s[1] = scale[N + i];
+    gl.s[2] = scale[2 * N + i];
+}
+
 // Returns false when the Gaussian is behind the near plane (only x, y, z are
 // valid then).
-__device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, const float *__restrict__ scale,
-                                             const float *__restrict__ quat, int N, int i, const DevCam &cam,
-                                             float eps2d, float near_z, Proj &p)
+__device__ __forceinline__ bool project_cam(const GaussLocal &gl, const DevCam &cam, float eps2d, float near_z,
+                                            Proj &p)
 {
-    const double px = mean[i], py = mean[N + i], pz = mean[2 * N + i];
+    const double px = gl.px, py = gl.py, pz = gl.pz;
     for (int k = 0; k < 9; k++) p.W[k] = cam.R[k];
     p.x = p.W[0] * px + p.W[1] * py + p.W[2] * pz + (double)cam.t[0];
     p.y = p.W[3] * px + p.W[4] * py + p.W[5] * pz + (double)cam.t[1];
@@ -89,14 +113,10 @@ __device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, con
         p.M[k] = fx * iz * (p.W[k] - ux * p.W[6 + k]);
         p.M[3 + k] = fy * iz * (p.W[3 + k] - uy * p.W[6 + k]);
     }
-    double q[4] = {quat[i], quat[N + i], quat[2 * N + i], quat[3 * N + i]};
-    p.qlen = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const double il = 1.0 / p.qlen;
-    for (int k = 0; k < 4; k++) p.qn[k] = q[k] * il;
-    quat_rot(p.qn, p.Rg);
-    p.s[0] = scale[i];
-    p.s[1] = scale[N + i];
-    p.s[2] = scale[2 * N + i];
+    p.qlen = gl.qlen;
+    for (int k = 0; k < 4; k++) p.qn[k] = gl.qn[k];
+    for (int k = 0; k < 9; k++) p.Rg[k] = gl.Rg[k];
+    for (int k = 0; k < 3; k++) p.s[k] = gl.s[k];
     for (int r = 0; r < 2; r++)
         for (int k = 0; k < 3; k++) {
             const double mr = p.M[3 * r] * p.Rg[k] + p.M[3 * r + 1] * p.Rg[3 + k] + p.M[3 * r + 2] * p.Rg[6 + k];
@@ -107,6 +127,15 @@ __device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, con
     p.c = p.P[3] * p.P[3] + p.P[4] * p.P[4] + p.P[5] * p.P[5] + (double)eps2d;
     p.det = p.a * p.c - p.b * p.b;
     return true;
+}
+
+__device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, const float *__restrict__ scale,
+                                             const float *__restrict__ quat, int N, int i, const DevCam &cam,
+                                             float eps2d, float near_z, Proj &p)
+{
+    GaussLocal gl;
+    load_gauss(mean, scale, quat, N, i, gl);
+    return project_cam(gl, cam, eps2d, near_z, p);
 }
 
 // Also counts the tiles each splat's alpha_min ellipse reaches (tiles_touched)
@@ -360,6 +389,12 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
 
     double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0, gc[3] = {0, 0, 0};
+    GaussLocal gl;  // once per Gaussian, not per camera
+    double iql = 0.0;
+    if (valid) {
+        load_gauss(mean, scale, quat, N, i, gl);
+        iql = 1.0 / gl.qlen;
+    }
     for (int c = 0; c < C; c++) {
         double pose[6] = {0, 0, 0, 0, 0, 0};
         bool any = false;
@@ -374,7 +409,7 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
         if (any) {
             const DevCam cam = cams[c];
             Proj p;
-            compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
+            project_cam(gl, cam, o.eps2d, o.near_z, p);
             gop += g2[5];
             gc[0] += g2[6]; gc[1] += g2[7]; gc[2] += g2[8];
             // conic (A, B, C) = Sigma2D^{-1};  dL/dSigma2D = -Q Gq Q with
@@ -421,7 +456,7 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
                 double dz = 2.0 * (-2.0 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.0 * z * G[4] + y * G[5] +
                                    x * G[6] + y * G[7]);
                 const double dot = dw * w + dx * x + dy * y + dz * z;
-                const double il = 1.0 / p.qlen;
+                const double il = iql;
                 gq[0] += (dw - w * dot) * il;
                 gq[1] += (dx - x * dot) * il;
                 gq[2] += (dy - y * dot) * il;
