@@ -395,16 +395,20 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
         load_gauss(mean, scale, quat, N, i, gl);
         iql = 1.0 / gl.qlen;
     }
+    // the next camera's 2D gradients are loaded while this camera's are chained
+    float g2n[kG2];
+    for (int k = 0; k < kG2; k++) g2n[k] = valid && C > 0 ? g2d[(int64_t)i * kG2 + k] : 0.f;
     for (int c = 0; c < C; c++) {
         double pose[6] = {0, 0, 0, 0, 0, 0};
         bool any = false;
         float g2[kG2];
-        if (valid) {
-            const float *src = g2d + ((int64_t)c * N + i) * kG2;
-            for (int k = 0; k < kG2; k++) {
-                g2[k] = src[k];
-                any |= g2[k] != 0.f;
-            }
+        for (int k = 0; k < kG2; k++) {
+            g2[k] = g2n[k];
+            any |= g2[k] != 0.f;
+        }
+        if (valid && c + 1 < C) {
+            const float *src = g2d + ((int64_t)(c + 1) * N + i) * kG2;
+            for (int k = 0; k < kG2; k++) g2n[k] = src[k];
         }
         if (any) {
             const DevCam cam = cams[c];
