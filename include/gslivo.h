@@ -261,9 +261,11 @@ GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
 GSL_API int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile,
                                int32_t variant);
 
-/* Profiling hook: while enabled, every eager (use_graph == 0) window step
- * records HIP events on its stream between its stages.  gsl_profile_read
- * waits for the last profiled step and writes up to n milliseconds:
+/* Profiling hook: while enabled, every window step records HIP events on its
+ * stream between its stages (a graph step launches a graph captured for
+ * profiling, cached beside the plain one, whose event-record nodes are these
+ * events).  gsl_profile_read waits for the last profiled step and writes up
+ * to n milliseconds:
  * [0] upload + project, [1] bin_sort, [2] the fused render launch,
  * [3] loss reduction + projection adjoint, [4] the whole step. */
 GSL_API int gsl_profile(gsl_ctx *ctx, int enable);

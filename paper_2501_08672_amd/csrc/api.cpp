@@ -781,11 +781,16 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
         do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, s, ctx->profile);
         return check_launch("gsl_window_step");
     }
-    const VariantKey gk =
+    VariantKey gk =
         window_graph_key(vk, variant, loss, g, target, proj, bins, image, d_loss, grads, workspace, opts, cams, C);
-    return graph_run(ctx, gk, s, [&](hipStream_t cs) {
-        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, cs);
+    // a profiled step is its own graph, with the stage events as event-record nodes
+    const bool timed = ctx->profile;
+    gk.v.push_back(timed ? 1 : 0);
+    const int rc = graph_run(ctx, gk, s, [&](hipStream_t cs) {
+        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, cs, timed);
     });
+    if (rc == GSL_OK && timed) ctx->ev_recorded = true;  // also when the graph came from the cache
+    return rc;
 }
 
 int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, int32_t variant)

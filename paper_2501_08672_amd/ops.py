@@ -650,12 +650,13 @@ class Window:
                                             self.ws.numel(), int(bool(use_graph)), _stream()))
         return self._losses
 
-    def profiled_step(self):
-        """One eager step with HIP events between its stages; returns the
-        milliseconds of (project, bin_sort, fused render, adjoint, total)."""
+    def profiled_step(self, graph: bool = False):
+        """One step (eager, or a replay of the profiling graph) with HIP events
+        between its stages; returns the milliseconds of (project, bin_sort,
+        fused render, adjoint, total)."""
         A.check(A.lib().gsl_profile(self.ctx.h, 1))
         try:
-            self.step(use_graph=False)
+            self.step(use_graph=graph)
             ms = (C.c_float * 5)()
             A.check(A.lib().gsl_profile_read(self.ctx.h, ms, 5))
         finally:

@@ -568,6 +568,31 @@ def test_window_graph_replay_and_variants():
     np.testing.assert_array_equal(w.image.cpu().numpy(), ref[3].cpu().numpy())
 
 
+def test_profiled_steps_time_the_same_work():
+    """The profiling hook on eager steps and on replays of the profiling
+    graph: five positive stage times whose first four add up to the fifth,
+    and the same image, loss and gradients as an unprofiled step."""
+    sc = _scene_multi(3000, 45)
+    tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda")
+    w = _window(sc, tgt, 16, "l1")
+    w.step(use_graph=True)
+    torch.cuda.synchronize()
+    ref = (w.image.clone(), float(w.d_loss.item()), w.grads.mean.clone(), w.grads.pose.clone())
+    for graph in (False, True, True):
+        ms = w.profiled_step(graph=graph)
+        torch.cuda.synchronize()
+        assert len(ms) == 5 and all(x > 0.0 for x in ms), ms
+        assert abs(sum(ms[:4]) - ms[4]) <= 1e-3 * ms[4] + 2e-3, ms
+        assert torch.equal(w.image, ref[0])
+        assert abs(float(w.d_loss.item()) - ref[1]) <= 1e-9 * abs(ref[1])
+        torch.testing.assert_close(w.grads.mean, ref[2], rtol=1e-5, atol=1e-6 * float(ref[2].abs().max()))
+        torch.testing.assert_close(w.grads.pose, ref[3], rtol=1e-5, atol=1e-6 * float(ref[3].abs().max()))
+    # the plain graph still runs unprofiled after the profiling graph
+    w.step(use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(w.image, ref[0])
+
+
 @pytest.mark.parametrize("tile", [16, 32])
 def test_window_variants_agree(tile):
     """Every fused-kernel variant (plain, persistent, longest first, both,
