@@ -1,13 +1,15 @@
 // Front-to-back alpha compositing (eq. eq:raster) and its hand-written
 // adjoint (eq. eq:gaussian_optimization), per (camera, tile) work item.
 //
-// Layout for wave64: a workgroup of NW waves owns one TS x TS tile; wave w
-// owns TS/NW rows of it and each lane owns PPL pixels of one column of that
-// strip (PPL = 4 for 16x16 tiles with one wave).  The tile's depth-ordered
-// instance list is staged through LDS in chunks of 64*NW splats (48 B each,
-// one lane loads one splat as three float4) and every lane walks the chunk
-// with broadcast LDS reads, evaluating its PPL pixels against each splat.
-// The walk ends for the wave as soon as none of its pixels is still open.
+// Layout for wave64: a workgroup of NW waves owns one TS x TS tile; each
+// wave owns a region of it (a 16x16 quadrant of a 32x32 tile, the whole of
+// a 16x16 or 8x8 tile) and each lane owns PPL pixels of one column of that
+// region (PPL = 4, or 1 for 8x8).  The tile's depth-ordered instance list is
+// staged through LDS in chunks of up to 256 splats (one lane loads one 48-B
+// record as three float4 and stores it in the form the walks use, see
+// stage_splat) and every lane walks the chunk with broadcast LDS reads,
+// evaluating its PPL pixels against each splat.  The walk ends for the wave
+// as soon as none of its pixels is still open.
 //
 // Per pixel (centre x = (u + 0.5, v + 0.5)):
 //   power = -1/2 |L (x - mu)|^2,  alpha = min(alpha_max, sigma exp(power))
