@@ -409,7 +409,8 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
         // everywhere), listed in order: no skip branch in the walk.
         const int nw_list = G::ONE_BAND ? wave_list<TS, NW, G::CH>(st, n, wv, lane) : n;
         for (int jj = 0; jj < nw_list; jj++) {
-            if (!__any(open())) break;
+            // finished pixels change nothing, so testing every fourth entry suffices
+            if ((jj & 3) == 0 && !__any(open())) break;
             const int j = G::ONE_BAND ? __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]) : jj;
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
