@@ -35,6 +35,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# settings the paper states (Sec. III-B, III-D): 10 optimisation iterations per
+# frame, outdoor root voxels of 0.5 m, and the window sizes the sweep spans
+OPT_ITERS = 10
+ROOT_VOXEL_M = 0.5
+SWEEP_N = (20_000, 100_000, 500_000, 2_000_000)
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CU x 4 SIMD x 16 lanes x 2 FMA x 2 packed x 2.4 GHz)
 # FLOPs per (pixel, Gaussian) pair, counted from the per-pair formulas of the
 # compositing and its adjoint (add/mul/min/exp = 1, fma = 2):
@@ -197,16 +202,16 @@ def optimize_bench(ctx, ops, torch, g, win):
     st = ops.AdamState.from_gaussians(g)
     ops.adam_activate(ctx, st, g)
     hp = ops.adam_hparams()
-    win.optimize(st, hp, iters=10)
+    win.optimize(st, hp, iters=OPT_ITERS)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     reps = 3
     for _ in range(reps):
-        losses = win.optimize(st, hp, iters=10)
+        losses = win.optimize(st, hp, iters=OPT_ITERS)
     torch.cuda.synchronize()
     t_opt = (time.perf_counter() - t1) / reps
     assert win.status() == 0, "instance capacity exceeded during the optimisation loop"
-    return {"iters": 10, "ms": round(t_opt * 1e3, 4), "ms_per_iter": round(t_opt * 1e3 / 10, 4),
+    return {"iters": OPT_ITERS, "ms": round(t_opt * 1e3, 4), "ms_per_iter": round(t_opt * 1e3 / OPT_ITERS, 4),
             "last_losses": [round(float(x), 6) for x in losses[[0, -1]].cpu().tolist()],
             "how": "gsl_window_optimize: 10 x (window step + Adam step over the 500k raw parameters), one graph"}
 
@@ -245,7 +250,7 @@ def window_update_bench(ctx, ops, S, torch, frames=8):
     moving 1 m per frame.  Per frame: gsl_window_classify, the host read of
     (D, A), and gsl_window_compact appending as many Gaussians per ADD voxel
     as the window holds per voxel on average (rows resident on the device)."""
-    n, P, cap, vs, R = 500_000, 100_000, 1 << 20, 0.5, 42
+    n, P, cap, vs, R = 500_000, 100_000, 1 << 20, ROOT_VOXEL_M, 42
     pts_np, means = S.lidar_stream(71, frames + 1, P, n)
     pts = [torch.from_numpy(p).cuda() for p in pts_np]
     sw = ops.SlidingWindow(ctx, cap, vs)
@@ -304,7 +309,7 @@ def sweep(args):
 
     ctx = ops.Context(0)
     for (W, H) in ((640, 512), (1280, 1024)):
-        for n in (20_000, 100_000, 500_000, 2_000_000):
+        for n in SWEEP_N:
             sc, tgt_sc = S.config3(per_plane=n // 50, width=W, height=H, f=0.78125 * W)
             cs = ops.CameraSet(sc.cams)
             g, gt = ops.Gaussians.from_scene(sc), ops.Gaussians.from_scene(tgt_sc)
