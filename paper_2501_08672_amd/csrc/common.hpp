@@ -152,8 +152,8 @@ struct WsLayout {
 };
 
 // Radix sort / scan geometry
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortThreads = 512;
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per block
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
