@@ -649,7 +649,25 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ 
     __shared__ double s_red[256 / kWave][6];
     const int c = blockIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < blocks; b += 256)
+    int b = threadIdx.x;
+    for (; b + 3 * 256 < blocks; b += 4 * 256) {  // four blocks' loads in flight, added in the same order
+        double v[4][6], v2[4][6];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                v[q][k] = part[((int64_t)(b + q * 256) * C + c) * 6 + k];
+                v2[q][k] = part2 ? part2[((int64_t)(b + q * 256) * C + c) * 6 + k] : 0.0;
+            }
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                acc[k] += v[q][k];
+                if (part2) acc[k] += v2[q][k];
+            }
+    }
+    for (; b < blocks; b += 256)
         for (int k = 0; k < 6; k++) {
             acc[k] += part[((int64_t)b * C + c) * 6 + k];
             if (part2) acc[k] += part2[((int64_t)b * C + c) * 6 + k];

@@ -792,7 +792,15 @@ __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ p
 {
     __shared__ double s[256 / kWave];
     double acc = 0;
-    for (int64_t k = threadIdx.x; k < n; k += 256) acc += part[k];
+    int64_t k = threadIdx.x;
+    for (; k + 7 * 256 < n; k += 8 * 256) {  // eight loads in flight, added in the same order
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] = part[k + q * 256];
+#pragma unroll
+        for (int q = 0; q < 8; q++) acc += v[q];
+    }
+    for (; k < n; k += 256) acc += part[k];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if ((threadIdx.x & 63) == 0) s[threadIdx.x / kWave] = acc;
     __syncthreads();
