@@ -568,14 +568,18 @@ __global__ __launch_bounds__(kPoseThreads) void k_sh_bwd(const float *__restrict
         py = mean[N + i];
         pz = mean[2 * N + i];
     }
+    // the next camera's colour gradient is loaded while this camera's is chained
+    float gcn[3] = {0.f, 0.f, 0.f};
+    if (valid && C > 0)
+        for (int k = 0; k < 3; k++) gcn[k] = g2d[(int64_t)i * kG2 + 6 + k];
     for (int c = 0; c < C; c++) {
         double gt[3] = {0, 0, 0};
-        float gc[3] = {0.f, 0.f, 0.f};
-        if (valid) {
-            const float *src = g2d + ((int64_t)c * N + i) * kG2 + 6;
-            gc[0] = src[0];
-            gc[1] = src[1];
-            gc[2] = src[2];
+        const float gc[3] = {gcn[0], gcn[1], gcn[2]};
+        if (valid && c + 1 < C) {
+            const float *src = g2d + ((int64_t)(c + 1) * N + i) * kG2 + 6;
+            gcn[0] = src[0];
+            gcn[1] = src[1];
+            gcn[2] = src[2];
         }
         const bool any = gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f;
         if (any) {
