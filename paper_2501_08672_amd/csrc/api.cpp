@@ -185,6 +185,7 @@ WsLayout ws_layout(const Layout &L, int64_t capacity)
     const int64_t scan_n = std::max<int64_t>(256 * nb, M);
     w.scan_partials = (scan_n + kScanTile - 1) / kScanTile + 1;
     w.partial = take(8 * (size_t)w.scan_partials);
+    w.rs_totals = take(4 * 256);
     w.g2d = take(4 * (size_t)M * kG2);
     w.pose_blocks = (int32_t)((L.N + kPoseThreads - 1) / kPoseThreads);
     w.pose_part = take(8 * (size_t)std::max<int64_t>(1, (int64_t)w.pose_blocks * L.C * 6));
@@ -282,7 +283,8 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     // Gaussian index per camera); the first pass drops the others
     int64_t *d_V = at<int64_t>(ws, W.misc + 64);
     launch_depth_keys(proj->depth_keys, proj->tiles_touched, L.M, dkey, dval, s);
-    int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, partial, s, d_V);
+    uint32_t *totals = at<uint32_t>(ws, W.rs_totals);
+    int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, totals, s, d_V);
     const uint32_t *order = where ? dval2 : dval;
     // 2. instance offsets in that order
     uint32_t *counts = at<uint32_t>(ws, W.counts), *offsets = at<uint32_t>(ws, W.offsets);
@@ -295,7 +297,7 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     if (passes & 1) std::swap(ek, ak), std::swap(ev, av);
     launch_emit(order, offsets, counts, proj->binrecs, at<DevCam>(ws, W.cams), L, bins->d_K, bins->capacity_K, ek, ev,
                 bins->d_status, at<uint32_t>(ws, W.big), at<uint32_t>(ws, W.misc + 128), s);
-    launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, partial, s);
+    launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, totals, s);
     // 4. per-tile ranges
     launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);
 }

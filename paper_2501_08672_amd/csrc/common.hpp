@@ -137,6 +137,7 @@ struct WsLayout {
     size_t hist = 0;        // u32[256 * max_blocks] digit histograms
     size_t hist_off = 0;    // u32[256 * max_blocks] scanned histograms
     size_t partial = 0;     // u64[...] scan partial sums
+    size_t rs_totals = 0;   // u32[256] per-digit totals of a radix pass
     size_t g2d = 0;         // float[C][N][kG2]
     size_t pose_part = 0;   // double[pose_blocks][C][6]
     size_t pose_part_sh = 0;  // the same for the SH colour's camera-centre term
@@ -221,7 +222,7 @@ void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint6
 // keys2/vals2.  With d_kept, keys 0xffffffff are dropped by the first pass and
 // the number kept is written to *d_kept (later passes sort only those).
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
-                      const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint64_t *partial,
+                      const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *totals,
                       hipStream_t s, int64_t *d_kept = nullptr);
 void launch_depth_keys(const uint32_t *depth_keys, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
                        hipStream_t s);

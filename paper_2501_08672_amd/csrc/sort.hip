@@ -203,24 +203,95 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__rest
     }
 }
 
-// Stable scatter of one block using the scanned digit-major histogram.
+// Exclusive scan of one digit's row of the digit-major histogram (workgroup
+// d scans hist[d][0 .. nb)), and the row's total in totals[d].  The scatter
+// adds the digit's base, the exclusive scan of the totals, itself.
+constexpr int kRowItems = 4;
+
+__global__ __launch_bounds__(256) void k_rs_rowscan(const uint32_t *__restrict__ hist, int64_t nb,
+                                                    uint32_t *__restrict__ hist_off, uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t s_w[256 / kWave];
+    __shared__ uint32_t s_carry;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
+    const uint32_t *row = hist + (int64_t)blockIdx.x * nb;
+    uint32_t *out = hist_off + (int64_t)blockIdx.x * nb;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 256 * kRowItems) {
+        const int64_t j0 = base + (int64_t)threadIdx.x * kRowItems;
+        uint32_t v[kRowItems], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kRowItems; q++) {
+            v[q] = j0 + q < nb ? row[j0 + q] : 0u;
+            sum += v[q];
+        }
+        uint32_t inc = sum;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        if (lane == kWave - 1) s_w[wv] = inc;
+        __syncthreads();
+        uint32_t wbase = 0, tot = 0;
+        for (int w = 0; w < 256 / kWave; w++) {
+            wbase += w < wv ? s_w[w] : 0u;
+            tot += s_w[w];
+        }
+        uint32_t run = s_carry + wbase + inc - sum;
+#pragma unroll
+        for (int q = 0; q < kRowItems; q++) {
+            if (j0 + q < nb) out[j0 + q] = run;
+            run += v[q];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = s_carry;
+}
+
+// Stable scatter of one block using the row-scanned digit-major histogram
+// and the digit totals.  With d_kept (the first pass of a dropping sort),
+// workgroup 0 writes the number of keys kept.
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__restrict__ kin,
                                                              const uint32_t *__restrict__ vin,
                                                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                              int64_t n_max, const int64_t *__restrict__ d_n, int shift,
                                                              int db, const uint32_t *__restrict__ hist_off, int64_t nb,
-                                                             bool drop)
+                                                             const uint32_t *__restrict__ totals, bool drop,
+                                                             int64_t *__restrict__ d_kept)
 {
     const uint32_t dmask = (1u << db) - 1u;
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t s_cnt[NW][256];   // per-wave running digit counts, then wave bases
     __shared__ uint32_t s_loc[256];       // block-local first position of each digit
-    __shared__ uint32_t s_glob[256];      // global first position of each digit for this block
+    __shared__ uint32_t s_glob[256];      // digit bases, then global first position of each digit for this block
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t s_nloc;           // keys of this block that are kept
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < NW * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
+    if (threadIdx.x < kWave) {
+        // digit bases: exclusive scan of the 256 digit totals by one wave (4 per lane)
+        uint32_t t[4], sum = 0;
+        for (int k = 0; k < 4; k++) {
+            const int d = lane * 4 + k;
+            t[k] = d <= (int)dmask ? totals[d] : 0u;
+            sum += t[k];
+        }
+        uint32_t inc = sum;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        uint32_t run = inc - sum;
+        for (int k = 0; k < 4; k++) {
+            s_glob[lane * 4 + k] = run;
+            run += t[k];
+        }
+        if (d_kept && blockIdx.x == 0 && lane == kWave - 1) *d_kept = (int64_t)run;  // every key kept
+    }
     __syncthreads();
     const int64_t n = live_count(d_n, n_max);
     const int64_t block_base = (int64_t)blockIdx.x * kSortTile;
@@ -256,7 +327,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
             run += c;
         }
         s_loc[d] = run;  // total of digit d in this block (scanned below)
-        s_glob[d] = d <= (int)dmask ? hist_off[(int64_t)d * nb + blockIdx.x] : 0u;
+        if (d <= (int)dmask) s_glob[d] += hist_off[(int64_t)d * nb + blockIdx.x];
     }
     __syncthreads();
     if (threadIdx.x < kWave) {
@@ -487,7 +558,7 @@ void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint6
 }
 
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
-                      const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint64_t *partial,
+                      const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *totals,
                       hipStream_t s, int64_t *d_kept)
 {
     const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
@@ -505,9 +576,9 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
         const bool drop = d_kept && shift == 0;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, n_max, d_n, shift, db, hist,
                            nb, drop);
-        launch_scan_u32(hist, hist_off, (int64_t)(1 << db) * nb, partial, drop ? d_kept : nullptr, s);
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << db), dim3(256), 0, s, hist, nb, hist_off, totals);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_max,
-                           d_n, shift, db, hist_off, nb, drop);
+                           d_n, shift, db, hist_off, nb, totals, drop, drop ? d_kept : nullptr);
         if (drop) d_n = d_kept;
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout;
