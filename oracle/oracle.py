@@ -466,6 +466,18 @@ def ieskf_pose_update(HtRH, HtRz, P_prior, x_minus_prior=None):
     return delta, (np.eye(n) - KH) @ P
 
 
+def ieskf_visual_update(HtH_cam, Htz_cam, A, P_prior, x_minus_prior=None, noise_var=1.0):
+    """The visual update of the IMU pose from one camera's photometric normal
+    equations (Sec. II-D, Appendix A): the measurement Jacobian in the IMU
+    twist is H_imu = H_cam A (A of imu_to_camera_twist) and the noise R =
+    noise_var I, so H_imu^T R^-1 H_imu = A^T (H_cam^T H_cam) A / noise_var and
+    H_imu^T R^-1 z = A^T (H_cam^T z) / noise_var enter ieskf_pose_update."""
+    A = np.asarray(A, np.float64)
+    HtRH = A.T @ np.asarray(HtH_cam, np.float64) @ A / noise_var
+    HtRz = A.T @ np.asarray(Htz_cam, np.float64) / noise_var
+    return ieskf_pose_update(HtRH, HtRz, P_prior, x_minus_prior)
+
+
 # ---------------------------------------------------------------- Adam over the map parameters
 
 # Raw (optimised) parameters, 14 rows per Gaussian: mean (3), log-scale (3),
@@ -484,6 +496,21 @@ def activate(raw):
     if raw.shape[0] > 14:
         out["sh"] = raw[14:]
     return out
+
+
+def deactivate(act):
+    """Inverse of `activate`: the raw rows (14 + 3K, N) of activated
+    parameters (dict of (k, N) arrays as `activate` returns): log-scale =
+    ln(scale), opacity logit = ln(o / (1 - o)); mean, quaternion, colour and
+    SH rows as they are.  The starting point of the optimisation of the map
+    parameters (Sec. II-B)."""
+    rows = [act["mean"], np.log(act["scale"]), act["quat"],
+            np.log(np.asarray(act["opacity"], np.float64) / (1.0 - np.asarray(act["opacity"], np.float64))),
+            act["color"]]
+    if "sh" in act:
+        rows.append(act["sh"])
+    n = np.asarray(act["mean"]).shape[-1]
+    return np.concatenate([np.asarray(r, np.float64).reshape(-1, n) for r in rows], 0)
 
 
 def raw_gradient(raw, g_act):

@@ -559,7 +559,49 @@ def test_ieskf_update_matches_gain_form(oracle):
     np.testing.assert_allclose(b, sum(ws[i] * Hs[i] * res.reshape(-1)[i] for i in range(len(ws))), rtol=1e-12)
 
 
+def test_ieskf_visual_update_matches_stacked_imu_model(oracle):
+    """The IMU-pose update from the camera's normal equations equals the gain
+    form on an explicitly stacked model in the IMU twist: H_imu = H_cam A row
+    by row, R = noise_var I, K = P H_imu^T (H_imu P H_imu^T + R)^-1."""
+    rng = np.random.default_rng(13)
+    m = 45
+    H_cam = rng.normal(size=(m, 6))
+    z = rng.normal(size=m)
+    from scipy.spatial.transform import Rotation
+    A = oracle.imu_to_camera_twist(Rotation.from_rotvec(rng.normal(size=3)).as_matrix(), rng.normal(0, 0.2, 3),
+                                   Rotation.from_rotvec(rng.normal(size=3)).as_matrix())
+    L = rng.normal(size=(6, 6))
+    P = L @ L.T + 0.3 * np.eye(6)
+    dxp = rng.normal(0, 0.05, 6)
+    nv = 0.7
+    delta, Pn = oracle.ieskf_visual_update(H_cam.T @ H_cam, H_cam.T @ z, A, P, dxp, noise_var=nv)
+    H = np.stack([A.T @ h for h in H_cam])  # each row h_imu = h_cam A
+    K = P @ H.T @ np.linalg.inv(H @ P @ H.T + nv * np.eye(m))
+    np.testing.assert_allclose(delta, -K @ z - (np.eye(6) - K @ H) @ dxp, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Pn, (np.eye(6) - K @ H) @ P, rtol=1e-9, atol=1e-12)
+
+
 # ---------------------------------------------------------------- Adam
+
+def test_deactivate_inverts_activate(oracle):
+    """deactivate is the inverse of activate (round trips both ways, with SH
+    rows), and hand-worked values: scale 1 -> 0, e -> 1; opacity 1/2 -> 0,
+    1 / (1 + e^-2) -> 2, 1 / (1 + e^3) -> -3."""
+    rng = np.random.default_rng(5)
+    raw = rng.normal(size=(14 + 9, 6))
+    back = oracle.deactivate(oracle.activate(raw))
+    np.testing.assert_allclose(back, raw, rtol=0, atol=1e-12)
+    act = oracle.activate(raw)
+    again = oracle.activate(oracle.deactivate(act))
+    for k in act:
+        np.testing.assert_allclose(again[k], act[k], rtol=1e-13, atol=1e-15)
+    e = np.e
+    act = {"mean": np.zeros((3, 3)), "scale": np.array([[1.0, e, e * e]] * 3), "quat": np.ones((4, 3)),
+           "opacity": np.array([[0.5, 1.0 / (1.0 + e ** -2), 1.0 / (1.0 + e ** 3)]]), "color": np.full((3, 3), 0.25)}
+    r = oracle.deactivate(act)
+    np.testing.assert_allclose(r[3:6], [[0.0, 1.0, 2.0]] * 3, atol=1e-15)
+    np.testing.assert_allclose(r[10], [0.0, 2.0, -3.0], atol=1e-14)
+    np.testing.assert_array_equal(r[11:14], act["color"])
 
 def test_adam_constant_gradient_closed_form(oracle):
     """For a gradient that stays g, the bias-corrected moments are exactly g
