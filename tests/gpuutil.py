@@ -7,7 +7,8 @@ Parity rules (FP32 GPU against FP64 oracle):
     FP32 error bound whose possible effect exceeds 5e-5 in sum, or a
     large-step transmittance-cutoff decision within its bound); flag 4
     (small-step cutoff) widens the tolerance by 2.01 T_min (max c + bg);
-    flagged pixels are counted and must stay a small fraction;
+    flagged pixels are counted, printed and capped (0.2 % of an image by
+    default; the measured rate on the test scenes is 0-0.1 %);
   * gradients: per tensor, max |GPU - oracle| <= 1e-3 max |oracle|, and per
     element |GPU - oracle| <= 1e-3 |oracle| wherever |oracle| >= 1e-2 max|oracle|
     (loosened only where the test says so, with the reason);
@@ -81,14 +82,15 @@ def pixel_tolerance(flags, tol=IMG_TOL, bg=0.0, cmax=1.0):
     return np.where((flags & 1) != 0, np.inf, t)
 
 
-def compare_images(gpu_img, orc_img, flags, tol=IMG_TOL, max_flag_frac=0.02, name="", bg=0.0, cmax=1.0):
+def compare_images(gpu_img, orc_img, flags, tol=IMG_TOL, max_flag_frac=0.002, name="", bg=0.0, cmax=1.0):
     """gpu_img, orc_img: (3, H, W); flags (H, W).  Returns (max error, excluded count)."""
     tl = pixel_tolerance(flags, tol, bg=max(abs(b) for b in np.atleast_1d(bg)), cmax=cmax)
     err = np.abs(gpu_img.astype(np.float64) - orc_img).max(0)
     bad = err > tl
     assert not bad.any(), f"{name}: {int(bad.sum())} pixels beyond tolerance, worst {float((err - tl)[bad].max()):.3g}"
     nflag = int(np.isinf(tl).sum())
-    assert nflag <= max_flag_frac * tl.size + 2, f"{name}: {nflag} alpha-ambiguous pixels of {tl.size}"
+    print(f"{name}: {nflag} flag-1 pixels of {tl.size}")
+    assert nflag <= max_flag_frac * tl.size + 1, f"{name}: {nflag} alpha-ambiguous pixels of {tl.size}"
     return float(err[np.isfinite(tl)].max()) if np.isfinite(tl).any() else 0.0, nflag
 
 

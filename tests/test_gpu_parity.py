@@ -397,7 +397,8 @@ def test_render_config2_sampled(oracle):
     tl = pixel_tolerance(r["flags"])
     err = np.abs(got.T - r["rgb"]).max(1)
     assert np.all(err <= tl), (err - tl).max()
-    assert np.isinf(tl).sum() <= 0.01 * len(tl)
+    print(f"config2 sampled: {int(np.isinf(tl).sum())} flag-1 pixels of {len(tl)}")
+    assert np.isinf(tl).sum() <= 0.002 * len(tl) + 1
 
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
@@ -448,25 +449,27 @@ def _cotangent(oracle, sc, cams, seed, o_kw=None):
     return vs
 
 
-def test_render_bwd_config1(oracle):
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_render_bwd_config1(oracle, tile):
     sc = S.config1()
-    st = gpu_forward(sc, sc.cams, tile=16)
+    st = gpu_forward(sc, sc.cams, tile=tile)
     vs = _cotangent(oracle, sc, sc.cams, 0)
     v_packed = torch.from_numpy(np.concatenate([v.astype(np.float32).ravel() for v in vs])).cuda()
     gg = gpu_backward(st, v_packed)
     go = oracle.render_bwd(sc, sc.cams, vs, oracle.Opts())
-    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name="config1")
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name=f"config1 tile {tile}")
 
 
-def test_render_bwd_multicam_pose(oracle):
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_render_bwd_multicam_pose(oracle, tile):
     sc = _scene_multi(2500, 21)
     bg = (0.2, 0.1, 0.3)
-    st = gpu_forward(sc, sc.cams, tile=16, bg=bg)
+    st = gpu_forward(sc, sc.cams, tile=tile, bg=bg)
     vs = _cotangent(oracle, sc, sc.cams, 1, {"bg": bg})
     v_packed = torch.from_numpy(np.concatenate([v.astype(np.float32).ravel() for v in vs])).cuda()
     gg = gpu_backward(st, v_packed)
     go = oracle.render_bwd(sc, sc.cams, vs, oracle.Opts(bg=bg))
-    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name="multicam")
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name=f"multicam tile {tile}")
 
 
 def test_render_bwd_accumulate():
@@ -484,22 +487,24 @@ def test_render_bwd_accumulate():
     np.testing.assert_allclose(gr.pose.cpu().numpy(), 2 * a["pose"], rtol=1e-5, atol=1e-6 * np.abs(a["pose"]).max())
 
 
-def test_render_bwd_config2_sampled(oracle):
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_render_bwd_config2_sampled(oracle, tile):
     """Full-size 100k / 640x512 with the cotangent non-zero on 400 sampled pixels."""
     sc, _ = S.config2()
     cam = sc.cams[0]
-    st = gpu_forward(sc, sc.cams, tile=16)
+    st = gpu_forward(sc, sc.cams, tile=tile)
     rng = np.random.default_rng(5)
     pix = np.stack([rng.integers(0, cam.width, 400), rng.integers(0, cam.height, 400)], 1).astype(np.int32)
     pix = np.unique(pix, axis=0)
     r = oracle.render(sc, cam, oracle.Opts(), pixels=pix)
+    assert int(((r["flags"] & 1) != 0).sum()) <= 1
     pix = pix[(r["flags"] & 3) == 0]
     v = rng.normal(size=(len(pix), 3))
     vimg = np.zeros((3, cam.height, cam.width), np.float32)
     vimg[:, pix[:, 1], pix[:, 0]] = v.T
     gg = gpu_backward(st, torch.from_numpy(vimg.ravel()).cuda())
     go = oracle.render_bwd(sc, [cam], [v], oracle.Opts(), pixels=[pix])
-    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name="config2")
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "pose"), name=f"config2 tile {tile}")
 
 
 # ------------------------------------------------------------------ window

@@ -59,14 +59,14 @@ def test_sh_images_match_oracle(oracle, degree, tile):
                        cmax=cm)
 
 
-@pytest.mark.parametrize("degree", [1, 3])
-def test_sh_gradients_match_oracle(oracle, degree):
+@pytest.mark.parametrize("degree,tile", [(1, 16), (3, 16), (1, 8), (3, 32)])
+def test_sh_gradients_match_oracle(oracle, degree, tile):
     """Coefficients, means (now also through the view direction), colours,
     the other parameters and the camera poses (now also through the camera
     centre), to the gradient tolerance."""
     sc = _scene(2500, 31, degree)
     bg = (0.2, 0.1, 0.3)
-    st = gpu_forward(sc, sc.cams, tile=16, bg=bg)
+    st = gpu_forward(sc, sc.cams, tile=tile, bg=bg)
     rng = np.random.default_rng(5)
     vs = []
     for cam in sc.cams:
@@ -77,7 +77,7 @@ def test_sh_gradients_match_oracle(oracle, degree):
     v_packed = torch.from_numpy(np.concatenate([v.astype(np.float32).ravel() for v in vs])).cuda()
     gg = gpu_backward(st, v_packed)
     go = oracle.render_bwd(sc, sc.cams, vs, oracle.Opts(bg=bg))
-    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "sh", "pose"), name=f"sh{degree}")
+    compare_grads(gg, go, keys=("mean", "scale", "quat", "opacity", "color", "sh", "pose"), name=f"sh{degree} tile {tile}")
 
 
 def test_sh_window_step_matches_separate_calls():
