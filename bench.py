@@ -208,7 +208,7 @@ def optimize_bench(ctx, ops, torch, g, win):
     """The optimisation loop of one keyframe: 10 iterations of window step +
     Adam recorded as one graph (it moves the Gaussians, so it runs after the
     window-step measurements)."""
-    st = ops.AdamState.from_gaussians(g)
+    st = ops.AdamState.from_gaussians(ctx, g)
     ops.adam_activate(ctx, st, g)
     hp = ops.adam_hparams()
     win.optimize(st, hp, iters=OPT_ITERS)

@@ -176,7 +176,8 @@ GSL_API void gsl_default_opts(gsl_opts *opts);
 /* Number of tiles and pixels of a camera set at opts->tile (host only). */
 GSL_API int gsl_layout(const gsl_camera *cams, int32_t C, int32_t tile, int64_t *T_total, int64_t *P_total);
 
-/* Bytes of device workspace the calls below need for these shapes. */
+/* Bytes of device workspace the calls below need for these shapes (host
+ * only; ctx is not used and may be NULL). */
 GSL_API int gsl_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
                        int64_t capacity_K, size_t *bytes);
 
@@ -192,7 +193,9 @@ GSL_API int gsl_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, 
 GSL_API int gsl_project(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
                 gsl_proj *out, void *workspace, size_t workspace_bytes, void *stream);
 
-/* Tile binning and sorting: orders the Gaussians of every camera by depth
+/* Tile binning and sorting (Sec. II-C, the tile-based depth sorting of the
+ * Gaussians in the GPU rasteriser; the front-to-back order eq. eq:raster
+ * composites in): orders the Gaussians of every camera by depth
  * (32-bit float key, ties by index), emits one instance per overlapped tile
  * and sorts the instances by tile with a stable LSD radix sort, so the
  * instance order equals a sort by the 64-bit key (tile << 32 | depth bits)
@@ -239,7 +242,10 @@ GSL_API int gsl_render_stats(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, in
 
 enum { GSL_LOSS_L1 = 1, GSL_LOSS_L2 = 2 };
 
-/* One optimisation pass over a window of keyframes: project, bin_sort, then
+/* One optimisation pass over the sliding window of keyframes (Sec. II-C: the
+ * window's Gaussians are optimised on the GPU against its keyframes; Sec.
+ * III-B: 10 such passes per frame, see gsl_window_optimize), the photometric
+ * loss of eq. eq:gaussian_optimization and its gradient: project, bin_sort, then
  * one fused launch over all (camera, tile) items that composites,
  * forms the per-pixel loss gradient against `target` (packed like the image;
  * L1: mean absolute error per frame summed over frames, L2: 1/2 sum of
@@ -247,9 +253,12 @@ enum { GSL_LOSS_L1 = 1, GSL_LOSS_L2 = 2 };
  * *d_loss (device float64) and the gradients (overwritten); image may be NULL.
  * The fused launch uses the kernel variant (persistent work queue or one
  * workgroup per item; items in tile order or longest list first) that
- * gsl_window_tune chose for these shapes, else the default.  With use_graph != 0 the sequence is recorded
- * once into a HIP graph per (shapes, buffers, options, camera poses) and
- * replayed on later calls with the same arguments. */
+ * gsl_window_tune chose for these shapes, else the default.  With
+ * use_graph != 0 the sequence is recorded once into a HIP graph per (camera
+ * sizes, Gaussian count, buffers, options, variant, loss) and replayed on
+ * later calls with the same arguments; the camera table (poses and
+ * intrinsics) is uploaded on the stream before each launch, so new poses of
+ * the same cameras replay the cached graph. */
 GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
                     const float *target, int loss, gsl_proj *proj, gsl_bins *bins, float *image,
                     double *d_loss, gsl_grads *grads, void *workspace, size_t workspace_bytes,
@@ -260,6 +269,10 @@ GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
  * longest list first, 4 = contiguous tile runs per XCD; 0..4 are valid. */
 GSL_API int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile,
                                int32_t variant);
+
+/* Number of HIP graphs the context holds (window steps and optimisation
+ * loops recorded so far, at most 65 before the cache is flushed). */
+GSL_API int gsl_graph_count(gsl_ctx *ctx, int64_t *count);
 
 /* Profiling hook: while enabled, every window step records HIP events on its
  * stream between its stages (a graph step launches a graph captured for
@@ -311,6 +324,14 @@ typedef struct {
                         * the activated Gaussians' sh_degree */
 } gsl_adam_state;
 
+/* Starting point of the optimisation of the map parameters (Sec. II-B):
+ * raw <- the inverse activation of act (log-scale = ln(scale), opacity
+ * logit = ln(o / (1 - o)); mean, quaternion, colour and SH rows as they are),
+ * m = v = 0 and *d_step = 0, in float32 on the device.  act.N and
+ * act.sh_degree must equal the state's; scales must be > 0 and opacities in
+ * (0, 1) (otherwise the raw value is not finite).  d_step must not be NULL. */
+GSL_API int gsl_adam_init(gsl_ctx *ctx, const gsl_gaussians *act, gsl_adam_state *st, void *stream);
+
 /* act <- activation(raw).  No optimiser step. */
 GSL_API int gsl_adam_activate(gsl_ctx *ctx, const gsl_adam_state *st, gsl_gaussians *act, void *stream);
 
@@ -327,7 +348,8 @@ GSL_API int gsl_adam_step(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, 
  * loss of iteration k going to d_losses[k] (device float64 [iters]).  act must
  * hold activation(raw) on entry (gsl_adam_activate).  With use_graph != 0 the
  * whole sequence is recorded once into a HIP graph per (shapes, buffers,
- * options, camera poses, iters) and replayed. */
+ * options, Adam hyper-parameters, iters) and replayed; as for
+ * gsl_window_step, the camera table is uploaded before each launch. */
 GSL_API int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gsl_gaussians *act,
                                 const gsl_camera *cams, int32_t C, const gsl_opts *opts, const float *target,
                                 int loss, gsl_proj *proj, gsl_bins *bins, double *d_losses, gsl_grads *grads,
@@ -418,7 +440,8 @@ GSL_API int gsl_window_compact(gsl_ctx *ctx, uint64_t *keys, float *rows, int32_
 /* Workspace bytes for gsl_pose_jacobian: the bytes gsl_workspace_size gives
  * for the same arguments, plus 160 B per (camera, Gaussian) record for its
  * twist tangents (those of the 2D mean and conic, and of the colour when it
- * is view-dependent) and 224 B per tile for the per-tile partial sums. */
+ * is view-dependent) and 224 B per tile for the per-tile partial sums (host
+ * only; ctx is not used and may be NULL). */
 GSL_API int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,
                                              const gsl_opts *opts, int64_t capacity_K, size_t *bytes);
 
@@ -463,6 +486,20 @@ GSL_API int gsl_imu_to_camera_twist(const double R_CI[9], const double t_CI[3], 
  * delta 6-vectors.  GSL_EINVAL when P or H^T R^-1 H + P^-1 is singular. */
 GSL_API int gsl_ieskf_pose_update(const double HtRH[36], const double HtRz[6], const double P[36],
                                   const double dx_prior[6], double delta[6], double P_post[36]);
+
+/* The visual update of the IMU pose from one camera's photometric normal
+ * equations (Sec. II-D, eq. eq:minimization; Appendix A): with A from
+ * gsl_imu_to_camera_twist the measurement Jacobian in the IMU twist is
+ * H_imu = H_cam A, and with the noise R = noise_var I the update of
+ * gsl_ieskf_pose_update takes H_imu^T R^-1 H_imu = A^T (H_cam^T H_cam) A /
+ * noise_var and H_imu^T R^-1 z = A^T (H_cam^T z) / noise_var.  HtH_cam and
+ * Htz_cam are a camera's HtH and Htz as gsl_pose_jacobian writes them (any
+ * per-pixel weights already applied), copied to the host; the other
+ * arguments as for gsl_ieskf_pose_update.  GSL_EINVAL for a NULL argument,
+ * noise_var not finite and > 0, or a singular system. */
+GSL_API int gsl_ieskf_visual_update(const double HtH_cam[36], const double Htz_cam[6], const double A[36],
+                                    double noise_var, const double P[36], const double dx_prior[6], double delta[6],
+                                    double P_post[36]);
 
 #ifdef __cplusplus
 }

@@ -28,9 +28,9 @@ _NAMES = {GSL_EINVAL: "EINVAL", GSL_ENOTSUP: "ENOTSUP", GSL_ECAPACITY: "ECAPACIT
 
 EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "gsl_layout", "gsl_workspace_size",
            "gsl_project", "gsl_bin_sort", "gsl_render_fwd", "gsl_render_bwd", "gsl_render_stats", "gsl_window_step",
-           "gsl_window_tune", "gsl_window_variant", "gsl_profile", "gsl_profile_read",
+           "gsl_window_tune", "gsl_window_variant", "gsl_graph_count", "gsl_profile", "gsl_profile_read",
            "gsl_pose_jacobian_workspace_size", "gsl_pose_jacobian", "gsl_imu_to_camera_twist",
-           "gsl_ieskf_pose_update", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
+           "gsl_ieskf_pose_update", "gsl_ieskf_visual_update", "gsl_adam_init", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
            "gsl_voxel_keys", "gsl_window_workspace_size", "gsl_window_classify", "gsl_window_compact",
            "gsl_color_init"]
 
@@ -112,6 +112,7 @@ def lib() -> C.CDLL:
     L.gsl_render_bwd.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, C.c_int, pgr, P, C.c_size_t, P]
     L.gsl_render_stats.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, P, C.c_size_t, P]
     L.gsl_window_variant.argtypes = [P, pc, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.gsl_graph_count.argtypes = [P, C.POINTER(C.c_int64)]
     L.gsl_profile.argtypes = [P, C.c_int]
     L.gsl_profile_read.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
     L.gsl_window_step.argtypes = [P, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, P, pgr, P, C.c_size_t, C.c_int, P]
@@ -122,7 +123,9 @@ def lib() -> C.CDLL:
     L.gsl_pose_jacobian.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, P, P, P, P, P, C.c_size_t, P]
     L.gsl_imu_to_camera_twist.argtypes = [P, P, P, P]
     L.gsl_ieskf_pose_update.argtypes = [P, P, P, P, P, P]
+    L.gsl_ieskf_visual_update.argtypes = [P, P, P, C.c_double, P, P, P, P]
     pa, ps = C.POINTER(Adam), C.POINTER(AdamState)
+    L.gsl_adam_init.argtypes = [P, pg, ps, P]
     L.gsl_adam_activate.argtypes = [P, ps, pg, P]
     L.gsl_adam_step.argtypes = [P, ps, pa, pgr, pg, P]
     L.gsl_window_optimize.argtypes = [P, ps, pa, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, pgr, C.c_int32, P,

@@ -211,6 +211,14 @@ struct Prepared {
     DevOpts o;
 };
 
+int check_device(const gsl_ctx *ctx)
+{
+    int cur = -1;
+    GSL_TRY(check_hip(hipGetDevice(&cur), "hipGetDevice"));
+    if (cur != ctx->device) return fail(GSL_ESTATE, "current device %d is not the context's device %d", cur, ctx->device);
+    return GSL_OK;
+}
+
 int prepare(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts, int64_t capacity,
             void *ws, size_t ws_bytes, Prepared &p)
 {
@@ -223,10 +231,7 @@ int prepare(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gs
     if (!ws) return fail(GSL_EINVAL, "workspace is NULL");
     if (ws_bytes < p.W.total)
         return fail(GSL_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, p.W.total);
-    int cur = -1;
-    GSL_TRY(check_hip(hipGetDevice(&cur), "hipGetDevice"));
-    if (cur != ctx->device) return fail(GSL_ESTATE, "current device %d is not the context's device %d", cur, ctx->device);
-    return GSL_OK;
+    return check_device(ctx);
 }
 
 int check_gauss(const gsl_gaussians *g, bool need_all)
@@ -338,17 +343,35 @@ void do_project_bwd(const Prepared &p, const gsl_gaussians *g, gsl_grads *grads,
     }
 }
 
+// Enqueues the raster adjoint and the projection adjoint.  Everything of the
+// scratch memory the kernels accumulate into is cleared here first: the 2D
+// gradients by a fill kernel, the pose partials by the adjoint that writes
+// every one of them.
+void do_render_bwd(const Prepared &p, const gsl_gaussians *g, const gsl_proj *proj, const gsl_bins *bins,
+                   const float *T_final, const uint32_t *n_walk, const float *dL_dimage, int accumulate,
+                   gsl_grads *grads, void *ws, hipStream_t s)
+{
+    do_upload(p, ws, s);
+    launch_fill_f32(at<float>(ws, p.W.g2d), 0.f, p.L.M * kG2, s);
+    RenderArgs a = render_args(p, proj, bins, ws);
+    a.T_final = const_cast<float *>(T_final);
+    a.n_walk = const_cast<uint32_t *>(n_walk);
+    a.dL_dimage = dL_dimage;
+    launch_render_bwd(a, s);
+    do_project_bwd(p, g, grads, accumulate, ws, s);
+}
+
 // Enqueues one window step.  With `timed`, HIP events are recorded on the
 // stream between the stages (never while capturing a graph).
 void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const float *target, int loss,
                gsl_proj *proj, gsl_bins *bins, float *image, double *d_loss, gsl_grads *grads, void *ws, int variant,
-               hipStream_t s, bool timed = false)
+               hipStream_t s, bool timed = false, bool upload = true)
 {
     auto mark = [&](int k) {
         if (timed) (void)hipEventRecord(ctx->ev[k], s);
     };
     mark(kStProject);
-    do_upload(p, ws, s);
+    if (upload) do_upload(p, ws, s);
     do_project(p, g, proj, ws, s);
     mark(kStBinSort);
     do_bin_sort(p, proj, bins, ws, s);
@@ -416,12 +439,14 @@ int graph_run(gsl_ctx *ctx, const VariantKey &key, hipStream_t s, F &&enqueue)
     return check_hip(hipGraphLaunch(it->second.exec, s), "hipGraphLaunch");
 }
 
-// Graph key of a window pass: shapes, variant, loss, every pointer, options
-// and camera contents.
+// Graph key of a window pass: shapes (camera sizes are in vk), variant, loss,
+// every pointer and the options.  Poses and intrinsics are not part of it:
+// the graphs read the camera table from the workspace, which the caller
+// uploads on the stream before each launch, so a new keyframe pose replays
+// the same graph.
 VariantKey window_graph_key(const VariantKey &vk, int variant, int loss, const gsl_gaussians *g, const float *target,
                             const gsl_proj *proj, const gsl_bins *bins, const float *image, const double *d_loss,
-                            const gsl_grads *grads, const void *workspace, const gsl_opts *opts,
-                            const gsl_camera *cams, int32_t C)
+                            const gsl_grads *grads, const void *workspace, const gsl_opts *opts)
 {
     VariantKey gk = vk;
     gk.v.push_back(variant);
@@ -436,10 +461,6 @@ VariantKey window_graph_key(const VariantKey &vk, int variant, int loss, const g
     ptr(grads->g_opacity); ptr(grads->g_color); ptr(grads->g_pose); ptr(grads->g_sh); ptr(workspace);
     const int32_t *ow = reinterpret_cast<const int32_t *>(opts);
     for (size_t k = 0; k < sizeof(gsl_opts) / 4; k++) gk.v.push_back(ow[k]);
-    for (int c = 0; c < C; c++) {
-        const int32_t *cw = reinterpret_cast<const int32_t *>(&cams[c]);
-        for (size_t k = 0; k < sizeof(gsl_camera) / 4; k++) gk.v.push_back(cw[k]);
-    }
     return gk;
 }
 
@@ -665,7 +686,8 @@ int gsl_layout(const gsl_camera *cams, int32_t C, int32_t tile, int64_t *T_total
 int gsl_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
                        int64_t capacity_K, size_t *bytes)
 {
-    if (!ctx || !bytes) return fail(GSL_EINVAL, "NULL argument");
+    (void)ctx;  // sizes depend on the shapes only
+    if (!bytes) return fail(GSL_EINVAL, "NULL argument");
     GSL_TRY(check_opts(opts));
     if (capacity_K < 0 || capacity_K > 0xffffffffll) return fail(GSL_EINVAL, "capacity_K out of range");
     Layout L;
@@ -748,15 +770,7 @@ int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams,
     GSL_TRY(prepare(ctx, cams, C, g->N, opts, bins->capacity_K, workspace, workspace_bytes, p));
     GSL_TRY(check_proj(proj, p.L));
     if (!T_final || !n_walk || !dL_dimage) return fail(GSL_EINVAL, "input buffer is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    do_upload(p, workspace, s);
-    launch_fill_f32(at<float>(workspace, p.W.g2d), 0.f, p.L.M * kG2, s);
-    RenderArgs a = render_args(p, proj, bins, workspace);
-    a.T_final = const_cast<float *>(T_final);
-    a.n_walk = const_cast<uint32_t *>(n_walk);
-    a.dL_dimage = dL_dimage;
-    launch_render_bwd(a, s);
-    do_project_bwd(p, g, grads, accumulate, workspace, s);
+    do_render_bwd(p, g, proj, bins, T_final, n_walk, dL_dimage, accumulate, grads, workspace, (hipStream_t)stream);
     return check_launch("gsl_render_bwd");
 }
 
@@ -783,16 +797,24 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
         do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, s, ctx->profile);
         return check_launch("gsl_window_step");
     }
-    VariantKey gk =
-        window_graph_key(vk, variant, loss, g, target, proj, bins, image, d_loss, grads, workspace, opts, cams, C);
+    VariantKey gk = window_graph_key(vk, variant, loss, g, target, proj, bins, image, d_loss, grads, workspace, opts);
     // a profiled step is its own graph, with the stage events as event-record nodes
     const bool timed = ctx->profile;
     gk.v.push_back(timed ? 1 : 0);
+    do_upload(p, workspace, s);
     const int rc = graph_run(ctx, gk, s, [&](hipStream_t cs) {
-        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, cs, timed);
+        do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, cs, timed, false);
     });
     if (rc == GSL_OK && timed) ctx->ev_recorded = true;  // also when the graph came from the cache
     return rc;
+}
+
+int gsl_graph_count(gsl_ctx *ctx, int64_t *count)
+{
+    if (!ctx || !count) return fail(GSL_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *count = (int64_t)ctx->graphs.size();
+    return GSL_OK;
 }
 
 int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, int32_t variant)
@@ -911,6 +933,18 @@ int gsl_adam_activate(gsl_ctx *ctx, const gsl_adam_state *st, gsl_gaussians *act
     return check_launch("gsl_adam_activate");
 }
 
+int gsl_adam_init(gsl_ctx *ctx, const gsl_gaussians *act, gsl_adam_state *st, void *stream)
+{
+    if (!ctx || !act) return fail(GSL_EINVAL, "NULL argument");
+    GSL_TRY(check_adam(st, nullptr));
+    if (!st->d_step) return fail(GSL_EINVAL, "adam step counter is NULL");
+    GSL_TRY(check_adam_act(st, act, nullptr));
+    GSL_TRY(check_gauss(act, true));
+    const float *a[6] = {act->mean, act->scale, act->quat, act->opacity, act->color, act->sh};
+    launch_adam_init(a, st->raw, st->m, st->v, st->d_step, st->N, st->sh_degree, adam_ld(st), (hipStream_t)stream);
+    return check_launch("gsl_adam_init");
+}
+
 int gsl_adam_step(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, const gsl_grads *grads, gsl_gaussians *act,
                   void *stream)
 {
@@ -948,9 +982,12 @@ int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gs
         auto it = ctx->variant.find(vk);
         if (it != ctx->variant.end()) variant = it->second;
     }
+    // the camera table is uploaded once; the iterations read it from the workspace
+    do_upload(p, workspace, s);
     auto enqueue = [&](hipStream_t q) {
         for (int k = 0; k < iters; k++) {
-            do_window(ctx, p, act, target, loss, proj, bins, nullptr, d_losses + k, grads, workspace, variant, q);
+            do_window(ctx, p, act, target, loss, proj, bins, nullptr, d_losses + k, grads, workspace, variant, q,
+                      false, false);
             do_adam(st, hp, grads, act, q);
         }
     };
@@ -959,7 +996,7 @@ int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gs
         return check_launch("gsl_window_optimize");
     }
     VariantKey gk = window_graph_key(vk, variant, loss, act, target, proj, bins, nullptr, d_losses, grads,
-                                     workspace, opts, cams, C);
+                                     workspace, opts);
     gk.v.push_back(-1);  // a separator from the single-step keys
     gk.v.push_back(iters);
     for (const void *q : {(const void *)st->raw, (const void *)st->m, (const void *)st->v, (const void *)st->d_step})
@@ -1054,7 +1091,8 @@ int gsl_window_compact(gsl_ctx *ctx, uint64_t *keys, float *rows, int32_t R, int
 int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,
                                      const gsl_opts *opts, int64_t capacity_K, size_t *bytes)
 {
-    if (!ctx || !bytes) return fail(GSL_EINVAL, "NULL argument");
+    (void)ctx;  // sizes depend on the shapes only
+    if (!bytes) return fail(GSL_EINVAL, "NULL argument");
     GSL_TRY(check_opts(opts));
     if (capacity_K < 0 || capacity_K > 0xffffffffll) return fail(GSL_EINVAL, "capacity_K out of range");
     Layout L;
@@ -1148,6 +1186,32 @@ int gsl_ieskf_pose_update(const double HtRH[36], const double HtRz[6], const dou
             P_post[6 * r + c] = v;
         }
     return GSL_OK;
+}
+
+int gsl_ieskf_visual_update(const double HtH_cam[36], const double Htz_cam[6], const double A[36], double noise_var,
+                            const double P[36], const double dx_prior[6], double delta[6], double P_post[36])
+{
+    if (!HtH_cam || !Htz_cam || !A) return fail(GSL_EINVAL, "NULL argument");
+    if (!(noise_var > 0.0) || !std::isfinite(noise_var)) return fail(GSL_EINVAL, "noise variance must be finite and > 0");
+    // H_imu = H_cam A:  H_imu^T R^-1 H_imu = A^T (H_cam^T H_cam) A / var,  H_imu^T R^-1 z = A^T (H_cam^T z) / var
+    double HA[36], HtRH[36], HtRz[6];
+    for (int r = 0; r < 6; r++)
+        for (int c = 0; c < 6; c++) {
+            double v = 0.0;
+            for (int k = 0; k < 6; k++) v += HtH_cam[6 * r + k] * A[6 * k + c];
+            HA[6 * r + c] = v;
+        }
+    for (int r = 0; r < 6; r++) {
+        for (int c = 0; c < 6; c++) {
+            double v = 0.0;
+            for (int k = 0; k < 6; k++) v += A[6 * k + r] * HA[6 * k + c];
+            HtRH[6 * r + c] = v / noise_var;
+        }
+        double z = 0.0;
+        for (int k = 0; k < 6; k++) z += A[6 * k + r] * Htz_cam[k];
+        HtRz[r] = z / noise_var;
+    }
+    return gsl_ieskf_pose_update(HtRH, HtRz, P, dx_prior, delta, P_post);
 }
 
 }  // extern "C"

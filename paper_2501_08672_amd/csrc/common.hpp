@@ -167,6 +167,9 @@ constexpr int kPoseThreads = 256;
 void launch_adam(const float *const g[6], float *const act[6], float *raw, float *m, float *v, const int32_t *d_step,
                  const float lr[6], float beta1, float beta2, float eps, int N, int sh_degree, int64_t ld,
                  bool update, hipStream_t s);
+// raw <- inverse activation of act (same layouts), m = v = 0, *d_step = 0.
+void launch_adam_init(const float *const act[6], float *raw, float *m, float *v, int32_t *d_step, int N,
+                      int sh_degree, int64_t ld, hipStream_t s);
 
 // window.hip: maintenance of the sliding window (hash set of the frame's
 // voxel keys, DELETE / ADD classification, in-place compaction).

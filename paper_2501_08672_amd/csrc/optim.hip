@@ -78,6 +78,30 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a)
 
 __global__ void k_step_advance(int32_t *d_step) { *d_step += 1; }
 
+// Starting point of the optimisation: raw <- inverse activation of the
+// activated parameters (log-scale = ln s, opacity logit = ln(o / (1 - o)),
+// the other rows as they are), both moments zero.
+__global__ __launch_bounds__(256) void k_adam_init(AdamArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const int64_t N = a.N, ld = a.ld;
+#pragma unroll
+    for (int r = 0; r < kMaxRows; r++) {
+        if (r >= a.rows) break;
+        const int grp = row_group(r), k = row_in_group(r);
+        const float y = a.g[grp][k * N + i];
+        float x = y;
+        if (grp == 1) x = logf(y);
+        else if (grp == 3) x = logf(y / (1.f - y));
+        a.raw[r * ld + i] = x;
+        a.m[r * ld + i] = 0.f;
+        a.v[r * ld + i] = 0.f;
+    }
+}
+
+__global__ void k_step_reset(int32_t *d_step) { *d_step = 0; }
+
 }  // namespace
 
 void launch_adam(const float *const g[6], float *const act[6], float *raw, float *m, float *v, const int32_t *d_step,
@@ -104,6 +128,22 @@ void launch_adam(const float *const g[6], float *const act[6], float *raw, float
     a.update = update;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a);
     if (update) hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, const_cast<int32_t *>(d_step));
+}
+
+void launch_adam_init(const float *const act[6], float *raw, float *m, float *v, int32_t *d_step, int N,
+                      int sh_degree, int64_t ld, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(1), 0, s, d_step);
+    if (N == 0) return;
+    AdamArgs a = {};
+    for (int k = 0; k < 6; k++) a.g[k] = act[k];
+    a.rows = kBaseRows + 3 * sh_count(sh_degree);
+    a.raw = raw;
+    a.m = m;
+    a.v = v;
+    a.N = N;
+    a.ld = ld;
+    hipLaunchKernelGGL(k_adam_init, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a);
 }
 
 }  // namespace gsl

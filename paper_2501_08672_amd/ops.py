@@ -78,6 +78,13 @@ class Context:
             pass
 
 
+def graph_count(ctx: "Context") -> int:
+    """HIP graphs the context holds (gsl_graph_count)."""
+    n = C.c_int64()
+    A.check(A.lib().gsl_graph_count(ctx.h, C.byref(n)))
+    return int(n.value)
+
+
 class CameraSet:
     """Host description of the C cameras of a window."""
 
@@ -351,12 +358,14 @@ class AdamState:
         return self.n
 
     @staticmethod
-    def from_gaussians(g: "Gaussians") -> "AdamState":
-        """Raw parameters of activated ones (initialisation, outside the step)."""
-        rows = [g.mean, torch.log(g.scale), g.quat, torch.logit(g.opacity)[None], g.color]
-        if g.sh is not None:
-            rows.append(g.sh)
-        return AdamState(torch.cat(rows, 0).float())
+    def from_gaussians(ctx: "Context", g: "Gaussians") -> "AdamState":
+        """Raw parameters of activated ones, zero moments and step count
+        (gsl_adam_init)."""
+        rows = 14 + 3 * (0 if g.sh is None else int(g.sh.shape[0]) // 3)
+        st = AdamState(torch.empty(rows, g.N, dtype=torch.float32, device=ctx.device))
+        gs, ss = g.struct(), st.struct()
+        A.check(A.lib().gsl_adam_init(ctx.h, C.byref(gs), C.byref(ss), _stream()))
+        return st
 
     def struct(self) -> A.AdamState:
         st = A.AdamState()
@@ -586,10 +595,15 @@ def ieskf_visual_update(HtH_cam, Htz_cam, A_imu, P, dx_prior=None, noise_var: fl
     """IESKF update of the IMU pose from one camera's photometric normal
     equations: H_imu = H_cam A, R = noise_var I (the per-pixel weights, if
     any, already applied)."""
-    HtH_cam = np.asarray(HtH_cam, np.float64)
-    Htz_cam = np.asarray(Htz_cam, np.float64)
-    A_imu = np.asarray(A_imu, np.float64)
-    return ieskf_pose_update(A_imu.T @ HtH_cam @ A_imu / noise_var, A_imu.T @ Htz_cam / noise_var, P, dx_prior)
+    HtH_cam = np.ascontiguousarray(HtH_cam, np.float64).reshape(36)
+    Htz_cam = np.ascontiguousarray(Htz_cam, np.float64).reshape(6)
+    A_imu = np.ascontiguousarray(A_imu, np.float64).reshape(36)
+    P = np.ascontiguousarray(P, np.float64).reshape(36)
+    dx = None if dx_prior is None else np.ascontiguousarray(dx_prior, np.float64).reshape(6)
+    delta, Pn = np.zeros(6), np.zeros(36)
+    A.check(A.lib().gsl_ieskf_visual_update(_dptr(HtH_cam), _dptr(Htz_cam), _dptr(A_imu), float(noise_var), _dptr(P),
+                                            None if dx is None else _dptr(dx), _dptr(delta), _dptr(Pn)))
+    return delta, Pn.reshape(6, 6)
 
 
 # ---------------------------------------------------------------- window

@@ -43,6 +43,52 @@ def test_adam_activate_matches_oracle(oracle):
         np.testing.assert_allclose(got[k], want[k], rtol=2e-6, atol=1e-7, err_msg=k)
 
 
+@pytest.mark.parametrize("sh_degree", [0, 2])
+def test_adam_init_matches_oracle(oracle, sh_degree):
+    """gsl_adam_init: raw rows = the oracle's inverse activation of the
+    activated parameters (log-scale, opacity logit, the rest as they are),
+    moments and step count zero; at a row stride above N (a window kept at a
+    fixed capacity) the padding columns are left alone."""
+    O = ops()
+    ctx = context()
+    N, ld = 2999, 3072
+    rng = np.random.default_rng(11)
+    act = {"mean": rng.normal(size=(3, N)), "scale": np.exp(rng.uniform(-5, 0, (3, N))),
+           "quat": rng.normal(size=(4, N)), "opacity": rng.uniform(1e-3, 1 - 1e-3, (1, N)),
+           "color": rng.uniform(0, 1, (3, N))}
+    K = (sh_degree + 1) ** 2 - 1
+    if K:
+        act["sh"] = rng.normal(0, 0.3, (3 * K, N))
+    act = {k: a.astype(np.float32) for k, a in act.items()}
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    g = O.Gaussians(t(act["mean"]), t(act["scale"]), t(act["quat"]), t(act["opacity"][0]), t(act["color"]),
+                    t(act["sh"]) if K else None)
+    rows = 14 + 3 * K
+    block = torch.full((3 * rows, ld), 7.0, dtype=torch.float32, device="cuda")
+    st = O.AdamState(block[:rows], block[rows:2 * rows], block[2 * rows:], n=N)
+    st.d_step.fill_(5)
+    gs, ss = g.struct(), st.struct()
+    import ctypes as C
+    from paper_2501_08672_amd import _abi as A
+    A.check(A.lib().gsl_adam_init(ctx.h, C.byref(gs), C.byref(ss), None))
+    torch.cuda.synchronize()
+    want = oracle.deactivate({k: a.astype(np.float64) for k, a in act.items()})
+    b = block.cpu().numpy()
+    # float32 log of float32 inputs: a few ulp of the result
+    np.testing.assert_allclose(b[:rows, :N], want, rtol=1e-6, atol=2e-7)
+    assert np.all(b[rows:, :N] == 0.0)
+    assert np.all(b[:, N:] == 7.0)
+    assert int(st.d_step.item()) == 0
+    # round trip through the activation
+    g2 = O.Gaussians(*(torch.empty_like(x) for x in (g.mean, g.scale, g.quat, g.opacity, g.color)),
+                     torch.empty_like(g.sh) if K else None)
+    O.adam_activate(ctx, st, g2)
+    torch.cuda.synchronize()
+    for k in ("mean", "scale", "quat", "opacity", "color") + (("sh",) if K else ()):
+        np.testing.assert_allclose(getattr(g2, k).cpu().numpy().reshape(-1, N), act[k].reshape(-1, N), rtol=2e-6,
+                                   atol=1e-7, err_msg=k)
+
+
 def test_adam_steps_match_oracle(oracle):
     """Three steps with changing gradients: raw values, moments and the
     activated outputs follow the oracle (float32 against float64)."""
@@ -92,7 +138,7 @@ def _optim_setup(O, ctx, seed=5):
     bt = O.bin_sort(ctx, cs, gt.N, o, pt)
     target, _, _ = O.render_fwd(ctx, cs, gt.N, o, pt, bt)
     g = O.Gaussians.from_scene(sc)
-    st = O.AdamState.from_gaussians(g)
+    st = O.AdamState.from_gaussians(ctx, g)
     O.adam_activate(ctx, st, g)
     win = O.Window(ctx, g, cs, o, target.clone(), loss="l1", headroom=1.5)
     return win, st

@@ -573,6 +573,35 @@ def test_window_graph_replay_and_variants():
     np.testing.assert_array_equal(w.image.cpu().numpy(), ref[3].cpu().numpy())
 
 
+def test_window_graph_follows_new_poses():
+    """New keyframe poses replay the cached graph (no new capture) and give
+    what an eager step at those poses gives: the camera table is uploaded
+    before each launch, not baked into the graph."""
+    O = ops()
+    sc = _scene_multi(3000, 47)
+    tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda")
+    w = _window(sc, tgt, 16, "l1")
+    w.step(use_graph=True)
+    torch.cuda.synchronize()
+    n0 = O.graph_count(w.ctx)
+    rng = np.random.default_rng(48)
+    for it in range(3):
+        for c in range(w.cams.C):
+            for j in range(3):
+                w.cams.arr[c].t_cw[j] += float(rng.normal(0, 0.01))
+        w.step(use_graph=True)
+        torch.cuda.synchronize()
+        assert w.status() == 0
+        assert O.graph_count(w.ctx) == n0, it
+        got = (w.image.clone(), float(w.d_loss.item()), w.grads.mean.clone(), w.grads.pose.clone())
+        w.step(use_graph=False)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], w.image), it
+        assert abs(got[1] - float(w.d_loss.item())) <= 1e-9 * abs(got[1])
+        torch.testing.assert_close(got[2], w.grads.mean, rtol=1e-5, atol=1e-6 * float(got[2].abs().max()))
+        torch.testing.assert_close(got[3], w.grads.pose, rtol=1e-5, atol=1e-6 * float(got[3].abs().max()))
+
+
 def test_profiled_steps_time_the_same_work():
     """The profiling hook on eager steps and on replays of the profiling
     graph: five positive stage times whose first four add up to the fifth,
