@@ -227,6 +227,24 @@ GSL_API int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camer
                    const float *dL_dimage, int accumulate, gsl_grads *grads, void *workspace,
                    size_t workspace_bytes, void *stream);
 
+/* gsl_render_bwd without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and error
+ * behaviour as gsl_render_bwd; its scratch memory (the camera table, the
+ * per-(camera, Gaussian) 2D gradients, 36 B each, and the per-block pose
+ * partials) lives in a file-scope device array of 160 MiB per GPU, created
+ * with the library's code object and held until the process ends.  Shapes
+ * whose scratch exceeds it (about C * N <= 4.6M records) are rejected with
+ * GSL_EINVAL before any launch; GSL_EHIP when the array's address could not
+ * be obtained at gsl_create.  The call allocates nothing.  Every call on one
+ * GPU shares that GPU's array and clears what it accumulates into at its
+ * start: calls that overlap on one GPU (other streams, other threads or
+ * contexts) race and must be serialised by the caller. */
+GSL_API int gsl_render_bwd_noalloc(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C,
+                                   const gsl_opts *opts, const gsl_proj *proj, const gsl_bins *bins,
+                                   const float *T_final, const uint32_t *n_walk, const float *dL_dimage,
+                                   int accumulate, gsl_grads *grads, void *stream);
+
 /* Work counts of the compositing on these bins (for throughput accounting):
  * d_counts[0] = (pixel, Gaussian) pairs the forward walk evaluates, up to
  * and including the one that stops it; d_counts[1] = contributing pairs;

@@ -27,7 +27,7 @@ _NAMES = {GSL_EINVAL: "EINVAL", GSL_ENOTSUP: "ENOTSUP", GSL_ECAPACITY: "ECAPACIT
           GSL_ESTATE: "ESTATE"}
 
 EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "gsl_layout", "gsl_workspace_size",
-           "gsl_project", "gsl_bin_sort", "gsl_render_fwd", "gsl_render_bwd", "gsl_render_stats", "gsl_window_step",
+           "gsl_project", "gsl_bin_sort", "gsl_render_fwd", "gsl_render_bwd", "gsl_render_bwd_noalloc", "gsl_render_stats", "gsl_window_step",
            "gsl_window_tune", "gsl_window_variant", "gsl_graph_count", "gsl_profile", "gsl_profile_read",
            "gsl_pose_jacobian_workspace_size", "gsl_pose_jacobian", "gsl_imu_to_camera_twist",
            "gsl_ieskf_pose_update", "gsl_ieskf_visual_update", "gsl_adam_init", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
@@ -110,6 +110,7 @@ def lib() -> C.CDLL:
     L.gsl_bin_sort.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, C.c_size_t, P]
     L.gsl_render_fwd.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, P, P, P, C.c_size_t, P]
     L.gsl_render_bwd.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, C.c_int, pgr, P, C.c_size_t, P]
+    L.gsl_render_bwd_noalloc.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, C.c_int, pgr, P]
     L.gsl_render_stats.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, P, C.c_size_t, P]
     L.gsl_window_variant.argtypes = [P, pc, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.gsl_graph_count.argtypes = [P, C.POINTER(C.c_int64)]

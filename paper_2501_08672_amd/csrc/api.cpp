@@ -86,6 +86,8 @@ struct gsl_ctx {
     std::mutex mu;
     std::map<VariantKey, int> variant;  // (window shapes, tile) -> fused variant
     std::map<VariantKey, GraphEntry> graphs;
+    void *scratch = nullptr;                   // device address of the static scratch array
+    hipError_t scratch_err = hipErrorNotReady;  // why it is NULL
 };
 
 namespace {
@@ -232,6 +234,29 @@ int prepare(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gs
     if (ws_bytes < p.W.total)
         return fail(GSL_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, p.W.total);
     return check_device(ctx);
+}
+
+// Scratch regions of the backward pass alone (camera table, 2D gradients,
+// pose partials), for gsl_render_bwd_noalloc.
+WsLayout bwd_scratch_layout(const Layout &L)
+{
+    WsLayout w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    w.cams = take(sizeof(DevCam) * (size_t)L.C);
+    w.g2d = take(4 * (size_t)L.M * kG2);
+    w.pose_blocks = (int32_t)((L.N + kPoseThreads - 1) / kPoseThreads);
+    w.pose_part = take(8 * (size_t)std::max<int64_t>(1, (int64_t)w.pose_blocks * L.C * 6));
+    w.pose_part_sh = take(8 * (size_t)std::max<int64_t>(1, (int64_t)w.pose_blocks * L.C * 6));
+    w.loss_part = take(8);
+    w.order = take(4);
+    w.misc = take(256);
+    w.total = o;
+    return w;
 }
 
 int check_gauss(const gsl_gaussians *g, bool need_all)
@@ -654,6 +679,10 @@ int gsl_create(gsl_ctx **out, int device)
         delete c;
         return fail(GSL_EHIP, "hipStreamCreateWithFlags failed");
     }
+    // device address of the static scratch array (gsl_render_bwd_noalloc);
+    // a failure here only disables that entry point
+    c->scratch_err = static_scratch_address(device, &c->scratch);
+    if (c->scratch_err != hipSuccess) c->scratch = nullptr;
     *out = c;
     g_err.clear();
     return GSL_OK;
@@ -772,6 +801,32 @@ int gsl_render_bwd(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams,
     if (!T_final || !n_walk || !dL_dimage) return fail(GSL_EINVAL, "input buffer is NULL");
     do_render_bwd(p, g, proj, bins, T_final, n_walk, dL_dimage, accumulate, grads, workspace, (hipStream_t)stream);
     return check_launch("gsl_render_bwd");
+}
+
+int gsl_render_bwd_noalloc(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C,
+                           const gsl_opts *opts, const gsl_proj *proj, const gsl_bins *bins, const float *T_final,
+                           const uint32_t *n_walk, const float *dL_dimage, int accumulate, gsl_grads *grads,
+                           void *stream)
+{
+    if (!ctx) return fail(GSL_EINVAL, "ctx is NULL");
+    GSL_TRY(check_gauss(g, false));
+    GSL_TRY(check_bins(bins));
+    if (!grads) return fail(GSL_EINVAL, "grads is NULL");
+    GSL_TRY(check_opts(opts));
+    Prepared p;
+    GSL_TRY(make_layout(cams, C, g->N, opts->tile, p.L, &p.dc));
+    p.W = bwd_scratch_layout(p.L);
+    p.o = dev_opts(opts);
+    if (p.W.total > kStaticScratchBytes)
+        return fail(GSL_EINVAL, "%d cameras x %d Gaussians need %zu bytes of scratch; the static array holds %zu",
+                    C, g->N, p.W.total, kStaticScratchBytes);
+    GSL_TRY(check_proj(proj, p.L));
+    if (!T_final || !n_walk || !dL_dimage) return fail(GSL_EINVAL, "input buffer is NULL");
+    GSL_TRY(check_device(ctx));
+    if (!ctx->scratch)
+        return fail(GSL_EHIP, "static scratch array unavailable: %s", hipGetErrorString(ctx->scratch_err));
+    do_render_bwd(p, g, proj, bins, T_final, n_walk, dL_dimage, accumulate, grads, ctx->scratch, (hipStream_t)stream);
+    return check_launch("gsl_render_bwd_noalloc");
 }
 
 int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,

@@ -152,6 +152,13 @@ struct WsLayout {
     int32_t pose_blocks = 0;
 };
 
+// noalloc.hip: the file-scope scratch array of gsl_render_bwd_noalloc (bytes
+// per GPU) and its device address on `device` (which must be current; looked
+// up once per device and cached).
+constexpr size_t kStaticScratchBytes = (size_t)160 << 20;
+constexpr int kMaxScratchDevices = 64;
+hipError_t static_scratch_address(int device, void **ptr);
+
 // Radix sort / scan geometry
 constexpr int kSortThreads = 512;
 constexpr int kSortItems = 8;

@@ -318,6 +318,20 @@ def render_bwd(ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, proj: Pro
     return out
 
 
+def render_bwd_noalloc(ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, proj: Proj, bins: Bins, T_final,
+                       n_walk, dL_dimage: torch.Tensor, accumulate: bool = False, out: Grads = None) -> Grads:
+    """gsl_render_bwd_noalloc: the backward pass on the library's static
+    scratch array (no workspace; the call allocates nothing when `out` is
+    given)."""
+    out = out or Grads(g.N, cams.C, ctx.device, g.sh_degree)
+    gs, ps, bs, gr = g.struct(), proj.struct(), bins.struct(), out.struct()
+    dl = dL_dimage.contiguous()
+    A.check(A.lib().gsl_render_bwd_noalloc(ctx.h, C.byref(gs), cams.arr, cams.C, C.byref(o), C.byref(ps),
+                                           C.byref(bs), _p(T_final), _p(n_walk), _p(dl), int(bool(accumulate)),
+                                           C.byref(gr), _stream()))
+    return out
+
+
 def render_stats(ctx: Context, cams: CameraSet, N: int, o: A.Opts, proj: Proj, bins: Bins):
     """(forward pairs evaluated, contributing pairs, backward pairs evaluated)."""
     counts = torch.zeros(3, dtype=torch.int64, device=ctx.device)

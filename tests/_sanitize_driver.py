@@ -85,7 +85,7 @@ def run_abi(path):
                            L.gsl_last_error().decode()]
     # every device entry point rejects NULL arguments on the host
     nulls = {"gsl_project": 9, "gsl_bin_sort": 10, "gsl_render_fwd": 13, "gsl_render_bwd": 15,
-             "gsl_render_stats": 11, "gsl_window_step": 16, "gsl_window_tune": 16,
+             "gsl_render_bwd_noalloc": 13, "gsl_render_stats": 11, "gsl_window_step": 16, "gsl_window_tune": 16,
              "gsl_pose_jacobian": 17, "gsl_adam_init": 4, "gsl_adam_activate": 4, "gsl_adam_step": 6,
              "gsl_window_optimize": 18, "gsl_voxel_keys": 8, "gsl_window_classify": 11, "gsl_window_compact": 16,
              "gsl_color_init": 11, "gsl_window_variant": 6, "gsl_graph_count": 2}

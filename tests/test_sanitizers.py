@@ -98,6 +98,6 @@ def test_abi_host_code_under_asan_ubsan(tmp_path):
     want = _run("abi", _abi.LIB_PATH)
     _close(got, want)
     # sanity of what was exercised
-    assert got["null_gsl_render_bwd"][0] == -1 and got["vis_bad"] == -1
+    assert got["null_gsl_render_bwd_noalloc"][0] == -1 and got["vis_bad"] == -1
     assert got["layout_c3_32"][:3] == [0, 0, 0] and got["layout_c3_32"][3] == 8 * 40 * 32
     assert got["bad_tile"][0] == -2 and "tile size 12" in got["bad_tile"][1]
