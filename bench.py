@@ -367,6 +367,20 @@ def sweep(args):
     ctx.close()
 
 
+def tune_table(ops, times, tile):
+    """The autotuner's grid of eager step times, tile -> LDS chunk depth ->
+    the five fused-kernel variants, and the configuration it chose (the
+    fastest at the chosen tile)."""
+    grid, k = {}, 0
+    for t in ops.TUNE_TILES:
+        grid[str(t)] = {}
+        for ch in ops.TUNE_CHUNKS:
+            grid[str(t)][str(ch)] = [round(x, 3) for x in times[k:k + ops.TUNE_VARIANTS]]
+            k += ops.TUNE_VARIANTS
+    best = min(((ms, int(ch), v) for ch, row in grid[str(tile)].items() for v, ms in enumerate(row)))
+    return {"grid_ms": grid, "chosen": {"tile": tile, "chunk": best[1], "variant": best[2], "ms": best[0]}}
+
+
 def main():
     args = parse()
     if args.sweep:
@@ -408,7 +422,7 @@ def main():
     tune_times = None
     if args.tile == 0:
         tile, tune_times = win.tune()
-        log(f"autotune: tile {tile}; ms per (tile, variant) tried: {['%.2f' % t for t in tune_times]}")
+        log(f"autotune: {json.dumps(tune_table(ops, tune_times, tile)['chosen'])}")
     else:
         win.opts = ops._opts_copy(o, tile=args.tile)
         win._alloc(None)
@@ -584,7 +598,7 @@ def main():
     if sh3 is not None:
         result["sh3_window"] = sh3
     if tune_times is not None:
-        result["autotune_ms"] = [round(t, 3) for t in tune_times]
+        result["autotune"] = tune_table(ops, tune_times, tile)
     if not args.no_cpu:
         log("oracle baseline on a pixel sample ...")
         result["cpu_baseline"] = cpu_baseline(sc, sc.cams, args.cpu_pixels)

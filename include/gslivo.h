@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define GSL_ABI_VERSION 2
+#define GSL_ABI_VERSION 3
 
 #ifndef GSL_API
 #define GSL_API __attribute__((visibility("default")))
@@ -74,6 +74,9 @@ typedef struct {
     float bg[3];     /* background colour (0) */
     float guard;     /* cull when the 2D mean lies beyond guard*W / guard*H outside the image (0.15) */
     int32_t tile;    /* tile edge in pixels: 8, 16 or 32 */
+    int32_t chunk;   /* splats the fused window kernel stages in LDS per chunk: 64, 128 or
+                      * 256; 0 = the one gsl_window_tune chose for these shapes, else 256
+                      * at tile 32 and 64 at tiles 16 and 8 (gsl_default_opts: 0) */
 } gsl_opts;
 
 /* Gaussians of the window (SoA, component-major, device).
@@ -282,11 +285,13 @@ GSL_API int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_came
                     double *d_loss, gsl_grads *grads, void *workspace, size_t workspace_bytes,
                     int use_graph, void *stream);
 
-/* Pins the fused-kernel variant gsl_window_step uses for these shapes (the
- * value gsl_window_tune would store): bit 0 persistent work queue, bit 1
- * longest list first, 4 = contiguous tile runs per XCD; 0..4 are valid. */
+/* Pins the fused-kernel variant and LDS chunk depth gsl_window_step uses
+ * for these shapes (what gsl_window_tune would store): variant bit 0
+ * persistent work queue, bit 1 longest list first, 4 = contiguous tile runs
+ * per XCD (0..4 are valid); chunk 64, 128 or 256, or 0 for the tile size's
+ * default. */
 GSL_API int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile,
-                               int32_t variant);
+                               int32_t variant, int32_t chunk);
 
 /* Number of HIP graphs the context holds (window steps and optimisation
  * loops recorded so far, at most 65 before the cache is flushed). */
@@ -302,14 +307,17 @@ GSL_API int gsl_graph_count(gsl_ctx *ctx, int64_t *count);
 GSL_API int gsl_profile(gsl_ctx *ctx, int enable);
 GSL_API int gsl_profile_read(gsl_ctx *ctx, float *ms, int32_t n);
 
-/* Autotuner for gsl_window_step: times every tile size in {8, 16, 32} and
- * every fused-kernel variant on the given window (eager launches on
- * `stream`, synchronising it), keeps the fastest variant per tile size in
- * the context and writes the fastest tile size to opts_inout->tile.  The
+/* Autotuner for gsl_window_step: times every tile size in {8, 16, 32}, every
+ * LDS chunk depth in {64, 128, 256} and every fused-kernel variant on the
+ * given window (eager launches on `stream`, synchronising it), keeps the
+ * fastest (variant, chunk) per tile size in the context and writes the
+ * fastest tile size to opts_inout->tile (opts_inout->chunk is left as it
+ * is; 0 uses the tuned chunk).  The
  * buffers must be sized for tile 8 (the largest T_total) and enough
  * capacity_K for every tile size; times_ms (may be NULL) receives up to
- * `ntimes` measured milliseconds in the order tried (tiles 8, 16, 32; per
- * tile the five variants 0..4 of gsl_window_variant). */
+ * `ntimes` measured milliseconds in the order tried: tiles 8, 16, 32; per
+ * tile the chunks 64, 128, 256; per chunk the five variants 0..4 (45 in
+ * all). */
 GSL_API int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, gsl_opts *opts_inout,
                     const float *target, int loss, gsl_proj *proj, gsl_bins *bins, double *d_loss,
                     gsl_grads *grads, void *workspace, size_t workspace_bytes, float *times_ms, int32_t ntimes,

@@ -48,7 +48,8 @@ class Camera(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("near_z", C.c_float), ("eps2d", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
-                ("T_min", C.c_float), ("bg", C.c_float * 3), ("guard", C.c_float), ("tile", C.c_int32)]
+                ("T_min", C.c_float), ("bg", C.c_float * 3), ("guard", C.c_float), ("tile", C.c_int32),
+                ("chunk", C.c_int32)]
 
 
 class Gaussians(C.Structure):
@@ -112,7 +113,7 @@ def lib() -> C.CDLL:
     L.gsl_render_bwd.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, C.c_int, pgr, P, C.c_size_t, P]
     L.gsl_render_bwd_noalloc.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, C.c_int, pgr, P]
     L.gsl_render_stats.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, P, C.c_size_t, P]
-    L.gsl_window_variant.argtypes = [P, pc, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.gsl_window_variant.argtypes = [P, pc, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.gsl_graph_count.argtypes = [P, C.POINTER(C.c_int64)]
     L.gsl_profile.argtypes = [P, C.c_int]
     L.gsl_profile_read.argtypes = [P, C.POINTER(C.c_float), C.c_int32]

@@ -84,7 +84,7 @@ struct gsl_ctx {
     hipEvent_t ev[kStages + 1] = {};
     bool ev_recorded = false;
     std::mutex mu;
-    std::map<VariantKey, int> variant;  // (window shapes, tile) -> fused variant
+    std::map<VariantKey, int> variant;  // (window shapes, tile) -> fused variant | chunk << 8
     std::map<VariantKey, GraphEntry> graphs;
     void *scratch = nullptr;                   // device address of the static scratch array
     hipError_t scratch_err = hipErrorNotReady;  // why it is NULL
@@ -103,6 +103,8 @@ int check_opts(const gsl_opts *o)
     if (!(o->near_z > 0.f)) return fail(GSL_EINVAL, "need near_z > 0");
     if (!(o->eps2d >= 0.f)) return fail(GSL_EINVAL, "need eps2d >= 0");
     if (!(o->guard >= 0.f)) return fail(GSL_EINVAL, "need guard >= 0");
+    if (o->chunk != 0 && o->chunk != 64 && o->chunk != 128 && o->chunk != 256)
+        return fail(GSL_EINVAL, "chunk %d not in {0, 64, 128, 256}", o->chunk);
     return GSL_OK;
 }
 
@@ -406,18 +408,39 @@ void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const fl
     a.image = image;
     a.target = target;
     a.loss = loss;
-    if (variant & 2) {
+    if (variant & 2) {  // bit 1 of the variant: longest list first
         uint32_t *order = at<uint32_t>(ws, p.W.order);
         launch_order_by_length(bins->ranges, p.L.T_total, order, s);
         a.order = order;
     }
     mark(kStRender);
-    launch_render_fused(a, variant, ctx->num_cus, s);
+    launch_render_fused(a, variant & 0xff, variant >> 8, ctx->num_cus, s);
     mark(kStProjectBwd);
     launch_reduce_f64(at<double>(ws, p.W.loss_part), p.L.T_total, d_loss, s);
     do_project_bwd(p, g, grads, 0, ws, s);
     mark(kStages);
     if (timed) ctx->ev_recorded = true;
+}
+
+// LDS chunk depth a tile size uses unless tuned or set: one staged splat per
+// lane of the workgroup.
+int default_chunk(int tile) { return tile == 32 ? 256 : 64; }
+
+VariantKey window_key(const Layout &L, const gsl_camera *cams);
+
+// Fused-kernel launch configuration of a window, variant | chunk << 8: the
+// tuned one for these shapes (else variant 0 and the tile's default chunk),
+// with opts->chunk, when set, in place of the chunk.
+int fused_config(gsl_ctx *ctx, const VariantKey &vk, const gsl_opts *opts)
+{
+    int cfg = default_chunk(opts->tile) << 8;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->variant.find(vk);
+        if (it != ctx->variant.end()) cfg = it->second;
+    }
+    if (opts->chunk) cfg = (cfg & 0xff) | (opts->chunk << 8);
+    return cfg;
 }
 
 VariantKey window_key(const Layout &L, const gsl_camera *cams)
@@ -660,6 +683,7 @@ void gsl_default_opts(gsl_opts *o)
     o->bg[0] = o->bg[1] = o->bg[2] = 0.f;
     o->guard = 0.15f;
     o->tile = 16;
+    o->chunk = 0;
 }
 
 int gsl_create(gsl_ctx **out, int device)
@@ -842,12 +866,7 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
     GSL_TRY(check_proj(proj, p.L));
     hipStream_t s = (hipStream_t)stream;
     const VariantKey vk = window_key(p.L, cams);
-    int variant = 0;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto it = ctx->variant.find(vk);
-        if (it != ctx->variant.end()) variant = it->second;
-    }
+    const int variant = fused_config(ctx, vk, opts);
     if (!use_graph) {
         do_window(ctx, p, g, target, loss, proj, bins, image, d_loss, grads, workspace, variant, s, ctx->profile);
         return check_launch("gsl_window_step");
@@ -872,14 +891,17 @@ int gsl_graph_count(gsl_ctx *ctx, int64_t *count)
     return GSL_OK;
 }
 
-int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, int32_t variant)
+int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, int32_t tile, int32_t variant,
+                       int32_t chunk)
 {
     if (!ctx) return fail(GSL_EINVAL, "ctx is NULL");
     if (variant < 0 || variant >= kVariants) return fail(GSL_EINVAL, "variant %d not in [0, %d)", variant, kVariants);
+    if (chunk != 0 && chunk != 64 && chunk != 128 && chunk != 256)
+        return fail(GSL_EINVAL, "chunk %d not in {0, 64, 128, 256}", chunk);
     Layout L;
     GSL_TRY(make_layout(cams, C, N, tile, L, nullptr));
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->variant[window_key(L, cams)] = variant;
+    ctx->variant[window_key(L, cams)] = variant | ((chunk ? chunk : default_chunk(tile)) << 8);
     return GSL_OK;
 }
 
@@ -932,7 +954,8 @@ int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
         if (rc != GSL_OK) break;
         float best = 1e30f;
         int best_v = 0;
-        for (int variant = 0; variant < kVariants; variant++) {
+        for (int cv = 0; cv < 3 * kVariants; cv++) {
+            const int variant = (cv % kVariants) | ((64 << (cv / kVariants)) << 8);
             // one untimed run, then check the capacity status
             do_window(ctx, p, g, target, loss, proj, bins, nullptr, d_loss, grads, workspace, variant, s);
             int32_t status = 0;
@@ -1031,12 +1054,7 @@ int gsl_window_optimize(gsl_ctx *ctx, gsl_adam_state *st, const gsl_adam *hp, gs
     GSL_TRY(check_proj(proj, p.L));
     hipStream_t s = (hipStream_t)stream;
     const VariantKey vk = window_key(p.L, cams);
-    int variant = 0;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto it = ctx->variant.find(vk);
-        if (it != ctx->variant.end()) variant = it->second;
-    }
+    const int variant = fused_config(ctx, vk, opts);
     // the camera table is uploaded once; the iterations read it from the workspace
     do_upload(p, workspace, s);
     auto enqueue = [&](hipStream_t q) {

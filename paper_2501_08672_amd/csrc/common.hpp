@@ -292,7 +292,8 @@ void launch_render_bwd(const RenderArgs &a, hipStream_t s);
 // bit 2: one workgroup per item with contiguous runs of tiles per XCD
 // (variants 0..4 are the distinct ones)
 constexpr int kVariants = 5;
-void launch_render_fused(const RenderArgs &a, int variant, int num_cus, hipStream_t s);
+// chunk: splats staged in LDS per chunk (64, 128 or 256)
+void launch_render_fused(const RenderArgs &a, int variant, int chunk, int num_cus, hipStream_t s);
 void launch_order_by_length(const uint32_t *ranges, int64_t T, uint32_t *order, hipStream_t s);
 // counts[3] (device, accumulated): forward pairs evaluated, contributors, backward pairs
 void launch_render_count(const RenderArgs &a, unsigned long long *counts, hipStream_t s);

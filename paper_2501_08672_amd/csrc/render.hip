@@ -51,6 +51,10 @@ constexpr float kPowScaleInv2 = 1.3862943611198906f;
 
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Does any active lane hold p?  The ballot's mask feeds the branch directly
+// (no round trip of the condition through a VGPR).
+__device__ __forceinline__ bool any_lane(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0ull; }
+
 // Where the pixels of a workgroup are.  Wave w owns a region of CW columns
 // by ROWS rows of the TS x TS tile: with four waves on a 32x32 tile each
 // takes a 16x16 quadrant (QUAD), otherwise a full-width strip of TS/NW rows.
@@ -240,14 +244,32 @@ __device__ __forceinline__ TileInfo<TS, NW> tile_info(const RenderArgs &a, int t
     return ti;
 }
 
+// Index of a chunk entry in a per-wave list: bytes while the chunk and its
+// sentinel (index CH) fit, else 16-bit.
 template <int CH>
+using list_t = typename std::conditional<(CH < 255), uint8_t, uint16_t>::type;
+
+// A chunk of CH staged splats (the LDS chunk depth, 64, 128 or 256) for a
+// workgroup of NWV waves.  Entry CH is a sentinel whose alpha is 0 at every
+// pixel (log2 opacity = -inf, no tile parts): the forward walk pads its lists
+// with it to whole groups of four entries.
+template <int CH, int NWV>
 struct Stage {
-    float4 p0[CH];  // mx, my, l11', l12'  (factor scaled by kPowScale)
-    float4 p1[CH];  // l22', log2(opacity), r, g
-    float p2[CH];   // b
-    uint32_t gid[CH];  // Gaussian index | band mask << 28
-    uint8_t wl[CH / kWave][CH];  // per wave: the chunk entries that reach its region, in order
+    float4 p0[CH + 1];  // mx, my, l11', l12'  (factor scaled by kPowScale)
+    float4 p1[CH + 1];  // l22', log2(opacity), r, g
+    float p2[CH + 1];   // b
+    uint32_t gid[CH + 1];  // Gaussian index | band mask << 28
+    list_t<CH> wl[NWV][CH + 4];  // per wave: the chunk entries that reach its region, in order
 };
+
+template <typename St, int CH>
+__device__ __forceinline__ void stage_sentinel(St &st)
+{
+    st.p0[CH] = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.p1[CH] = make_float4(0.f, -__builtin_inff(), 0.f, 0.f);
+    st.p2[CH] = 0.f;
+    st.gid[CH] = 0u;
+}
 
 // A projection record (mx, my, l11, l12 | l22, opacity, r, g | b ...) in the
 // staged form that eval_pair reads.
@@ -261,16 +283,29 @@ __device__ __forceinline__ void stage_splat(const float4 *__restrict__ r4, float
     p1.y = log2f(p1.y);
 }
 
-template <int CH>
-__device__ __forceinline__ void stage_load(Stage<CH> &st, const RenderArgs &a, const gsl_splat *__restrict__ rec,
-                                           uint32_t k, uint32_t end)
+// Stages list positions [start, min(start + CH, end)) into entries 0.. of the
+// chunk, each of the BS lanes of the workgroup loading every BS-th entry
+// (all loads of a lane issued before the first store).
+template <int CH, int BS, typename St>
+__device__ __forceinline__ void stage_load(St &st, const RenderArgs &a, const gsl_splat *__restrict__ rec,
+                                           uint32_t start, uint32_t end)
 {
-    if (k < end) {
-        const uint32_t val = a.gauss_ids[k];
-        const float4 *r4 = reinterpret_cast<const float4 *>(rec + (val & kGidMask));
-        stage_splat(r4, st.p0[threadIdx.x], st.p1[threadIdx.x]);
-        st.p2[threadIdx.x] = r4[2].x;
-        st.gid[threadIdx.x] = val;
+    constexpr int PER = CH > BS ? CH / BS : 1;
+    uint32_t val[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int e = (int)threadIdx.x + q * BS;
+        val[q] = (e < CH && start + (uint32_t)e < end) ? a.gauss_ids[start + e] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int e = (int)threadIdx.x + q * BS;
+        if (e < CH && start + (uint32_t)e < end) {
+            const float4 *r4 = reinterpret_cast<const float4 *>(rec + (val[q] & kGidMask));
+            stage_splat(r4, st.p0[e], st.p1[e]);
+            st.p2[e] = r4[2].x;
+            st.gid[e] = val[q];
+        }
     }
 }
 
@@ -309,10 +344,14 @@ __device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1
 // band test per splat and wave) in Stage::wl; returns its length.  Every lane
 // of the workgroup calls it after the chunk is staged; on return the lists
 // are visible to their waves.
+// The list is followed by sentinel entries up to the next multiple of four
+// (for lists with room for them).
 template <int TS, int NW, int CH, typename St>
 __device__ __forceinline__ int wave_list(St &st, int n, int wv, int lane)
 {
-    static_assert(CH <= 256, "list entries are bytes");
+    static_assert(CH <= 256, "chunk entries");
+    using L = typename std::remove_reference<decltype(st.wl[0][0])>::type;
+    constexpr int cap = sizeof(st.wl[0]) / sizeof(L);
     const uint64_t below = (1ull << lane) - 1ull;
     int c = 0;
 #pragma unroll
@@ -320,9 +359,10 @@ __device__ __forceinline__ int wave_list(St &st, int n, int wv, int lane)
         const int e = g + lane;
         const bool in = e < n && in_band<TS, NW>(st.gid[e], wv, 0);
         const uint64_t m = __ballot(in);
-        if (in) st.wl[wv][c + __popcll(m & below)] = (uint8_t)e;
+        if (in) st.wl[wv][c + __popcll(m & below)] = (L)e;
         c += __popcll(m);
     }
+    if (cap >= CH + 4 && lane < ((c + 3) & ~3) - c) st.wl[wv][c + lane] = (L)CH;
     __syncthreads();
     return c;
 }
@@ -365,9 +405,9 @@ constexpr int kHitWords = 128;  // 4096 positions
 
 // Forward walk over the tile list; every lane of the workgroup calls it.
 // `hits` (may be null) receives this wave's contribution bits.
-template <int TS, int NW, typename Counter>
+template <int TS, int NW, int CH, typename Counter>
 __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti,
-                                                                Stage<Geo<TS, NW>::CH> &st, Counter &cnt,
+                                                                Stage<CH, NW> &st, Counter &cnt,
                                                                 uint32_t *hits = nullptr)
 {
     using G = Geo<TS, NW>;
@@ -399,19 +439,25 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
         for (int k = 0; k < PPL; k++) o |= ps.T[k] > 0.f;
         return o;
     };
-    for (uint32_t start = ti.rs; start < ti.re; start += G::CH) {
+    if (threadIdx.x == 0) stage_sentinel<Stage<CH, NW>, CH>(st);
+    for (uint32_t start = ti.rs; start < ti.re; start += CH) {
         if (__syncthreads_count(open()) == 0) break;
-        stage_load<G::CH>(st, a, rec, start + threadIdx.x, ti.re);
+        stage_load<CH, G::BS>(st, a, rec, start, ti.re);
         __syncthreads();
-        const int n = (int)min((uint32_t)G::CH, ti.re - start);
+        const int n = (int)min((uint32_t)CH, ti.re - start);
         // With one band test per wave, the wave walks only the entries that
         // reach its region (a band the ellipse misses has alpha < alpha_min
         // everywhere), listed in order: no skip branch in the walk.
-        const int nw_list = G::ONE_BAND ? wave_list<TS, NW, G::CH>(st, n, wv, lane) : n;
-        for (int jj = 0; jj < nw_list; jj++) {
-            // finished pixels change nothing, so testing every fourth entry suffices
-            if ((jj & 3) == 0 && !__any(open())) break;
-            const int j = G::ONE_BAND ? __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]) : jj;
+        const int nw_list = G::ONE_BAND ? wave_list<TS, NW, CH>(st, n, wv, lane) : n;
+        // Groups of four entries, the last one padded with the sentinel, and
+        // the open-pixel test once per group (finished pixels change
+        // nothing): one exit from the loop, straight-line groups.
+        for (int j4 = 0; j4 < nw_list && any_lane(open()); j4 += 4)
+#pragma unroll 1
+        for (int u = 0; u < 4; u++) {
+            const int jj = j4 + u;
+            const int j = G::ONE_BAND ? __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj])
+                                      : (jj < nw_list ? jj : CH);
             const float4 p0 = st.p0[j];
             const float4 p1 = st.p1[j];
             const float cb = st.p2[j];
@@ -426,7 +472,7 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
                 // predicated: every lane evaluates, selects decide what changes
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const float T = ps.T[k];
-                cnt.eval(k, T > 0.f);
+                cnt.eval(k, T > 0.f && j < CH);  // the sentinel is not a pair
                 const bool hit = e.alpha >= amin;
                 const float Tn = T * (1.f - e.alpha);
                 const bool acc = hit && Tn >= Tmin;  // false for a finished pixel
@@ -446,8 +492,11 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
                     hbits = 0;
                     hword = wd;
                 }
-                if (__any(used)) hbits |= 1u << (pos & 31);
+                if (any_lane(used)) hbits |= 1u << (pos & 31);
             }
+            // keep the four entries of a group apart: hoisting their LDS
+            // reads ahead costs more registers than the waves have
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
     }
@@ -460,12 +509,11 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
 // The backward walk's list: entries that reach the wave's region, lie before
 // the wave's last contributor (pos < maxn) and, within the first 32 *
 // kHitWords positions, where the forward walk saw one of its contributors.
-template <int TS, int NW>
-__device__ __forceinline__ int wave_list_bwd(Stage<Geo<TS, NW>::CH> &st, int n, uint32_t pos0, uint32_t maxn,
+template <int TS, int NW, int CH>
+__device__ __forceinline__ int wave_list_bwd(Stage<CH, NW> &st, int n, uint32_t pos0, uint32_t maxn,
                                              const uint32_t *hits, int wv, int lane)
 {
-    constexpr int CH = Geo<TS, NW>::CH;
-    static_assert(CH <= 256, "list entries are bytes");
+    static_assert(CH <= 256, "chunk entries");
     const uint64_t below = (1ull << lane) - 1ull;
     int c = 0;
 #pragma unroll
@@ -475,7 +523,7 @@ __device__ __forceinline__ int wave_list_bwd(Stage<Geo<TS, NW>::CH> &st, int n, 
         bool in = e < n && pos < maxn && (!Geo<TS, NW>::ONE_BAND || in_band<TS, NW>(st.gid[e], wv, 0));
         if (in && hits && pos < 32u * kHitWords) in = ((hits[pos >> 5] >> (pos & 31)) & 1u) != 0u;
         const uint64_t m = __ballot(in);
-        if (in) st.wl[wv][c + __popcll(m & below)] = (uint8_t)e;
+        if (in) st.wl[wv][c + __popcll(m & below)] = (list_t<CH>)e;
         c += __popcll(m);
     }
     __syncthreads();
@@ -483,8 +531,8 @@ __device__ __forceinline__ int wave_list_bwd(Stage<Geo<TS, NW>::CH> &st, int n, 
 }
 
 // Backward walk.  Tf[k] is the final transmittance of pixel k, v its cotangent.
-template <int TS, int NW>
-__device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti, Stage<Geo<TS, NW>::CH> &st,
+template <int TS, int NW, int CH>
+__device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS, NW> &ti, Stage<CH, NW> &st,
                                          const float (&Tf)[Geo<TS, NW>::PPL],
                                          const uint32_t (&nw_in)[Geo<TS, NW>::PPL],
                                          const float (&v)[Geo<TS, NW>::PPL][3], uint32_t *s_max,
@@ -523,13 +571,14 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
     const int64_t lo = ti.rs;
     // the last list position any pixel of this wave walks to
     const uint32_t wave_max = __builtin_amdgcn_readfirstlane(wave_max_u32(lane_max));
-    for (int64_t end = lo + maxn; end > lo; end -= G::CH) {
-        const int64_t start = end - G::CH > lo ? end - G::CH : lo;
+    for (int64_t end = lo + maxn; end > lo; end -= CH) {
+        const int64_t start = end - CH > lo ? end - CH : lo;
         __syncthreads();
-        stage_load<G::CH>(st, a, rec, (uint32_t)(start + threadIdx.x), (uint32_t)end);
+        stage_load<CH, G::BS>(st, a, rec, (uint32_t)start, (uint32_t)end);
         __syncthreads();
         // the entries this wave has to visit, in order (walked in reverse)
-        const int nl = wave_list_bwd<TS, NW>(st, (int)(end - start), (uint32_t)(start - lo), wave_max, hits, wv, lane);
+        const int nl = wave_list_bwd<TS, NW, CH>(st, (int)(end - start), (uint32_t)(start - lo), wave_max, hits, wv,
+                                                 lane);
         for (int jj = nl - 1; jj >= 0; jj--) {
             const int j = __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]);
             const uint32_t pos = (uint32_t)(start - lo) + (uint32_t)j;
@@ -549,16 +598,21 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
                 if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;  // wave-uniform skips
-                if (!__any(pos < nw[k])) continue;
+                const bool inwalk = pos < nw[k];
+                if (!any_lane(inwalk)) continue;    // wave-uniform skips
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
-                const bool hit = pos < nw[k] && e.alpha >= amin;
-                if (!__any(hit)) continue;          // wave-uniform skip
+                const float ae = inwalk ? e.alpha : 0.f;
+                const bool hit = ae >= amin;        // one compare: its mask feeds the ballot
+                if (!any_lane(hit)) continue;
                 used = true;
-                // predicated from here: non-contributing lanes add zeros
-                const float r = rcp_fast(1.f - e.alpha);
-                const float Tk = hit ? T[k] * r : T[k];  // transmittance before this Gaussian
+                // predicated from here: a non-contributing lane takes alpha = 0,
+                // so its T stays (r = 1), its colour weight is 0 and its
+                // suffix does not change; its alpha gradient is zeroed below
+                const float al = hit ? ae : 0.f;
+                const float r = rcp_fast(1.f - al);
+                const float Tk = T[k] * r;  // transmittance before this Gaussian
                 T[k] = Tk;
-                const float w = hit ? e.alpha * Tk : 0.f;
+                const float w = al * Tk;
                 gc0 = fmaf(w, v[k][0], gc0);
                 gc1 = fmaf(w, v[k][1], gc1);
                 gc2 = fmaf(w, v[k][2], gc2);
@@ -596,10 +650,10 @@ template <int TS, int NW>
 __global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_render_fwd(RenderArgs a)
 {
     using G = Geo<TS, NW>;
-    __shared__ Stage<G::CH> st;
+    __shared__ Stage<G::CH, NW> st;
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, (int)blockIdx.x);
     NoCount nc;
-    const PixState<G::PPL> ps = fwd_walk<TS, NW>(a, ti, st, nc);
+    const PixState<G::PPL> ps = fwd_walk<TS, NW, G::CH>(a, ti, st, nc);
 #pragma unroll
     for (int k = 0; k < G::PPL; k++) {
         if (!ti.inside(k)) continue;
@@ -616,7 +670,7 @@ template <int TS, int NW>
 __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_bwd(RenderArgs a)
 {
     using G = Geo<TS, NW>;
-    __shared__ Stage<G::CH> st;
+    __shared__ Stage<G::CH, NW> st;
     __shared__ uint32_t s_max;
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, (int)blockIdx.x);
     float T[G::PPL], v[G::PPL][3];
@@ -635,12 +689,12 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_bwd(RenderArgs a)
             v[k][2] = a.dL_dimage[ti.plane0 + 2 * ti.npix + off];
         }
     }
-    bwd_walk<TS, NW>(a, ti, st, T, nw, v, &s_max);
+    bwd_walk<TS, NW, G::CH>(a, ti, st, T, nw, v, &s_max);
 }
 
 // Forward, per-pixel loss and its gradient, backward for one item.
-template <int TS, int NW>
-__device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<Geo<TS, NW>::CH> &st, uint32_t *s_max,
+template <int TS, int NW, int CH>
+__device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<CH, NW> &st, uint32_t *s_max,
                                            float *s_loss, uint32_t (*s_hits)[kHitWords])
 {
     using G = Geo<TS, NW>;
@@ -648,7 +702,7 @@ __device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<Geo
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, t);
     NoCount nc;
     uint32_t *hits = s_hits[threadIdx.x / kWave];
-    const PixState<PPL> ps = fwd_walk<TS, NW>(a, ti, st, nc, hits);
+    const PixState<PPL> ps = fwd_walk<TS, NW, CH>(a, ti, st, nc, hits);
     float v[PPL][3];
     float lsum = 0.f;
     const float inv = 1.f / (3.f * (float)ti.npix);
@@ -690,7 +744,7 @@ __device__ __forceinline__ void fused_item(const RenderArgs &a, int t, Stage<Geo
         for (int w = 0; w < NW; w++) tot += s_loss[w];
         a.loss_part[t] = tot;
     }
-    bwd_walk<TS, NW>(a, ti, st, ps.T, ps.nwalk, v, s_max, hits);
+    bwd_walk<TS, NW, CH>(a, ti, st, ps.T, ps.nwalk, v, s_max, hits);
 }
 
 // Item of workgroup b.  Workgroups are dispatched to the 8 XCDs round-robin
@@ -705,22 +759,22 @@ __device__ __forceinline__ int item_of_block(const RenderArgs &a, uint32_t b, bo
     return (int)((b & 7u) * chunk + (b >> 3));
 }
 
-template <int TS, int NW, bool XCD>
+template <int TS, int NW, bool XCD, int CH>
 __global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_render_fused(RenderArgs a)
 {
-    __shared__ Stage<Geo<TS, NW>::CH> st;
+    __shared__ Stage<CH, NW> st;
     __shared__ uint32_t s_max;
     __shared__ float s_loss[NW];
     __shared__ uint32_t s_hits[NW][kHitWords];
     const int t = item_of_block(a, blockIdx.x, XCD);
     if (t >= a.T_total) return;  // padding of the XCD-chunked grid (uniform per workgroup)
-    fused_item<TS, NW>(a, t, st, &s_max, s_loss, s_hits);
+    fused_item<TS, NW, CH>(a, t, st, &s_max, s_loss, s_hits);
 }
 
-template <int TS, int NW>
+template <int TS, int NW, int CH>
 __global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_render_fused_persistent(RenderArgs a)
 {
-    __shared__ Stage<Geo<TS, NW>::CH> st;
+    __shared__ Stage<CH, NW> st;
     __shared__ uint32_t s_max;
     __shared__ uint32_t s_item;
     __shared__ float s_loss[NW];
@@ -732,7 +786,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_re
         const uint32_t item = s_item;
         if (item >= (uint32_t)a.T_total) break;
         const int t = a.order ? (int)a.order[item] : (int)item;
-        fused_item<TS, NW>(a, t, st, &s_max, s_loss, s_hits);
+        fused_item<TS, NW, CH>(a, t, st, &s_max, s_loss, s_hits);
     }
 }
 
@@ -744,10 +798,10 @@ template <int TS, int NW>
 __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_count(RenderArgs a, unsigned long long *counts)
 {
     using G = Geo<TS, NW>;
-    __shared__ Stage<G::CH> st;
+    __shared__ Stage<G::CH, NW> st;
     const TileInfo<TS, NW> ti = tile_info<TS, NW>(a, (int)blockIdx.x);
     Count<G::PPL> cnt;
-    const PixState<G::PPL> ps = fwd_walk<TS, NW>(a, ti, st, cnt);
+    const PixState<G::PPL> ps = fwd_walk<TS, NW, G::CH>(a, ti, st, cnt);
     (void)ps;
     uint32_t nw = 0;
 #pragma unroll
@@ -1088,21 +1142,31 @@ void launch_count_t(const RenderArgs &a, unsigned long long *counts, hipStream_t
     constexpr int NW = Waves<TS>::NW;
     hipLaunchKernelGGL((k_render_count<TS, NW>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s, a, counts);
 }
-template <int TS>
-void launch_fused_t(const RenderArgs &a, int variant, int num_cus, hipStream_t s)
+template <int TS, int CH>
+void launch_fused_tc(const RenderArgs &a, int variant, int num_cus, hipStream_t s)
 {
     constexpr int NW = Waves<TS>::NW;
     if (variant & 1) {
         const int per_cu = 32 / NW;
         int64_t g = (int64_t)num_cus * per_cu;
         if (g > a.T_total) g = a.T_total;
-        hipLaunchKernelGGL((k_render_fused_persistent<TS, NW>), dim3((unsigned)g), dim3(Geo<TS, NW>::BS), 0, s, a);
+        hipLaunchKernelGGL((k_render_fused_persistent<TS, NW, CH>), dim3((unsigned)g), dim3(Geo<TS, NW>::BS), 0, s,
+                           a);
     } else if ((variant & 4) && !a.order) {
         const int64_t g = 8 * ((a.T_total + 7) / 8);
-        hipLaunchKernelGGL((k_render_fused<TS, NW, true>), dim3((unsigned)g), dim3(Geo<TS, NW>::BS), 0, s, a);
+        hipLaunchKernelGGL((k_render_fused<TS, NW, true, CH>), dim3((unsigned)g), dim3(Geo<TS, NW>::BS), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_render_fused<TS, NW, false>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0, s,
-                           a);
+        hipLaunchKernelGGL((k_render_fused<TS, NW, false, CH>), dim3((unsigned)a.T_total), dim3(Geo<TS, NW>::BS), 0,
+                           s, a);
+    }
+}
+template <int TS>
+void launch_fused_t(const RenderArgs &a, int variant, int chunk, int num_cus, hipStream_t s)
+{
+    switch (chunk) {
+    case 64: launch_fused_tc<TS, 64>(a, variant, num_cus, s); break;
+    case 128: launch_fused_tc<TS, 128>(a, variant, num_cus, s); break;
+    default: launch_fused_tc<TS, 256>(a, variant, num_cus, s); break;
     }
 }
 
@@ -1138,13 +1202,13 @@ void launch_render_bwd(const RenderArgs &a, hipStream_t s)
     }
 }
 
-void launch_render_fused(const RenderArgs &a, int variant, int num_cus, hipStream_t s)
+void launch_render_fused(const RenderArgs &a, int variant, int chunk, int num_cus, hipStream_t s)
 {
     if (a.T_total == 0) return;
     switch (a.o.tile) {
-    case 8: launch_fused_t<8>(a, variant, num_cus, s); break;
-    case 16: launch_fused_t<16>(a, variant, num_cus, s); break;
-    default: launch_fused_t<32>(a, variant, num_cus, s); break;
+    case 8: launch_fused_t<8>(a, variant, chunk, num_cus, s); break;
+    case 16: launch_fused_t<16>(a, variant, chunk, num_cus, s); break;
+    default: launch_fused_t<32>(a, variant, chunk, num_cus, s); break;
     }
 }
 

@@ -47,6 +47,12 @@ def _opts_copy(o: A.Opts, **kw) -> A.Opts:
     return n
 
 
+TUNE_TILES = (8, 16, 32)
+TUNE_CHUNKS = (64, 128, 256)
+TUNE_VARIANTS = 5
+TUNE_TIMES = len(TUNE_TILES) * len(TUNE_CHUNKS) * TUNE_VARIANTS
+
+
 class Context:
     """A gsl_ctx bound to one device, plus a growable scratch workspace."""
 
@@ -691,26 +697,29 @@ class Window:
             A.lib().gsl_profile(self.ctx.h, 0)
         return [float(x) for x in ms]
 
-    def set_variant(self, variant: int):
-        """Pin the fused-kernel variant for this window's shapes (see gsl_window_variant)."""
+    def set_variant(self, variant: int, chunk: int = 0):
+        """Pin the fused-kernel variant and LDS chunk depth (0: the tile's
+        default) for this window's shapes (see gsl_window_variant)."""
         A.check(A.lib().gsl_window_variant(self.ctx.h, self.cams.arr, self.cams.C, self.g.N, int(self.opts.tile),
-                                           int(variant)))
+                                           int(variant), int(chunk)))
 
     def status(self) -> int:
         return int(self.bins.d_status.item())
 
     def tune(self):
-        """Autotune tile size and fused variant; re-allocates for the chosen tile."""
+        """Autotune tile size, LDS chunk depth and fused variant; re-allocates
+        for the chosen tile.  Returns (tile, times) with the 45 times in the
+        order tile (8, 16, 32) x chunk (64, 128, 256) x variant (0..4)."""
         o8 = _opts_copy(self.opts, tile=8)
         save = self.opts
         self.opts = o8
         self._alloc(None)  # capacity and ranges for tile 8 bound every tile size
-        times = (C.c_float * 15)()
+        times = (C.c_float * TUNE_TIMES)()
         gs, ps, bs, gr = self.g.struct(), self.proj.struct(), self.bins.struct(), self.grads.struct()
         ot = _opts_copy(save)
         A.check(A.lib().gsl_window_tune(self.ctx.h, C.byref(gs), self.cams.arr, self.cams.C, C.byref(ot),
                                         _p(self.target), self.loss, C.byref(ps), C.byref(bs), _p(self.d_loss),
-                                        C.byref(gr), _p(self.ws), self.ws.numel(), times, 15, _stream()))
+                                        C.byref(gr), _p(self.ws), self.ws.numel(), times, TUNE_TIMES, _stream()))
         self.opts = ot
         self._alloc(None)
         return int(ot.tile), [float(t) for t in times]

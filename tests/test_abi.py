@@ -76,6 +76,12 @@ def test_default_opts_and_layout(abi):
     # sizes are host-only: no context needed
     assert abi.lib().gsl_workspace_size(None, arr, 2, 10, C.byref(o), 100, C.byref(n)) == abi.GSL_OK and n.value > 0
     assert abi.lib().gsl_workspace_size(None, arr, 2, 10, C.byref(o), 100, None) == abi.GSL_EINVAL
+    # LDS chunk depth: 0 (tuned or the tile's default), 64, 128 or 256
+    assert o.chunk == 0
+    for ch, rc in ((64, abi.GSL_OK), (128, abi.GSL_OK), (256, abi.GSL_OK), (96, abi.GSL_EINVAL), (512, abi.GSL_EINVAL)):
+        oc = abi.default_opts(16, chunk=ch)
+        assert abi.lib().gsl_workspace_size(None, arr, 2, 10, C.byref(oc), 100, C.byref(n)) == rc, ch
+    assert abi.lib().gsl_window_variant(None, arr, 2, 10, 16, 0, 64) == abi.GSL_EINVAL
     assert abi.lib().gsl_project(None, None, arr, 2, C.byref(o), None, None, 0, None) == abi.GSL_EINVAL
     assert "NULL" in abi.lib().gsl_last_error().decode()
 

@@ -121,13 +121,16 @@ def test_fused_window_step_vs_oracle(oracle, name, tile, loss):
     want = case["grads"][loss]
     nflag = sum(int(((r["flags"] & 1) != 0).sum()) for r in case["refs"])
     print(f"{name} tile {tile} {loss}: flag-1 pixels {nflag} of {sum(r['flags'].size for r in case['refs'])}")
-    for variant in range(5):
-        w.set_variant(variant)
-        for use_graph in (False, True):
+    # every variant at every LDS chunk depth eagerly, and every variant replayed
+    # as a graph at the tile's default depth
+    configs = [(v, ch, False) for v in range(5) for ch in (64, 128, 256)] + [(v, 0, True) for v in range(5)]
+    for variant, chunk, use_graph in configs:
+        w.set_variant(variant, chunk)
+        if True:
             for _ in range(2 if use_graph else 1):
                 w.step(use_graph=use_graph)
             torch.cuda.synchronize()
-            tag = f"{name} tile {tile} variant {variant} graph {use_graph} {loss}"
+            tag = f"{name} tile {tile} variant {variant} chunk {chunk} graph {use_graph} {loss}"
             assert w.status() == 0, tag
             imgs = unpack_np(cs, w.image)
             for c, r in enumerate(case["refs"]):
@@ -201,12 +204,12 @@ def test_bench_window_fused_vs_oracle(bench_case, loss):
     sc = bench_case["scene"]
     g = O.Gaussians.from_scene(sc)
     w = O.Window(ctx, g, bench_case["cams"], O.opts(32), bench_case["target"], loss=loss, keep_image=True)
-    for variant in range(5):
-        w.set_variant(variant)
+    for variant, chunk in [(v, 0) for v in range(5)] + [(0, 64), (0, 128), (2, 64)]:
+        w.set_variant(variant, chunk)
         for _ in range(2):
             w.step(use_graph=True)
         torch.cuda.synchronize()
-        tag = f"bench window variant {variant} {loss}"
+        tag = f"bench window variant {variant} chunk {chunk} {loss}"
         assert w.status() == 0, tag
         assert torch.equal(w.image, bench_case["image"]), tag
         want, bound = bench_case["loss"][loss], bench_case["bound"][loss]

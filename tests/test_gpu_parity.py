@@ -627,16 +627,17 @@ def test_profiled_steps_time_the_same_work():
     assert torch.equal(w.image, ref[0])
 
 
-@pytest.mark.parametrize("tile", [16, 32])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_window_variants_agree(tile):
     """Every fused-kernel variant (plain, persistent, longest first, both,
-    XCD-chunked) gives the same image, loss and gradients."""
+    XCD-chunked) at every LDS chunk depth gives the same image, loss and
+    gradients."""
     sc = _scene_multi(3000, 43)
     tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda")
     w = _window(sc, tgt, tile, "l1")
     res = []
-    for variant in range(5):
-        w.set_variant(variant)
+    for variant, chunk in [(v, ch) for v in range(5) for ch in (64, 128, 256)]:
+        w.set_variant(variant, chunk)
         w.step(use_graph=False)
         torch.cuda.synchronize()
         res.append((w.image.clone(), float(w.d_loss.item()), w.grads.mean.clone(), w.grads.pose.clone()))
