@@ -61,13 +61,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=320, help="oracle sample: pixels per camera")
+    ap.add_argument("--cpu-pixels", type=int, default=1024, help="oracle sample: pixels per camera")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-jac", action="store_true", help="skip the pose-Jacobian measurement")
     ap.add_argument("--no-window-update", action="store_true", help="skip the window-update measurement")
     ap.add_argument("--no-sh", action="store_true", help="skip the SH-colour window measurement")
     ap.add_argument("--no-optimize", action="store_true", help="skip the 10-iteration optimisation loop")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the 1k forward, 100k forward+backward and 2M uneven-batch measurements")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line: window step time vs N in {20k, 100k, 500k, 2M} at "
                          "640x512 and 1280x1024 (8 keyframes), one JSON line per point")
@@ -97,6 +99,32 @@ def read_traffic():
         w = float(kv["copy_bytes"]) / (float(kv["copy_write_kib"]) * 1024)
         return float(kv["fused_fetch_kib"]) * 1024 * f + float(kv["fused_write_kib"]) * 1024 * w
     except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
+COUNTER_FILE = os.path.join(ROOT, "profiles", "fused_render_counters.txt")
+# L2 atomic requests the MI355X can retire per second, derived (no published
+# figure): one request per L2 channel per clock, 16 channels in each of the 8
+# XCDs at 2.4 GHz
+L2_ATOMIC_PEAK_PER_S = 8 * 16 * 2.4e9
+
+
+def read_atomics():
+    """(L2 atomic requests, atomic wave instructions) per fused launch from
+    the committed SQ/TCC counter summary, or None when it is missing or was
+    taken on a different render.hip."""
+    if not os.path.exists(COUNTER_FILE):
+        return None
+    kv = {}
+    for ln in open(COUNTER_FILE):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("render_hip_sha1") != source_digest():
+            return None
+        return float(kv["TCC_ATOMIC"]), float(kv["TA_FLAT_ATOMIC_WAVEFRONTS"])
+    except (KeyError, ValueError):
         return None
 
 
@@ -223,6 +251,110 @@ def optimize_bench(ctx, ops, torch, g, win):
     return {"iters": OPT_ITERS, "ms": round(t_opt * 1e3, 4), "ms_per_iter": round(t_opt * 1e3 / OPT_ITERS, 4),
             "last_losses": [round(float(x), 6) for x in losses[[0, -1]].cpu().tolist()],
             "how": "gsl_window_optimize: 10 x (window step + Adam step over the 500k raw parameters), one graph"}
+
+
+def _target_image(ops, ctx, cs, tgt_sc, tile=16):
+    gt = ops.Gaussians.from_scene(tgt_sc)
+    o = ops.opts(tile)
+    pt = ops.project(ctx, gt, cs, o)
+    bt = ops.bin_sort(ctx, cs, gt.N, o, pt)
+    target, _, _ = ops.render_fwd(ctx, cs, gt.N, o, pt, bt)
+    return target
+
+
+def _timed_steps(torch, win, steps):
+    """Median of HIP-event times around `steps` graph replays of the window step (ms)."""
+    for _ in range(3):
+        win.step(True)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    for k in range(steps):
+        evs[2 * k].record()
+        win.step(True)
+        evs[2 * k + 1].record()
+    torch.cuda.synchronize()
+    assert win.status() == 0, "instance capacity exceeded"
+    return float(np.median([evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(steps)]))
+
+
+def workloads_bench(ctx, ops, S, torch, steps, with_oracle):
+    """The other workloads of the metric, beside the headline window:
+    the 1k / 128x96 plain forward render (ms per frame: project + bin_sort +
+    render_fwd, eager, tile 16), the 100k / 640x512 forward + backward
+    (L1, tuned window step replayed as a graph, Mpixels/s) and the 2M /
+    16-camera uneven batch (tuned tile, chunk and variant, graph, Mpixels/s);
+    with the oracle's full-frame times for the first two."""
+    from oracle import oracle as O
+    out = {}
+    # 1k Gaussians, one 128x96 camera: plain forward
+    sc1 = S.config1()
+    cs1 = ops.CameraSet(sc1.cams)
+    g1 = ops.Gaussians.from_scene(sc1)
+    o1 = ops.opts(16)
+    proj = ops.project(ctx, g1, cs1, o1)
+    bins = ops.bin_sort(ctx, cs1, g1.N, o1, proj)
+    ops.render_fwd(ctx, cs1, g1.N, o1, proj, bins)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(20, steps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ops.project(ctx, g1, cs1, o1, out=proj)
+        ops.bin_sort(ctx, cs1, g1.N, o1, proj, capacity=bins.capacity, bins=bins, grow=False)
+        ops.render_fwd(ctx, cs1, g1.N, o1, proj, bins)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    c1 = {"workload": "plain forward render: 1,000 Gaussians, one 128x96 camera, tile 16",
+          "fwd_ms_per_frame": round(float(np.median(times)), 4), "instances_K": bins.K,
+          "how": "project + bin_sort + render_fwd, eager launches, HIP events, median"}
+    if with_oracle:
+        O.build(force=False)
+        t0 = time.perf_counter()
+        O.render_image(sc1, sc1.cams[0], O.Opts())
+        c1["oracle_fwd_ms_per_frame"] = round((time.perf_counter() - t0) * 1e3, 2)
+    out["config1"] = c1
+    del proj, bins
+    # 100k Gaussians, one 640x512 camera: forward + backward, L1
+    sc2, tgt2 = S.config2()
+    cs2 = ops.CameraSet(sc2.cams)
+    target = _target_image(ops, ctx, cs2, tgt2)
+    win = ops.Window(ctx, ops.Gaussians.from_scene(sc2), cs2, ops.opts(16), target, loss="l1")
+    tile, _ = win.tune()
+    ms = _timed_steps(torch, win, steps)
+    c2 = {"workload": "forward + backward: 100k Gaussians, one 640x512 camera, L1 against a jittered copy",
+          "tile": tile, "ms_per_step": round(ms, 4), "mpix_s": round(cs2.P_total / (ms * 1e-3) / 1e6, 2),
+          "instances_K": win.bins.K, "how": "tuned window step replayed as a graph, HIP events, median"}
+    del win
+    if with_oracle:
+        cam = sc2.cams[0]
+        rng = np.random.default_rng(7)
+        t0 = time.perf_counter()
+        O.render_image(sc2, cam, O.Opts())
+        t1 = time.perf_counter()
+        O.render_bwd(sc2, [cam], [rng.normal(size=(3, cam.height, cam.width))], O.Opts())
+        t2 = time.perf_counter()
+        c2["oracle"] = {"fwd_s": round(t1 - t0, 2), "bwd_s": round(t2 - t1, 2),
+                        "mpix_s": round(cs2.P_total / (t2 - t0) / 1e6, 6), "cores": O.num_threads(),
+                        "how": "full frame, forward then the adjoint of a random cotangent image"}
+    out["config2"] = c2
+    # 2M Gaussians, 16 cameras of mixed resolution
+    sc5, tgt5 = S.config5()
+    cs5 = ops.CameraSet(sc5.cams)
+    target = _target_image(ops, ctx, cs5, tgt5)
+    win = ops.Window(ctx, ops.Gaussians.from_scene(sc5), cs5, ops.opts(16), target, loss="l1")
+    tile, times5 = win.tune()
+    ms = _timed_steps(torch, win, steps)
+    out["config5"] = {"workload": "uneven batch: 2M surfel Gaussians on 200 planes, 16 cameras from 320x256 to "
+                                  "1920x1080, each seeing 50k-600k Gaussians, L1",
+                      "pixels": cs5.P_total, "ms_per_step": round(ms, 4),
+                      "mpix_s": round(cs5.P_total / (ms * 1e-3) / 1e6, 2), "instances_K": win.bins.K,
+                      "autotune": tune_table(ops, times5, tile),
+                      "how": "tuned tile, LDS chunk depth and variant; window step replayed as a graph, HIP "
+                             "events, median"}
+    del win
+    torch.cuda.empty_cache()
+    return out
 
 
 def sh_window_bench(ctx, ops, S, torch, sc, cs, target, tile, steps=10):
@@ -540,12 +672,18 @@ def main():
         win_upd = window_update_bench(ctx, ops, S, torch)
         log(f"window update: {win_upd}")
 
+    workloads = None
+    if not args.no_workloads:
+        workloads = workloads_bench(ctx, ops, S, torch, 20, not args.no_cpu)
+        log(f"workloads: {workloads}")
+
     pose_jac = None
     if not args.no_jac:
         pose_jac = pose_jacobian_bench(ctx, ops, S, torch)
         log(f"pose Jacobian batch: {pose_jac}")
 
     traffic = read_traffic()
+    atomics = read_atomics()
     result = {
         "metric": "fwd+bwd Mpixels/s at 500k Gaussians, 8-frame window; fwd ms/frame",
         "value": round(mpix, 2),
@@ -581,6 +719,14 @@ def main():
                      "algorithmic_flops": int(flops),
                      "pairs": {"fwd_evaluated": ev_f, "contributors": n_contrib, "bwd_evaluated": ev_b,
                                "fwd_per_pixel": round(ev_f / P, 2), "contributors_per_pixel": round(n_contrib / P, 2)},
+                     "atomics": None if atomics is None else {
+                         "l2_requests_per_launch": int(atomics[0]), "wave_instructions_per_launch": int(atomics[1]),
+                         "l2_requests_per_s": round(atomics[0] / (fused_ms * 1e-3), 0),
+                         "peak_per_s": L2_ATOMIC_PEAK_PER_S,
+                         "frac": round(atomics[0] / (fused_ms * 1e-3) / L2_ATOMIC_PEAK_PER_S, 4),
+                         "source": "TCC_ATOMIC and TA_FLAT_ATOMIC_WAVEFRONTS per dispatch from the committed "
+                                   "counter summary of the same render.hip; peak derived: one request per L2 "
+                                   "channel per clock, 8 XCDs x 16 channels x 2.4 GHz"},
                      "hbm_view": {"algorithmic_bytes": int(fused_bytes),
                                   "gbs": round(fused_bytes / (fused_ms * 1e-3) / 1e9, 1),
                                   "frac": round(fused_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
@@ -589,6 +735,8 @@ def main():
                        "copy_peak_gbs": round(copy_gbs, 1),
                        "frac_of_copy_peak": round(step_bytes / t_win / 1e9 / copy_gbs, 4)},
     }
+    if workloads is not None:
+        result["workloads"] = workloads
     if optimize is not None:
         result["optimize"] = optimize
     if pose_jac is not None:

@@ -340,6 +340,32 @@ __device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1
     return e;
 }
 
+// One front-to-back step of a pixel of transmittance T (negative once the
+// pixel is finished) past a Gaussian of alpha a: hit = a >= alpha_min; the
+// transmittance behind it T (1 - a), formed as T - a T with one rounding; the
+// Gaussian contributes when hit and that stays >= T_min (never for a finished
+// pixel, whose product is negative).  The colour weight is T minus the new
+// transmittance (a T up to that rounding, 0 when it does not contribute), so
+// the weights of a pixel add up to 1 - T_final.  A hit that would cross T_min
+// finishes the pixel (T becomes -|T|).  Every walk that composites uses this,
+// so their images agree bit for bit.
+struct CompStep {
+    float T, w;
+    bool acc;
+};
+
+__device__ __forceinline__ CompStep comp_step(float T, float a, float amin, float Tmin)
+{
+    CompStep r;
+    const bool hit = a >= amin;
+    const float Tn = fmaf(-T, a, T);
+    r.acc = hit && Tn >= Tmin;
+    const float Tsel = r.acc ? Tn : T;
+    r.w = T - Tsel;
+    r.T = (hit && !r.acc) ? -fabsf(T) : Tsel;
+    return r;
+}
+
 // Builds this wave's list of the chunk entries that reach its region (one
 // band test per splat and wave) in Stage::wl; returns its length.  Every lane
 // of the workgroup calls it after the chunk is staged; on return the lists
@@ -473,16 +499,14 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const float T = ps.T[k];
                 cnt.eval(k, T > 0.f && j < CH);  // the sentinel is not a pair
-                const bool hit = e.alpha >= amin;
-                const float Tn = T * (1.f - e.alpha);
-                const bool acc = hit && Tn >= Tmin;  // false for a finished pixel
-                cnt.contrib(k, acc);
-                const float w = acc ? e.alpha * T : 0.f;
-                ps.C0[k] = fmaf(w, p1.z, ps.C0[k]);
-                ps.C1[k] = fmaf(w, p1.w, ps.C1[k]);
-                ps.C2[k] = fmaf(w, cb, ps.C2[k]);
-                ps.T[k] = acc ? Tn : (hit ? -fabsf(T) : T);
-                ps.nwalk[k] = acc ? pos1 : ps.nwalk[k];
+                const CompStep cs = comp_step(T, e.alpha, amin, Tmin);
+                cnt.contrib(k, cs.acc);
+                ps.C0[k] = fmaf(cs.w, p1.z, ps.C0[k]);
+                ps.C1[k] = fmaf(cs.w, p1.w, ps.C1[k]);
+                ps.C2[k] = fmaf(cs.w, cb, ps.C2[k]);
+                ps.T[k] = cs.T;
+                ps.nwalk[k] = cs.acc ? pos1 : ps.nwalk[k];
+                const bool acc = cs.acc;
                 used = used || acc;
             }
             if (hits) {
@@ -958,11 +982,10 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
             for (int k = 0; k < PPL; k++) {
                 if (!G::ONE_BAND && !in_band<TS, NW>(val, wv, k)) continue;
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
-                const bool hit = e.alpha >= amin;
-                const float Tn = T[k] * (1.f - e.alpha);
-                const bool acc = hit && Tn >= Tmin;  // false for a finished pixel
-                if (!__any(acc)) {
-                    T[k] = hit ? -fabsf(T[k]) : T[k];
+                const CompStep cs = comp_step(T[k], e.alpha, amin, Tmin);
+                const bool acc = cs.acc;
+                if (!any_lane(acc)) {
+                    T[k] = cs.T;
                     continue;
                 }
                 // a contributor moves the state; others act as alpha = 0, dalpha = 0
@@ -996,7 +1019,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
                     dC[k][2][q] = fmaf(cb, w, dC[k][2][q]);
                     dT[k][q] = fmaf(dT[k][q], 1.f - al, -Tk * da[q]);
                 }
-                const float wgt = al * Tk;
+                const float wgt = cs.w;  // al Tk up to the rounding of the transmittance
                 if (SHC) {  // the colour's own derivative along dt: + alpha T dc
                     const float4 c0 = st.t[7][j], c1 = st.t[8][j], c2 = st.t[9][j];
                     const float dc[9] = {c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x, c2.y, c2.z};
@@ -1008,7 +1031,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
                 C0[k] = fmaf(wgt, p1.z, C0[k]);
                 C1[k] = fmaf(wgt, p1.w, C1[k]);
                 C2[k] = fmaf(wgt, cb, C2[k]);
-                T[k] = acc ? Tn : (hit ? -fabsf(Tk) : Tk);
+                T[k] = cs.T;
             }
         }
         __syncthreads();

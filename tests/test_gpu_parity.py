@@ -645,7 +645,8 @@ def test_window_variants_agree(tile):
         assert torch.equal(img, res[0][0])
         assert abs(loss - res[0][1]) <= 1e-9 * abs(res[0][1])
         torch.testing.assert_close(gm, res[0][2], rtol=1e-5, atol=1e-6 * float(res[0][2].abs().max()))
-        torch.testing.assert_close(gp, res[0][3], rtol=1e-5, atol=1e-9)
+        # float32 atomics add the 2D gradients in a variant-dependent order
+        torch.testing.assert_close(gp, res[0][3], rtol=1e-5, atol=1e-6 * float(res[0][3].abs().max()))
 
 
 def test_rasterize_autograd():
