@@ -312,23 +312,29 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     uint32_t *hist = at<uint32_t>(ws, W.hist), *hist_off = at<uint32_t>(ws, W.hist_off);
     uint64_t *partial = at<uint64_t>(ws, W.partial);
     // 1. depth order of the records that reach a tile (ties by record index =
-    // Gaussian index per camera); the first pass drops the others
+    // Gaussian index per camera); the first pass reads the projection's depth
+    // keys and tile counts directly and drops the records that reach no tile,
+    // the last pass also writes each kept record's tile count in depth order
+    // (positions beyond the kept records are never read)
     int64_t *d_V = at<int64_t>(ws, W.misc + 64);
-    launch_depth_keys(proj->depth_keys, proj->tiles_touched, L.M, dkey, dval, s);
+    uint32_t *counts = at<uint32_t>(ws, W.counts), *offsets = at<uint32_t>(ws, W.offsets);
     uint32_t *totals = at<uint32_t>(ws, W.rs_totals);
-    int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, totals, s, d_V);
+    DepthSortIO io;
+    io.first_keys = proj->depth_keys;
+    io.first_tiles = proj->tiles_touched;
+    io.gather_tiles = proj->tiles_touched;
+    io.counts_out = counts;
+    int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, totals, s, d_V, &io);
     const uint32_t *order = where ? dval2 : dval;
     // 2. instance offsets in that order
-    uint32_t *counts = at<uint32_t>(ws, W.counts), *offsets = at<uint32_t>(ws, W.offsets);
-    launch_gather_counts(order, proj->tiles_touched, L.M, d_V, counts, s);
-    launch_scan_u32(counts, offsets, L.M, partial, bins->d_K, s);
+    launch_scan_u32(counts, offsets, L.M, partial, bins->d_K, s, d_V);
     // 3. emit and sort by tile; the pass count decides which buffer is emitted into
     const int passes = (L.tile_bits + 7) / 8;
     uint32_t *ek = bins->tile_ids, *ev = bins->gauss_ids;
     uint32_t *ak = at<uint32_t>(ws, W.ikey2), *av = at<uint32_t>(ws, W.ival2);
     if (passes & 1) std::swap(ek, ak), std::swap(ev, av);
     launch_emit(order, offsets, counts, proj->binrecs, at<DevCam>(ws, W.cams), L, bins->d_K, bins->capacity_K, ek, ev,
-                bins->d_status, at<uint32_t>(ws, W.big), at<uint32_t>(ws, W.misc + 128), s);
+                bins->d_status, at<uint32_t>(ws, W.big), at<uint32_t>(ws, W.misc + 128), d_V, s);
     launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, totals, s);
     // 4. per-tile ranges
     launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);

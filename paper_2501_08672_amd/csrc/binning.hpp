@@ -21,72 +21,44 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane)
     return v;
 }
 
-// Extreme dy (sgn = +1: largest, -1: smallest) of the ellipse
-// |L d|^2 <= kq on the vertical line dx = const: the roots of
-// (l12^2 + l22^2) dy^2 + 2 l11 l12 dx dy + l11^2 dx^2 - kq = 0.
-__device__ __forceinline__ float ellipse_dy_on_line(const EllipseTest &e, float dx, float sgn)
+// Which parts of tile (tx, ty) the splat's alpha_min ellipse reaches: for
+// 32x32 tiles the 16x16 quadrants (bit 2 * row half + column half), for 16x16
+// tiles the quarter-row bands (bit q: rows [4q, 4q + 4)), for 8x8 tiles none.
+// A part is marked when the ellipse reaches the rectangle of its pixel
+// centres (clipped to the image): the same exact test as the tile's, on the
+// part, so a pixel of an unmarked part has alpha < alpha_min.
+__device__ __forceinline__ uint32_t tile_parts(const EllipseTest &e, int W, int H, int tile, int tx, int ty)
 {
-    const float cc = fmaf(e.l12, e.l12, e.l22 * e.l22);
-    const float u = e.l22 * e.l11 * dx;
-    const float disc = fmaxf(fmaf(cc, e.kq, -u * u), 0.f);
-    // approximate reciprocal: the band test only has to be conservative, and
-    // the +0.01 in kq leaves far more room than its error
-    return (fmaf(sgn, sqrtf(disc), -e.l11 * e.l12 * dx)) * __builtin_amdgcn_rcpf(cc);
-}
-
-// The rows (relative to the mean) that the ellipse reaches within the
-// column strip [ux0, ux1] (relative to the mean): the ellipse and the strip
-// are convex, so these form one interval [lo, hi].  Its top is the
-// ellipse's topmost point (dy = sqrt(kq) / l22 at dx = kh dy) when that lies
-// within the strip, else the top of the ellipse on the strip edge nearest to
-// it; likewise the bottom.
-__device__ __forceinline__ void ellipse_rows_in_strip(const EllipseTest &e, float ux0, float ux1, float &lo,
-                                                      float &hi)
-{
-    const float yext = sqrtf(e.kq) * __builtin_amdgcn_rcpf(e.l22);
-    const float xt = e.kh * yext;  // dx of the topmost point; the bottommost is at -xt
-    hi = (xt >= ux0 && xt <= ux1) ? yext : ellipse_dy_on_line(e, fminf(fmaxf(xt, ux0), ux1), 1.f);
-    lo = (-xt >= ux0 && -xt <= ux1) ? -yext : ellipse_dy_on_line(e, fminf(fmaxf(-xt, ux0), ux1), -1.f);
+    uint32_t b = 0;
+    if (tile == 32) {
+#pragma unroll
+        for (int rh = 0; rh < 2; rh++)
+#pragma unroll
+            for (int ch = 0; ch < 2; ch++) {
+                const float x0 = (float)(tx * 32 + ch * 16) + 0.5f, x1 = (float)min(tx * 32 + ch * 16 + 16, W) - 0.5f;
+                const float y0 = (float)(ty * 32 + rh * 16) + 0.5f, y1 = (float)min(ty * 32 + rh * 16 + 16, H) - 0.5f;
+                if (x0 <= x1 && y0 <= y1 && ellipse_hits_rect(e, x0, x1, y0, y1)) b |= 1u << (2 * rh + ch);
+            }
+    } else if (tile == 16) {
+        const float x0 = (float)(tx * 16) + 0.5f, x1 = (float)min(tx * 16 + 16, W) - 0.5f;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const float y0 = (float)(ty * 16 + 4 * q) + 0.5f, y1 = (float)min(ty * 16 + 4 * q + 4, H) - 0.5f;
+            if (y0 <= y1 && ellipse_hits_rect(e, x0, x1, y0, y1)) b |= 1u << q;
+        }
+    }
+    return b;
 }
 
 // Does the splat's alpha_min ellipse reach tile (tx, ty), and which parts of
-// it?  For 32x32 tiles the parts are the quadrants (bit 2 * row half +
-// column half), for 16x16 tiles the quarter-row bands (bit q: rows
-// [4q, 4q + 4)), for 8x8 tiles none; a part is marked when the rows the
-// ellipse reaches within the part's columns overlap the part's rows.
+// it (tile_parts; only when `bands` is given)?
 __device__ __forceinline__ bool tile_hit(const EllipseTest &e, int W, int H, int tile, int tx, int ty,
                                          uint32_t *bands)
 {
     float rx0, rx1, ry0, ry1;
     tile_rect(tx, ty, tile, W, H, rx0, rx1, ry0, ry1);
     if (!ellipse_hits_rect(e, rx0, rx1, ry0, ry1)) return false;
-    if (bands) {
-        uint32_t b = 0;
-        if (tile == 32) {
-            for (int ch = 0; ch < 2; ch++) {
-                const float cx0 = (float)(tx * 32 + ch * 16) + 0.5f;
-                const float cx1 = fminf((float)(tx * 32 + ch * 16 + 16) - 0.5f, rx1);
-                if (cx0 > cx1) continue;  // the half lies beyond the image
-                float lo, hi;
-                ellipse_rows_in_strip(e, cx0 - e.mx, cx1 - e.mx, lo, hi);
-                for (int rh = 0; rh < 2; rh++) {
-                    const float by0 = (float)(ty * 32 + rh * 16) + 0.5f - e.my;
-                    const float by1 = fminf((float)(ty * 32 + rh * 16 + 16) - 0.5f, ry1) - e.my;
-                    if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << (2 * rh + ch);
-                }
-            }
-        } else if (tile == 16) {
-            float lo, hi;
-            ellipse_rows_in_strip(e, rx0 - e.mx, rx1 - e.mx, lo, hi);
-            const int q = tile / 4;
-            for (int k = 0; k < 4; k++) {
-                const float by0 = (float)(ty * tile + k * q) + 0.5f - e.my;
-                const float by1 = fminf((float)(ty * tile + (k + 1) * q) - 0.5f, ry1) - e.my;
-                if (by0 <= by1 && lo <= by1 && hi >= by0) b |= 1u << k;
-            }
-        }
-        *bands = b;
-    }
+    if (bands) *bands = tile_parts(e, W, H, tile, tx, ty);
     return true;
 }
 

@@ -222,29 +222,37 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 // exclusive scan of n u32 counts (n known on the host) into u32 offsets; the
-// 64-bit total goes to *d_total.
+// 64-bit total goes to *d_total.  With d_n (device), counts at or beyond *d_n
+// are taken as 0 (they are not read; every position still gets its offset).
 void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint64_t *partial, int64_t *d_total,
-                     hipStream_t s);
-// stable LSD radix sort of (key, val) pairs over bits [0, bits); n_max bounds
-// the grid, d_n (may be null) holds the live count on the device.  Returns the
-// buffer index (0: keys/vals, 1: keys2/vals2) that holds the result.
-// Stable LSD sort of `bits` low key bits; returns 1 when the result is in
-// keys2/vals2.  With d_kept, keys 0xffffffff are dropped by the first pass and
-// the number kept is written to *d_kept (later passes sort only those).
+                     hipStream_t s, const int64_t *d_n = nullptr);
+// Extra inputs and outputs of the depth sort, folded into its first and last
+// passes: the first pass reads record j's key from first_keys[j], drops it
+// when first_tiles[j] == 0 and takes j as its value; the last pass also
+// writes counts_out[p] = gather_tiles[value] at every output position p < kept.
+struct DepthSortIO {
+    const uint32_t *first_keys;
+    const int32_t *first_tiles;
+    const int32_t *gather_tiles;
+    uint32_t *counts_out;
+};
+// Stable LSD radix sort of (key, val) pairs over bits [0, bits) in as few
+// passes of at most 8 bits as cover them; n_max bounds the grid, d_n (may be
+// null) holds the live count on the device.  Returns 1 when the result is in
+// keys2/vals2, 0 when in keys/vals.  With d_kept, keys 0xffffffff are dropped
+// by the first pass and the number kept is written to *d_kept (later passes
+// sort only those).
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *totals,
-                      hipStream_t s, int64_t *d_kept = nullptr);
-void launch_depth_keys(const uint32_t *depth_keys, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
-                       hipStream_t s);
-void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, const int64_t *d_V,
-                          uint32_t *counts, hipStream_t s);
+                      hipStream_t s, int64_t *d_kept = nullptr, const DepthSortIO *io = nullptr);
 // tiles_touched of every (camera, Gaussian) record under the binning rule
 // the records k_project put on the big-record list (tiles_touched of each)
 void launch_count_big(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
                       uint32_t *big_list, uint32_t *big_n, hipStream_t s);
 void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
                  const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
-                 uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, hipStream_t s);
+                 uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, const int64_t *d_V,
+                 hipStream_t s);
 void launch_ranges(const uint32_t *tile_ids, const int64_t *d_K, int64_t capacity, int64_t T_total,
                    uint32_t *ranges, hipStream_t s);
 

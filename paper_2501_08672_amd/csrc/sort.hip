@@ -56,10 +56,13 @@ inline unsigned fill_blocks(int64_t n)
 
 
 // Sum of each kScanTile-sized block.
+// With d_n, entries at or beyond *d_n count as 0.
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                              const int64_t *__restrict__ d_n,
                                                               uint64_t *__restrict__ partial)
 {
     __shared__ uint64_t s[kScanThreads / kWave];
+    if (d_n && *d_n < n) n = *d_n;
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint32_t v[kScanItems];  // all loads in flight before the first add
 #pragma unroll
@@ -112,10 +115,13 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ p
 // Block-local exclusive scan plus the block's offset.  Offsets beyond 2^32
 // wrap; the callers compare the 64-bit total against their capacity first.
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *__restrict__ in, int64_t n,
+                                                            const int64_t *__restrict__ d_n,
                                                             const uint64_t *__restrict__ partial,
                                                             uint32_t *__restrict__ out)
 {
     __shared__ uint64_t s_w[kScanThreads / kWave];
+    const int64_t n_all = n;  // every position gets an offset; those at or beyond *d_n add 0
+    if (d_n && *d_n < n) n = *d_n;
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     // each thread owns kScanItems consecutive elements
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *__re
     uint64_t run = partial[blockIdx.x] + wbase + inc - sum;
     for (int k = 0; k < kScanItems; k++) {
         const int64_t j = mybase + k;
-        if (j < n) out[j] = (uint32_t)run;
+        if (j < n_all) out[j] = (uint32_t)run;
         run += v[k];
     }
 }
@@ -170,9 +176,12 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int db)
 // that also compacts).
 constexpr uint32_t kDropKey = 0xffffffffu;
 
+// With first_tiles (the first pass of the depth sort), the key of record j
+// is keys[j] where first_tiles[j] > 0 and kDropKey elsewhere.
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__restrict__ keys, int64_t n_max,
                                                           const int64_t *__restrict__ d_n, int shift, int db,
-                                                          uint32_t *__restrict__ hist, int64_t nb, bool drop)
+                                                          uint32_t *__restrict__ hist, int64_t nb, bool drop,
+                                                          const int32_t *__restrict__ first_tiles)
 {
     __shared__ uint32_t s_cnt[kSortThreads / kWave][256];
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
@@ -182,11 +191,15 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__rest
     const int64_t n = live_count(d_n, n_max);
     const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wv * (kSortTile / (kSortThreads / kWave));
     uint32_t kk[kSortItems];  // all loads in flight before the first ballot
+    int32_t tt[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
         kk[r] = j < n ? keys[j] : kDropKey;
+        tt[r] = (first_tiles && j < n) ? first_tiles[j] : 1;
     }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) kk[r] = tt[r] > 0 ? kk[r] : kDropKey;
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
@@ -260,7 +273,10 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
                                                              int64_t n_max, const int64_t *__restrict__ d_n, int shift,
                                                              int db, const uint32_t *__restrict__ hist_off, int64_t nb,
                                                              const uint32_t *__restrict__ totals, bool drop,
-                                                             int64_t *__restrict__ d_kept)
+                                                             int64_t *__restrict__ d_kept,
+                                                             const int32_t *__restrict__ first_tiles,
+                                                             const int32_t *__restrict__ gather_tiles,
+                                                             uint32_t *__restrict__ counts_out)
 {
     const uint32_t dmask = (1u << db) - 1u;
     constexpr int NW = kSortThreads / kWave;
@@ -298,12 +314,17 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     if (block_base >= n) return;
     const int64_t base = block_base + (int64_t)wv * (kSortTile / NW);
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    int32_t tt[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {  // all loads in flight before the first ballot
         const int64_t j = base + (int64_t)r * kWave + lane;
         key[r] = j < n ? kin[j] : kDropKey;
-        val[r] = j < n ? vin[j] : 0u;
+        // the first pass of the depth sort: values are the record indices
+        val[r] = j < n ? (first_tiles ? (uint32_t)j : vin[j]) : 0u;
+        tt[r] = (first_tiles && j < n) ? first_tiles[j] : 1;
     }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) key[r] = tt[r] > 0 ? key[r] : kDropKey;
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
@@ -365,28 +386,12 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
         const uint32_t dst = s_glob[d] + (uint32_t)p - s_loc[d];
         kout[dst] = k;
         vout[dst] = s_val[p];
+        // the last pass of the depth sort: the record's tile count at its place in depth order
+        if (counts_out) counts_out[dst] = (uint32_t)gather_tiles[s_val[p]];
     }
 }
 
 // ------------------------------------------------------------------ binning
-
-__global__ void k_depth_keys(const uint32_t *__restrict__ depth_keys, const int32_t *__restrict__ tiles, int64_t M,
-                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
-{
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    keys[m] = tiles[m] > 0 ? depth_keys[m] : 0xffffffffu;
-    vals[m] = (uint32_t)m;
-}
-
-// Positions at or beyond the number of kept records (*d_V) get 0.
-__global__ void k_gather_counts(const uint32_t *__restrict__ order, const int32_t *__restrict__ tiles, int64_t M,
-                                const int64_t *__restrict__ d_V, uint32_t *__restrict__ counts)
-{
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
-    counts[j] = j < *d_V ? (uint32_t)tiles[order[j]] : 0u;
-}
 
 // The listed records, one per workgroup of 256 lanes (grid-stride over the
 // list): 256 bbox tiles per step in row-major order, a hit's slot from the
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
                                               const int64_t *__restrict__ d_K, int64_t capacity,
                                               uint32_t *__restrict__ tile_ids, uint32_t *__restrict__ gauss_ids,
                                               int32_t *__restrict__ d_status, uint32_t *__restrict__ big_list,
-                                              uint32_t *__restrict__ big_n)
+                                              uint32_t *__restrict__ big_n, const int64_t *__restrict__ d_V)
 {
     __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
@@ -469,8 +474,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
     const int64_t K = *d_K;
     if (j == 0) *d_status = K > capacity ? GSL_ECAPACITY : GSL_OK;
     if (K > capacity) return;  // uniform: every thread reads the same K
+    const int64_t V = *d_V;    // records kept by the depth sort (the positions beyond carry no count)
     uint32_t nt = 0;
-    if (j < M) {
+    if (j < V) {
         // three independent loads first (order[j] is only used where cnt != 0)
         const uint32_t cnt = counts[j], m = order[j], off = offsets[j];
         if (cnt) {
@@ -545,21 +551,21 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
 }
 
 void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint64_t *partial, int64_t *d_total,
-                     hipStream_t s)
+                     hipStream_t s, const int64_t *d_n)
 {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) {
         if (d_total) launch_fill_f64(reinterpret_cast<double *>(d_total), 0.0, 1, s);  // all-zero bits == int64 0
         return;
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, partial);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, d_n, partial);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, d_total);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, partial, offsets);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, d_n, partial, offsets);
 }
 
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *totals,
-                      hipStream_t s, int64_t *d_kept)
+                      hipStream_t s, int64_t *d_kept, const DepthSortIO *io)
 {
     const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
     if (nb == 0 || bits <= 0) {
@@ -567,6 +573,7 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
         return 0;
     }
     uint32_t *kin = keys, *vin = vals, *kout = keys2, *vout = vals2;
+    const uint32_t *kin0 = io ? io->first_keys : keys;  // the first pass reads its keys from here
     int where = 0;
     // as few passes of at most 8 bits as cover `bits`, the digits split evenly
     // (fewer buckets per pass write longer runs)
@@ -574,11 +581,15 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
     for (int shift = 0; shift < bits; shift += db) {
         // with d_kept the first pass drops kDropKey keys and counts the rest
         const bool drop = d_kept && shift == 0;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, n_max, d_n, shift, db, hist,
-                           nb, drop);
+        const bool first = shift == 0, last = shift + db >= bits;
+        const uint32_t *kp = first ? kin0 : kin;
+        const int32_t *ft = (io && first) ? io->first_tiles : nullptr;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kp, n_max, d_n, shift, db, hist,
+                           nb, drop, ft);
         hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << db), dim3(256), 0, s, hist, nb, hist_off, totals);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_max,
-                           d_n, shift, db, hist_off, nb, totals, drop, drop ? d_kept : nullptr);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kp, vin, kout, vout, n_max,
+                           d_n, shift, db, hist_off, nb, totals, drop, drop ? d_kept : nullptr, ft,
+                           (io && last) ? io->gather_tiles : nullptr, (io && last) ? io->counts_out : nullptr);
         if (drop) d_n = d_kept;
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout;
@@ -586,22 +597,6 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
         where ^= 1;
     }
     return where;
-}
-
-void launch_depth_keys(const uint32_t *depth_keys, const int32_t *tiles, int64_t M, uint32_t *keys, uint32_t *vals,
-                       hipStream_t s)
-{
-    if (M > 0)
-        hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, depth_keys, tiles, M, keys,
-                           vals);
-}
-
-void launch_gather_counts(const uint32_t *order, const int32_t *tiles, int64_t M, const int64_t *d_V,
-                          uint32_t *counts, hipStream_t s)
-{
-    if (M > 0)
-        hipLaunchKernelGGL(k_gather_counts, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, order, tiles, M, d_V,
-                           counts);
 }
 
 void launch_count_big(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
@@ -614,12 +609,13 @@ void launch_count_big(const gsl_binrec *binrecs, const DevCam *cams, const Layou
 
 void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
                  const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
-                 uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, hipStream_t s)
+                 uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, const int64_t *d_V,
+                 hipStream_t s)
 {
     const int64_t blocks = L.M > 0 ? (L.M + 255) / 256 : 1;
     launch_fill_u32(big_n, 0u, 1, s);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, counts, binrecs, cams, L.N,
-                       L.M, L.tile, d_K, capacity, tile_ids, gauss_ids, d_status, big_list, big_n);
+                       L.M, L.tile, d_K, capacity, tile_ids, gauss_ids, d_status, big_list, big_n, d_V);
     if (L.M > 0)
         hipLaunchKernelGGL((k_tiles_big<true>), dim3(kBigBlocks), dim3(256), 0, s, binrecs, cams, L.N, L.tile,
                            big_list, big_n, nullptr, order, offsets, counts, d_K, capacity, tile_ids, gauss_ids);
