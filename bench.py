@@ -389,8 +389,10 @@ def window_update_bench(ctx, ops, S, torch, frames=8):
     a 500k-Gaussian window (42 rows: raw parameters and Adam moments) at a
     capacity of 2^20, 100k points per frame, root voxels of 0.5 m, the sensor
     moving 1 m per frame.  Per frame: gsl_window_classify, the host read of
-    (D, A), and gsl_window_compact appending as many Gaussians per ADD voxel
-    as the window holds per voxel on average (rows resident on the device)."""
+    (D, A), the appended Gaussians (as many per ADD voxel as the window holds
+    per voxel on average) copied from pinned host memory to the device,
+    gsl_window_compact, and the evicted Gaussians copied back to pinned host
+    memory (gsl_window_transfer both ways)."""
     n, P, cap, vs, R = 500_000, 100_000, 1 << 20, ROOT_VOXEL_M, 42
     pts_np, means = S.lidar_stream(71, frames + 1, P, n)
     pts = [torch.from_numpy(p).cuda() for p in pts_np]
@@ -400,9 +402,15 @@ def window_update_bench(ctx, ops, S, torch, frames=8):
     sw.block.normal_(generator=gen)
     sw.n = n
     per_voxel = max(1, round(n / int(torch.unique(sw.keys[:n]).numel())))
-    pool = torch.randn(R, cap, generator=gen, device="cuda")
+    # host-side map stand-in: pinned rows of the Gaussians to append, and pinned room for the evicted ones
+    pool_h = torch.randn(R, cap // 4, generator=torch.Generator().manual_seed(6)).pin_memory()
+    keys_in_h = torch.empty(cap // 4, dtype=torch.int64).pin_memory()
+    keys_out_h = torch.empty(cap, dtype=torch.int64).pin_memory()
+    rows_out_h = torch.empty(R, cap, dtype=torch.float32).pin_memory()
+    add_k = torch.empty(cap // 4, dtype=torch.int64, device="cuda")
+    add_r = torch.empty(R, cap // 4, dtype=torch.float32, device="cuda")
     ws = ops.window_workspace(ctx, cap, P)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     rows = []
     for f in range(frames + 1):
         torch.cuda.synchronize()
@@ -411,22 +419,27 @@ def window_update_bench(ctx, ops, S, torch, frames=8):
         counts, addv = ops.window_classify(ctx, pts[f], vs, sw.keys, sw.n, ws)
         ev[1].record()
         D, A = (int(x) for x in counts.cpu())
-        akeys = addv[:A].repeat_interleave(per_voxel)
-        arows = pool[:, :akeys.shape[0]].contiguous()
+        Ag = A * per_voxel
+        keys_in_h[:Ag].copy_(addv[:A].cpu().repeat_interleave(per_voxel))
         ev[2].record()
-        _, _, status = ops.window_compact(ctx, sw.keys, sw.block, sw.n, D, akeys, arows, ws)
+        ops.window_transfer(ctx, ops.A.GSL_H2D, keys_in_h, pool_h, add_k, add_r, Ag)
         ev[3].record()
+        ek, er, status = ops.window_compact(ctx, sw.keys, sw.block, sw.n, D, add_k[:Ag],
+                                            add_r[:, :Ag].contiguous(), ws)
+        ev[4].record()
+        ops.window_transfer(ctx, ops.A.GSL_D2H, ek, er, keys_out_h, rows_out_h, D)
+        ev[5].record()
         torch.cuda.synchronize()
         t_frame = time.perf_counter() - t0
         assert int(status.item()) == 0
         n_before = sw.n
-        sw.n = sw.n - D + int(akeys.shape[0])
+        sw.n = sw.n - D + Ag
         if f == 0:
             continue  # warm-up frame
-        rows.append((n_before, D, A, int(akeys.shape[0]), ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]),
-                     t_frame * 1e3))
+        rows.append((n_before, D, A, Ag, ev[0].elapsed_time(ev[1]), ev[3].elapsed_time(ev[4]),
+                     ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5]), t_frame * 1e3))
     a = np.array(rows, dtype=np.float64)
-    n_m, D_m, Av_m, Ag_m, cls_ms, cmp_ms, frame_ms = (float(x) for x in a.mean(0))
+    n_m, D_m, Av_m, Ag_m, cls_ms, cmp_ms, h2d_ms, d2h_ms, frame_ms = (float(x) for x in a.mean(0))
     rec = 8 + 4 * R
     cls_bytes = 12 * P + 8 * n_m + 8 * Av_m
     cmp_bytes = 2 * D_m * rec + 2 * D_m * rec + 2 * Ag_m * rec  # evict, move (<= D), append
@@ -434,12 +447,16 @@ def window_update_bench(ctx, ops, S, torch, frames=8):
                         "100k LiDAR points per frame, 0.5 m root voxels, sensor moving 1 m per frame",
             "frames": frames, "window": round(n_m), "deleted": round(D_m), "add_voxels": round(Av_m),
             "appended": round(Ag_m), "classify_ms": round(cls_ms, 4), "compact_ms": round(cmp_ms, 4),
-            "frame_ms": round(frame_ms, 4),
+            "h2d_ms": round(h2d_ms, 4), "d2h_ms": round(d2h_ms, 4), "frame_ms": round(frame_ms, 4),
             "hbm": {"classify_bytes": int(cls_bytes), "compact_bytes_max": int(cmp_bytes),
                     "classify_gbs": round(cls_bytes / (cls_ms * 1e-3) / 1e9, 1),
                     "compact_gbs": round(cmp_bytes / (cmp_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS},
-            "how": "HIP events around each call; frame_ms adds the host read of (D, A) and the appended rows' "
-                   "staging, the per-frame synchronisation the host-side global map needs"}
+            "pcie": {"h2d_bytes": int(Ag_m * rec), "d2h_bytes": int(D_m * rec),
+                     "h2d_gbs": round(Ag_m * rec / (h2d_ms * 1e-3) / 1e9, 1),
+                     "d2h_gbs": round(D_m * rec / (d2h_ms * 1e-3) / 1e9, 1)},
+            "how": "HIP events around each call; frame_ms is the host's clock over the frame, with the read of "
+                   "(D, A) and the pinned staging both ways (the per-frame synchronisation the host-side global map "
+                   "needs)"}
 
 
 def sweep(args):
@@ -469,9 +486,14 @@ def sweep(args):
                 win.step(True)
             torch.cuda.synchronize()
             t = (time.perf_counter() - t0) / args.steps
+            st_ms = np.array([win.profiled_step() for _ in range(3)]).mean(0)
             print(json.dumps({"gaussians": n, "frames": cs.C, "width": W, "height": H, "tile": tile,
-                              "instances_K": win.bins.K, "ms_per_step": round(t * 1e3, 4),
-                              "mpix_s": round(cs.P_total / t / 1e6, 2)}), flush=True)
+                              "instances_K": win.bins.K, "instances_per_pixel": round(win.bins.K / cs.P_total, 2),
+                              "ms_per_step": round(t * 1e3, 4), "mpix_s": round(cs.P_total / t / 1e6, 2),
+                              "stage_ms_eager": {"project": round(float(st_ms[0]), 4),
+                                                 "bin_sort": round(float(st_ms[1]), 4),
+                                                 "fused_render": round(float(st_ms[2]), 4),
+                                                 "adjoint": round(float(st_ms[3]), 4)}}), flush=True)
             del win, g, target
             torch.cuda.empty_cache()
     # the uneven batch: 2M surfels, 16 cameras from 320x256 to 1920x1080

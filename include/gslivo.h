@@ -461,6 +461,25 @@ GSL_API int gsl_window_compact(gsl_ctx *ctx, uint64_t *keys, float *rows, int32_
                                uint64_t *evicted_keys, float *evicted_rows, const void *workspace,
                                size_t workspace_bytes, int32_t *status, void *stream);
 
+enum { GSL_D2H = 0, GSL_H2D = 1 };
+
+/* Moves `count` Gaussians of the window update between the device and pinned
+ * host memory (Sec. II-C: the Gaussians that leave the window go back to the
+ * global map in host RAM, those that enter come from it): count uint64 keys
+ * and R rows of 4-byte words, row r of Gaussian i at rows[r * ld + i], with
+ * the source's and the destination's row strides src_ld and dst_ld
+ * (>= count).  Asynchronous copies on the stream: one for the keys, one
+ * strided 2D copy for the rows.  dir GSL_D2H: sources in device memory,
+ * destinations in pinned host memory; GSL_H2D the reverse.  Keys or rows may
+ * be NULL on both sides (not moved).  GSL_EINVAL when a host-side buffer is
+ * not pinned (hipHostMalloc, or a pinned torch tensor) or a device-side one
+ * is not device memory, so that no copy silently goes through a pageable
+ * staging path.  Host buffers must stay untouched until the stream reaches
+ * the copies. */
+GSL_API int gsl_window_transfer(gsl_ctx *ctx, int dir, const uint64_t *src_keys, const float *src_rows,
+                                int64_t src_ld, uint64_t *dst_keys, float *dst_rows, int64_t dst_ld, int32_t R,
+                                int32_t count, void *stream);
+
 /* ---- pose Jacobians for the IESKF visual update -------------------------- */
 
 /* Workspace bytes for gsl_pose_jacobian: the bytes gsl_workspace_size gives

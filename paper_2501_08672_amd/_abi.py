@@ -20,6 +20,8 @@ GSL_ENOTSUP = -2
 GSL_ECAPACITY = -3
 GSL_EHIP = -4
 GSL_ESTATE = -5
+GSL_D2H = 0
+GSL_H2D = 1
 GSL_LOSS_L1 = 1
 GSL_LOSS_L2 = 2
 
@@ -32,6 +34,7 @@ EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "g
            "gsl_pose_jacobian_workspace_size", "gsl_pose_jacobian", "gsl_imu_to_camera_twist",
            "gsl_ieskf_pose_update", "gsl_ieskf_visual_update", "gsl_adam_init", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
            "gsl_voxel_keys", "gsl_window_workspace_size", "gsl_window_classify", "gsl_window_compact",
+           "gsl_window_transfer",
            "gsl_color_init"]
 
 
@@ -136,6 +139,7 @@ def lib() -> C.CDLL:
     L.gsl_voxel_keys.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, C.c_float, P, P]
     L.gsl_window_workspace_size.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
     L.gsl_window_classify.argtypes = [P, P, C.c_int32, C.c_float, P, C.c_int32, P, P, P, C.c_size_t, P]
+    L.gsl_window_transfer.argtypes = [P, C.c_int, P, P, C.c_int64, P, P, C.c_int64, C.c_int32, C.c_int32, P]
     L.gsl_window_compact.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, C.c_int32, P, P, C.c_int32, P, P, P,
                                      C.c_size_t, P, P]
     for name in EXPORTS:

@@ -1167,6 +1167,55 @@ int gsl_window_compact(gsl_ctx *ctx, uint64_t *keys, float *rows, int32_t R, int
     return check_launch("gsl_window_compact");
 }
 
+namespace {
+
+// Is p (not NULL) memory of the wanted kind: pinned host memory, or device
+// memory?  Pageable host memory reports no attributes or an unregistered
+// type.
+bool is_memory(const void *p, bool host)
+{
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();  // clear the error the query left for pageable memory
+        return false;
+    }
+    return host ? at.type == hipMemoryTypeHost : at.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+int gsl_window_transfer(gsl_ctx *ctx, int dir, const uint64_t *src_keys, const float *src_rows, int64_t src_ld,
+                        uint64_t *dst_keys, float *dst_rows, int64_t dst_ld, int32_t R, int32_t count, void *stream)
+{
+    if (!ctx) return fail(GSL_EINVAL, "ctx is NULL");
+    if (dir != GSL_D2H && dir != GSL_H2D) return fail(GSL_EINVAL, "direction %d is not GSL_D2H or GSL_H2D", dir);
+    if (R < 0 || count < 0) return fail(GSL_EINVAL, "negative size");
+    if (!src_keys != !dst_keys) return fail(GSL_EINVAL, "keys: source and destination must both be given or both NULL");
+    if (!src_rows != !dst_rows) return fail(GSL_EINVAL, "rows: source and destination must both be given or both NULL");
+    const bool rows = src_rows && R > 0;
+    if (rows && (src_ld < count || dst_ld < count)) return fail(GSL_EINVAL, "row strides must be >= count");
+    if (count == 0) return GSL_OK;
+    GSL_TRY(check_device(ctx));
+    const bool src_host = dir == GSL_H2D;
+    const void *srcs[2] = {src_keys, rows ? (const void *)src_rows : nullptr};
+    const void *dsts[2] = {dst_keys, rows ? (const void *)dst_rows : nullptr};
+    for (int k = 0; k < 2; k++) {
+        if (srcs[k] && !is_memory(srcs[k], src_host))
+            return fail(GSL_EINVAL, "source %s is not %s", k ? "rows" : "keys", src_host ? "pinned host memory" : "device memory");
+        if (dsts[k] && !is_memory(dsts[k], !src_host))
+            return fail(GSL_EINVAL, "destination %s is not %s", k ? "rows" : "keys",
+                        src_host ? "device memory" : "pinned host memory");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = src_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    if (src_keys) GSL_TRY(check_hip(hipMemcpyAsync(dst_keys, src_keys, 8 * (size_t)count, kind, s), "hipMemcpyAsync"));
+    if (rows)
+        GSL_TRY(check_hip(hipMemcpy2DAsync(dst_rows, 4 * (size_t)dst_ld, src_rows, 4 * (size_t)src_ld, 4 * (size_t)count,
+                                           (size_t)R, kind, s),
+                          "hipMemcpy2DAsync"));
+    return GSL_OK;
+}
+
 int gsl_pose_jacobian_workspace_size(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N,
                                      const gsl_opts *opts, int64_t capacity_K, size_t *bytes)
 {

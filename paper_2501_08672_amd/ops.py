@@ -503,6 +503,41 @@ def window_compact(ctx: Context, keys: torch.Tensor, rows: Optional[torch.Tensor
     return ek, er, status
 
 
+def window_transfer(ctx: Context, direction: int, src_keys: Optional[torch.Tensor], src_rows: Optional[torch.Tensor],
+                    dst_keys: Optional[torch.Tensor], dst_rows: Optional[torch.Tensor], count: int):
+    """gsl_window_transfer: `count` Gaussians' keys (int64 (>= count,)) and
+    rows (float32 (R, ld) with unit column stride) between device tensors and
+    pinned host tensors, asynchronously on the current stream.  direction:
+    A.GSL_D2H or A.GSL_H2D."""
+    R = 0
+    sld = dld = 0
+    if src_rows is not None:
+        for t in (src_rows, dst_rows):
+            if t is None or t.dtype != torch.float32 or t.dim() != 2 or t.stride(1) != 1:
+                raise ValueError("rows must be float32 (R, ld) tensors with unit column stride")
+        if src_rows.shape[0] != dst_rows.shape[0]:
+            raise ValueError("source and destination row counts differ")
+        R, sld, dld = int(src_rows.shape[0]), int(src_rows.stride(0)), int(dst_rows.stride(0))
+    A.check(A.lib().gsl_window_transfer(ctx.h, int(direction), _p(src_keys), _p(src_rows), sld, _p(dst_keys),
+                                        _p(dst_rows), dld, R, int(count), _stream()))
+
+
+class _Pinned:
+    """A growable pinned host buffer of (rows, columns) (rows = 0: 1-D)."""
+
+    def __init__(self, dtype, rows=0):
+        self.dtype, self.rows, self.t = dtype, rows, None
+
+    def get(self, cols: int) -> torch.Tensor:
+        cols = max(1, int(cols))
+        have = 0 if self.t is None else self.t.shape[-1]
+        if have < cols:
+            n = max(cols, int(have * 1.5))
+            shape = (self.rows, n) if self.rows else (n,)
+            self.t = torch.empty(shape, dtype=self.dtype, pin_memory=True)
+        return self.t
+
+
 class SlidingWindow:
     """The window of Gaussians at a fixed capacity on the device (Sec. II-C):
     one float32 block (3R, capacity) — R = 14 + 3K raw parameter rows, then
@@ -518,6 +553,9 @@ class SlidingWindow:
         self.keys = torch.full((self.capacity,), -1, dtype=torch.int64, device=dev)
         self.d_step = torch.zeros(1, dtype=torch.int32, device=dev)
         self.n = 0
+        # pinned staging of the Gaussians that enter (from the host-side map) and leave
+        self._in_keys, self._in_rows = _Pinned(torch.int64), _Pinned(torch.float32, self.ROWS)
+        self._out_keys, self._out_rows = _Pinned(torch.int64), _Pinned(torch.float32, self.ROWS)
 
     def adam_state(self) -> AdamState:
         b, R = self.block, self.params
@@ -525,23 +563,39 @@ class SlidingWindow:
 
     def update(self, points: torch.Tensor, fetch, ws: Optional[torch.Tensor] = None):
         """One frame: classify against the frame's points, then call
-        fetch(add_keys int64 (A_vox,) on the host) -> (keys (A,), rows (3R, A)),
-        the Gaussians to append (from the global map or newly initialised;
-        moments zero), and compact.  Returns (evicted_keys, evicted_rows) on
-        the device, for the global map."""
+        fetch(add_keys int64 (A_vox,) on the host) -> (keys (A,), rows (3R, A))
+        on the host, the Gaussians to append (from the global map or newly
+        initialised; moments zero).  They are staged in pinned memory and
+        copied to the device (gsl_window_transfer), the window is compacted,
+        and the evicted Gaussians are copied back to pinned memory.  Returns
+        (evicted_keys int64 (D,), evicted_rows float32 (3R, D)) on the host,
+        views of the pinned staging valid until the next update, for the
+        global map."""
+        dev = self.keys.device
         ws = window_workspace(self.ctx, self.n, points.shape[0]) if ws is None else ws
         counts, add_vox = window_classify(self.ctx, points, self.voxel_size, self.keys, self.n, ws)
         D, A_vox = (int(x) for x in counts.cpu())
         akeys, arows = fetch(add_vox[:A_vox].cpu())
-        akeys = torch.as_tensor(akeys, dtype=torch.int64).to(self.keys.device)
-        arows = torch.as_tensor(arows, dtype=torch.float32).to(self.keys.device).reshape(self.ROWS, -1)
-        if self.n - D + akeys.shape[0] > self.capacity:
+        akeys = torch.as_tensor(akeys, dtype=torch.int64).reshape(-1)
+        Aadd = int(akeys.shape[0])
+        arows = torch.as_tensor(arows, dtype=torch.float32).reshape(self.ROWS, Aadd)
+        if self.n - D + Aadd > self.capacity:
             raise ValueError("window capacity exceeded")
-        ek, er, status = window_compact(self.ctx, self.keys, self.block, self.n, D, akeys, arows, ws)
+        hk, hr = self._in_keys.get(Aadd), self._in_rows.get(Aadd)
+        hk[:Aadd].copy_(akeys)
+        hr[:, :Aadd].copy_(arows)
+        dk = torch.empty(max(1, Aadd), dtype=torch.int64, device=dev)
+        dr = torch.empty(self.ROWS, max(1, Aadd), dtype=torch.float32, device=dev)
+        window_transfer(self.ctx, A.GSL_H2D, hk, hr, dk, dr, Aadd)
+        ek, er, status = window_compact(self.ctx, self.keys, self.block, self.n, D, dk[:Aadd], dr[:, :Aadd], ws)
+        ok, orows = self._out_keys.get(D), self._out_rows.get(D)
+        if D:
+            window_transfer(self.ctx, A.GSL_D2H, ek, er, ok, orows, D)
+        torch.cuda.current_stream().synchronize()
         if int(status.item()) != 0:
             raise RuntimeError("window compaction rejected: stale classification")
-        self.n = self.n - D + int(akeys.shape[0])
-        return ek, er
+        self.n = self.n - D + Aadd
+        return ok[:D], orows[:, :D]
 
 
 # ---------------------------------------------------------------- pose Jacobians (IESKF visual update)

@@ -271,3 +271,116 @@ def test_sliding_window_update_and_adam_on_capacity_layout(oracle):
     assert torch.equal(sw.block[0:14, :N], dense.raw) and torch.equal(sw.block[28:42, :N], dense.v)
     for k in ("mean", "scale", "quat", "opacity", "color"):
         assert torch.equal(getattr(g1, k), getattr(g2, k)), k
+
+
+def test_window_transfer_pinned_staging():
+    """gsl_window_transfer: keys and strided rows between device memory and
+    pinned host memory, both directions, bit for bit; pageable host memory
+    and wrong-side pointers are rejected on the host (nothing is copied)."""
+    O = ops()
+    A = O.A
+    ctx = context()
+    R, n = 42, 1000
+    rng = np.random.default_rng(3)
+    keys_h = torch.from_numpy(rng.integers(0, 2 ** 62, 3000, dtype=np.int64)).pin_memory()
+    rows_h = torch.from_numpy(rng.normal(size=(R, 3000)).astype(np.float32)).pin_memory()
+    keys_d = torch.full((n,), -7, dtype=torch.int64, device="cuda")
+    rows_d = torch.zeros(R, 1500, dtype=torch.float32, device="cuda")
+    O.window_transfer(ctx, A.GSL_H2D, keys_h, rows_h, keys_d, rows_d, n)  # ld 3000 -> 1500
+    torch.cuda.synchronize()
+    assert torch.equal(keys_d.cpu(), keys_h[:n])
+    assert torch.equal(rows_d[:, :n].cpu(), rows_h[:, :n])
+    assert torch.all(rows_d[:, n:] == 0)
+    back_k = torch.zeros(2000, dtype=torch.int64).pin_memory()
+    back_r = torch.zeros(R, 2000, dtype=torch.float32).pin_memory()
+    O.window_transfer(ctx, A.GSL_D2H, keys_d, rows_d, back_k, back_r, n)
+    torch.cuda.synchronize()
+    assert torch.equal(back_k[:n], keys_h[:n]) and torch.equal(back_r[:, :n], rows_h[:, :n])
+    assert torch.all(back_r[:, n:] == 0) and torch.all(back_k[n:] == 0)
+    # keys only, rows only, nothing
+    O.window_transfer(ctx, A.GSL_D2H, keys_d, None, back_k, None, 10)
+    O.window_transfer(ctx, A.GSL_H2D, None, rows_h, None, rows_d, 10)
+    O.window_transfer(ctx, A.GSL_H2D, keys_h, rows_h, keys_d, rows_d, 0)
+    torch.cuda.synchronize()
+    # rejected before any copy: pageable host memory, device memory on the host side
+    pageable = torch.zeros(n, dtype=torch.int64)
+    for args in ((A.GSL_D2H, keys_d, None, pageable, None), (A.GSL_H2D, pageable, None, keys_d, None),
+                 (A.GSL_D2H, keys_d, None, keys_d, None), (A.GSL_H2D, keys_h, None, keys_h, None)):
+        with pytest.raises(A.GslError) as e:
+            O.window_transfer(ctx, args[0], args[1], args[2], args[3], args[4], 10)
+        assert e.value.code == A.GSL_EINVAL
+
+
+def test_window_stream_through_host_map(oracle):
+    """Six frames of a LiDAR stream that turns back: every evicted Gaussian
+    goes to a host-side map (copied from the device through pinned memory),
+    an ADD voxel the map holds gets its Gaussians back, others get new ones.
+    The window (keys, 42 rows), the evicted Gaussians and the map agree bit
+    for bit with the oracle's same sequence, and returning Gaussians come
+    back with the rows they left with."""
+    O = ops()
+    ctx = context()
+    vs = 0.5
+    n, P, cap = 8000, 6000, 20_000
+    frames, means = S.lidar_stream(41, 7, P, n, extent=40.0, n_planes=150, range_m=12.0, step=1.0)
+    order = [1, 2, 3, 2, 1, 0]  # forward, then back over the same ground
+    sw = O.SlidingWindow(ctx, cap, vs)
+    win_keys = _okeys(oracle, means, vs)
+    sw.keys[:n] = _dev(win_keys)
+    win_rows = _rows(12, R_ROWS, n)
+    sw.block[:, :n] = torch.from_numpy(win_rows).cuda()
+    sw.n = n
+    map_gpu, map_orc = {}, {}
+    returned = 0
+    for step, f in enumerate(order):
+        rng = np.random.default_rng(400 + step)
+        made = {}
+
+        def fetch(add_vox):
+            vox = add_vox.numpy().view(np.uint64)
+            ks, rs = [], []
+            for k in vox:
+                if int(k) in map_gpu:
+                    kk, rr = map_gpu.pop(int(k))
+                else:
+                    kk = np.repeat(k, 2)
+                    rr = rng.normal(size=(R_ROWS, 2)).astype(np.float32)
+                ks.append(kk)
+                rs.append(rr)
+            ak = np.concatenate(ks) if ks else np.zeros(0, np.uint64)
+            ar = np.concatenate(rs, 1) if rs else np.zeros((R_ROWS, 0), np.float32)
+            made["k"], made["r"] = ak, ar
+            return torch.from_numpy(ak.view(np.int64).copy()), torch.from_numpy(ar)
+
+        ek, er = sw.update(torch.from_numpy(frames[f]).cuda(), fetch)
+        ek_np, er_np = _u64(ek).copy(), er.numpy().copy()
+        for k in np.unique(ek_np):
+            sel = ek_np == k
+            assert int(k) not in map_gpu
+            map_gpu[int(k)] = (ek_np[sel], er_np[:, sel])
+        # the oracle: the same map logic on its own evictions
+        pk, pok = oracle.voxel_key(frames[f], vs)
+        _, add_o = oracle.window_classify(win_keys, pk, pok)
+        ks, rs = [], []
+        for k in add_o:
+            if int(k) in map_orc:
+                kk, rr = map_orc.pop(int(k))
+                returned += len(kk)
+            else:
+                idx = np.nonzero(made["k"] == k)[0]  # new Gaussians: the rows the GPU side drew
+                kk, rr = made["k"][idx], made["r"][:, idx]
+            ks.append(kk)
+            rs.append(rr)
+        ak = np.concatenate(ks) if ks else np.zeros(0, np.uint64)
+        ar = np.concatenate(rs, 1) if rs else np.zeros((R_ROWS, 0), np.float32)
+        assert np.array_equal(ak, made["k"]) and np.array_equal(ar.view(np.uint32), made["r"].view(np.uint32))
+        win_keys, win_rows, ek_w, er_w = oracle.window_maintain(win_keys, win_rows, pk[pok], ak, ar)
+        for k in np.unique(ek_w):
+            sel = ek_w == k
+            map_orc[int(k)] = (ek_w[sel], er_w[:, sel])
+        assert sw.n == len(win_keys)
+        assert np.array_equal(_u64(sw.keys[:sw.n]), win_keys)
+        assert np.array_equal(sw.block[:, :sw.n].cpu().numpy().view(np.uint32), win_rows.view(np.uint32))
+        assert np.array_equal(ek_np, ek_w) and np.array_equal(er_np.view(np.uint32), er_w.view(np.uint32))
+        assert sorted(map_gpu) == sorted(map_orc)
+    assert returned > 0  # the stream turned back: some Gaussians came back from the map
