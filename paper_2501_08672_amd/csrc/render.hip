@@ -253,22 +253,47 @@ using list_t = typename std::conditional<(CH < 255), uint8_t, uint16_t>::type;
 // workgroup of NWV waves.  Entry CH is a sentinel whose alpha is 0 at every
 // pixel (log2 opacity = -inf, no tile parts): the forward walk pads its lists
 // with it to whole groups of four entries.
+// One staged splat, 48 bytes: a walk reads an entry through one address
+// (two 16-byte loads and one 8-byte load).
+struct StageEntry {
+    float4 p0;     // mx, my, l11', l12'  (factor scaled by kPowScale)
+    float4 p1;     // l22', log2(opacity), r, g
+    float p2;      // b
+    uint32_t gid;  // Gaussian index | band mask << 28
+    uint32_t pad[2];
+};
+
 template <int CH, int NWV>
 struct Stage {
-    float4 p0[CH + 1];  // mx, my, l11', l12'  (factor scaled by kPowScale)
-    float4 p1[CH + 1];  // l22', log2(opacity), r, g
-    float p2[CH + 1];   // b
-    uint32_t gid[CH + 1];  // Gaussian index | band mask << 28
-    list_t<CH> wl[NWV][CH + 4];  // per wave: the chunk entries that reach its region, in order
+    StageEntry e[CH + 1];
+    __device__ uint32_t gid_at(int k) const { return e[k].gid; }
+    // per wave: the chunk entries that reach its region, in order (rows start
+    // 8-byte aligned: groups of four entries are read with one load)
+    alignas(8) list_t<CH> wl[NWV][CH + 4];
 };
+
+// Entries [j4, j4 + 4) of wave wv's list (j4 a multiple of four) as one
+// scalar, entry u in bits [u * 8 * sizeof(list_t), ...).
+template <int CH, int NWV>
+__device__ __forceinline__ uint64_t list_group(const Stage<CH, NWV> &st, int wv, int j4)
+{
+    static_assert(((CH + 4) * sizeof(list_t<CH>)) % (4 * sizeof(list_t<CH>)) == 0, "list rows hold whole groups");
+    const list_t<CH> *p = &st.wl[wv][j4];
+    if (sizeof(list_t<CH>) == 2) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        return (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(v.x) |
+               ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(v.y) << 32);
+    }
+    return (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t *>(p));
+}
 
 template <typename St, int CH>
 __device__ __forceinline__ void stage_sentinel(St &st)
 {
-    st.p0[CH] = make_float4(0.f, 0.f, 0.f, 0.f);
-    st.p1[CH] = make_float4(0.f, -__builtin_inff(), 0.f, 0.f);
-    st.p2[CH] = 0.f;
-    st.gid[CH] = 0u;
+    st.e[CH].p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.e[CH].p1 = make_float4(0.f, -__builtin_inff(), 0.f, 0.f);
+    st.e[CH].p2 = 0.f;
+    st.e[CH].gid = 0u;
 }
 
 // A projection record (mx, my, l11, l12 | l22, opacity, r, g | b ...) in the
@@ -302,9 +327,9 @@ __device__ __forceinline__ void stage_load(St &st, const RenderArgs &a, const gs
         const int e = (int)threadIdx.x + q * BS;
         if (e < CH && start + (uint32_t)e < end) {
             const float4 *r4 = reinterpret_cast<const float4 *>(rec + (val[q] & kGidMask));
-            stage_splat(r4, st.p0[e], st.p1[e]);
-            st.p2[e] = r4[2].x;
-            st.gid[e] = val[q];
+            stage_splat(r4, st.e[e].p0, st.e[e].p1);
+            st.e[e].p2 = r4[2].x;
+            st.e[e].gid = val[q];
         }
     }
 }
@@ -336,7 +361,11 @@ __device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1
     const float t2 = p1.x * e.dy;
     const float lg = fmaf(-t1, t1, fmaf(-t2, t2, p1.y));
     e.s = __builtin_amdgcn_exp2f(lg);
-    e.alpha = fminf(amax, e.s);
+    // min(alpha_max, s) on the bit patterns: both are >= 0 (exp2 never
+    // returns a negative value), where the unsigned order is the float order,
+    // and a NaN s (any sign) gives alpha_max as fminf does.  One integer min
+    // instead of a float min that re-canonicalises alpha_max at every step.
+    e.alpha = __uint_as_float(min(__float_as_uint(e.s), __float_as_uint(amax)));
     return e;
 }
 
@@ -360,9 +389,14 @@ __device__ __forceinline__ CompStep comp_step(float T, float a, float amin, floa
     const bool hit = a >= amin;
     const float Tn = fmaf(-T, a, T);
     r.acc = hit && Tn >= Tmin;
-    const float Tsel = r.acc ? Tn : T;
+    float Tsel = r.acc ? Tn : T;
     r.w = T - Tsel;
-    r.T = (hit && !r.acc) ? -fabsf(T) : Tsel;
+    // A hit that does not contribute keeps Tsel == T, so the new state is
+    // formed from Tsel alone.  The empty statement orders the weight first:
+    // T's last use is then the weight and the new state takes T's register
+    // (no copy at the loop's back edge).  It emits no instruction.
+    asm("" : "+v"(Tsel) : "v"(r.w));
+    r.T = (hit && !r.acc) ? -fabsf(Tsel) : Tsel;
     return r;
 }
 
@@ -383,7 +417,7 @@ __device__ __forceinline__ int wave_list(St &st, int n, int wv, int lane)
 #pragma unroll
     for (int g = 0; g < CH; g += kWave) {
         const int e = g + lane;
-        const bool in = e < n && in_band<TS, NW>(st.gid[e], wv, 0);
+        const bool in = e < n && in_band<TS, NW>(st.gid_at(e), wv, 0);
         const uint64_t m = __ballot(in);
         if (in) st.wl[wv][c + __popcll(m & below)] = (L)e;
         c += __popcll(m);
@@ -478,16 +512,22 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
         // Groups of four entries, the last one padded with the sentinel, and
         // the open-pixel test once per group (finished pixels change
         // nothing): one exit from the loop, straight-line groups.
-        for (int j4 = 0; j4 < nw_list && any_lane(open()); j4 += 4)
-#pragma unroll 1
-        for (int u = 0; u < 4; u++) {
-            const int jj = j4 + u;
-            const int j = G::ONE_BAND ? __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj])
-                                      : (jj < nw_list ? jj : CH);
-            const float4 p0 = st.p0[j];
-            const float4 p1 = st.p1[j];
-            const float cb = st.p2[j];
-            const uint32_t val = __builtin_amdgcn_readfirstlane(st.gid[j]);  // same for every lane
+        // (one loop with one exit test, at the end of each group: nested
+        // loops make the register allocator copy every accumulator at each
+        // group's end)
+        constexpr int EB = 8 * (int)sizeof(list_t<CH>);
+        const int nw_pad = (nw_list + 3) & ~3;
+        uint64_t grp = 0;
+        bool go = nw_pad > 0 && any_lane(open());
+        for (int jj = 0; go; ) {
+            const int u = jj & 3;
+            if (G::ONE_BAND && u == 0) grp = list_group(st, wv, jj);
+            const int j = G::ONE_BAND ? (int)((grp >> (u * EB)) & ((1u << EB) - 1u)) : (jj < nw_list ? jj : CH);
+            const StageEntry &se = st.e[j];
+            const float4 p0 = se.p0;
+            const float4 p1 = se.p1;
+            const float cb = se.p2;
+            const uint32_t val = __builtin_amdgcn_readfirstlane(se.gid);  // same for every lane
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
             const uint32_t pos1 = start + (uint32_t)j + 1u - ti.rs;
@@ -512,15 +552,15 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
             if (hits) {
                 const int pos = (int)pos1 - 1, wd = pos >> 5;
                 if (wd != hword) {
-                    if (lane == 0 && hword < kHitWords) hits[hword] = hbits;
+                    // every lane stores the same word: no divergent branch in the loop
+                    if (hword < kHitWords) hits[hword] = hbits;
                     hbits = 0;
                     hword = wd;
                 }
                 if (any_lane(used)) hbits |= 1u << (pos & 31);
             }
-            // keep the four entries of a group apart: hoisting their LDS
-            // reads ahead costs more registers than the waves have
-            __builtin_amdgcn_sched_barrier(0);
+            jj++;
+            if ((jj & 3) == 0) go = jj < nw_pad && any_lane(open());
         }
         __syncthreads();
     }
@@ -544,7 +584,7 @@ __device__ __forceinline__ int wave_list_bwd(Stage<CH, NW> &st, int n, uint32_t 
     for (int g = 0; g < CH; g += kWave) {
         const int e = g + lane;
         const uint32_t pos = pos0 + (uint32_t)e;
-        bool in = e < n && pos < maxn && (!Geo<TS, NW>::ONE_BAND || in_band<TS, NW>(st.gid[e], wv, 0));
+        bool in = e < n && pos < maxn && (!Geo<TS, NW>::ONE_BAND || in_band<TS, NW>(st.e[e].gid, wv, 0));
         if (in && hits && pos < 32u * kHitWords) in = ((hits[pos >> 5] >> (pos & 31)) & 1u) != 0u;
         const uint64_t m = __ballot(in);
         if (in) st.wl[wv][c + __popcll(m & below)] = (list_t<CH>)e;
@@ -603,13 +643,19 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
         // the entries this wave has to visit, in order (walked in reverse)
         const int nl = wave_list_bwd<TS, NW, CH>(st, (int)(end - start), (uint32_t)(start - lo), wave_max, hits, wv,
                                                  lane);
+        constexpr int EB = 8 * (int)sizeof(list_t<CH>);
+        uint64_t grp = 0;
         for (int jj = nl - 1; jj >= 0; jj--) {
-            const int j = __builtin_amdgcn_readfirstlane((int)st.wl[wv][jj]);
+            // the group of four holding jj (entries past the list are read, never used)
+            const int u = jj & 3;
+            if (u == 3 || jj == nl - 1) grp = list_group(st, wv, jj & ~3);
+            const int j = (int)((grp >> (u * EB)) & ((1u << EB) - 1u));
             const uint32_t pos = (uint32_t)(start - lo) + (uint32_t)j;
-            const float4 p0 = st.p0[j];
-            const float4 p1 = st.p1[j];
-            const float cb = st.p2[j];
-            const uint32_t val = __builtin_amdgcn_readfirstlane(st.gid[j]);  // same for every lane
+            const StageEntry &se = st.e[j];
+            const float4 p0 = se.p0;
+            const float4 p1 = se.p1;
+            const float cb = se.p2;
+            const uint32_t val = __builtin_amdgcn_readfirstlane(se.gid);  // same for every lane
             const float dx = fx - p0.x;
             const float ax = p0.z * dx;
             // Per lane: gp = dL/dpower of each pixel; the lane's pixels share
@@ -912,6 +958,7 @@ struct TanStage {
     uint32_t gid[CH];
     float4 t[NQ][CH];
     uint8_t wl[NWV][CH];  // per wave: the entries that reach its region
+    __device__ uint32_t gid_at(int k) const { return gid[k]; }
 };
 
 template <int TS, int NW, bool SHC>
