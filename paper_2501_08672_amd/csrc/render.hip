@@ -76,10 +76,11 @@ struct Geo {
     static constexpr int RSTEP = kWave / CW;              // row stride between a lane's pixels
     static constexpr int CH = BS;                         // splats staged per chunk
     // workgroups per CU the compositing kernels ask the compiler to fit: four
-    // waves per workgroup, seven workgroups = seven waves per SIMD (at most 72
-    // VGPRs, which the fused kernel fits without spilling); measured faster
-    // than eight with spills and than fewer, larger-register waves
-    static constexpr int MIN_WG = BS == 256 ? 7 : 1;
+    // waves per workgroup, eight workgroups = eight waves per SIMD (at most 64
+    // VGPRs, which the fused kernel fits without spilling); the persistent
+    // kernel keeps seven (72 VGPRs: it spills at 64)
+    static constexpr int MIN_WG = BS == 256 ? 8 : 1;
+    static constexpr int MIN_WG_PERSISTENT = BS == 256 ? 7 : 1;
     static constexpr bool MASKED = TS >= 16;
     static_assert(CW * ROWS % kWave == 0 && PPL >= 1 && ROWS * (QUAD ? 2 : NW) == TS, "tile/wave layout");
     __device__ static int col0(int w) { return QUAD ? (w & 1) * 16 : 0; }
@@ -842,7 +843,8 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_re
 }
 
 template <int TS, int NW, int CH>
-__global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG)) void k_render_fused_persistent(RenderArgs a)
+__global__ __launch_bounds__((Geo<TS, NW>::BS), (Geo<TS, NW>::MIN_WG_PERSISTENT)) void k_render_fused_persistent(
+    RenderArgs a)
 {
     __shared__ Stage<CH, NW> st;
     __shared__ uint32_t s_max;
