@@ -610,14 +610,22 @@ def main():
     # stage times: HIP events on the launch stream between the stages of eager
     # steps (the fused kernel's duration for the roofline: in the kernel trace
     # these dispatches take what the events show), and of replays of the
-    # step's profiling graph, whose event nodes add their own time
-    st_ms = np.array([win.profiled_step() for _ in range(5)]).mean(0)
+    # step's profiling graph, whose event nodes add their own time.  Reading
+    # the events waits for the GPU, and after such an idle gap the clock takes
+    # some ten steps to come back: every profiled step is queued behind ten
+    # plain replays, so it runs at the clock of the timed region.
+    def behind_replays(graph=False):
+        for _ in range(10):
+            win.step(use_graph)
+        return win.profiled_step(graph=graph)
+
+    st_ms = np.array([behind_replays() for _ in range(5)]).mean(0)
     log("eager stage ms (project, bin_sort, fused render, adjoint, total): " + " ".join(f"{x:.3f}" for x in st_ms))
     st_graph = None
     if use_graph:
         try:
             win.profiled_step(graph=True)  # capture
-            st_graph = np.array([win.profiled_step(graph=True) for _ in range(10)]).mean(0)
+            st_graph = np.array([behind_replays(graph=True) for _ in range(10)]).mean(0)
             log("graph stage ms (project, bin_sort, fused render, adjoint, total): "
                 + " ".join(f"{x:.3f}" for x in st_graph))
         except Exception as e:
