@@ -109,6 +109,22 @@ COUNTER_FILE = os.path.join(ROOT, "profiles", "fused_render_counters.txt")
 L2_ATOMIC_PEAK_PER_S = 8 * 16 * 2.4e9
 
 
+def read_counter(name):
+    """One per-dispatch counter of the fused kernel from the committed SQ/TCC
+    summary, or None when it is missing or was taken on a different render.hip."""
+    if not os.path.exists(COUNTER_FILE):
+        return None
+    kv = {}
+    for ln in open(COUNTER_FILE):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        return float(kv[name]) if kv.get("render_hip_sha1") == source_digest() else None
+    except (KeyError, ValueError):
+        return None
+
+
 def read_atomics():
     """(L2 atomic requests, atomic wave instructions) per fused launch from
     the committed SQ/TCC counter summary, or None when it is missing or was
@@ -714,6 +730,10 @@ def main():
 
     traffic = read_traffic()
     atomics = read_atomics()
+    # the VALU issue ceilings the compositing kernel's instruction mix meets
+    valu_ceiling = {m: round(ops.valu_probe(ctx, m), 3) for m in ops.VALU_PROBE_MODES}
+    valu_insts = read_counter("SQ_INSTS_VALU")
+    log(f"VALU issue ceilings (wave64 instructions per CU per 2.4-GHz cycle): {valu_ceiling}")
     result = {
         "metric": "fwd+bwd Mpixels/s at 500k Gaussians, 8-frame window; fwd ms/frame",
         "value": round(mpix, 2),
@@ -757,6 +777,12 @@ def main():
                          "source": "TCC_ATOMIC and TA_FLAT_ATOMIC_WAVEFRONTS per dispatch from the committed "
                                    "counter summary of the same render.hip; peak derived: one request per L2 "
                                    "channel per clock, 8 XCDs x 16 channels x 2.4 GHz"},
+                     "valu_issue": {"insts_per_cu_cycle": round(valu_insts / (fused_ms * 1e-3 * 2.4e9 * 256), 3)
+                                    if valu_insts else None,
+                                    "ceiling_per_kind": valu_ceiling,
+                                    "source": "kernel's SQ_INSTS_VALU from the committed counter summary of the "
+                                              "same render.hip over its duration here; ceilings from gsl_valu_probe "
+                                              "(independent chains, eight waves per SIMD)"},
                      "hbm_view": {"algorithmic_bytes": int(fused_bytes),
                                   "gbs": round(fused_bytes / (fused_ms * 1e-3) / 1e9, 1),
                                   "frac": round(fused_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},

@@ -35,7 +35,7 @@ EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "g
            "gsl_ieskf_pose_update", "gsl_ieskf_visual_update", "gsl_adam_init", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
            "gsl_voxel_keys", "gsl_window_workspace_size", "gsl_window_classify", "gsl_window_compact",
            "gsl_window_transfer",
-           "gsl_color_init"]
+           "gsl_color_init", "gsl_valu_probe"]
 
 
 class GslError(RuntimeError):
@@ -118,6 +118,7 @@ def lib() -> C.CDLL:
     L.gsl_render_stats.argtypes = [P, pc, C.c_int32, C.c_int32, po, pp, pb, P, P, C.c_size_t, P]
     L.gsl_window_variant.argtypes = [P, pc, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.gsl_graph_count.argtypes = [P, C.POINTER(C.c_int64)]
+    L.gsl_valu_probe.argtypes = [P, C.c_int32, P, C.POINTER(C.c_double)]
     L.gsl_profile.argtypes = [P, C.c_int]
     L.gsl_profile_read.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
     L.gsl_window_step.argtypes = [P, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, P, pgr, P, C.c_size_t, C.c_int, P]

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libgslivo.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 ARCH = os.environ.get("GSL_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["project.hip", "sort.hip", "render.hip", "optim.hip", "window.hip", "sh.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["project.hip", "sort.hip", "render.hip", "optim.hip", "window.hip", "sh.hip", "noalloc.hip", "probe.hip", "api.cpp"]
 # no packed FP32, and no implicit contraction: every fused multiply-add in the
 # kernels is written out, so the same expression rounds the same way in every
 # kernel and template instantiation

@@ -317,4 +317,9 @@ void launch_pose_reduce(const double *pose_part, const double *pose_part2, int b
 void launch_sh_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const float *g2d, float *g_sh,
                    float *g_mean, int accumulate, double *pose_part, int pose_blocks, hipStream_t s);
 
+// probe.hip: wave64 VALU instructions per CU and 2.4-GHz cycle of an
+// instruction kind (0 FMA, 1 multiply + exp2, 2 integer min + add) over the
+// whole chip; 0 on success
+int run_valu_probe(int mode, int num_cus, float *sink, double *rate);
+
 }  // namespace gsl

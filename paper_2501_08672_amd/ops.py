@@ -91,6 +91,20 @@ def graph_count(ctx: "Context") -> int:
     return int(n.value)
 
 
+VALU_PROBE_MODES = {"fma": 0, "mul_exp2": 1, "umin_add": 2}
+
+
+def valu_probe(ctx: "Context", mode: str) -> float:
+    """Wave64 VALU instructions the chip issues per CU per 2.4-GHz cycle for
+    one instruction kind (gsl_valu_probe; a measurement aid for the
+    compositing kernels' roofline): "fma", "mul_exp2" or "umin_add"."""
+    import torch
+    sink = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+    r = C.c_double()
+    A.check(A.lib().gsl_valu_probe(ctx.h, VALU_PROBE_MODES[mode], C.c_void_p(sink.data_ptr()), C.byref(r)))
+    return float(r.value)
+
+
 class CameraSet:
     """Host description of the C cameras of a window."""
 
