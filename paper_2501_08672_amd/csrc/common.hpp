@@ -139,7 +139,7 @@ struct WsLayout {
     size_t partial = 0;     // u64[...] scan partial sums
     size_t rs_totals = 0;   // u32[256] per-digit totals of a radix pass
     size_t g2d = 0;         // float[C][N][kG2]
-    size_t pose_part = 0;   // double[pose_blocks][C][6]
+    size_t pose_part = 0;   // double[C][6][pose_blocks]
     size_t pose_part_sh = 0;  // the same for the SH colour's camera-centre term
     size_t loss_part = 0;   // double[T_total]
     size_t order = 0;       // u32[T_total] work order of the fused kernel
@@ -309,7 +309,7 @@ void launch_reduce_f64(const double *part, int64_t n, double *out, hipStream_t s
 // sh.hip: bilinear colour of new Gaussians from a camera image
 void launch_color_init(const float *mean, int64_t mean_ld, int n, const gsl_camera &c, float near_z,
                        const float *image, float *color, int64_t color_ld, uint8_t *valid, hipStream_t s);
-// sums pose_part (and pose_part2 when not null), [blocks][C][6] each
+// sums pose_part (and pose_part2 when not null), [C][6][blocks] each
 void launch_pose_reduce(const double *pose_part, const double *pose_part2, int blocks, int C, double *g_pose,
                         int accumulate, hipStream_t s);
 // adjoint of the SH colour (no-op at sh_degree 0): g_sh written or

@@ -516,11 +516,11 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
             if (threadIdx.x < 6) {
                 double v = 0;
                 for (int w = 0; w < kPoseThreads / kWave; w++) v += s_red[w][threadIdx.x];
-                pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = v;
+                pose_part[((int64_t)c * 6 + threadIdx.x) * gridDim.x + blockIdx.x] = v;
             }
             __syncthreads();
         } else if (threadIdx.x < 6) {
-            pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = 0.0;
+            pose_part[((int64_t)c * 6 + threadIdx.x) * gridDim.x + blockIdx.x] = 0.0;
         }
     }
     if (!valid) return;
@@ -623,11 +623,11 @@ __global__ __launch_bounds__(kPoseThreads) void k_sh_bwd(const float *__restrict
                 double v = 0;
                 if (threadIdx.x >= 3)
                     for (int w = 0; w < kPoseThreads / kWave; w++) v += s_red[w][threadIdx.x - 3];
-                pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = v;
+                pose_part[((int64_t)c * 6 + threadIdx.x) * gridDim.x + blockIdx.x] = v;
             }
             __syncthreads();
         } else if (threadIdx.x < 6) {
-            pose_part[((int64_t)blockIdx.x * C + c) * 6 + threadIdx.x] = 0.0;
+            pose_part[((int64_t)c * 6 + threadIdx.x) * gridDim.x + blockIdx.x] = 0.0;
         }
     }
     if (!valid) return;
@@ -650,43 +650,40 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const double *__restrict__ 
                                                      const double *__restrict__ part2, int blocks, int C,
                                                      double *__restrict__ g_pose, int accumulate)
 {
-    __shared__ double s_red[256 / kWave][6];
-    const int c = blockIdx.x;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    // workgroup (c, k) sums the contiguous row part[c][k][0 .. blocks) (and
+    // part2's) in a fixed order: the result does not depend on the run
+    __shared__ double s_red[256 / kWave];
+    const int c = blockIdx.x / 6, k = blockIdx.x - 6 * c;
+    const double *row = part + ((int64_t)c * 6 + k) * blocks;
+    const double *row2 = part2 ? part2 + ((int64_t)c * 6 + k) * blocks : nullptr;
+    double acc = 0.0;
     int b = threadIdx.x;
-    for (; b + 3 * 256 < blocks; b += 4 * 256) {  // four blocks' loads in flight, added in the same order
-        double v[4][6], v2[4][6];
+    for (; b + 3 * 256 < blocks; b += 4 * 256) {  // four loads in flight, added in the same order
+        double v[4], v2[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++)
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                v[q][k] = part[((int64_t)(b + q * 256) * C + c) * 6 + k];
-                v2[q][k] = part2 ? part2[((int64_t)(b + q * 256) * C + c) * 6 + k] : 0.0;
-            }
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                acc[k] += v[q][k];
-                if (part2) acc[k] += v2[q][k];
-            }
-    }
-    for (; b < blocks; b += 256)
-        for (int k = 0; k < 6; k++) {
-            acc[k] += part[((int64_t)b * C + c) * 6 + k];
-            if (part2) acc[k] += part2[((int64_t)b * C + c) * 6 + k];
+        for (int q = 0; q < 4; q++) {
+            v[q] = row[b + q * 256];
+            v2[q] = row2 ? row2[b + q * 256] : 0.0;
         }
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    for (int k = 0; k < 6; k++) {
-        const double v = wave_sum_f64(acc[k]);
-        if (lane == 0) s_red[wv][k] = v;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            acc += v[q];
+            if (row2) acc += v2[q];
+        }
     }
+    for (; b < blocks; b += 256) {
+        acc += row[b];
+        if (row2) acc += row2[b];
+    }
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const double w = wave_sum_f64(acc);
+    if (lane == 0) s_red[wv] = w;
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x == 0) {
         double v = 0;
-        for (int w = 0; w < 256 / kWave; w++) v += s_red[w][threadIdx.x];
-        if (accumulate) g_pose[c * 6 + threadIdx.x] += v;
-        else g_pose[c * 6 + threadIdx.x] = v;
+        for (int q = 0; q < 256 / kWave; q++) v += s_red[q];
+        if (accumulate) g_pose[c * 6 + k] += v;
+        else g_pose[c * 6 + k] = v;
     }
 }
 
@@ -747,7 +744,7 @@ void launch_pose_reduce(const double *pose_part, const double *pose_part2, int b
                         int accumulate, hipStream_t s)
 {
     if (!g_pose || C == 0) return;
-    hipLaunchKernelGGL(k_pose_reduce, dim3(C), dim3(256), 0, s, pose_part, pose_part2, blocks, C, g_pose,
+    hipLaunchKernelGGL(k_pose_reduce, dim3(6 * C), dim3(256), 0, s, pose_part, pose_part2, blocks, C, g_pose,
                        accumulate);
 }
 

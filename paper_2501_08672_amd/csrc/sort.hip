@@ -83,7 +83,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__
     }
 }
 
-// Exclusive scan of the block sums in one workgroup; writes the total.
+// Exclusive scan of the block sums in one workgroup (four consecutive sums
+// per thread, 4096 per step); writes the total.
+constexpr int kPartialItems = 4;
+
 __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ partial, int64_t nb,
                                                         int64_t *__restrict__ d_total)
 {
@@ -92,10 +95,15 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ p
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    for (int64_t base = 0; base < nb; base += 1024) {
-        const int64_t j = base + threadIdx.x;
-        const uint64_t v = j < nb ? partial[j] : 0;
-        const uint64_t inc = wave_incl_scan_u64(v, lane);
+    for (int64_t base = 0; base < nb; base += 1024 * kPartialItems) {
+        const int64_t j0 = base + (int64_t)threadIdx.x * kPartialItems;
+        uint64_t v[kPartialItems], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kPartialItems; q++) {
+            v[q] = j0 + q < nb ? partial[j0 + q] : 0;
+            sum += v[q];
+        }
+        const uint64_t inc = wave_incl_scan_u64(sum, lane);
         if (lane == 63) s_w[wv] = inc;
         __syncthreads();
         uint64_t wbase = 0, tot = 0;
@@ -103,10 +111,14 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *__restrict__ p
             if (w < wv) wbase += s_w[w];
             tot += s_w[w];
         }
-        const uint64_t carry = s_carry;
-        if (j < nb) partial[j] = carry + wbase + inc - v;
+        uint64_t run = s_carry + wbase + inc - sum;
+#pragma unroll
+        for (int q = 0; q < kPartialItems; q++) {
+            if (j0 + q < nb) partial[j0 + q] = run;
+            run += v[q];
+        }
         __syncthreads();
-        if (threadIdx.x == 0) s_carry = carry + tot;
+        if (threadIdx.x == 0) s_carry += tot;
         __syncthreads();
     }
     if (threadIdx.x == 0 && d_total) *d_total = (int64_t)s_carry;
@@ -205,8 +217,19 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__rest
         const int64_t j = base + (int64_t)r * kWave + lane;
         const uint32_t kj = kk[r];
         const bool valid = j < n && !(drop && kj == kDropKey);
-        // the counts do not depend on the order of the adds
-        if (valid) atomicAdd(&s_cnt[wv][(kj >> shift) & dmask], 1u);
+        const uint32_t d = (kj >> shift) & dmask;
+        // the counts do not depend on the order of the adds; a wave whose
+        // keys share one digit (the top byte of depth keys, mostly) adds its
+        // count once instead of 64 conflicting LDS atomics on one counter
+        const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+        if (vm == 0ull) continue;
+        const int first = __builtin_amdgcn_readfirstlane((int)__ffsll((unsigned long long)vm) - 1);
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, first);
+        if (__builtin_amdgcn_ballot_w64(valid && d != d0) == 0ull) {
+            if (lane == first) atomicAdd(&s_cnt[wv][d0], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&s_cnt[wv][d], 1u);
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < (1 << db); d += kSortThreads) {
