@@ -296,11 +296,15 @@ void do_upload(const Prepared &p, void *ws, hipStream_t s)
     launch_upload_cams(at<DevCam>(ws, p.W.cams), p.dc.data(), p.L.C, s);
 }
 
-void do_project(const Prepared &p, const gsl_gaussians *g, gsl_proj *out, void *ws, hipStream_t s)
+// With clear_g2d (the fused window step) the projection also clears the
+// 2D-gradient records the compositing kernel accumulates into.
+void do_project(const Prepared &p, const gsl_gaussians *g, gsl_proj *out, void *ws, hipStream_t s,
+                bool clear_g2d = false)
 {
     launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->binrecs, out->depth_keys,
                    out->tiles_touched,
-                   at<uint32_t>(ws, p.W.big), at<uint32_t>(ws, p.W.misc + 128), s);
+                   at<uint32_t>(ws, p.W.big), at<uint32_t>(ws, p.W.misc + 128), s,
+                   clear_g2d ? at<float>(ws, p.W.g2d) : nullptr);
 }
 
 void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *ws, hipStream_t s)
@@ -405,10 +409,9 @@ void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const fl
     };
     mark(kStProject);
     if (upload) do_upload(p, ws, s);
-    do_project(p, g, proj, ws, s);
+    do_project(p, g, proj, ws, s, true);  // also clears the 2D-gradient records
     mark(kStBinSort);
     do_bin_sort(p, proj, bins, ws, s);
-    launch_fill_f32(at<float>(ws, p.W.g2d), 0.f, p.L.M * kG2, s);
     launch_fill_u32(at<uint32_t>(ws, p.W.misc), 0u, 1, s);
     RenderArgs a = render_args(p, proj, bins, ws);
     a.image = image;

@@ -204,7 +204,7 @@ void launch_window_compact(uint64_t *keys, float *rows, int R, int64_t ld, int64
 void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t s);
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                     gsl_splat *splats, gsl_binrec *binrecs, uint32_t *depth_keys, int32_t *tiles_touched,
-                    uint32_t *big_list, uint32_t *big_n, hipStream_t s);
+                    uint32_t *big_list, uint32_t *big_n, hipStream_t s, float *g2d_zero = nullptr);
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                         const float *g2d, const gsl_grads &out, int accumulate, double *pose_part,
                         int pose_blocks, hipStream_t s);

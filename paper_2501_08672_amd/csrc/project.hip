@@ -150,11 +150,23 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                                                  const DevCam *__restrict__ cams, DevOpts o,
                                                  gsl_splat *__restrict__ out, gsl_binrec *__restrict__ bout,
                                                  uint32_t *__restrict__ kout, int32_t *__restrict__ tiles,
-                                                 uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_n)
+                                                 uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_n,
+                                                 float *__restrict__ g2d_zero)
 {
     __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // with g2d_zero (the fused window step): clear the 2D-gradient records of
+    // this workgroup's records, one contiguous block written coalesced, in
+    // place of a separate fill before the compositing kernel
+    if (g2d_zero) {
+        const int64_t base = (int64_t)blockIdx.x * blockDim.x * kG2, end = M * kG2;
+#pragma unroll
+        for (int q = 0; q < kG2; q++) {
+            const int64_t k = base + (int64_t)q * blockDim.x + threadIdx.x;
+            if (k < end) g2d_zero[k] = 0.f;
+        }
+    }
     uint32_t nt = 0;
     bool big = false;
     if (m < M) {
@@ -702,7 +714,7 @@ void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t
 
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                     gsl_splat *splats, gsl_binrec *binrecs, uint32_t *depth_keys, int32_t *tiles_touched,
-                    uint32_t *big_list, uint32_t *big_n, hipStream_t s)
+                    uint32_t *big_list, uint32_t *big_n, hipStream_t s, float *g2d_zero)
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
@@ -710,11 +722,11 @@ void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L,
     if (g.sh_degree > 0)
         hipLaunchKernelGGL(k_project<true>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat,
                            g.opacity, g.color, g.sh, g.sh_degree, g.N, L.M, cams, o, splats, binrecs, depth_keys,
-                           tiles_touched, big_list, big_n);
+                           tiles_touched, big_list, big_n, g2d_zero);
     else
         hipLaunchKernelGGL(k_project<false>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat,
                            g.opacity, g.color, g.sh, 0, g.N, L.M, cams, o, splats, binrecs, depth_keys,
-                           tiles_touched, big_list, big_n);
+                           tiles_touched, big_list, big_n, g2d_zero);
     launch_count_big(binrecs, cams, L, tiles_touched, big_list, big_n, s);
 }
 
