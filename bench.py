@@ -10,7 +10,7 @@ opacities, colours and the 8 camera poses — replayed as one HIP graph.
 Inputs are resident in HBM before the timed region.
 
 Prints one JSON line; besides the metric it carries
-  fwd_ms_per_frame  forward only (project + bin_sort + render_fwd) per frame
+  fwd_ms_per_frame  forward only (gsl_window_render: project + bin_sort + render_fwd as one graph) per frame
   per_frame         the same window as 8 sequential single-camera eager steps
   roofline          the fused render kernel (dominant), ALU-bound: algorithmic
                     FLOPs from the pair counts / its duration (HIP events on
@@ -295,8 +295,9 @@ def _timed_steps(torch, win, steps):
 
 def workloads_bench(ctx, ops, S, torch, steps, with_oracle):
     """The other workloads of the metric, beside the headline window:
-    the 1k / 128x96 plain forward render (ms per frame: project + bin_sort +
-    render_fwd, eager, tile 16), the 100k / 640x512 forward + backward
+    the 1k / 128x96 plain forward render (ms per frame: gsl_window_render
+    replayed as a graph, and the eager three calls; tile 16), the 100k /
+    640x512 forward + backward
     (L1, tuned window step replayed as a graph, Mpixels/s) and the 2M /
     16-camera uneven batch (tuned tile, chunk and variant, graph, Mpixels/s);
     with the oracle's full-frame times for the first two."""
@@ -321,9 +322,36 @@ def workloads_bench(ctx, ops, S, torch, steps, with_oracle):
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
+    # the same render as one recorded unit (gsl_window_render), replayed
+    r1 = ops.WindowRender(ctx, g1, cs1, o1, capacity=bins.capacity)
+    for _ in range(20):
+        r1(use_graph=True)
+    torch.cuda.synchronize()
+    # back-to-back frames (throughput), then each frame on its own (latency)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(100):
+        r1(use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    b2b = e0.elapsed_time(e1) / 100
+    gtimes = []
+    for _ in range(max(20, steps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r1(use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        gtimes.append(e0.elapsed_time(e1))
+    assert r1.status() == 0
     c1 = {"workload": "plain forward render: 1,000 Gaussians, one 128x96 camera, tile 16",
-          "fwd_ms_per_frame": round(float(np.median(times)), 4), "instances_K": bins.K,
-          "how": "project + bin_sort + render_fwd, eager launches, HIP events, median"}
+          "fwd_ms_per_frame": round(float(np.median(gtimes)), 4), "instances_K": bins.K,
+          "how": "gsl_window_render replayed as a HIP graph (camera upload + projection + binning + "
+                 "compositing), HIP events around each frame, median",
+          "fwd_ms_per_frame_back_to_back": round(b2b, 4),
+          "fwd_ms_per_frame_eager": round(float(np.median(times)), 4),
+          "eager_how": "gsl_project + gsl_bin_sort + gsl_render_fwd, eager launches, HIP events, median"}
+    del r1
     if with_oracle:
         O.build(force=False)
         t0 = time.perf_counter()
@@ -662,21 +690,34 @@ def main():
     N, C_ = g.N, cs.C
     step_bytes = N * 144 + C_ * N * 60 + sum(visible) * 144 + K * 48 + cs.tiles(tile) * 16 + P * 32
 
-    # forward only, eager: project + bin_sort + render_fwd over the window
+    # forward only: the window's render as one recorded unit (gsl_window_render,
+    # camera upload + projection + binning + compositing) replayed as a graph,
+    # and the same kernels as eager gsl_project + gsl_bin_sort + gsl_render_fwd
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rw = ops.WindowRender(ctx, g, cs, win.opts, capacity=win.bins.capacity)
+    for it in range(20):  # the first ten bring the clock back after the last synchronisation
+        if it == 10:
+            ev0.record()
+        rw(use_graph=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    assert rw.status() == 0
+    fwd_ms = ev0.elapsed_time(ev1) / 10
+    del rw
     proj = ops.Proj(cs.C, g.N, ctx.device)
     bins = ops.Bins(win.bins.capacity, cs.tiles(tile), ctx.device)
-    for it in range(4):
-        if it == 1:
+    for it in range(13):
+        if it == 3:
             ev0.record()
         ops.project(ctx, g, cs, win.opts, out=proj)
         ops.bin_sort(ctx, cs, g.N, win.opts, proj, capacity=bins.capacity, bins=bins, grow=False)
         ops.render_fwd(ctx, cs, g.N, win.opts, proj, bins)
     ev1.record()
     torch.cuda.synchronize()
-    fwd_ms = ev0.elapsed_time(ev1) / 3
+    fwd_ms_eager = ev0.elapsed_time(ev1) / 10
     del proj, bins
-    log(f"forward only {fwd_ms:.3f} ms per window, {fwd_ms / cs.C:.3f} ms/frame")
+    log(f"forward only {fwd_ms:.3f} ms per window, {fwd_ms / cs.C:.3f} ms/frame (graph); "
+        f"{fwd_ms_eager:.3f} ms per window eager")
 
     per_frame = None
     if not args.no_per_frame:
@@ -753,6 +794,9 @@ def main():
                    "instances_K": K, "hip_graph": use_graph},
         "step_ms_events": step_pct,
         "fwd_ms_per_frame": round(fwd_ms / cs.C, 4),
+        "fwd_how": "the window's forward render (camera upload, projection, binning, compositing of all 8 "
+                   "keyframes) as gsl_window_render replayed as a HIP graph, 10 back-to-back replays after 10 untimed ÷ 8 frames",
+        "fwd_ms_per_frame_eager": round(fwd_ms_eager / cs.C, 4),
         "per_frame": per_frame,
         "stage_ms": {"project": round(float(st_ms[0]), 4), "bin_sort": round(float(st_ms[1]), 4),
                      "fused_render": round(float(st_ms[2]), 4), "adjoint": round(float(st_ms[3]), 4),

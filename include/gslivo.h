@@ -303,6 +303,22 @@ GSL_API int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, 
  * [0, 2] or host memory; GSL_EHIP when the launch or its timing fails. */
 GSL_API int gsl_valu_probe(gsl_ctx *ctx, int32_t mode, float *d_sink, double *insts_per_cu_cycle);
 
+/* Forward render of a window (the compositing of Sec. II-B, eq. raster, over
+ * tile lists built as in Sec. II-C) as one unit: gsl_project, gsl_bin_sort
+ * and gsl_render_fwd of all C cameras, the same kernels in the same order, so
+ * proj, bins, image, T_final and n_walk are bit-identical to those three
+ * calls'.  Buffers, layouts and workspace as for those calls (the workspace
+ * must satisfy gsl_workspace_size).  With use_graph the launches are recorded
+ * once per shape (camera sizes, N, tile, every pointer and the options; not
+ * the poses or intrinsics: the camera table is uploaded on the stream before
+ * each launch) into a HIP graph held by the context and replayed.  Errors as
+ * for the three calls; GSL_EHIP when recording or launching the graph
+ * fails. */
+GSL_API int gsl_window_render(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C,
+                              const gsl_opts *opts, gsl_proj *proj, gsl_bins *bins, float *image, float *T_final,
+                              uint32_t *n_walk, void *workspace, size_t workspace_bytes, int use_graph,
+                              void *stream);
+
 /* Number of HIP graphs the context holds (window steps and optimisation
  * loops recorded so far, at most 65 before the cache is flushed). */
 GSL_API int gsl_graph_count(gsl_ctx *ctx, int64_t *count);

@@ -35,7 +35,7 @@ EXPORTS = ["gsl_create", "gsl_destroy", "gsl_last_error", "gsl_default_opts", "g
            "gsl_ieskf_pose_update", "gsl_ieskf_visual_update", "gsl_adam_init", "gsl_adam_activate", "gsl_adam_step", "gsl_window_optimize",
            "gsl_voxel_keys", "gsl_window_workspace_size", "gsl_window_classify", "gsl_window_compact",
            "gsl_window_transfer",
-           "gsl_color_init", "gsl_valu_probe"]
+           "gsl_color_init", "gsl_valu_probe", "gsl_window_render"]
 
 
 class GslError(RuntimeError):
@@ -122,6 +122,7 @@ def lib() -> C.CDLL:
     L.gsl_profile.argtypes = [P, C.c_int]
     L.gsl_profile_read.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
     L.gsl_window_step.argtypes = [P, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, P, pgr, P, C.c_size_t, C.c_int, P]
+    L.gsl_window_render.argtypes = [P, pg, pc, C.c_int32, po, pp, pb, P, P, P, P, C.c_size_t, C.c_int, P]
     L.gsl_window_tune.argtypes = [P, pg, pc, C.c_int32, po, P, C.c_int, pp, pb, P, pgr, P, C.c_size_t,
                                   C.POINTER(C.c_float), C.c_int32, P]
     L.gsl_pose_jacobian_workspace_size.argtypes = [P, pc, C.c_int32, C.c_int32, po, C.c_int64,

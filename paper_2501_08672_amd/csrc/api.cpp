@@ -892,6 +892,46 @@ int gsl_window_step(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
     return rc;
 }
 
+int gsl_window_render(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams, int32_t C, const gsl_opts *opts,
+                      gsl_proj *proj, gsl_bins *bins, float *image, float *T_final, uint32_t *n_walk,
+                      void *workspace, size_t workspace_bytes, int use_graph, void *stream)
+{
+    GSL_TRY(check_gauss(g, true));
+    GSL_TRY(check_bins(bins));
+    if (!image || !T_final || !n_walk) return fail(GSL_EINVAL, "output buffer is NULL");
+    Prepared p;
+    GSL_TRY(prepare(ctx, cams, C, g->N, opts, bins->capacity_K, workspace, workspace_bytes, p));
+    GSL_TRY(check_proj(proj, p.L));
+    hipStream_t s = (hipStream_t)stream;
+    // the kernels of gsl_project, gsl_bin_sort and gsl_render_fwd, in order
+    auto body = [&](hipStream_t cs) {
+        do_project(p, g, proj, workspace, cs);
+        do_bin_sort(p, proj, bins, workspace, cs);
+        RenderArgs a = render_args(p, proj, bins, workspace);
+        a.image = image;
+        a.T_final = T_final;
+        a.n_walk = n_walk;
+        launch_render_fwd(a, cs);
+    };
+    do_upload(p, workspace, s);  // the camera table, outside the graph (poses are not in the key)
+    if (!use_graph) {
+        body(s);
+        return check_launch("gsl_window_render");
+    }
+    VariantKey gk = window_key(p.L, cams);
+    gk.v.push_back(-2);  // forward-render graphs (window-step keys continue with a variant >= 0)
+    auto ptr = [&](const void *q) { gk.v.push_back((int64_t)(uintptr_t)q); };
+    ptr(g->mean); ptr(g->scale); ptr(g->quat); ptr(g->opacity); ptr(g->color); ptr(g->sh);
+    gk.v.push_back(g->sh_degree);
+    ptr(proj->splats); ptr(proj->tiles_touched); ptr(proj->binrecs); ptr(proj->depth_keys);
+    ptr(bins->tile_ids); ptr(bins->gauss_ids); ptr(bins->ranges); ptr(bins->d_K); ptr(bins->d_status);
+    gk.v.push_back(bins->capacity_K);
+    ptr(image); ptr(T_final); ptr(n_walk); ptr(workspace);
+    const int32_t *ow = reinterpret_cast<const int32_t *>(opts);
+    for (size_t k = 0; k < sizeof(gsl_opts) / 4; k++) gk.v.push_back(ow[k]);
+    return graph_run(ctx, gk, s, body);
+}
+
 int gsl_graph_count(gsl_ctx *ctx, int64_t *count)
 {
     if (!ctx || !count) return fail(GSL_EINVAL, "NULL argument");

@@ -696,6 +696,44 @@ def ieskf_visual_update(HtH_cam, Htz_cam, A_imu, P, dx_prior=None, noise_var: fl
 
 # ---------------------------------------------------------------- window
 
+class WindowRender:
+    """Forward render of a camera set as one unit (gsl_window_render):
+    projection, binning and compositing of every camera, recorded into a HIP
+    graph on the first call and replayed afterwards (new poses replay the same
+    graph).  The buffers live here, so replays find them at the addresses the
+    graph was recorded with.  `capacity` bounds the instance count; by default
+    an eager binning at construction sizes it with `headroom`."""
+
+    def __init__(self, ctx: Context, g: Gaussians, cams: CameraSet, o: A.Opts, capacity: Optional[int] = None,
+                 headroom: float = 1.25):
+        self.ctx, self.g, self.cams, self.opts = ctx, g, cams, _opts_copy(o)
+        self.proj = Proj(cams.C, g.N, ctx.device)
+        if capacity is None:
+            project(ctx, g, cams, self.opts, out=self.proj)
+            b = bin_sort(ctx, cams, g.N, self.opts, self.proj)
+            capacity = int(b.K * headroom) + 4096
+            del b
+        self.bins = Bins(capacity, cams.tiles(self.opts.tile), ctx.device)
+        self.ws = torch.empty(workspace_size(ctx, cams, g.N, self.opts, capacity), dtype=torch.uint8,
+                              device=ctx.device)
+        self.image = torch.empty(3 * cams.P_total, dtype=torch.float32, device=ctx.device)
+        self.T_final = torch.empty(cams.P_total, dtype=torch.float32, device=ctx.device)
+        self.n_walk = torch.empty(cams.P_total, dtype=torch.int32, device=ctx.device)
+
+    def __call__(self, use_graph: bool = True):
+        """Enqueues one render; returns (packed image, T_final, n_walk), valid
+        once the stream reaches them and status() is 0."""
+        gs, ps, bs = self.g.struct(), self.proj.struct(), self.bins.struct()
+        A.check(A.lib().gsl_window_render(self.ctx.h, C.byref(gs), self.cams.arr, self.cams.C, C.byref(self.opts),
+                                          C.byref(ps), C.byref(bs), _p(self.image), _p(self.T_final),
+                                          _p(self.n_walk), _p(self.ws), self.ws.numel(), int(bool(use_graph)),
+                                          _stream()))
+        return self.image, self.T_final, self.n_walk
+
+    def status(self) -> int:
+        return int(self.bins.d_status.item())
+
+
 class Window:
     """All buffers of one batched-window optimisation pass (gsl_window_step).
 

@@ -89,7 +89,8 @@ def run_abi(path):
              "gsl_pose_jacobian": 17, "gsl_adam_init": 4, "gsl_adam_activate": 4, "gsl_adam_step": 6,
              "gsl_window_optimize": 18, "gsl_voxel_keys": 8, "gsl_window_classify": 11, "gsl_window_compact": 16,
              "gsl_color_init": 11, "gsl_window_variant": 7, "gsl_graph_count": 2,
-             "gsl_window_transfer": 11, "gsl_valu_probe": 4}
+             "gsl_window_transfer": 11, "gsl_valu_probe": 4,
+             "gsl_window_render": 14}
     for name, nargs in nulls.items():
         fn = getattr(L, name)
         args = [None if t is C.c_void_p or issubclass(t, C._Pointer) else t(0) for t in fn.argtypes]
