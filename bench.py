@@ -61,7 +61,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=1024, help="oracle sample: pixels per camera")
+    ap.add_argument("--cpu-pixels", type=int, default=4096,
+                    help="oracle sample: pixels per camera (the default is about 20 s of host time, which keeps "
+                         "the default run within minutes; full frames of this window would take hours)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--no-jac", action="store_true", help="skip the pose-Jacobian measurement")

@@ -304,7 +304,7 @@ void do_project(const Prepared &p, const gsl_gaussians *g, gsl_proj *out, void *
     launch_project(*g, at<DevCam>(ws, p.W.cams), p.L, p.o, out->splats, out->binrecs, out->depth_keys,
                    out->tiles_touched,
                    at<uint32_t>(ws, p.W.big), at<uint32_t>(ws, p.W.misc + 128), s,
-                   clear_g2d ? at<float>(ws, p.W.g2d) : nullptr);
+                   clear_g2d ? at<float>(ws, p.W.g2d) : nullptr, clear_g2d ? at<uint32_t>(ws, p.W.misc) : nullptr);
 }
 
 void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *ws, hipStream_t s)
@@ -328,6 +328,7 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     io.first_tiles = proj->tiles_touched;
     io.gather_tiles = proj->tiles_touched;
     io.counts_out = counts;
+    io.zero_word = at<uint32_t>(ws, W.misc + 128);  // the emit's big-record counter
     int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, totals, s, d_V, &io);
     const uint32_t *order = where ? dval2 : dval;
     // 2. instance offsets in that order
@@ -409,10 +410,12 @@ void do_window(gsl_ctx *ctx, const Prepared &p, const gsl_gaussians *g, const fl
     };
     mark(kStProject);
     if (upload) do_upload(p, ws, s);
-    do_project(p, g, proj, ws, s, true);  // also clears the 2D-gradient records
+    // the projection also clears the 2D-gradient records and the persistent
+    // kernel's work counter (with no records it launches nothing: fill here)
+    do_project(p, g, proj, ws, s, true);
     mark(kStBinSort);
     do_bin_sort(p, proj, bins, ws, s);
-    launch_fill_u32(at<uint32_t>(ws, p.W.misc), 0u, 1, s);
+    if (p.L.M == 0) launch_fill_u32(at<uint32_t>(ws, p.W.misc), 0u, 1, s);
     RenderArgs a = render_args(p, proj, bins, ws);
     a.image = image;
     a.target = target;

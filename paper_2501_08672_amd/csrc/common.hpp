@@ -204,7 +204,8 @@ void launch_window_compact(uint64_t *keys, float *rows, int R, int64_t ld, int64
 void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t s);
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                     gsl_splat *splats, gsl_binrec *binrecs, uint32_t *depth_keys, int32_t *tiles_touched,
-                    uint32_t *big_list, uint32_t *big_n, hipStream_t s, float *g2d_zero = nullptr);
+                    uint32_t *big_list, uint32_t *big_n, hipStream_t s, float *g2d_zero = nullptr,
+                    uint32_t *queue_zero = nullptr);
 void launch_project_bwd(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                         const float *g2d, const gsl_grads &out, int accumulate, double *pose_part,
                         int pose_blocks, hipStream_t s);
@@ -235,6 +236,7 @@ struct DepthSortIO {
     const int32_t *first_tiles;
     const int32_t *gather_tiles;
     uint32_t *counts_out;
+    uint32_t *zero_word = nullptr;  // cleared by the first pass's histogram kernel (may be null)
 };
 // Stable LSD radix sort of (key, val) pairs over bits [0, bits) in as few
 // passes of at most 8 bits as cover them; n_max bounds the grid, d_n (may be
@@ -249,6 +251,8 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
 // the records k_project put on the big-record list (tiles_touched of each)
 void launch_count_big(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,
                       uint32_t *big_list, uint32_t *big_n, hipStream_t s);
+// instances of the depth-ordered records; *big_n must be zero on entry (the
+// depth sort's first histogram pass clears it through DepthSortIO::zero_word)
 void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t *counts, const gsl_binrec *binrecs,
                  const DevCam *cams, const Layout &L, const int64_t *d_K, int64_t capacity, uint32_t *tile_ids,
                  uint32_t *gauss_ids, int32_t *d_status, uint32_t *big_list, uint32_t *big_n, const int64_t *d_V,

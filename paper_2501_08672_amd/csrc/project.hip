@@ -151,8 +151,9 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                                                  gsl_splat *__restrict__ out, gsl_binrec *__restrict__ bout,
                                                  uint32_t *__restrict__ kout, int32_t *__restrict__ tiles,
                                                  uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_n,
-                                                 float *__restrict__ g2d_zero)
+                                                 float *__restrict__ g2d_zero, uint32_t *__restrict__ queue_zero)
 {
+    if (queue_zero && blockIdx.x == 0 && threadIdx.x == 0) *queue_zero = 0u;
     __shared__ RecTiles rec[256];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -714,7 +715,7 @@ void launch_upload_cams(DevCam *d_cams, const DevCam *h_cams, int C, hipStream_t
 
 void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L, const DevOpts &o,
                     gsl_splat *splats, gsl_binrec *binrecs, uint32_t *depth_keys, int32_t *tiles_touched,
-                    uint32_t *big_list, uint32_t *big_n, hipStream_t s, float *g2d_zero)
+                    uint32_t *big_list, uint32_t *big_n, hipStream_t s, float *g2d_zero, uint32_t *queue_zero)
 {
     if (L.M == 0) return;
     const int64_t blocks = (L.M + 255) / 256;
@@ -722,11 +723,11 @@ void launch_project(const gsl_gaussians &g, const DevCam *cams, const Layout &L,
     if (g.sh_degree > 0)
         hipLaunchKernelGGL(k_project<true>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat,
                            g.opacity, g.color, g.sh, g.sh_degree, g.N, L.M, cams, o, splats, binrecs, depth_keys,
-                           tiles_touched, big_list, big_n, g2d_zero);
+                           tiles_touched, big_list, big_n, g2d_zero, queue_zero);
     else
         hipLaunchKernelGGL(k_project<false>, dim3((unsigned)blocks), dim3(256), 0, s, g.mean, g.scale, g.quat,
                            g.opacity, g.color, g.sh, 0, g.N, L.M, cams, o, splats, binrecs, depth_keys,
-                           tiles_touched, big_list, big_n, g2d_zero);
+                           tiles_touched, big_list, big_n, g2d_zero, queue_zero);
     launch_count_big(binrecs, cams, L, tiles_touched, big_list, big_n, s);
 }
 

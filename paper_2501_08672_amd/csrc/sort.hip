@@ -193,8 +193,10 @@ constexpr uint32_t kDropKey = 0xffffffffu;
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *__restrict__ keys, int64_t n_max,
                                                           const int64_t *__restrict__ d_n, int shift, int db,
                                                           uint32_t *__restrict__ hist, int64_t nb, bool drop,
-                                                          const int32_t *__restrict__ first_tiles)
+                                                          const int32_t *__restrict__ first_tiles,
+                                                          uint32_t *__restrict__ zero_word)
 {
+    if (zero_word && blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;
     __shared__ uint32_t s_cnt[kSortThreads / kWave][256];
     const int lane = threadIdx.x & 63, wv = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < (kSortThreads / kWave) * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
@@ -593,6 +595,7 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
     const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
     if (nb == 0 || bits <= 0) {
         if (d_kept) launch_fill_f64(reinterpret_cast<double *>(d_kept), 0.0, 1, s);  // all-zero bits == int64 0
+        if (io && io->zero_word) launch_fill_u32(io->zero_word, 0u, 1, s);
         return 0;
     }
     uint32_t *kin = keys, *vin = vals, *kout = keys2, *vout = vals2;
@@ -608,7 +611,7 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
         const uint32_t *kp = first ? kin0 : kin;
         const int32_t *ft = (io && first) ? io->first_tiles : nullptr;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kp, n_max, d_n, shift, db, hist,
-                           nb, drop, ft);
+                           nb, drop, ft, (io && first) ? io->zero_word : nullptr);
         hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << db), dim3(256), 0, s, hist, nb, hist_off, totals);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kp, vin, kout, vout, n_max,
                            d_n, shift, db, hist_off, nb, totals, drop, drop ? d_kept : nullptr, ft,
@@ -636,7 +639,7 @@ void launch_emit(const uint32_t *order, const uint32_t *offsets, const uint32_t 
                  hipStream_t s)
 {
     const int64_t blocks = L.M > 0 ? (L.M + 255) / 256 : 1;
-    launch_fill_u32(big_n, 0u, 1, s);
+    // *big_n is zero here: the depth sort's first histogram pass cleared it
     hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(256), 0, s, order, offsets, counts, binrecs, cams, L.N,
                        L.M, L.tile, d_K, capacity, tile_ids, gauss_ids, d_status, big_list, big_n, d_V);
     if (L.M > 0)
