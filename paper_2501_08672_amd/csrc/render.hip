@@ -6,9 +6,8 @@
 // a 16x16 or 8x8 tile) and each lane owns PPL pixels of one column of that
 // region (PPL = 4, or 1 for 8x8).  The tile's depth-ordered instance list is
 // staged through LDS in chunks of up to 256 splats (one lane loads one 48-B
-// record as three float4 and stores it, in the form the walks use, as one
-// 48-B LDS entry, see stage_splat) and every lane walks the chunk with
-// broadcast LDS reads,
+// record as three float4 and stores it in the form the walks use, see
+// stage_splat) and every lane walks the chunk with broadcast LDS reads,
 // evaluating its PPL pixels against each splat.  The walk ends for the wave
 // as soon as none of its pixels is still open.
 //
