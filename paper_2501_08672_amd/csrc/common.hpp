@@ -84,18 +84,21 @@ __device__ __forceinline__ bool ellipse_hits_rect(const EllipseTest &e, float x0
 {
     const bool in_x = e.mx >= x0 && e.mx <= x1, in_y = e.my >= y0 && e.my <= y1;
     if (in_x && in_y) return true;
+    // The clamp of the unconstrained minimiser to the edge is a median of
+    // three (the edge's ends are ordered), one v_med3_f32; the quadratic form
+    // takes two fused multiply-adds.
     float best = 3.0e38f;
     if (!in_x) {  // the vertical edge facing mu
         const float dx = (e.mx < x0 ? x0 : x1) - e.mx;
-        const float dy = fminf(fmaxf(e.kv * dx, y0 - e.my), y1 - e.my);
-        const float u = e.l11 * dx + e.l12 * dy, w = e.l22 * dy;
-        best = u * u + w * w;
+        const float dy = __builtin_amdgcn_fmed3f(e.kv * dx, y0 - e.my, y1 - e.my);
+        const float u = fmaf(e.l12, dy, e.l11 * dx), w = e.l22 * dy;
+        best = fmaf(u, u, w * w);
     }
     if (!in_y) {  // the horizontal edge facing mu
         const float dy = (e.my < y0 ? y0 : y1) - e.my;
-        const float dx = fminf(fmaxf(e.kh * dy, x0 - e.mx), x1 - e.mx);
-        const float u = e.l11 * dx + e.l12 * dy, w = e.l22 * dy;
-        best = fminf(best, u * u + w * w);
+        const float dx = __builtin_amdgcn_fmed3f(e.kh * dy, x0 - e.mx, x1 - e.mx);
+        const float u = fmaf(e.l12, dy, e.l11 * dx), w = e.l22 * dy;
+        best = fminf(best, fmaf(u, u, w * w));
     }
     return best <= e.kq;
 }

@@ -90,10 +90,12 @@ F32 = np.float32
 
 
 def _ellipse_hits_f32(mx, my, l11, l12, l22, kq, x0, x1, y0, y1):
-    """CPU recount of the binning rule in float32 (same operations, same order
-    as the kernel): minimum of |L d|^2 over a rectangle of pixel centres,
-    evaluated on the edges that face the centre.  Returns (hit, best) so
-    callers can spot exact-boundary cases."""
+    """CPU recount of the binning rule in float32 (the kernel's operations in
+    its order, except that the kernel fuses the two multiply-adds of each
+    quadratic form, which moves `best` by about an ulp): minimum of |L d|^2
+    over a rectangle of pixel centres, evaluated on the edges that face the
+    centre.  Returns (hit, best) so callers can spot boundary cases (within
+    1e-5 of kq, far wider than that rounding)."""
     cc = l12 * l12 + l22 * l22
     kv = -(l11 * l12) / cc
     kh = -l12 / l11
