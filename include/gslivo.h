@@ -297,10 +297,11 @@ GSL_API int gsl_window_variant(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, 
  * operation of the method: runs a kernel of independent dependency chains on
  * every CU (eight waves per SIMD) and writes the wave64 VALU instructions it
  * issued per CU per 2.4-GHz cycle.  mode 0: FP32 fused multiply-add; 1: FP32
- * multiply + v_exp_f32; 2: unsigned integer min + FP32 add.  d_sink: one
+ * multiply + v_exp_f32; 2: unsigned integer min + FP32 add; 3: FP32 add;
+ * 4: FP32 multiply.  d_sink: one
  * float of device memory the kernel could write (it never does).  Waits for
  * the device (default stream).  GSL_EINVAL for a NULL pointer, a mode outside
- * [0, 2] or host memory; GSL_EHIP when the launch or its timing fails. */
+ * [0, 4] or host memory; GSL_EHIP when the launch or its timing fails. */
 GSL_API int gsl_valu_probe(gsl_ctx *ctx, int32_t mode, float *d_sink, double *insts_per_cu_cycle);
 
 /* Forward render of a window (the compositing of Sec. II-B, eq. raster, over

@@ -1391,7 +1391,7 @@ int gsl_ieskf_visual_update(const double HtH_cam[36], const double Htz_cam[6], c
 int gsl_valu_probe(gsl_ctx *ctx, int32_t mode, float *d_sink, double *insts_per_cu_cycle)
 {
     if (!ctx || !d_sink || !insts_per_cu_cycle) return fail(GSL_EINVAL, "NULL argument");
-    if (mode < 0 || mode > 2) return fail(GSL_EINVAL, "probe mode %d not in [0, 2]", mode);
+    if (mode < 0 || mode > 4) return fail(GSL_EINVAL, "probe mode %d not in [0, 4]", mode);
     GSL_TRY(check_device(ctx));
     if (!is_memory(d_sink, false)) return fail(GSL_EINVAL, "d_sink is not device memory");
     if (run_valu_probe(mode, ctx->num_cus, d_sink, insts_per_cu_cycle) != 0)

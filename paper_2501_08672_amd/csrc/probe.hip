@@ -14,7 +14,9 @@ constexpr int kProbeChains = 8;
 
 // mode 0: one FP32 fused multiply-add per chain and iteration;
 // mode 1: an FP32 multiply and a v_exp_f32 per chain and iteration;
-// mode 2: an unsigned min and an FP32 add per chain and iteration.
+// mode 2: an unsigned min and an FP32 add per chain and iteration;
+// mode 3: one FP32 add per chain and iteration;
+// mode 4: one FP32 multiply per chain and iteration.
 // The result is stored only if negative, which no chain becomes, so the
 // loop cannot be removed and nothing is written.
 template <int MODE>
@@ -29,6 +31,8 @@ __global__ __launch_bounds__(256) void k_valu_probe(float *__restrict__ sink, in
             if (MODE == 0) x[i] = fmaf(x[i], b, c);
             if (MODE == 1) x[i] = __builtin_amdgcn_exp2f(x[i] * b);
             if (MODE == 2) x[i] = __uint_as_float(min(__float_as_uint(x[i]), 0x3f800000u)) + c;
+            if (MODE == 3) x[i] = x[i] + c;
+            if (MODE == 4) x[i] = x[i] * b;
         }
     }
     float s = 0.f;
@@ -44,10 +48,13 @@ int run_valu_probe(int mode, int num_cus, float *sink, double *rate)
     constexpr int kIters = 4096, kReps = 5;
     const int blocks = num_cus * 8;  // eight 4-wave workgroups per CU: eight waves per SIMD
     auto launch = [&](hipStream_t s) {
-        // b and c keep every chain positive and finite (x -> c / (1 - b), exp2 of a value below 1, min then add)
+        // b and c keep every chain positive and finite (x -> c / (1 - b), exp2 of a value below 1, min then
+        // add, a slow climb by c, a slow decay by b)
         if (mode == 0) hipLaunchKernelGGL(k_valu_probe<0>, dim3(blocks), dim3(256), 0, s, sink, kIters, 0.999f, 1e-4f);
         if (mode == 1) hipLaunchKernelGGL(k_valu_probe<1>, dim3(blocks), dim3(256), 0, s, sink, kIters, 0.5f, 1e-4f);
         if (mode == 2) hipLaunchKernelGGL(k_valu_probe<2>, dim3(blocks), dim3(256), 0, s, sink, kIters, 0.999f, 1e-4f);
+        if (mode == 3) hipLaunchKernelGGL(k_valu_probe<3>, dim3(blocks), dim3(256), 0, s, sink, kIters, 0.999f, 1e-4f);
+        if (mode == 4) hipLaunchKernelGGL(k_valu_probe<4>, dim3(blocks), dim3(256), 0, s, sink, kIters, 0.999f, 1e-4f);
     };
     hipStream_t s = nullptr;
     hipEvent_t e0, e1;
@@ -66,8 +73,8 @@ int run_valu_probe(int mode, int num_cus, float *sink, double *rate)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess || ms <= 0.f) return -1;
-    // wave64 VALU instructions of the loop: 8 per iteration in mode 0, 16 in modes 1 and 2
-    const double per_wave = (mode == 0 ? 8.0 : 16.0) * kIters;
+    // wave64 VALU instructions of the loop: 16 per iteration in modes 1 and 2, 8 in the others
+    const double per_wave = (mode == 1 || mode == 2 ? 16.0 : 8.0) * kIters;
     const double insts = per_wave * blocks * 4.0 * kReps;
     const double cu_cycles = (double)num_cus * (ms * 1e-3) * 2.4e9;
     *rate = insts / cu_cycles;

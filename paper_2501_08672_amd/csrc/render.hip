@@ -379,6 +379,17 @@ __device__ __forceinline__ PairEval eval_pair(const float4 &p0, const float4 &p1
 // the weights of a pixel add up to 1 - T_final.  A hit that would cross T_min
 // finishes the pixel (T becomes -|T|).  Every walk that composites uses this,
 // so their images agree bit for bit.
+// Order tests on float bit patterns as integer compares, which issue beside
+// the walks' floating-point work instead of taking its slots.  For x, y >= 0
+// the unsigned order of the bits is the float order; for a bound y >= 0 and
+// any x other than -0 and NaN (neither occurs where these are used) the
+// signed order decides x >= y as the float compare does, a negative x having
+// the sign bit set.
+__device__ __forceinline__ bool ge_nonneg(float x, float y) { return __float_as_uint(x) >= __float_as_uint(y); }
+__device__ __forceinline__ bool lt_nonneg(float x, float y) { return __float_as_uint(x) < __float_as_uint(y); }
+__device__ __forceinline__ bool ge_bound(float x, float y) { return __float_as_int(x) >= __float_as_int(y); }
+__device__ __forceinline__ bool positive(float x) { return __float_as_int(x) > 0; }
+
 struct CompStep {
     float T, w;
     bool acc;
@@ -387,9 +398,9 @@ struct CompStep {
 __device__ __forceinline__ CompStep comp_step(float T, float a, float amin, float Tmin)
 {
     CompStep r;
-    const bool hit = a >= amin;
+    const bool hit = ge_nonneg(a, amin);  // alpha and alpha_min are >= 0
     const float Tn = fmaf(-T, a, T);
-    r.acc = hit && Tn >= Tmin;
+    r.acc = hit && ge_bound(Tn, Tmin);     // Tn < 0 for a finished pixel, never -0
     float Tsel = r.acc ? Tn : T;
     r.w = T - Tsel;
     // A hit that does not contribute keeps Tsel == T, so the new state is
@@ -497,7 +508,7 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
     auto open = [&]() {
         bool o = false;
 #pragma unroll
-        for (int k = 0; k < PPL; k++) o |= ps.T[k] > 0.f;
+        for (int k = 0; k < PPL; k++) o |= positive(ps.T[k]);
         return o;
     };
     if (threadIdx.x == 0) stage_sentinel<Stage<CH, NW>, CH>(st);
@@ -539,7 +550,7 @@ __device__ __forceinline__ PixState<Geo<TS, NW>::PPL> fwd_walk(const RenderArgs 
                 // predicated: every lane evaluates, selects decide what changes
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const float T = ps.T[k];
-                cnt.eval(k, T > 0.f && j < CH);  // the sentinel is not a pair
+                cnt.eval(k, positive(T) && j < CH);  // the sentinel is not a pair
                 const CompStep cs = comp_step(T, e.alpha, amin, Tmin);
                 cnt.contrib(k, cs.acc);
                 ps.C0[k] = fmaf(cs.w, p1.z, ps.C0[k]);
@@ -673,7 +684,7 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
                 if (!any_lane(inwalk)) continue;    // wave-uniform skips
                 const PairEval e = eval_pair(p0, p1, ax, fy[k], amax);
                 const float ae = inwalk ? e.alpha : 0.f;
-                const bool hit = ae >= amin;        // one compare: its mask feeds the ballot
+                const bool hit = ge_nonneg(ae, amin);  // one compare: its mask feeds the ballot
                 if (!any_lane(hit)) continue;
                 used = true;
                 // predicated from here: a non-contributing lane takes alpha = 0,
@@ -691,7 +702,7 @@ __device__ __forceinline__ void bwd_walk(const RenderArgs &a, const TileInfo<TS,
                 const float ga = fmaf(Tk, vc, -SV[k] * r);
                 SV[k] = fmaf(w, vc, SV[k]);
                 // alpha is clamped where sigma G >= alpha_max: no gradient to sigma, G
-                const float gam = (hit && e.s < amax) ? ga : 0.f;
+                const float gam = (hit && lt_nonneg(e.s, amax)) ? ga : 0.f;
                 const float gp = e.s * gam;
                 const float hy = gp * e.dy;
                 P += gp;
@@ -996,7 +1007,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
     auto open = [&]() {
         bool o = false;
 #pragma unroll
-        for (int k = 0; k < PPL; k++) o |= T[k] > 0.f;
+        for (int k = 0; k < PPL; k++) o |= positive(T[k]);
         return o;
     };
     for (uint32_t start = ti.rs; start < ti.re; start += CH) {
@@ -1039,7 +1050,7 @@ __global__ __launch_bounds__((Geo<TS, NW>::BS)) void k_render_jvp(RenderArgs a)
                 }
                 // a contributor moves the state; others act as alpha = 0, dalpha = 0
                 const float al = acc ? e.alpha : 0.f;
-                const float sg = (acc && e.s < amax) ? e.alpha : 0.f;  // dalpha = sg * dpower
+                const float sg = (acc && lt_nonneg(e.s, amax)) ? e.alpha : 0.f;  // dalpha = sg * dpower
                 const float gx = fmaf(cA, dx, cB * e.dy), gy = fmaf(cB, dx, cC * e.dy);
                 const float k2 = -0.5f * dx * dx, k3 = -dx * e.dy, k4 = -0.5f * e.dy * e.dy;
                 float da[6];

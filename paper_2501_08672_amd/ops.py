@@ -91,7 +91,7 @@ def graph_count(ctx: "Context") -> int:
     return int(n.value)
 
 
-VALU_PROBE_MODES = {"fma": 0, "mul_exp2": 1, "umin_add": 2}
+VALU_PROBE_MODES = {"fma": 0, "mul_exp2": 1, "umin_add": 2, "add": 3, "mul": 4}
 
 
 def valu_probe(ctx: "Context", mode: str) -> float:

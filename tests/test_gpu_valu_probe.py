@@ -20,6 +20,7 @@ def test_probe_rates():
     for m, v in r.items():
         assert 0.05 < v < 16.0, (m, v)
     assert r["umin_add"] >= 0.9 * r["fma"]
+    assert r["add"] >= 0.9 * r["fma"]
 
 
 def test_probe_rejects_bad_arguments():
@@ -28,7 +29,7 @@ def test_probe_rejects_bad_arguments():
     sink = torch.zeros(1, device="cuda")
     out = C.c_double()
     L = A.lib()
-    assert L.gsl_valu_probe(ctx.h, 3, C.c_void_p(sink.data_ptr()), C.byref(out)) == A.GSL_EINVAL
+    assert L.gsl_valu_probe(ctx.h, 5, C.c_void_p(sink.data_ptr()), C.byref(out)) == A.GSL_EINVAL
     assert "mode" in L.gsl_last_error().decode()
     host = (C.c_float * 1)()
     assert L.gsl_valu_probe(ctx.h, 0, C.cast(host, C.c_void_p), C.byref(out)) == A.GSL_EINVAL

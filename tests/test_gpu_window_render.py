@@ -39,7 +39,7 @@ def _same(r, ref):
         assert torch.equal(getattr(r.proj, name), getattr(proj, name)), name
 
 
-@pytest.mark.parametrize("tile", [16, 32])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_window_render_is_the_three_calls(tile):
     O = ops()
     ctx = context()
@@ -58,6 +58,20 @@ def test_window_render_is_the_three_calls(tile):
     torch.cuda.synchronize()
     assert O.graph_count(ctx) == n0
     _same(r, ref)
+
+
+def test_window_render_sh_colour():
+    """SH degree 3 colour (evaluated in the projection) through the recorded
+    unit: bit-identical to the three calls."""
+    O = ops()
+    ctx = context()
+    sc = S.with_sh(_scene_multi(3000, 64), 3, 65)
+    g, cams, o = O.Gaussians.from_scene(sc), O.CameraSet(sc.cams), O.opts(32)
+    r = O.WindowRender(ctx, g, cams, o)
+    for _ in range(2):
+        r(use_graph=True)
+    torch.cuda.synchronize()
+    _same(r, _three_calls(O, ctx, g, cams, o, r.bins.capacity))
 
 
 def test_window_render_graph_follows_new_poses():
