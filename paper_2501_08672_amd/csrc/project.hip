@@ -424,6 +424,11 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
             for (int k = 0; k < kG2; k++) g2n[k] = src[k];
         }
         if (any) {
+            // The chain rule below may fuse its multiplies and adds (only this
+            // block's expressions: the projection it recomputes rounds as in
+            // every other kernel); gradients need no bit-level agreement with
+            // anything but themselves.
+#pragma clang fp contract(fast)
             const DevCam cam = cams[c];
             Proj p;
             project_cam(gl, cam, o.eps2d, o.near_z, p);
