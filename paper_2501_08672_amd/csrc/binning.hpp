@@ -63,21 +63,27 @@ __device__ __forceinline__ bool tile_hit(const EllipseTest &e, int W, int H, int
 }
 
 // Counting and emitting share one walk.  A wave expands the bbox tiles of its
-// 64 records into one flat list (an exclusive scan of the bbox tile counts
-// gives each record its segment) and tests 64 list entries per step, lane l
-// entry t0 + l; the entry's record is found by a binary search over the
-// lanes' inclusive scan values and its parameters are read from LDS.  Every
-// lane is busy whatever the mix of small and large splats, and no step waits
-// on a global load.  Within a record the hits keep bbox order (row-major),
-// so an instance's slot is the record's hits before this step plus the hits
-// of the same record on lower lanes.
+// records into one flat list (an exclusive scan of the bbox tile counts gives
+// each record its segment) and tests 64 list entries per step, lane l entry
+// t0 + l.  The records with at least one bbox tile sit in LDS in lane order,
+// compacted, so an entry's record index is the number of segments starting at
+// or before it, minus one: each record's lane marks its segment start in the
+// `mark` word of the array slot at that window position (tagged with the
+// step; these words are not part of the record in the slot), one ballot over
+// the marks gives the starts inside the window, and a popcount finishes the
+// lookup (one LDS round trip per step).  Every lane is busy whatever the mix of small and
+// large splats, and no step waits on a global load.  Within a record the hits
+// keep bbox order (row-major), so an instance's slot is the record's hits
+// before this window plus the hits of the same record on lower lanes.
 struct alignas(16) RecTiles {
     float mx, my, l11, l12, l22, kq, kv, kh;
     int32_t tx0, ty0, nx, tiles_x;
-    int32_t tile_base, W, H;
+    int32_t tile_base;
+    uint32_t wh;  // image width | height << 16 (both below 2^15)
     uint32_t gid;
     uint32_t base, limit, excl;
-    float rnx;  // 1 / nx
+    float rnx;     // 1 / nx
+    uint32_t mark;  // walk: segment-start tag of this window position
 };
 static_assert(sizeof(RecTiles) == 80, "RecTiles layout");
 
@@ -88,7 +94,7 @@ __device__ __forceinline__ int bbox_tiles(const gsl_binrec &s, int tile)
 }
 
 __device__ __forceinline__ void rec_fill(RecTiles &r, const gsl_binrec &s, const DevCam &cam, int tile,
-                                         uint32_t gid, uint32_t base, uint32_t limit)
+                                         uint32_t gid, uint32_t base, uint32_t limit, uint32_t excl)
 {
     const EllipseTest e = ellipse_test(s);
     r.mx = e.mx;
@@ -104,11 +110,11 @@ __device__ __forceinline__ void rec_fill(RecTiles &r, const gsl_binrec &s, const
     r.nx = s.x1 / tile - r.tx0 + 1;
     r.tiles_x = cam.tiles_x;
     r.tile_base = cam.tile_offset;
-    r.W = cam.W;
-    r.H = cam.H;
+    r.wh = (uint32_t)cam.W | ((uint32_t)cam.H << 16);
     r.gid = gid;
     r.base = base;
     r.limit = limit;
+    r.excl = excl;
     r.rnx = 1.0f / (float)r.nx;
 }
 
@@ -122,24 +128,46 @@ __device__ __forceinline__ uint64_t lane_range(int64_t lo, int64_t hi)
     return below_hi & ~below_lo;
 }
 
-// Walks the flat tile list of the wave's records (rec: this wave's 64
-// entries, already visible to all its lanes).  Returns the hit count of the
-// calling lane's own record ([excl, incl) is its segment).
+// Highest set bit of a non-zero 64-bit mask.
+__device__ __forceinline__ int top_bit(uint64_t m) { return 63 - __clzll(m); }
+
+// The caller's slot among the lanes of its wave that have bbox tiles (records
+// are stored at this index in the wave's RecTiles array).
+__device__ __forceinline__ int rec_slot(uint32_t nt, int lane)
+{
+    return __popcll(__ballot(nt != 0u) & lanemask_lt(lane));
+}
+
+// Walks the flat tile list of the wave's records.  rec: the wave's 64 slots,
+// holding its records with at least one bbox tile compacted in lane order
+// (rec_slot), visible to all its lanes.  [excl, incl) is the calling lane's own segment (empty for a lane without
+// bbox tiles).  Returns the hit count of the calling lane's own record.
 template <bool emit>
-__device__ __forceinline__ uint32_t expand_tiles(const RecTiles *rec, int lane, uint32_t excl, uint32_t incl,
-                                                 uint32_t total, int tile, uint32_t *__restrict__ tile_ids,
+__device__ __forceinline__ uint32_t expand_tiles(RecTiles *rec, int lane, uint32_t excl, uint32_t incl, uint32_t total,
+                                                 int tile, uint32_t *__restrict__ tile_ids,
                                                  uint32_t *__restrict__ gauss_ids)
 {
     uint32_t own = 0;
+    int started = 0;      // records whose segment starts before this window
+    uint32_t carry = 0;   // hits of the record running into this window, before it
+    const uint64_t upto = ~0ull >> (kWave - 1 - lane);  // lanes 0 .. lane
+    const uint64_t below = lanemask_lt(lane);
+    rec[lane].mark = 0u;  // no step's tag (t0 + 1 >= 1)
+    __builtin_amdgcn_wave_barrier();
     for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
         const uint32_t g = t0 + (uint32_t)lane;
-        int o = 0;  // number of lanes whose segment ends at or before g
-        for (int b = 32; b; b >>= 1)
-            if (__shfl(incl, o + b - 1, kWave) <= g) o += b;
+        const uint32_t tag = t0 + 1u;
+        if (incl > excl && excl >= t0 && excl - t0 < (uint32_t)kWave) rec[excl - t0].mark = tag;
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t starts = __ballot(rec[lane].mark == tag);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t mine = starts & upto;  // starts at or below this entry
+        int o = started + __popcll(mine) - 1;  // the entry's record (>= 0 for g < total)
+        o = o < 0 ? 0 : o;
         bool hit = false;
-        uint32_t bands = 0, slot = 0;
+        uint32_t bands = 0;
         int tx = 0, ty = 0;
-        const RecTiles &r = rec[o < kWave ? o : kWave - 1];
+        const RecTiles &r = rec[o];
         if (g < total) {
             const uint32_t t = g - r.excl;
             uint32_t q = (uint32_t)((float)t * r.rnx);
@@ -156,20 +184,23 @@ __device__ __forceinline__ uint32_t expand_tiles(const RecTiles *rec, int lane, 
             e.kq = r.kq;
             e.kv = r.kv;
             e.kh = r.kh;
-            hit = tile_hit(e, r.W, r.H, tile, tx, ty, emit ? &bands : nullptr);
+            hit = tile_hit(e, (int)(r.wh & 0xffffu), (int)(r.wh >> 16), tile, tx, ty, emit ? &bands : nullptr);
         }
         const uint64_t mask = __ballot(hit);
-        if (emit) {
-            const uint32_t before = __shfl(own, o < kWave ? o : kWave - 1, kWave);
-            if (hit) {
-                const uint64_t seg = lane_range((int64_t)r.excl - (int64_t)t0, lane);
-                slot = before + (uint32_t)__popcll(mask & seg);
-                if (slot < r.limit) {  // never beyond the record's counted range
-                    tile_ids[r.base + slot] = (uint32_t)(r.tile_base + ty * r.tiles_x + tx);
-                    gauss_ids[r.base + slot] = r.gid | (bands << kGidBits);
-                }
+        if (emit && hit) {
+            // the entry's record starts at the highest start at or below it,
+            // else it runs in from before the window with `carry` hits
+            const uint64_t seg = mine ? below & ~lanemask_lt(top_bit(mine)) : below;
+            const uint32_t slot = (mine ? 0u : carry) + (uint32_t)__popcll(mask & seg);
+            if (slot < r.limit) {  // never beyond the record's counted range
+                tile_ids[r.base + slot] = (uint32_t)(r.tile_base + ty * r.tiles_x + tx);
+                gauss_ids[r.base + slot] = r.gid | (bands << kGidBits);
             }
         }
+        // the record running into the next window: its hits up to there
+        const uint64_t last = starts ? ~lanemask_lt(top_bit(starts)) : ~0ull;
+        carry = (starts ? 0u : carry) + (uint32_t)__popcll(mask & last);
+        started += __popcll(starts);
         own += (uint32_t)__popcll(mask & lane_range((int64_t)excl - (int64_t)t0, (int64_t)incl - (int64_t)t0));
     }
     return own;

@@ -170,8 +170,10 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
     }
     uint32_t nt = 0;
     bool big = false;
+    int c = 0;
+    gsl_binrec br;
     if (m < M) {
-        const int c = (int)(m / N);
+        c = (int)(m / N);
         const int i = (int)(m - (int64_t)c * N);
         const DevCam cam = cams[c];
 
@@ -239,7 +241,6 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
             }
         }
         out[m] = sp;
-        gsl_binrec br;
         br.mx = sp.mx;
         br.my = sp.my;
         br.l11 = sp.l11;
@@ -257,16 +258,15 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
             push_big(big_list, big_n, (uint32_t)m);
             big = true;
             nt = 0;
-        } else if (nt) {
-            rec_fill(rec[threadIdx.x], br, cam, o.tile, 0, 0, 0);
         }
     }
     const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
-    rec[threadIdx.x].excl = excl;
+    const int wave0 = threadIdx.x & ~(kWave - 1);
+    const int slot = rec_slot(nt, lane);
+    if (nt) rec_fill(rec[wave0 + slot], br, cams[c], o.tile, 0, 0, 0, excl);
     const uint32_t total = __shfl(incl, kWave - 1, kWave);
     __syncthreads();
-    const uint32_t n = expand_tiles<false>(rec + (threadIdx.x & ~(kWave - 1)), lane, excl, incl, total, o.tile,
-                                           nullptr, nullptr);
+    const uint32_t n = expand_tiles<false>(rec + wave0, lane, excl, incl, total, o.tile, nullptr, nullptr);
     if (m < M && !big) tiles[m] = (int32_t)n;
 }
 

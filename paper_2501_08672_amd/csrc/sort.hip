@@ -500,27 +500,32 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ order
     if (j == 0) *d_status = K > capacity ? GSL_ECAPACITY : GSL_OK;
     if (K > capacity) return;  // uniform: every thread reads the same K
     const int64_t V = *d_V;    // records kept by the depth sort (the positions beyond carry no count)
-    uint32_t nt = 0;
+    uint32_t nt = 0, cnt = 0, m = 0, off = 0;
+    gsl_binrec s;
     if (j < V) {
         // three independent loads first (order[j] is only used where cnt != 0)
-        const uint32_t cnt = counts[j], m = order[j], off = offsets[j];
+        cnt = counts[j];
+        m = order[j];
+        off = offsets[j];
         if (cnt) {
-            const gsl_binrec s = binrecs[m];
-            const uint32_t c = m / (uint32_t)N;
+            s = binrecs[m];
             nt = (uint32_t)bbox_tiles(s, tile);
             if (nt > kBigTiles) {
                 push_big(big_list, big_n, (uint32_t)j);
                 nt = 0;
-            } else {
-                rec_fill(rec[threadIdx.x], s, cams[c], tile, m - c * (uint32_t)N, off, cnt);
             }
         }
     }
     const uint32_t incl = (uint32_t)wave_incl_scan_u64(nt, lane), excl = incl - nt;
-    rec[threadIdx.x].excl = excl;
+    const int wave0 = threadIdx.x & ~(kWave - 1);
+    const int slot = rec_slot(nt, lane);
+    if (nt) {
+        const uint32_t c = m / (uint32_t)N;
+        rec_fill(rec[wave0 + slot], s, cams[c], tile, m - c * (uint32_t)N, off, cnt, excl);
+    }
     const uint32_t total = __shfl(incl, kWave - 1, kWave);
     __syncthreads();
-    expand_tiles<true>(rec + (threadIdx.x & ~(kWave - 1)), lane, excl, incl, total, tile, tile_ids, gauss_ids);
+    expand_tiles<true>(rec + wave0, lane, excl, incl, total, tile, tile_ids, gauss_ids);
 }
 
 // Four consecutive positions per thread: the ids at k0-1 .. k0+4 (a sentinel
