@@ -45,9 +45,13 @@ constexpr int kG2 = 9;
 // power in the renderer.  Computed in float64 and rounded once, so every
 // kernel that needs it gets the same float.
 // kq of the alpha_min ellipse (binning record), in float64 then rounded once.
+__device__ __forceinline__ double ellipse_k64(float opacity, float alpha_min)
+{
+    return 2.0 * log((double)opacity / (double)alpha_min) + 0.01;
+}
 __device__ __forceinline__ float ellipse_k(float opacity, float alpha_min)
 {
-    return (float)(2.0 * log((double)opacity / (double)alpha_min) + 0.01);
+    return (float)ellipse_k64(opacity, alpha_min);
 }
 
 // Does the ellipse |L (x - mu)|^2 <= kq reach a rectangle [x0, x1] x [y0, y1]

@@ -187,6 +187,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
         sp.x0 = 0; sp.y0 = 0; sp.x1 = -1; sp.y1 = -1;
 
         Proj p;
+        double k = 0.0;  // the binning threshold, kept for the record's kq
         bool kept = compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
         if (kept) {
             const double W = cam.W, H = cam.H, g = o.guard;
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                 // |L d|^2 <= k  <=>  sigma G(d) >= alpha_min;  the bbox of that
                 // ellipse is |dx| <= sqrt(k a), |dy| <= sqrt(k c).  The margin
                 // covers float32 evaluation of the power in the renderer.
-                const double k = 2.0 * log(sigma / (double)o.alpha_min) + 0.01;
+                k = ellipse_k64(sp.opacity, o.alpha_min);
                 const double hx = sqrt(k * p.a) + 0.01, hy = sqrt(k * p.c) + 0.01;
                 double x0 = ceil(p.mx - hx - 0.5), x1 = floor(p.mx + hx - 0.5);
                 double y0 = ceil(p.my - hy - 0.5), y1 = floor(p.my + hy - 0.5);
@@ -210,9 +211,13 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
                     const int ix0 = (int)x0, ix1 = (int)x1, iy0 = (int)y0, iy1 = (int)y1;
                     sp.x0 = (int16_t)ix0; sp.x1 = (int16_t)ix1;
                     sp.y0 = (int16_t)iy0; sp.y1 = (int16_t)iy1;
-                    const double l22 = 1.0 / sqrt(p.c);
-                    const double l11 = sqrt(p.c / p.det);
-                    const double l12 = -p.b / sqrt(p.c * p.det);
+                    // L = [[sqrt(c/det), -b/sqrt(c det)], [0, 1/sqrt(c)]]: two
+                    // square roots and one division
+                    const double sc = sqrt(p.c), sd = sqrt(p.det);
+                    const double rcd = 1.0 / (sc * sd);
+                    const double l22 = sd * rcd;
+                    const double l11 = p.c * rcd;
+                    const double l12 = -p.b * rcd;
                     sp.mx = (float)p.mx;
                     sp.my = (float)p.my;
                     sp.l11 = (float)l11;
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
         br.l11 = sp.l11;
         br.l12 = sp.l12;
         br.l22 = sp.l22;
-        br.kq = kept ? ellipse_k(sp.opacity, o.alpha_min) : 0.f;
+        br.kq = kept ? (float)k : 0.f;  // ellipse_k, without a second logarithm
         br.x0 = sp.x0;
         br.y0 = sp.y0;
         br.x1 = sp.x1;
