@@ -238,6 +238,9 @@ void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint6
 // passes: the first pass reads record j's key from first_keys[j], drops it
 // when first_tiles[j] == 0 and takes j as its value; the last pass also
 // writes counts_out[p] = gather_tiles[value] at every output position p < kept.
+// When the record indices leave at least four high bits free, the values
+// carry the tile count there from the first pass (a count that does not fit
+// is marked all-ones and gathered), so the last pass gathers almost nothing.
 struct DepthSortIO {
     const uint32_t *first_keys;
     const int32_t *first_tiles;

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
                                                              int64_t *__restrict__ d_kept,
                                                              const int32_t *__restrict__ first_tiles,
                                                              const int32_t *__restrict__ gather_tiles,
-                                                             uint32_t *__restrict__ counts_out)
+                                                             uint32_t *__restrict__ counts_out, int pack_shift)
 {
     const uint32_t dmask = (1u << db) - 1u;
     constexpr int NW = kSortThreads / kWave;
@@ -350,6 +350,14 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     }
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) key[r] = tt[r] > 0 ? key[r] : kDropKey;
+    // with pack_shift, the record index takes the low pack_shift bits of the
+    // value and the tile count the rest (all-ones: look it up)
+    const uint32_t cnt_cap = pack_shift ? (0xffffffffu >> pack_shift) : 0u;
+    if (first_tiles && pack_shift) {
+#pragma unroll
+        for (int r = 0; r < kSortItems; r++)
+            val[r] |= min((uint32_t)max(tt[r], 0), cnt_cap) << pack_shift;
+    }
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const int64_t j = base + (int64_t)r * kWave + lane;
@@ -410,9 +418,17 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
         const uint32_t d = (k >> shift) & dmask;
         const uint32_t dst = s_glob[d] + (uint32_t)p - s_loc[d];
         kout[dst] = k;
-        vout[dst] = s_val[p];
-        // the last pass of the depth sort: the record's tile count at its place in depth order
-        if (counts_out) counts_out[dst] = (uint32_t)gather_tiles[s_val[p]];
+        const uint32_t v = s_val[p];
+        if (counts_out) {
+            // the last pass of the depth sort: the record index, and its tile
+            // count at its place in depth order
+            const uint32_t idx = pack_shift ? (v & ((1u << pack_shift) - 1u)) : v;
+            const uint32_t c = pack_shift ? (v >> pack_shift) : cnt_cap;
+            vout[dst] = idx;
+            counts_out[dst] = c != cnt_cap ? c : (uint32_t)gather_tiles[idx];
+        } else {
+            vout[dst] = v;
+        }
     }
 }
 
@@ -609,6 +625,14 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
     // as few passes of at most 8 bits as cover `bits`, the digits split evenly
     // (fewer buckets per pass write longer runs)
     const int passes = (bits + 7) / 8, db = (bits + passes - 1) / passes;
+    // the depth sort's values carry the tile counts in their free high bits
+    // when the record indices leave at least four
+    int pack_shift = 0;
+    if (io && io->counts_out) {
+        int ib = 1;
+        while (ib < 32 && ((uint64_t)1 << ib) < (uint64_t)n_max) ib++;
+        if (ib <= 28) pack_shift = ib;
+    }
     for (int shift = 0; shift < bits; shift += db) {
         // with d_kept the first pass drops kDropKey keys and counts the rest
         const bool drop = d_kept && shift == 0;
@@ -620,7 +644,8 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
         hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << db), dim3(256), 0, s, hist, nb, hist_off, totals);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kp, vin, kout, vout, n_max,
                            d_n, shift, db, hist_off, nb, totals, drop, drop ? d_kept : nullptr, ft,
-                           (io && last) ? io->gather_tiles : nullptr, (io && last) ? io->counts_out : nullptr);
+                           (io && last) ? io->gather_tiles : nullptr, (io && last) ? io->counts_out : nullptr,
+                           pack_shift);
         if (drop) d_n = d_kept;
         uint32_t *tk = kin, *tv = vin;
         kin = kout; vin = vout;
