@@ -42,16 +42,13 @@ constexpr int kG2 = 9;
 // ---------------------------------------------------------------- binning rule
 // Threshold of the alpha_min ellipse, |L d|^2 <= kq, with a margin of 0.01 on
 // top of 2 ln(sigma / alpha_min) that covers the float32 evaluation of the
-// power in the renderer.  Computed in float64 and rounded once, so every
-// kernel that needs it gets the same float.
-// kq of the alpha_min ellipse (binning record), in float64 then rounded once.
-__device__ __forceinline__ double ellipse_k64(float opacity, float alpha_min)
-{
-    return 2.0 * log((double)opacity / (double)alpha_min) + 0.01;
-}
+// power in the renderer.  The projection computes it once per record, in
+// float32 (the hardware base-2 logarithm, a few ulps: far inside the margin),
+// and stores it in the binning record that counting and emission both read.
 __device__ __forceinline__ float ellipse_k(float opacity, float alpha_min)
 {
-    return (float)ellipse_k64(opacity, alpha_min);
+    constexpr float kTwoLn2 = 1.3862943611198906f;
+    return fmaf(kTwoLn2, __builtin_amdgcn_logf(opacity / alpha_min), 0.01f);
 }
 
 // Does the ellipse |L (x - mu)|^2 <= kq reach a rectangle [x0, x1] x [y0, y1]

@@ -76,6 +76,9 @@ struct GaussLocal {
     double s[3];
 };
 
+// LEN: also the quaternion's length (the adjoint needs it); without it the
+// normalisation takes one reciprocal square root.
+template <bool LEN = true>
 __device__ __forceinline__ void load_gauss(const float *__restrict__ mean, const float *__restrict__ scale,
                                            const float *__restrict__ quat, int N, int i, GaussLocal &gl)
 {
@@ -83,8 +86,9 @@ __device__ __forceinline__ void load_gauss(const float *__restrict__ mean, const
     gl.py = mean[N + i];
     gl.pz = mean[2 * N + i];
     double q[4] = {quat[i], quat[N + i], quat[2 * N + i], quat[3 * N + i]};
-    gl.qlen = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const double il = 1.0 / gl.qlen;
+    const double qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    gl.qlen = LEN ? sqrt(qq) : 0.0;
+    const double il = LEN ? 1.0 / gl.qlen : rsqrt(qq);
     for (int k = 0; k < 4; k++) gl.qn[k] = q[k] * il;
     quat_rot(gl.qn, gl.Rg);
     gl.s[0] = scale[i];
@@ -129,12 +133,13 @@ __device__ __forceinline__ bool project_cam(const GaussLocal &gl, const DevCam &
     return true;
 }
 
+template <bool LEN = true>
 __device__ __forceinline__ bool compute_proj(const float *__restrict__ mean, const float *__restrict__ scale,
                                              const float *__restrict__ quat, int N, int i, const DevCam &cam,
                                              float eps2d, float near_z, Proj &p)
 {
     GaussLocal gl;
-    load_gauss(mean, scale, quat, N, i, gl);
+    load_gauss<LEN>(mean, scale, quat, N, i, gl);
     return project_cam(gl, cam, eps2d, near_z, p);
 }
 
@@ -187,8 +192,8 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
         sp.x0 = 0; sp.y0 = 0; sp.x1 = -1; sp.y1 = -1;
 
         Proj p;
-        double k = 0.0;  // the binning threshold, kept for the record's kq
-        bool kept = compute_proj(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
+        float kq = 0.f;  // the binning threshold of the record
+        bool kept = compute_proj<false>(mean, scale, quat, N, i, cam, o.eps2d, o.near_z, p);
         if (kept) {
             const double W = cam.W, H = cam.H, g = o.guard;
             if (p.mx < -g * W || p.mx > (1.0 + g) * W || p.my < -g * H || p.my > (1.0 + g) * H) kept = false;
@@ -196,11 +201,12 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
             const double sigma = sp.opacity;
             if (!(sigma >= (double)o.alpha_min)) kept = false;
             if (kept) {
-                // |L d|^2 <= k  <=>  sigma G(d) >= alpha_min;  the bbox of that
-                // ellipse is |dx| <= sqrt(k a), |dy| <= sqrt(k c).  The margin
-                // covers float32 evaluation of the power in the renderer.
-                k = ellipse_k64(sp.opacity, o.alpha_min);
-                const double hx = sqrt(k * p.a) + 0.01, hy = sqrt(k * p.c) + 0.01;
+                // |L d|^2 <= kq  <=>  sigma G(d) >= alpha_min (up to kq's margin);
+                // the bbox of that ellipse is |dx| <= sqrt(kq a), |dy| <= sqrt(kq c),
+                // widened by 0.01 px (far more than the float32 square roots' error)
+                kq = ellipse_k(sp.opacity, o.alpha_min);
+                const double hx = (double)sqrtf(kq * (float)p.a) + 0.01;
+                const double hy = (double)sqrtf(kq * (float)p.c) + 0.01;
                 double x0 = ceil(p.mx - hx - 0.5), x1 = floor(p.mx + hx - 0.5);
                 double y0 = ceil(p.my - hy - 0.5), y1 = floor(p.my + hy - 0.5);
                 x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ mean,
         br.l11 = sp.l11;
         br.l12 = sp.l12;
         br.l22 = sp.l22;
-        br.kq = kept ? (float)k : 0.f;  // ellipse_k, without a second logarithm
+        br.kq = kept ? kq : 0.f;
         br.x0 = sp.x0;
         br.y0 = sp.y0;
         br.x1 = sp.x1;
