@@ -53,8 +53,12 @@ struct Proj {
     double mx, my;
 };
 
+// The projection's arithmetic (quat_rot, load_gauss, project_cam) may fuse
+// multiplies and adds: every kernel inlines these same functions, so the
+// projection, its adjoint and the pose tangents still see one projection.
 __device__ __forceinline__ void quat_rot(const double q[4], double R[9])
 {
+#pragma clang fp contract(fast)
     const double w = q[0], x = q[1], y = q[2], z = q[3];
     R[0] = 1.0 - 2.0 * (y * y + z * z);
     R[1] = 2.0 * (x * y - w * z);
@@ -82,6 +86,7 @@ template <bool LEN = true>
 __device__ __forceinline__ void load_gauss(const float *__restrict__ mean, const float *__restrict__ scale,
                                            const float *__restrict__ quat, int N, int i, GaussLocal &gl)
 {
+#pragma clang fp contract(fast)
     gl.px = mean[i];
     gl.py = mean[N + i];
     gl.pz = mean[2 * N + i];
@@ -101,6 +106,7 @@ __device__ __forceinline__ void load_gauss(const float *__restrict__ mean, const
 __device__ __forceinline__ bool project_cam(const GaussLocal &gl, const DevCam &cam, float eps2d, float near_z,
                                             Proj &p)
 {
+#pragma clang fp contract(fast)
     const double px = gl.px, py = gl.py, pz = gl.pz;
     for (int k = 0; k < 9; k++) p.W[k] = cam.R[k];
     p.x = p.W[0] * px + p.W[1] * py + p.W[2] * pz + (double)cam.t[0];
@@ -435,10 +441,9 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
             for (int k = 0; k < kG2; k++) g2n[k] = src[k];
         }
         if (any) {
-            // The chain rule below may fuse its multiplies and adds (only this
-            // block's expressions: the projection it recomputes rounds as in
-            // every other kernel); gradients need no bit-level agreement with
-            // anything but themselves.
+            // The chain rule below may fuse its multiplies and adds, as the
+            // projection it recomputes does (gradients need no bit-level
+            // agreement with anything but themselves).
 #pragma clang fp contract(fast)
             const DevCam cam = cams[c];
             Proj p;
