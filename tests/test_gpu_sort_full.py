@@ -12,7 +12,9 @@ is strictly increasing in (tile id, depth bits, Gaussian index), which is the
 one sorted order of its own multiset (no two instances share a (tile,
 Gaussian) pair); each record's instance count is its tiles_touched; every
 instance's tile lies inside its record's bbox tile span; and the ranges are
-the first and one-past-last position of every tile.
+the first and one-past-last position of every tile.  The uneven batch also
+has records whose tile count does not fit beside the record index in the
+depth sort's values, so its last pass looks those counts up.
 """
 import numpy as np
 import pytest
@@ -60,6 +62,13 @@ def _check_full(sc, tile, min_K):
     cnt = np.bincount(cam * N + gid, minlength=C * N)
     np.testing.assert_array_equal(cnt, f["tiles_touched"].astype(np.int64).ravel())
     del cnt
+    # the depth sort carries tile counts in the free high bits of its values
+    # (record indices take ceil(log2(C N)) bits); a count that does not fit
+    # is looked up by the last pass: how many records took that path
+    ib = max(1, int(np.ceil(np.log2(C * N))))
+    cap = (1 << (32 - ib)) - 1 if ib <= 28 else 0
+    n_lookup = int((f["tiles_touched"] >= cap).sum()) if cap else int((f["tiles_touched"] > 0).sum())
+    print(f"tile {tile}: count field cap {cap}, records whose count is looked up {n_lookup}")
     # every instance's tile is inside the bbox tile span of its record
     local = tid - toff[cam]
     ix, iy = local % tx[cam], local // tx[cam]
@@ -76,7 +85,7 @@ def _check_full(sc, tile, min_K):
     np.testing.assert_array_equal(rng[occ, 0], starts[occ])
     np.testing.assert_array_equal(rng[occ, 1], ends[occ])
     assert np.all(rng[~occ, 0] == rng[~occ, 1])
-    return K
+    return K, n_lookup
 
 
 @pytest.fixture(scope="module")
@@ -95,4 +104,7 @@ def test_bin_sort_uneven_batch_bit_exact():
     sc, _ = S.config5()
     C, N = len(sc.cams), sc.n
     assert C * N > 1024 * 4096 * 4  # the depth pass spans several row-scan chunks
-    _check_full(sc, 16, 1024 * 4096 + 1)
+    _, n_lookup = _check_full(sc, 16, 1024 * 4096 + 1)
+    # 32M records leave 7 bits for the count: the records of 127 tiles or
+    # more take the look-up path of the last depth pass
+    assert n_lookup > 0
