@@ -312,6 +312,11 @@ def workloads_bench(ctx, ops, S, torch, steps, with_oracle):
     o1 = ops.opts(16)
     proj = ops.project(ctx, g1, cs1, o1)
     bins = ops.bin_sort(ctx, cs1, g1.N, o1, proj)
+    # the instance capacity both timed paths use: the window render's own
+    # sizing (K with 25 % headroom + 4096), which at this size keeps the
+    # tile sort in one workgroup
+    cap1 = int(bins.K * 1.25) + 4096
+    bins = ops.bin_sort(ctx, cs1, g1.N, o1, proj, capacity=cap1)
     ops.render_fwd(ctx, cs1, g1.N, o1, proj, bins)
     torch.cuda.synchronize()
     times = []
@@ -325,7 +330,7 @@ def workloads_bench(ctx, ops, S, torch, steps, with_oracle):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     # the same render as one recorded unit (gsl_window_render), replayed
-    r1 = ops.WindowRender(ctx, g1, cs1, o1, capacity=bins.capacity)
+    r1 = ops.WindowRender(ctx, g1, cs1, o1, capacity=cap1)
     for _ in range(20):
         r1(use_graph=True)
     torch.cuda.synchronize()

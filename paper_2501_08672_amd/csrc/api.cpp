@@ -329,12 +329,15 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     io.gather_tiles = proj->tiles_touched;
     io.counts_out = counts;
     io.zero_word = at<uint32_t>(ws, W.misc + 128);  // the emit's big-record counter
+    // 2. instance offsets in that order (a one-workgroup sort scans them itself)
+    io.offsets_out = offsets;
+    io.d_total = bins->d_K;
     int where = launch_radix_sort(dkey, dval, dkey2, dval2, L.M, nullptr, 32, hist, hist_off, totals, s, d_V, &io);
     const uint32_t *order = where ? dval2 : dval;
-    // 2. instance offsets in that order
-    launch_scan_u32(counts, offsets, L.M, partial, bins->d_K, s, d_V);
-    // 3. emit and sort by tile; the pass count decides which buffer is emitted into
-    const int passes = (L.tile_bits + 7) / 8;
+    if (!radix_one_block(L.M)) launch_scan_u32(counts, offsets, L.M, partial, bins->d_K, s, d_V);
+    // 3. emit and sort by tile; the pass count decides which buffer is emitted
+    // into (a one-workgroup sort writes the other buffer, as one pass does)
+    const int passes = L.tile_bits <= 0 ? 0 : radix_one_block(bins->capacity_K) ? 1 : (L.tile_bits + 7) / 8;
     uint32_t *ek = bins->tile_ids, *ev = bins->gauss_ids;
     uint32_t *ak = at<uint32_t>(ws, W.ikey2), *av = at<uint32_t>(ws, W.ival2);
     if (passes & 1) std::swap(ek, ak), std::swap(ev, av);

@@ -244,13 +244,24 @@ struct DepthSortIO {
     const int32_t *gather_tiles;
     uint32_t *counts_out;
     uint32_t *zero_word = nullptr;  // cleared by the first pass's histogram kernel (may be null)
+    // single-workgroup sorts (radix_one_block) also write the exclusive scan of
+    // counts_out (positions at or beyond the kept count get the total) and
+    // the total; the caller then skips its own scan
+    uint32_t *offsets_out = nullptr;
+    int64_t *d_total = nullptr;
 };
+// Up to this many keys one workgroup sorts them through all passes in LDS in
+// one launch (and, for the depth sort, scans the tile counts): at these sizes
+// the three launches per pass of the multi-block sort cost more than the work.
+constexpr int64_t kOneBlockSortKeys = 16384;
+inline bool radix_one_block(int64_t n_max) { return n_max > 0 && n_max <= kOneBlockSortKeys; }
 // Stable LSD radix sort of (key, val) pairs over bits [0, bits) in as few
 // passes of at most 8 bits as cover them; n_max bounds the grid, d_n (may be
 // null) holds the live count on the device.  Returns 1 when the result is in
 // keys2/vals2, 0 when in keys/vals.  With d_kept, keys 0xffffffff are dropped
 // by the first pass and the number kept is written to *d_kept (later passes
-// sort only those).
+// sort only those).  For n_max <= kOneBlockSortKeys one workgroup runs every
+// pass (and, with io->offsets_out, the scan of the counts) in one launch.
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *totals,
                       hipStream_t s, int64_t *d_kept = nullptr, const DepthSortIO *io = nullptr);

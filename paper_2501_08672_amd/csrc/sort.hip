@@ -432,6 +432,168 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
     }
 }
 
+// ------------------------------------------------------------------ one-block sort
+
+// The whole sort of n <= kOneBlockSortKeys pairs by one workgroup of 1024
+// lanes: the keys stay in registers (R per lane, R the smallest power of two
+// with 1024 R >= n; wave w owns positions [64 R w, 64 R (w + 1)), row r at
+// 64 R w + 64 r + lane, so small sorts spread over every wave) and each pass ranks them with
+// the same ballot multisplit as the multi-block scatter, reorders them
+// through LDS and reads them back in position order, so the result is the
+// multi-block sort's, bit for bit.  The depth sort's extras are folded in as
+// there: the first pass reads first_keys, drops records without tiles and
+// packs each tile count beside its record index; the last pass unpacks them,
+// writes counts_out and, with offsets_out, their exclusive scan and total.
+constexpr int kObThreads = 1024;
+constexpr int kObWaves = kObThreads / kWave;
+
+template <int R>
+__global__ __launch_bounds__(kObThreads) void k_rs_one_block(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, int64_t n_max, const int64_t *__restrict__ d_n, int bits, int db, int64_t *d_kept,
+    const int32_t *__restrict__ first_tiles, const int32_t *__restrict__ gather_tiles,
+    uint32_t *__restrict__ counts_out, uint32_t *__restrict__ offsets_out, int64_t *__restrict__ d_total,
+    int pack_shift, uint32_t *__restrict__ zero_word)
+{
+    constexpr int kObItems = R;
+    __shared__ uint32_t s_key[kObThreads * R];
+    __shared__ uint32_t s_val[kObThreads * R];
+    __shared__ uint32_t s_cnt[kObWaves][256];
+    __shared__ uint32_t s_loc[256];
+    __shared__ uint32_t s_wsum[kObWaves];
+    __shared__ uint32_t s_n;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    if (zero_word && threadIdx.x == 0) *zero_word = 0u;
+    const uint32_t dmask = (1u << db) - 1u;
+    const uint32_t cnt_cap = pack_shift ? (0xffffffffu >> pack_shift) : 0u;
+    int64_t n = live_count(d_n, n_max);
+    uint32_t key[kObItems], val[kObItems];
+    int rank[kObItems];
+#pragma unroll
+    for (int r = 0; r < kObItems; r++) {
+        const int64_t p = (int64_t)wv * (kObItems * kWave) + r * kWave + lane;
+        key[r] = p < n ? kin[p] : kDropKey;
+        val[r] = p < n ? (first_tiles ? (uint32_t)p : vin[p]) : 0u;
+        if (first_tiles) {
+            const int32_t t = p < n ? first_tiles[p] : 0;
+            key[r] = t > 0 ? key[r] : kDropKey;
+            if (pack_shift) val[r] |= min((uint32_t)max(t, 0), cnt_cap) << pack_shift;
+        }
+    }
+    const bool drop = d_kept != nullptr;  // the first pass drops kDropKey keys
+    for (int shift = 0; shift < bits; shift += db) {
+        const bool first = shift == 0;
+        for (int k = threadIdx.x; k < kObWaves * 256; k += kObThreads) (&s_cnt[0][0])[k] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kObItems; r++) {
+            const int64_t p = (int64_t)wv * (kObItems * kWave) + r * kWave + lane;
+            const bool valid = p < n && !(drop && first && key[r] == kDropKey);
+            const uint32_t d = (key[r] >> shift) & dmask;
+            const uint64_t peers = digit_peers(d, valid, db);
+            const uint32_t before = valid ? s_cnt[wv][d] : 0u;
+            rank[r] = valid ? (int)(before + (uint32_t)__popcll(peers & lanemask_lt(lane))) : -1;
+            if (valid && (int)(__ffsll((unsigned long long)peers) - 1) == lane) s_cnt[wv][d] = before + __popcll(peers);
+        }
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            const int d = threadIdx.x;
+            uint32_t run = 0;
+            for (int w = 0; w < kObWaves; w++) {
+                const uint32_t c = s_cnt[w][d];
+                s_cnt[w][d] = run;
+                run += c;
+            }
+            s_loc[d] = run;
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            // exclusive scan of the 256 digit totals (4 per lane)
+            uint32_t t[4], sum = 0;
+            for (int k = 0; k < 4; k++) {
+                t[k] = s_loc[lane * 4 + k];
+                sum += t[k];
+            }
+            uint32_t inc = sum;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t o = __shfl_up(inc, off, kWave);
+                if (lane >= off) inc += o;
+            }
+            uint32_t run = inc - sum;
+            for (int k = 0; k < 4; k++) {
+                s_loc[lane * 4 + k] = run;
+                run += t[k];
+            }
+            if (lane == kWave - 1) s_n = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kObItems; r++) {
+            if (rank[r] < 0) continue;
+            const uint32_t d = (key[r] >> shift) & dmask;
+            const uint32_t pos = s_loc[d] + s_cnt[wv][d] + (uint32_t)rank[r];
+            s_key[pos] = key[r];
+            s_val[pos] = val[r];
+        }
+        __syncthreads();
+        n = s_n;  // the kept keys (all of them after the first pass)
+        if (first && d_kept && threadIdx.x == 0) *d_kept = n;
+#pragma unroll
+        for (int r = 0; r < kObItems; r++) {
+            const int64_t p = (int64_t)wv * (kObItems * kWave) + r * kWave + lane;
+            key[r] = p < n ? s_key[p] : kDropKey;
+            val[r] = p < n ? s_val[p] : 0u;
+        }
+        __syncthreads();
+    }
+    // out, in position order (the last pass left it in LDS and in registers)
+    uint32_t cnt[kObItems];
+#pragma unroll
+    for (int r = 0; r < kObItems; r++) {
+        const int64_t p = (int64_t)wv * (kObItems * kWave) + r * kWave + lane;
+        cnt[r] = 0u;
+        if (p >= n) continue;
+        kout[p] = key[r];
+        if (counts_out) {
+            const uint32_t idx = pack_shift ? (val[r] & ((1u << pack_shift) - 1u)) : val[r];
+            const uint32_t c = pack_shift ? (val[r] >> pack_shift) : cnt_cap;
+            cnt[r] = c != cnt_cap ? c : (uint32_t)gather_tiles[idx];
+            vout[p] = idx;
+            counts_out[p] = cnt[r];
+        } else {
+            vout[p] = val[r];
+        }
+    }
+    if (!offsets_out) return;
+    // exclusive scan of the counts in position order: a wave's rows in turn,
+    // then the waves' totals
+    uint32_t run = 0;
+    uint32_t excl[kObItems];
+#pragma unroll
+    for (int r = 0; r < kObItems; r++) {
+        uint32_t inc = cnt[r];
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        excl[r] = run + inc - cnt[r];
+        run += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) s_wsum[wv] = run;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    for (int w = 0; w < kObWaves; w++) {
+        base += w < wv ? s_wsum[w] : 0u;
+        total += s_wsum[w];
+    }
+#pragma unroll
+    for (int r = 0; r < kObItems; r++) {
+        const int64_t p = (int64_t)wv * (kObItems * kWave) + r * kWave + lane;
+        if (p < n_max) offsets_out[p] = p < n ? base + excl[r] : total;
+    }
+    if (d_total && threadIdx.x == 0) *d_total = (int64_t)total;
+}
+
 // ------------------------------------------------------------------ binning
 
 // The listed records, one per workgroup of 256 lanes (grid-stride over the
@@ -621,6 +783,27 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
     }
     uint32_t *kin = keys, *vin = vals, *kout = keys2, *vout = vals2;
     const uint32_t *kin0 = io ? io->first_keys : keys;  // the first pass reads its keys from here
+    if (radix_one_block(n_max)) {
+        const int passes1 = (bits + 7) / 8, db1 = (bits + passes1 - 1) / passes1;
+        int ps = 0;
+        if (io && io->counts_out) {
+            int ib = 1;
+            while (ib < 32 && ((uint64_t)1 << ib) < (uint64_t)n_max) ib++;
+            if (ib <= 28) ps = ib;
+        }
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(1), dim3(kObThreads), 0, s, kin0, vals, keys2, vals2, n_max, d_n, bits, db1,
+                               d_kept, io ? io->first_tiles : nullptr, io ? io->gather_tiles : nullptr,
+                               io ? io->counts_out : nullptr, io ? io->offsets_out : nullptr,
+                               io ? io->d_total : nullptr, ps, io ? io->zero_word : nullptr);
+        };
+        if (n_max <= kObThreads) go(k_rs_one_block<1>);
+        else if (n_max <= 2 * kObThreads) go(k_rs_one_block<2>);
+        else if (n_max <= 4 * kObThreads) go(k_rs_one_block<4>);
+        else if (n_max <= 8 * kObThreads) go(k_rs_one_block<8>);
+        else go(k_rs_one_block<16>);
+        return 1;
+    }
     int where = 0;
     // as few passes of at most 8 bits as cover `bits`, the digits split evenly
     // (fewer buckets per pass write longer runs)
