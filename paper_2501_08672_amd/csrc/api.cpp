@@ -343,9 +343,11 @@ void do_bin_sort(const Prepared &p, const gsl_proj *proj, gsl_bins *bins, void *
     if (passes & 1) std::swap(ek, ak), std::swap(ev, av);
     launch_emit(order, offsets, counts, proj->binrecs, at<DevCam>(ws, W.cams), L, bins->d_K, bins->capacity_K, ek, ev,
                 bins->d_status, at<uint32_t>(ws, W.big), at<uint32_t>(ws, W.misc + 128), d_V, s);
-    launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, totals, s);
-    // 4. per-tile ranges
-    launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);
+    // 4. per-tile ranges (a one-workgroup tile sort writes them itself)
+    const bool one = L.tile_bits > 0 && radix_one_block(bins->capacity_K);
+    launch_radix_sort(ek, ev, ak, av, bins->capacity_K, bins->d_K, L.tile_bits, hist, hist_off, totals, s, nullptr,
+                      nullptr, one ? bins->ranges : nullptr, L.T_total);
+    if (!one) launch_ranges(bins->tile_ids, bins->d_K, bins->capacity_K, L.T_total, bins->ranges, s);
 }
 
 RenderArgs render_args(const Prepared &p, const gsl_proj *proj, const gsl_bins *bins, void *ws)

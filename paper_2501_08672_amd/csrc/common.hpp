@@ -261,10 +261,14 @@ inline bool radix_one_block(int64_t n_max) { return n_max > 0 && n_max <= kOneBl
 // keys2/vals2, 0 when in keys/vals.  With d_kept, keys 0xffffffff are dropped
 // by the first pass and the number kept is written to *d_kept (later passes
 // sort only those).  For n_max <= kOneBlockSortKeys one workgroup runs every
-// pass (and, with io->offsets_out, the scan of the counts) in one launch.
+// pass (and, with io->offsets_out, the scan of the counts) in one launch; it
+// then also writes the per-key-value ranges [first, one past last) of the
+// sorted keys into ranges[2 * T_total] when ranges is given (keys >= T_total
+// ignored), which the caller need not compute.
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *totals,
-                      hipStream_t s, int64_t *d_kept = nullptr, const DepthSortIO *io = nullptr);
+                      hipStream_t s, int64_t *d_kept = nullptr, const DepthSortIO *io = nullptr,
+                      uint32_t *ranges = nullptr, int64_t T_total = 0);
 // tiles_touched of every (camera, Gaussian) record under the binning rule
 // the records k_project put on the big-record list (tiles_touched of each)
 void launch_count_big(const gsl_binrec *binrecs, const DevCam *cams, const Layout &L, int32_t *tiles_touched,

@@ -453,7 +453,7 @@ __global__ __launch_bounds__(kObThreads) void k_rs_one_block(
     uint32_t *__restrict__ vout, int64_t n_max, const int64_t *__restrict__ d_n, int bits, int db, int64_t *d_kept,
     const int32_t *__restrict__ first_tiles, const int32_t *__restrict__ gather_tiles,
     uint32_t *__restrict__ counts_out, uint32_t *__restrict__ offsets_out, int64_t *__restrict__ d_total,
-    int pack_shift, uint32_t *__restrict__ zero_word)
+    int pack_shift, uint32_t *__restrict__ zero_word, uint32_t *__restrict__ ranges, int64_t T_total)
 {
     constexpr int kObItems = R;
     __shared__ uint32_t s_key[kObThreads * R];
@@ -562,6 +562,23 @@ __global__ __launch_bounds__(kObThreads) void k_rs_one_block(
             counts_out[p] = cnt[r];
         } else {
             vout[p] = val[r];
+        }
+    }
+    if (ranges) {
+        // the tile sort: every tile's first and one-past-last position (empty
+        // tiles [0, 0)), from the sorted keys still in LDS.  A live count above
+        // n_max (the instances overflowed their capacity and were never
+        // emitted) leaves every tile empty, so nothing reads those keys' ids.
+        for (int64_t t = threadIdx.x; t < 2 * T_total; t += kObThreads) ranges[t] = 0u;
+        __syncthreads();
+        const bool overflow = d_n && *d_n > n_max;
+#pragma unroll
+        for (int r = 0; r < kObItems; r++) {
+            if (overflow) break;
+            const int64_t p = (int64_t)wv * (kObItems * kWave) + r * kWave + lane;
+            if (p >= n || (int64_t)key[r] >= T_total) continue;  // never trust an id as an index
+            if (p == 0 || s_key[p - 1] != key[r]) ranges[2 * (int64_t)key[r]] = (uint32_t)p;
+            if (p == n - 1 || s_key[p + 1] != key[r]) ranges[2 * (int64_t)key[r] + 1] = (uint32_t)(p + 1);
         }
     }
     if (!offsets_out) return;
@@ -773,7 +790,7 @@ void launch_scan_u32(const uint32_t *counts, uint32_t *offsets, int64_t n, uint6
 
 int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t *vals2, int64_t n_max,
                       const int64_t *d_n, int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *totals,
-                      hipStream_t s, int64_t *d_kept, const DepthSortIO *io)
+                      hipStream_t s, int64_t *d_kept, const DepthSortIO *io, uint32_t *ranges, int64_t T_total)
 {
     const int64_t nb = (n_max + kSortTile - 1) / kSortTile;
     if (nb == 0 || bits <= 0) {
@@ -795,7 +812,7 @@ int launch_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys2, uint32_t 
             hipLaunchKernelGGL(kern, dim3(1), dim3(kObThreads), 0, s, kin0, vals, keys2, vals2, n_max, d_n, bits, db1,
                                d_kept, io ? io->first_tiles : nullptr, io ? io->gather_tiles : nullptr,
                                io ? io->counts_out : nullptr, io ? io->offsets_out : nullptr,
-                               io ? io->d_total : nullptr, ps, io ? io->zero_word : nullptr);
+                               io ? io->d_total : nullptr, ps, io ? io->zero_word : nullptr, ranges, T_total);
         };
         if (n_max <= kObThreads) go(k_rs_one_block<1>);
         else if (n_max <= 2 * kObThreads) go(k_rs_one_block<2>);
