@@ -113,3 +113,24 @@ def test_one_block_sort_nothing_binned():
     f, K, tid, gid, rng = _bins(sc, 16, ONE_BLOCK)
     assert K == 0
     _check(sc, 16, f, K, tid, gid, rng)
+
+
+def test_one_block_tile_sort_over_capacity():
+    # more instances than capacity: the emission writes none, the status says
+    # so, and every tile's range is empty (nothing reads the unwritten ids)
+    cams = [_cam(96, 80, 90.0, 71)]
+    sc = S.random_scene(1500, cams[0], 72, zmin=1.0, zmax=4.0)
+    sc.cams = cams
+    O = ops()
+    ctx = context()
+    o = O.opts(16)
+    g = O.Gaussians.from_scene(sc)
+    cs = O.CameraSet(sc.cams)
+    proj = O.project(ctx, g, cs, o)
+    K = int(proj.fields()["tiles_touched"].astype(np.int64).sum())
+    assert K > 2
+    b = O.bin_sort(ctx, cs, g.N, o, proj, capacity=K // 2, grow=False)
+    torch.cuda.synchronize()
+    assert int(b.d_status.item()) == O.A.GSL_ECAPACITY
+    assert b.K == K
+    assert not b.ranges.cpu().numpy().any()
