@@ -435,15 +435,17 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *__r
 // ------------------------------------------------------------------ one-block sort
 
 // The whole sort of n <= kOneBlockSortKeys pairs by one workgroup of 1024
-// lanes: the keys stay in registers (R per lane, R the smallest power of two
-// with 1024 R >= n; wave w owns positions [64 R w, 64 R (w + 1)), row r at
-// 64 R w + 64 r + lane, so small sorts spread over every wave) and each pass ranks them with
-// the same ballot multisplit as the multi-block scatter, reorders them
-// through LDS and reads them back in position order, so the result is the
-// multi-block sort's, bit for bit.  The depth sort's extras are folded in as
-// there: the first pass reads first_keys, drops records without tiles and
-// packs each tile count beside its record index; the last pass unpacks them,
-// writes counts_out and, with offsets_out, their exclusive scan and total.
+// lanes.  The keys stay in registers: R per lane, R the smallest power of two
+// with 1024 R >= n_max; wave w owns positions [64 R w, 64 R (w + 1)), row r
+// at 64 R w + 64 r + lane, so a small sort spreads over every wave.  Each
+// pass ranks them with the same ballot multisplit as the multi-block
+// scatter, reorders them through LDS and reads them back in position order:
+// a stable sort, so the result is the multi-block sort's, bit for bit.  The
+// depth sort's extras are folded in as there (the first pass reads
+// first_keys, drops records without tiles and packs each tile count beside
+// its record index; the last pass unpacks them and writes counts_out), and
+// with offsets_out the counts' exclusive scan and total follow; with ranges
+// (the tile sort), every tile's range of positions.
 constexpr int kObThreads = 1024;
 constexpr int kObWaves = kObThreads / kWave;
 
