@@ -408,6 +408,29 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
+// One DPP move of a double (both halves with the same control; rows the
+// masks leave out read 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum of a wave's doubles in a fixed order, by DPP moves (no LDS round
+// trips): the total lands in lane 63.
+__device__ __forceinline__ double dpp_sum63_f64(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);   // quad [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);   // quad [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31
+    return v;
+}
+
 __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
     const float *__restrict__ mean, const float *__restrict__ scale, const float *__restrict__ quat, int N, int C,
     const DevCam *__restrict__ cams, DevOpts o, const float *__restrict__ g2d, gsl_grads out, int accumulate,
@@ -543,8 +566,8 @@ __global__ __launch_bounds__(kPoseThreads) void k_project_bwd(
         // of the workgroup sees this camera)
         if (__syncthreads_or(any)) {
             for (int k = 0; k < 6; k++) {
-                const double v = wave_sum_f64(pose[k]);
-                if (lane == 0) s_red[wv][k] = v;
+                const double v = dpp_sum63_f64(pose[k]);
+                if (lane == kWave - 1) s_red[wv][k] = v;
             }
             __syncthreads();
             if (threadIdx.x < 6) {
@@ -649,8 +672,8 @@ __global__ __launch_bounds__(kPoseThreads) void k_sh_bwd(const float *__restrict
         }
         if (__syncthreads_or(any)) {
             for (int k = 0; k < 3; k++) {
-                const double v = wave_sum_f64(gt[k]);
-                if (lane == 0) s_red[wv][k] = v;
+                const double v = dpp_sum63_f64(gt[k]);
+                if (lane == kWave - 1) s_red[wv][k] = v;
             }
             __syncthreads();
             if (threadIdx.x < 6) {
