@@ -1022,7 +1022,11 @@ int gsl_window_tune(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *cams
                 rc = fail(GSL_ECAPACITY, "capacity_K too small for tile %d", tiles[ti]);
                 break;
             }
-            const int reps = 5;
+            // the status read left the GPU idle, and its clock takes some ten
+            // steps to come back: time only after untimed steps
+            for (int r = 0; r < 6; r++)
+                do_window(ctx, p, g, target, loss, proj, bins, nullptr, d_loss, grads, workspace, variant, s);
+            const int reps = 8;
             (void)hipEventRecord(e0, s);
             for (int r = 0; r < reps; r++)
                 do_window(ctx, p, g, target, loss, proj, bins, nullptr, d_loss, grads, workspace, variant, s);
