@@ -206,7 +206,8 @@ GSL_API int gsl_project(gsl_ctx *ctx, const gsl_gaussians *g, const gsl_camera *
  * rectangle its alpha_min ellipse reaches (a superset of every pixel where
  * alpha >= alpha_min, so the image does not depend on the tile size); N must
  * be below 2^28.  Writes K and, when K > capacity_K, GSL_ECAPACITY to
- * *d_status (then the bins are incomplete; call again with more capacity). */
+ * *d_status (then no instance is emitted and every tile's range is empty,
+ * so a render of these bins draws nothing; call again with more capacity). */
 GSL_API int gsl_bin_sort(gsl_ctx *ctx, const gsl_camera *cams, int32_t C, int32_t N, const gsl_opts *opts,
                  const gsl_proj *proj, gsl_bins *bins, void *workspace, size_t workspace_bytes, void *stream);
 
